@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""NLL + gradient evaluations per second at 1M events x 20 waves on one MI355X.
+
+Workload (the fit-iteration hot path of Eq. 3 in arXiv:1108.5673): 1,000,000
+synthetic J/psi -> gamma K+K- shaped data events, 20 waves (10 Breit-Wigner
+masses in 1.0-2.6 GeV x J in {0, 2}), MC normalisation from 2M accepted of 4M
+generated flat events, and 200 parameter points along a seeded random walk
+starting at the generating point.  One step = one pwa_nll_grad call: the NLL and
+its 40-component gradient for one parameter point, V in and results out through
+host memory, with the table already resident in HBM.
+
+Timed paths: the fused one-pass kernel over the packed complex64 table (the
+reported value), the plain two-pass FP64 table kernels (the baseline), and the
+fused kernel over a complex128 table (ablation).  The main kernel's device time
+is taken with HIP events on its own stream inside the timed region and turned
+into achieved bandwidth from the algorithmic bytes (1680 B per event).  The CPU
+oracle is timed on a bounded sample of the same walk on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "table_fused_w20_n1m_traffic.json")
+KERNEL_SOURCES = ["paper_1108_5673_amd/csrc/k_table.hip", "paper_1108_5673_amd/csrc/wave_ops.h",
+                  "paper_1108_5673_amd/csrc/pwa_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def time_model(model, points, steps, warmup):
+    import torch
+    for k in range(warmup):
+        model.nll_grad(points[k % len(points)])
+    torch.cuda.synchronize()
+    model.set_timing(True)
+    model.timing()
+    results = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        results.append(model.nll_grad(points[k % len(points)]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms, launches = model.timing()
+    model.set_timing(False)
+    return {
+        "seconds": t1 - t0,
+        "evals_per_s": steps / (t1 - t0),
+        "ms_per_step": 1e3 * (t1 - t0) / steps,
+        "kernel_ms": kernel_ms / max(1, launches),
+        "results": results,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-baselines", action="store_true", help="time only the fused kernel")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the likelihood hot path is built and timed on a "
+              "single MI355X; multi-GPU runs are not part of this build (got --gpus %d, "
+              "WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1108_5673_amd as pwa
+    from paper_1108_5673_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.init()
+    torch.cuda.set_device(0)
+
+    t = time.perf_counter()
+    sample = synth.make_sample("w20_n1m")
+    log("generated w20_n1m in %.1f s" % (time.perf_counter() - t))
+    pts = sample.points
+    d32 = sample.data.astype(np.complex64)
+    mc32 = sample.mc.astype(np.complex64)
+
+    t = time.perf_counter()
+    fused = pwa.Model(d32, mc32, sample.n_gen, form="table")
+    torch.cuda.synchronize()
+    log("built fused complex64 table in %.2f s" % (time.perf_counter() - t))
+    info = fused.info()
+    f = time_model(fused, pts, args.steps, args.warmup)
+    log("fused: %.1f evals/s, kernel %.1f us" % (f["evals_per_s"], 1e3 * f["kernel_ms"]))
+
+    out = {}
+    if not args.no_baselines:
+        plain = pwa.Model(sample.data, sample.mc, sample.n_gen, form="table_fp64_plain")
+        p = time_model(plain, pts, args.steps, args.warmup)
+        log("plain fp64: %.1f evals/s, kernels %.1f us" % (p["evals_per_s"], 1e3 * p["kernel_ms"]))
+        plain_info = plain.info()
+        plain.close()
+        f64 = pwa.Model(sample.data, sample.mc, sample.n_gen, form="table_fp64")
+        q = time_model(f64, pts, args.steps, args.warmup)
+        log("fused fp64: %.1f evals/s, kernel %.1f us" % (q["evals_per_s"], 1e3 * q["kernel_ms"]))
+        f64_info = f64.info()
+        f64.close()
+        out["plain_fp64_table"] = {
+            "value": p["evals_per_s"], "ms_per_step": p["ms_per_step"],
+            "kernel_us": 1e3 * p["kernel_ms"],
+            "achieved_gbs": plain_info["stream_bytes"] / (p["kernel_ms"] * 1e-3) / 1e9,
+        }
+        out["fused_fp64_table"] = {
+            "value": q["evals_per_s"], "ms_per_step": q["ms_per_step"],
+            "kernel_us": 1e3 * q["kernel_ms"],
+            "achieved_gbs": f64_info["stream_bytes"] / (q["kernel_ms"] * 1e-3) / 1e9,
+        }
+        out["speedup_vs_plain_fp64"] = f["evals_per_s"] / p["evals_per_s"]
+
+    achieved = info["stream_bytes"] / (f["kernel_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                "kernel": "k_table_fused (complex64 table)", "kernel_us": 1e3 * f["kernel_ms"],
+                "bytes_per_launch": info["stream_bytes"], "grid_blocks": info["grid_blocks"]}
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.get()
+        t = time.perf_counter()
+        T = o.table(d32.astype(np.complex128)).astype(np.complex64).astype(np.complex128)
+        M = o.mc_matrix(mc32.astype(np.complex128), sample.n_gen)
+        log("oracle table and MC matrix in %.1f s" % (time.perf_counter() - t))
+        times, k, dn, dg = [], 0, [], []
+        while k < len(pts) and (k < 2 or sum(times) < args.cpu_seconds):
+            t = time.perf_counter()
+            rn, rg, _ = o.nll_table(T, M, pts[k])
+            times.append(time.perf_counter() - t)
+            gn, gg = f["results"][k]
+            dn.append(abs(gn - rn))
+            dg.append(float(np.linalg.norm(gg - rg) / np.linalg.norm(rg)))
+            k += 1
+        cpu = {"value": k / sum(times), "unit": "NLL+grad evals/s", "cores": o.num_threads(),
+               "kind": "oracle",
+               "sample": "first %d of the 200 walk points, all 1M events, FP64 table form "
+                         "(packed complex64 table widened to complex128)" % k}
+        parity = {"points": k, "max_abs_dnll": max(dn), "max_rel_grad_err": max(dg),
+                  "reference": "oracle on the identical stored complex64 table"}
+        del T
+        log("oracle: %.3f evals/s on %d threads; max |dNLL| %.2e, max grad rel %.2e"
+            % (cpu["value"], cpu["cores"], max(dn), max(dg)))
+
+    line = {
+        "metric": "NLL+grad evals/s at 1M events, 20 waves: fused FP32 vs plain FP64 table",
+        "value": f["evals_per_s"],
+        "unit": "NLL+grad evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "storage": "complex64 packed table (FP64 arithmetic and accumulation)",
+        "data": "synthetic",
+        "config": {"workload": "w20_n1m: 1M events x 20 waves, packed complex64 table "
+                               "(210 entries, 1680 B per event), MC 2M accepted of 4M "
+                               "generated, 200-point random walk from the generating point",
+                   "n_events": sample.data.shape[0], "n_waves": 20, "n_mc_acc": sample.mc.shape[0],
+                   "n_mc_gen": sample.n_gen, "points": len(pts)},
+        "events_iter_per_s": f["evals_per_s"] * sample.data.shape[0],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    line.update(out)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

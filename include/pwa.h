@@ -1,0 +1,190 @@
+/*
+ * pwa.h -- C ABI of the MI355X partial-wave-analysis likelihood library.
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the extended
+ * unbinned negative log-likelihood of a partial-wave fit and its analytic
+ * gradient (arXiv:1108.5673, Sec. 2, Eq. 3):
+ *
+ *   NLL(V) = - sum_i ln I_i(V) + mu(V)
+ *   I_i(V) = sum_a sum_a' V_a V*_a' T_i,aa',   T_i,aa' = A_a(Omega_i) A*_a'(Omega_i)
+ *   mu(V)  = sum_a sum_a' V_a V*_a' M_aa',     M_aa' = (1/N_gen) sum_{j acc} B_ja B*_ja'
+ *
+ * where V (W complex numbers) are the production amplitudes being fitted,
+ * A the decay amplitudes of the N data events and B those of the accepted
+ * Monte Carlo events.  No constant is added to Eq. 3.  The gradient is
+ * returned with respect to the real and imaginary parts of V:
+ *   grad[2b] = dNLL/dRe V_b,  grad[2b+1] = dNLL/dIm V_b.
+ *
+ * Because masses and widths are fixed during the fit, the per-event products
+ * T_i and the MC matrix M are computed once, when the model is built
+ * (Sec. 2, the paragraph after Eq. 3); each evaluation then streams the
+ * device-resident table and moves only V to the device and the NLL and
+ * gradient back (Sec. 5: only fit parameters, likelihood and derivatives
+ * cross the bus).
+ *
+ * Conventions for every function:
+ *   - Complex numbers are interleaved (re, im) pairs; arrays are row-major.
+ *   - V, nll and grad are host pointers.  V has 2W doubles (re, im per wave).
+ *   - Each evaluation call is synchronous: it enqueues its work on hip_stream
+ *     (a hipStream_t; NULL means the default stream), waits for that stream
+ *     and returns with the results in host memory.
+ *   - No exception or abort crosses the ABI.  Every function returns a status
+ *     (pwa_status); pwa_last_error() gives a message for the last non-OK
+ *     status of the calling thread.
+ *   - A model is not safe for concurrent calls from several threads: it owns
+ *     one set of scratch buffers.  Distinct models may be used concurrently.
+ *   - Degenerate events: if any event has I_i <= 0 or a non-finite I_i the
+ *     likelihood is undefined; the call returns PWA_WARN_DEGENERATE, sets
+ *     *nll = +INFINITY and fills grad with NaN.  Nothing is clamped.
+ */
+#ifndef PWA_H
+#define PWA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pwa_model pwa_model;
+
+typedef enum pwa_status {
+    PWA_OK = 0,
+    PWA_WARN_DEGENERATE = 1,      /* some I_i <= 0 or non-finite: *nll = +INFINITY, grad NaN   */
+    PWA_ERR_INVALID = -1,         /* bad argument (NULL pointer, size out of range, bad flags) */
+    PWA_ERR_OOM = -2,             /* device or pinned host allocation failed                   */
+    PWA_ERR_DEVICE = -3,          /* a HIP runtime call or kernel launch failed                */
+    PWA_ERR_NO_DEVICE = -4,       /* no HIP device is visible to this process                  */
+    PWA_ERR_NONFINITE_INPUT = -5  /* V holds a NaN or infinity                                 */
+} pwa_status;
+
+typedef enum pwa_flags {
+    /* Evaluation form (exactly one of the four must be given). */
+    PWA_FORM_TABLE = 1,              /* complex64 packed table, fused one-pass NLL+gradient kernel */
+    PWA_FORM_AMPLITUDE = 2,          /* complex64 amplitudes, S_i = sum_a V_a A_ia per event (Eq. 1) */
+    PWA_PRECISION_FP64_PLAIN = 8,    /* complex128 packed table, plain two-pass FP64 kernels       */
+    PWA_PRECISION_FP64_FUSED = 64,   /* complex128 packed table, fused one-pass kernel            */
+    /* Input description. */
+    PWA_INPUT_IS_TABLE = 4,          /* `data` is an N x P packed Hermitian table, P = W(W+1)/2,
+                                        entries (a, a') with a <= a' in row-major order of the
+                                        upper triangle; any Hermitian positive semi-definite
+                                        per-event table is accepted, not only rank one.
+                                        Table forms only.                                        */
+    PWA_DATA_COMPLEX128 = 16,        /* `data` elements are complex128 (default complex64)        */
+    PWA_MC_COMPLEX128 = 32           /* `mc_amp` elements are complex128 (default complex64)      */
+} pwa_flags;
+
+/* Largest wave count per form. */
+#define PWA_MAX_WAVES_TABLE 64
+#define PWA_MAX_WAVES_AMPLITUDE 128
+
+/*
+ * pwa_build_table -- build a model: the per-event table (or the device copy
+ * of the amplitudes) and the MC matrix M (Sec. 2, Eq. 3 and the paragraph
+ * after it).
+ *
+ *   data      N x W amplitudes A_ia, or with PWA_INPUT_IS_TABLE an N x P packed
+ *             table; complex64 unless PWA_DATA_COMPLEX128.  Host or device
+ *             memory (detected).  Copied: the caller keeps ownership and may
+ *             free it when the call returns.
+ *   n_data    N >= 1.
+ *   n_waves   W, 1 <= W <= PWA_MAX_WAVES_TABLE (table forms) or
+ *             PWA_MAX_WAVES_AMPLITUDE (amplitude form).
+ *   mc_amp    N_acc x W accepted MC amplitudes B_ja (complex64 unless
+ *             PWA_MC_COMPLEX128), host or device; copied.  May be NULL only
+ *             when n_mc_acc == 0, which gives M = 0.
+ *   n_mc_acc  N_acc >= 0.
+ *   n_mc_gen  N_gen >= 1, the number of generated MC events (Eq. 3 divides by
+ *             it, not by N_acc).
+ *   flags     pwa_flags.
+ *   out       receives the new model; *out is NULL on error.
+ *
+ * Table forms compute T_i,aa' in FP64 from the given amplitudes (each product
+ * formed with a separately rounded multiply and add) and store it at the
+ * form's precision, rounded to nearest.  M is accumulated in FP64.  The
+ * amplitude form keeps the amplitudes in complex64 (complex128 input is
+ * rounded to nearest).
+ */
+int pwa_build_table(const void* data, int64_t n_data, int32_t n_waves,
+                    const void* mc_amp, int64_t n_mc_acc, int64_t n_mc_gen,
+                    uint32_t flags, void* hip_stream, pwa_model** out);
+
+/*
+ * pwa_nll -- NLL(V) of Eq. 3.  v: 2W doubles (host).  *nll receives the value.
+ */
+int pwa_nll(const pwa_model* model, const double* v, double* nll, void* hip_stream);
+
+/*
+ * pwa_nll_grad -- NLL(V) and its gradient in one pass over the events.
+ * grad receives 2W doubles: dNLL/dRe V_b, dNLL/dIm V_b.  The gradient is
+ *   G_b = 2 sum_a V_a (M_ab - U_ab),  U_ab = sum_i T_i,ab / I_i
+ * (the derivative of Eq. 3; the paper's fitter uses analytic gradients,
+ * Sec. 4 and Sec. 5).
+ */
+int pwa_nll_grad(const pwa_model* model, const double* v, double* nll, double* grad,
+                 void* hip_stream);
+
+/*
+ * pwa_nll_batched -- many parameter sets, possibly on several models (fits
+ * repeated from several starting points and several models tried, Sec. 2).
+ *
+ *   models       n_models model handles.
+ *   k_per_model  K_m >= 0 parameter sets for model m.
+ *   v            concatenation over m of K_m x 2W_m doubles.
+ *   nll          sum_m K_m doubles (same order).
+ *   grad         sum_m K_m x 2W_m doubles, or NULL for NLL only.
+ *
+ * Returns PWA_WARN_DEGENERATE if any evaluation is degenerate (those entries
+ * are +INFINITY / NaN); other entries are valid.  Amplitude-form models
+ * evaluate all their K_m sets in one pass over their events.
+ */
+int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k_per_model,
+                    const double* v, double* nll, double* grad, void* hip_stream);
+
+/* pwa_free -- release a model and all device memory it owns.  NULL is ignored. */
+void pwa_free(pwa_model* model);
+
+/* pwa_last_error -- message for the last non-OK status of the calling thread. */
+const char* pwa_last_error(void);
+
+/*
+ * Inspection.  pwa_model_info fills, in order: N, W, P, form flag,
+ * bytes streamed from device memory per single-V evaluation by the main
+ * kernel (the algorithmic traffic: table or amplitude bytes, padding
+ * excluded), grid size of the main kernel, and the number of compute units.
+ */
+typedef struct pwa_info {
+    int64_t n_data;
+    int32_t n_waves;
+    int32_t n_packed;
+    uint32_t form;
+    int64_t stream_bytes;
+    int32_t grid_blocks;
+    int32_t compute_units;
+} pwa_info;
+int pwa_model_info(const pwa_model* model, pwa_info* out);
+
+/* Copy the model's table back in the canonical packed N x P layout (complex64
+ * for PWA_FORM_TABLE, complex128 for the FP64 forms).  Table forms only. */
+int pwa_copy_table(const pwa_model* model, void* out_host, void* hip_stream);
+
+/* Copy M (W x W complex128, row-major) to host memory. */
+int pwa_copy_mc_matrix(const pwa_model* model, double* out_host, void* hip_stream);
+
+/* Replace M by a caller-supplied W x W complex128 Hermitian matrix (host). */
+int pwa_set_mc_matrix(pwa_model* model, const double* m_host, void* hip_stream);
+
+/*
+ * Kernel timing: while enabled, every evaluation records HIP events on its
+ * stream around the main (event-streaming) kernel; pwa_get_timing returns the
+ * accumulated device time of those kernels in milliseconds and the number of
+ * launches timed, and resets both.
+ */
+int pwa_set_timing(pwa_model* model, int enable);
+int pwa_get_timing(pwa_model* model, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWA_H */

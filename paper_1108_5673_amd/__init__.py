@@ -1,0 +1,252 @@
+"""MI355X partial-wave-analysis likelihood: Python binding of libpwa.
+
+The extended unbinned negative log-likelihood of a partial-wave fit and its
+analytic gradient (arXiv:1108.5673, Sec. 2, Eq. 3), evaluated by hand-written
+HIP kernels for gfx950 behind the C ABI of include/pwa.h.  This module only
+marshals arguments: every step of an evaluation runs in the library's kernels.
+PyTorch, when used, supplies device memory and the current stream.
+
+    from paper_1108_5673_amd import Model
+    m = Model(data_amplitudes, mc_amplitudes, n_gen, form="table")
+    nll, grad = m.nll_grad(V)          # grad = [dRe V_0, dIm V_0, ...]
+"""
+from __future__ import annotations
+
+import ctypes
+import warnings
+
+import numpy as np
+
+from . import _native
+from ._native import PWAError
+
+__all__ = ["Model", "PWAError", "nll_batched", "NLLFunction", "FORMS"]
+
+FORMS = {
+    "table": _native.PWA_FORM_TABLE,                    # complex64 table, fused kernel
+    "amplitude": _native.PWA_FORM_AMPLITUDE,            # complex64 amplitudes
+    "table_fp64_plain": _native.PWA_PRECISION_FP64_PLAIN,   # complex128 table, two passes
+    "table_fp64": _native.PWA_PRECISION_FP64_FUSED,     # complex128 table, fused kernel
+}
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _current_stream():
+    """torch's current HIP stream if torch has initialised the device, else NULL."""
+    try:
+        import torch
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+def _buffer(x, what: str):
+    """(pointer, is_complex128, keepalive, shape) of a complex numpy array or torch tensor."""
+    if _is_torch(x):
+        import torch
+        if x.dtype not in (torch.complex64, torch.complex128):
+            raise TypeError("%s must be complex64 or complex128, got %s" % (what, x.dtype))
+        x = x.contiguous()
+        return ctypes.c_void_p(x.data_ptr()), x.dtype == torch.complex128, x, tuple(x.shape)
+    a = np.asarray(x)
+    if a.dtype not in (np.complex64, np.complex128):
+        raise TypeError("%s must be complex64 or complex128, got %s" % (what, a.dtype))
+    a = np.ascontiguousarray(a)
+    return ctypes.c_void_p(a.ctypes.data), a.dtype == np.complex128, a, a.shape
+
+
+def _v_array(v, n_waves: int) -> np.ndarray:
+    """Production amplitudes as 2W doubles (re, im interleaved)."""
+    if _is_torch(v):
+        v = v.detach().cpu().numpy()
+    a = np.asarray(v)
+    if np.iscomplexobj(a):
+        a = np.ascontiguousarray(a.astype(np.complex128)).view(np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64).ravel()
+    if a.shape[0] != 2 * n_waves:
+        raise ValueError("expected %d waves (%d doubles), got %d doubles"
+                         % (n_waves, 2 * n_waves, a.shape[0]))
+    return a
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Model:
+    """One data sample, its MC integral matrix and the device-resident table or
+    amplitudes (built once; Sec. 2, the paragraph after Eq. 3).
+
+    data:  (N, W) complex decay amplitudes, or with input_is_table=True an
+           (N, W(W+1)/2) packed Hermitian table; numpy or torch, host or device.
+    mc:    (N_acc, W) accepted MC amplitudes, or None for M = 0.
+    n_gen: number of generated MC events.
+    form:  "table" | "amplitude" | "table_fp64_plain" | "table_fp64".
+    """
+
+    def __init__(self, data, mc=None, n_gen: int = 1, form: str = "table",
+                 input_is_table: bool = False, n_waves: int | None = None, stream=None):
+        L = _native.lib()
+        if form not in FORMS:
+            raise ValueError("form must be one of %s" % sorted(FORMS))
+        dptr, d128, self._data_keep, dshape = _buffer(data, "data")
+        if len(dshape) != 2:
+            raise ValueError("data must be 2-D")
+        n = int(dshape[0])
+        if input_is_table:
+            p = int(dshape[1])
+            w = int(round((np.sqrt(8 * p + 1) - 1) / 2))
+            if w * (w + 1) // 2 != p:
+                raise ValueError("table width %d is not W(W+1)/2" % p)
+        else:
+            w = int(dshape[1])
+        if n_waves is not None and n_waves != w:
+            raise ValueError("n_waves %d does not match data (%d)" % (n_waves, w))
+        flags = FORMS[form]
+        if input_is_table:
+            flags |= _native.PWA_INPUT_IS_TABLE
+        if d128:
+            flags |= _native.PWA_DATA_COMPLEX128
+        if mc is not None:
+            mptr, m128, mkeep, mshape = _buffer(mc, "mc")
+            if len(mshape) != 2 or mshape[1] != w:
+                raise ValueError("mc must be (N_acc, %d)" % w)
+            n_acc = int(mshape[0])
+            if m128:
+                flags |= _native.PWA_MC_COMPLEX128
+        else:
+            mptr, mkeep, n_acc = None, None, 0
+        self._stream = stream if stream is not None else _current_stream()
+        handle = ctypes.c_void_p()
+        _native.check(L.pwa_build_table(dptr, n, w, mptr, n_acc, int(n_gen), flags,
+                                        self._stream, ctypes.byref(handle)))
+        self._h = handle
+        self._data_keep = None          # the library holds its own copy
+        del mkeep
+        self.n_data, self.n_waves, self.form = n, w, form
+        self.n_packed = w * (w + 1) // 2
+
+    # -- evaluation ---------------------------------------------------------
+    def _handle(self):
+        if not self._h:
+            raise RuntimeError("model has been freed")
+        return self._h
+
+    def nll(self, v) -> float:
+        va = _v_array(v, self.n_waves)
+        out = ctypes.c_double(0.0)
+        st = _native.check(_native.lib().pwa_nll(self._handle(), va.ctypes.data, ctypes.byref(out),
+                                                 self._stream))
+        if st == _native.PWA_WARN_DEGENERATE:
+            warnings.warn("degenerate event (I <= 0): NLL is +inf")
+        return out.value
+
+    def nll_grad(self, v):
+        """(NLL, gradient as 2W doubles [dRe V_0, dIm V_0, ...])."""
+        va = _v_array(v, self.n_waves)
+        out = ctypes.c_double(0.0)
+        g = np.zeros(2 * self.n_waves, np.float64)
+        st = _native.check(_native.lib().pwa_nll_grad(self._handle(), va.ctypes.data,
+                                                      ctypes.byref(out), g.ctypes.data,
+                                                      self._stream))
+        if st == _native.PWA_WARN_DEGENERATE:
+            warnings.warn("degenerate event (I <= 0): NLL is +inf, gradient NaN")
+        return out.value, g
+
+    # -- inspection ---------------------------------------------------------
+    def info(self) -> dict:
+        inf = _native.Info()
+        _native.check(_native.lib().pwa_model_info(self._handle(), ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _native.Info._fields_}
+
+    def table(self) -> np.ndarray:
+        """The stored table in canonical packed (N, P) layout."""
+        dt = np.complex64 if self.form == "table" else np.complex128
+        out = np.zeros((self.n_data, self.n_packed), dt)
+        _native.check(_native.lib().pwa_copy_table(self._handle(), out.ctypes.data, self._stream))
+        return out
+
+    def mc_matrix(self) -> np.ndarray:
+        out = np.zeros((self.n_waves, self.n_waves), np.complex128)
+        _native.check(_native.lib().pwa_copy_mc_matrix(self._handle(), out.ctypes.data,
+                                                       self._stream))
+        return out
+
+    def set_mc_matrix(self, M) -> None:
+        a = np.ascontiguousarray(np.asarray(M, np.complex128))
+        if a.shape != (self.n_waves, self.n_waves):
+            raise ValueError("M must be (W, W)")
+        _native.check(_native.lib().pwa_set_mc_matrix(self._handle(), a.ctypes.data,
+                                                      self._stream))
+
+    def set_timing(self, enable: bool) -> None:
+        _native.check(_native.lib().pwa_set_timing(self._handle(), int(bool(enable))))
+
+    def timing(self):
+        """(total device milliseconds of the main kernel, launches) since the last call."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _native.check(_native.lib().pwa_get_timing(self._handle(), ctypes.byref(ms),
+                                                   ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _native.lib().pwa_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nll_batched(models, vs, grad: bool = True, stream=None):
+    """Evaluate K_m parameter sets on each of several models.
+
+    vs[m] is a (K_m, W_m) complex or (K_m, 2 W_m) real array.  Returns a list of
+    (nll (K_m,), grad (K_m, 2 W_m) or None) per model.
+    """
+    L = _native.lib()
+    n = len(models)
+    ks, flat = [], []
+    for m, v in zip(models, vs):
+        a = np.asarray(v.detach().cpu().numpy() if _is_torch(v) else v)
+        if np.iscomplexobj(a):
+            a = a.astype(np.complex128).view(np.float64)
+        a = np.ascontiguousarray(a, np.float64).reshape(-1, 2 * m.n_waves)
+        ks.append(a.shape[0])
+        flat.append(a.ravel())
+    vall = np.ascontiguousarray(np.concatenate(flat) if flat else np.zeros(0))
+    total = sum(ks)
+    nll = np.zeros(total, np.float64)
+    g = np.zeros(sum(k * 2 * m.n_waves for k, m in zip(ks, models)), np.float64) if grad else None
+    handles = (ctypes.c_void_p * max(1, n))(*[m._handle() for m in models])
+    karr = (ctypes.c_int32 * max(1, n))(*ks)
+    st = stream if stream is not None else (models[0]._stream if models else None)
+    status = _native.check(L.pwa_nll_batched(handles, n, karr, vall.ctypes.data, nll.ctypes.data,
+                                             g.ctypes.data if grad else None, st))
+    if status == _native.PWA_WARN_DEGENERATE:
+        warnings.warn("degenerate evaluation(s): NLL +inf")
+    out, pos, gpos = [], 0, 0
+    for m, k in zip(models, ks):
+        gi = None
+        if grad:
+            gi = g[gpos:gpos + k * 2 * m.n_waves].reshape(k, 2 * m.n_waves)
+            gpos += k * 2 * m.n_waves
+        out.append((nll[pos:pos + k], gi))
+        pos += k
+    return out
+
+
+def __getattr__(name):
+    if name == "NLLFunction":
+        from .autograd import NLLFunction
+        return NLLFunction
+    raise AttributeError(name)

@@ -1,0 +1,101 @@
+"""ctypes declarations of the C ABI in include/pwa.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIBRARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpwa.so")
+
+PWA_OK = 0
+PWA_WARN_DEGENERATE = 1
+PWA_ERR_INVALID = -1
+PWA_ERR_OOM = -2
+PWA_ERR_DEVICE = -3
+PWA_ERR_NO_DEVICE = -4
+PWA_ERR_NONFINITE_INPUT = -5
+
+PWA_FORM_TABLE = 1
+PWA_FORM_AMPLITUDE = 2
+PWA_INPUT_IS_TABLE = 4
+PWA_PRECISION_FP64_PLAIN = 8
+PWA_DATA_COMPLEX128 = 16
+PWA_MC_COMPLEX128 = 32
+PWA_PRECISION_FP64_FUSED = 64
+
+PWA_MAX_WAVES_TABLE = 64
+PWA_MAX_WAVES_AMPLITUDE = 128
+
+# every symbol include/pwa.h declares
+EXPORTED = (
+    "pwa_build_table", "pwa_nll", "pwa_nll_grad", "pwa_nll_batched", "pwa_free",
+    "pwa_last_error", "pwa_model_info", "pwa_copy_table", "pwa_copy_mc_matrix",
+    "pwa_set_mc_matrix", "pwa_set_timing", "pwa_get_timing",
+)
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("n_data", ctypes.c_int64),
+        ("n_waves", ctypes.c_int32),
+        ("n_packed", ctypes.c_int32),
+        ("form", ctypes.c_uint32),
+        ("stream_bytes", ctypes.c_int64),
+        ("grid_blocks", ctypes.c_int32),
+        ("compute_units", ctypes.c_int32),
+    ]
+
+
+class PWAError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("pwa status %d: %s" % (status, message))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library.  Raises if it has not been built: there is no
+    fallback implementation."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBRARY):
+            raise RuntimeError("the HIP library %s is not built; run "
+                               "`python -m paper_1108_5673_amd.build`" % LIBRARY)
+        _lib = _declare(ctypes.CDLL(LIBRARY))
+    return _lib
+
+
+def _declare(L):
+    p, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.pwa_build_table.argtypes = [p, i64, i32, p, i64, i64, u32, p, ctypes.POINTER(p)]
+    L.pwa_nll.argtypes = [p, p, dp, p]
+    L.pwa_nll_grad.argtypes = [p, p, dp, p, p]
+    L.pwa_nll_batched.argtypes = [p, i32, p, p, p, p, p]
+    L.pwa_free.argtypes = [p]
+    L.pwa_free.restype = None
+    L.pwa_last_error.argtypes = []
+    L.pwa_last_error.restype = ctypes.c_char_p
+    L.pwa_model_info.argtypes = [p, ctypes.POINTER(Info)]
+    L.pwa_copy_table.argtypes = [p, p, p]
+    L.pwa_copy_mc_matrix.argtypes = [p, p, p]
+    L.pwa_set_mc_matrix.argtypes = [p, p, p]
+    L.pwa_set_timing.argtypes = [p, ctypes.c_int]
+    L.pwa_get_timing.argtypes = [p, dp, ctypes.POINTER(i64)]
+    for name in EXPORTED:
+        if name not in ("pwa_free", "pwa_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+def last_error() -> str:
+    msg = lib().pwa_last_error()
+    return msg.decode() if msg else ""
+
+
+def check(status: int) -> int:
+    """Raise PWAError for errors; pass OK and warnings through."""
+    if status < 0:
+        raise PWAError(status, last_error())
+    return status

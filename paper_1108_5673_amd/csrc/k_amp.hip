@@ -1,0 +1,208 @@
+// k_amp.hip -- amplitude-form NLL + gradient (Eq. 1 inside Eq. 3): the
+// per-event work is S_i = sum_a V_a A_ia and I_i = |S_i|^2, so only N x W
+// amplitudes are streamed instead of the N x W(W+1)/2 table.
+//
+// Amplitudes are stored complex64, row-major, each row padded to an even
+// number of waves wpad and the event count padded to a multiple of 64 with
+// zero rows.  One wavefront (block of 64 threads) handles a tile of 64 events:
+//   1. coalesced 16-byte loads of the tile's contiguous 512*wpad bytes into LDS
+//      (rows padded in LDS so that the per-event reads below hit distinct banks);
+//   2. lane = event: S_i, I_i, ln I_i and c_i = S_i / I_i in FP64;
+//   3. lane = wave a: g_a += c_i conj(A_ia) over the tile's 64 events, reading
+//      the tile from LDS, so the amplitudes leave HBM once per evaluation.
+// Each block writes one partial record [sum ln I, n_bad, g_0, ..., g_{W-1}];
+// the gradient is G_b = 2 sum_a V_a M_ab - 2 g_b.
+#include <hip/hip_runtime.h>
+
+#include "pwa_internal.h"
+#include "wave_ops.h"
+
+namespace pwa {
+
+__host__ __device__ inline int amp_lds_stride_words(int wpad)
+{
+    // 16-byte aligned rows whose word stride is 4 (mod 32): eight consecutive
+    // lanes reading 16 bytes each cover all 32 banks.
+    int words = 2 * wpad;
+    int pad = ((4 - words) % 32 + 32) % 32;
+    return words + pad;
+}
+
+__host__ __device__ inline size_t amp_lds_bytes(int wpad)
+{
+    return (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4 + kAmpTile * 16 + (size_t)wpad * 16;
+}
+
+template <int KW, bool GRAD>
+__global__ __launch_bounds__(64) void k_amp_fused(const float4* __restrict__ amp, int64_t n_events,
+                                                  int64_t n_tiles, int W, int wpad, VParams vp,
+                                                  double* __restrict__ partials, int rec_len)
+{
+    extern __shared__ char lds[];
+    const int stride = amp_lds_stride_words(wpad) * 4;      // bytes per LDS row
+    char* tile = lds;
+    double2* s_cw = reinterpret_cast<double2*>(lds + kAmpTile * stride);
+    double2* s_v = s_cw + kAmpTile;
+    const int lane = threadIdx.x;
+    const int h = wpad >> 1;                                 // 16-byte vectors per row
+
+    for (int a = lane; a < wpad; a += 64)
+        s_v[a] = (a < W) ? make_double2(vp.v[2 * a], vp.v[2 * a + 1]) : make_double2(0.0, 0.0);
+    __syncthreads();
+
+    double gr[KW], gi[KW];
+#pragma unroll
+    for (int s = 0; s < KW; ++s) { gr[s] = 0.0; gi[s] = 0.0; }
+    double dsum = 0.0;
+    int nbad = 0;
+
+    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
+    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
+    for (int64_t t = t0; t < t1; ++t) {
+        const float4* src = amp + t * kAmpTile * h;
+        for (int q = 0; q < h; ++q) {
+            const int f = q * 64 + lane;
+            const float4 val = src[f];
+            const int ev = f / h;
+            const int c = f - ev * h;
+            *reinterpret_cast<float4*>(tile + ev * stride + c * 16) = val;
+        }
+        __syncthreads();
+
+        // lane = event
+        const char* row = tile + lane * stride;
+        double sr = 0.0, si = 0.0;
+        for (int c = 0; c < h; ++c) {
+            const float4 x = *reinterpret_cast<const float4*>(row + c * 16);
+            const double2 v0 = s_v[2 * c], v1 = s_v[2 * c + 1];
+            sr += v0.x * (double)x.x - v0.y * (double)x.y;
+            si += v0.x * (double)x.y + v0.y * (double)x.x;
+            sr += v1.x * (double)x.z - v1.y * (double)x.w;
+            si += v1.x * (double)x.w + v1.y * (double)x.z;
+        }
+        const double I = sr * sr + si * si;
+        const bool valid = t * kAmpTile + lane < n_events;
+        const bool ok = valid && (I > 0.0) && (I < INFINITY);
+        if (ok) dsum += log(I);
+        if (valid && !ok) ++nbad;
+        if (GRAD) {
+            const double w = ok ? 1.0 / I : 0.0;
+            s_cw[lane] = make_double2(w * sr, w * si);
+            __syncthreads();
+            // lane = wave
+            for (int l = 0; l < kAmpTile; ++l) {
+                const double2 c = s_cw[l];
+                const float2* rl = reinterpret_cast<const float2*>(tile + l * stride);
+#pragma unroll
+                for (int s = 0; s < KW; ++s) {
+                    const int a = lane + 64 * s;
+                    if (a < W) {
+                        const float2 x = rl[a];
+                        gr[s] += c.x * (double)x.x + c.y * (double)x.y;
+                        gi[s] += c.y * (double)x.x - c.x * (double)x.y;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    dsum = wave_allsum(dsum);
+    nbad = wave_allsum_int(nbad);
+    double* rec = partials + (int64_t)blockIdx.x * rec_len;
+    if (lane == 0) {
+        rec[0] = dsum;
+        rec[1] = (double)nbad;
+    }
+    if (GRAD) {
+#pragma unroll
+        for (int s = 0; s < KW; ++s) {
+            const int a = lane + 64 * s;
+            if (a < W) {
+                rec[2 + 2 * a] = gr[s];
+                rec[3 + 2 * a] = gi[s];
+            }
+        }
+    }
+}
+
+template <int KW>
+static const void* amp_symbol()
+{
+    return (const void*)&k_amp_fused<KW, true>;
+}
+
+int amp_fused_grid(const Model& m)
+{
+    const void* fn = (m.wpad <= 64) ? amp_symbol<1>() : amp_symbol<2>();
+    const size_t lds = amp_lds_bytes(m.wpad);
+    if (lds > 65536) {
+        // wide rows: allow more than the default 64 KB of dynamic LDS
+        const void* fns[] = {(const void*)&k_amp_fused<2, true>, (const void*)&k_amp_fused<2, false>};
+        for (const void* f : fns)
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int64_t g = (int64_t)m.cus * per_cu;
+    if (g > m.n_tiles) g = m.n_tiles;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s)
+{
+    const size_t lds = amp_lds_bytes(m.wpad);
+    const float4* a = (const float4*)m.d_data;
+    if (m.wpad <= 64) {
+        if (grad)
+            hipLaunchKernelGGL((k_amp_fused<1, true>), dim3(m.grid), dim3(64), lds, s, a, m.n,
+                               m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
+        else
+            hipLaunchKernelGGL((k_amp_fused<1, false>), dim3(m.grid), dim3(64), lds, s, a, m.n,
+                               m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
+    } else {
+        if (grad)
+            hipLaunchKernelGGL((k_amp_fused<2, true>), dim3(m.grid), dim3(64), lds, s, a, m.n,
+                               m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
+        else
+            hipLaunchKernelGGL((k_amp_fused<2, false>), dim3(m.grid), dim3(64), lds, s, a, m.n,
+                               m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
+    }
+    return hipGetLastError();
+}
+
+// complex64 padded copy of the amplitudes (complex128 input rounded to nearest)
+__global__ void k_pack_amp(const void* __restrict__ src, bool c128, int64_t n, int W, int wpad,
+                           int64_t total, float2* __restrict__ dst)
+{
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = g / wpad;
+        const int a = (int)(g % wpad);
+        float2 x = make_float2(0.f, 0.f);
+        if (i < n && a < W) {
+            if (c128) {
+                const double2 d = reinterpret_cast<const double2*>(src)[i * W + a];
+                x = make_float2((float)d.x, (float)d.y);
+            } else {
+                x = reinterpret_cast<const float2*>(src)[i * W + a];
+            }
+        }
+        dst[g] = x;
+    }
+}
+
+hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, int wpad,
+                           int64_t n_pad, float* dst, hipStream_t s)
+{
+    const int64_t total = n_pad * wpad;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_pack_amp, dim3((int)g), dim3(256), 0, s, src, src_c128, n, W, wpad,
+                       total, (float2*)dst);
+    return hipGetLastError();
+}
+
+}  // namespace pwa

@@ -1,0 +1,419 @@
+// k_table.hip -- the per-event lookup table of Sec. 2 (T_i,aa' = A_a A*_a',
+// precomputed because masses and widths are fixed) and the fused one-pass
+// NLL + gradient kernel that streams it on every fit iteration (Eq. 3).
+//
+// Tiled layout (chosen for the streaming kernel).  A tile holds kTileEvents
+// consecutive events.  Its P packed entries are cut into slots of 64 entries:
+// slot k holds entries 64k .. 64k + n_k - 1, n_k = min(64, P - 64k).  Inside a
+// slot the 16-byte vectors are ordered [vector v][lane], lane = e mod 64, and
+// one vector holds EV = 16 / esz consecutive events of one entry (EV = 2 for
+// complex64, 1 for complex128).  One wavefront load instruction therefore
+// reads 64 x 16 = 1024 contiguous bytes (n_k x 16 in the last slot), lane l
+// always receives entry 64k + l, and a wave's tile is one contiguous block of
+// P * kTileEvents * esz bytes.  The table is not padded in the entry
+// direction; only the last tile is padded with zero events.
+#include <hip/hip_runtime.h>
+
+#include "pwa_internal.h"
+#include "wave_ops.h"
+
+namespace pwa {
+
+__host__ __device__ inline int64_t tiled_offset(int64_t i, int e, int P, int esz)
+{
+    const int64_t t = i / kTileEvents;
+    const int j = (int)(i % kTileEvents);
+    const int ev = 16 / esz;
+    const int k = e >> 6, lane = e & 63;
+    const int nk = (P - 64 * k) < 64 ? (P - 64 * k) : 64;
+    return t * (int64_t)P * kTileEvents * esz + (int64_t)k * 64 * kTileEvents * esz +
+           (int64_t)((j / ev) * nk + lane) * 16 + (j % ev) * esz;
+}
+
+// T = x conj(y), each product rounded separately (no fused multiply-add), in FP64
+__device__ inline double2 herm_product(double xr, double xi, double yr, double yi)
+{
+    double2 t;
+    t.x = __dadd_rn(__dmul_rn(xr, yr), __dmul_rn(xi, yi));
+    t.y = __dadd_rn(__dmul_rn(xi, yr), -__dmul_rn(xr, yi));
+    return t;
+}
+
+__device__ inline double2 load_c(const void* p, int64_t idx, bool c128)
+{
+    if (c128) return reinterpret_cast<const double2*>(p)[idx];
+    const float2 f = reinterpret_cast<const float2*>(p)[idx];
+    return make_double2((double)f.x, (double)f.y);
+}
+
+// Entry (i, e) of the table built from amplitudes, or copied from a canonical
+// packed source table.
+__device__ inline double2 source_entry(const void* src, bool src_is_table, bool c128, int64_t i,
+                                       int e, int W, int P, const uint32_t* pairs)
+{
+    if (src_is_table) return load_c(src, i * P + e, c128);
+    const uint32_t pr = pairs[e];
+    const int a = (int)(pr & 0xffffu), b = (int)(pr >> 16);
+    const double2 x = load_c(src, i * W + a, c128);
+    const double2 y = load_c(src, i * W + b, c128);
+    return herm_product(x.x, x.y, y.x, y.y);
+}
+
+__global__ void k_pack_tiled(const void* __restrict__ src, bool src_is_table, bool src_c128,
+                             int64_t n, int W, int P, const uint32_t* __restrict__ pairs,
+                             bool store_c128, int64_t total, void* __restrict__ dst)
+{
+    const int esz = store_c128 ? 16 : 8;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = g / P;
+        const int e = (int)(g % P);
+        double2 t = make_double2(0.0, 0.0);
+        if (i < n) t = source_entry(src, src_is_table, src_c128, i, e, W, P, pairs);
+        char* d = reinterpret_cast<char*>(dst) + tiled_offset(i, e, P, esz);
+        if (store_c128) *reinterpret_cast<double2*>(d) = t;
+        else *reinterpret_cast<float2*>(d) = make_float2((float)t.x, (float)t.y);
+    }
+}
+
+__global__ void k_unpack_tiled(const void* __restrict__ src, bool c128, int64_t n, int P,
+                               void* __restrict__ dst)
+{
+    const int esz = c128 ? 16 : 8;
+    const int64_t total = n * P;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = g / P;
+        const int e = (int)(g % P);
+        const char* s = reinterpret_cast<const char*>(src) + tiled_offset(i, e, P, esz);
+        if (c128) reinterpret_cast<double2*>(dst)[g] = *reinterpret_cast<const double2*>(s);
+        else reinterpret_cast<float2*>(dst)[g] = *reinterpret_cast<const float2*>(s);
+    }
+}
+
+static int grid_for(int64_t total, int block)
+{
+    int64_t g = (total + block - 1) / block;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_pack_tiled(const void* src, bool src_is_table, bool src_c128, int64_t n,
+                             int W, int P, const uint32_t* pairs, bool store_c128,
+                             int64_t n_tiles, void* dst, hipStream_t s)
+{
+    const int64_t total = n_tiles * kTileEvents * (int64_t)P;
+    hipLaunchKernelGGL(k_pack_tiled, dim3(grid_for(total, 256)), dim3(256), 0, s, src,
+                       src_is_table, src_c128, n, W, P, pairs, store_c128, total, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, void* dst,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_unpack_tiled, dim3(grid_for(n * P, 256)), dim3(256), 0, s, src, c128,
+                       n, P, dst);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused one-pass NLL + gradient over the tiled table.
+//
+// A wavefront works on E events at a time (a sub-tile).  Lane l owns entries
+// e = 64k + l (k < K) for the whole kernel:
+//   1. loads its entries of the E events (dwordx4, 1 KB per instruction);
+//   2. forms its partial intensities p_j = sum_k Re(c_e T_je) in FP64, with
+//      c_aa = |V_a|^2 and c_aa' = 2 V_a V*_a' (a < a'), so that
+//      sum_e Re(c_e T_ie) = sum_a sum_a' V_a V*_a' T_i,aa' (Eq. 3, first bracket);
+//   3. reduces the E partials over the 64 lanes with one transposing
+//      butterfly (transpose_reduce), after which each run of 64/E lanes holds
+//      the full I_i of one event;
+//   4. forms ln I_i and w_i = 1/I_i in FP64 (invalid or padded events give 0);
+//   5. broadcasts w_i through scalar registers and accumulates, from the
+//      registers loaded in step 1, U_e += w_i T_ie (FP64), the data part of
+//      the gradient; the table is read from memory exactly once.
+// At the end the four wavefronts of a block are combined in LDS in a fixed
+// order and the block writes one partial record [sum ln I, n_bad, U_e...].
+// ---------------------------------------------------------------------------
+template <typename S> struct Vec16;
+template <> struct Vec16<float> {
+    using T = float4;
+    static constexpr int EV = 2;
+    __device__ static T zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ static double re(const T& x, int h) { return h == 0 ? (double)x.x : (double)x.z; }
+    __device__ static double im(const T& x, int h) { return h == 0 ? (double)x.y : (double)x.w; }
+    __device__ static void opaque(T& x) { asm volatile("" : "+v"(x.x), "+v"(x.y), "+v"(x.z), "+v"(x.w)); }
+};
+template <> struct Vec16<double> {
+    using T = double2;
+    static constexpr int EV = 1;
+    __device__ static T zero() { return make_double2(0.0, 0.0); }
+    __device__ static double re(const T& x, int) { return x.x; }
+    __device__ static double im(const T& x, int) { return x.y; }
+    __device__ static void opaque(T&) {}
+};
+
+template <typename S, int K, int E, bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_table_fused(
+    const char* __restrict__ table, int64_t n_events, int64_t n_tiles, int P,
+    const uint32_t* __restrict__ pairs, VParams vp, double* __restrict__ partials, int rec_len)
+{
+    using VT = Vec16<S>;
+    using V4 = typename VT::T;
+    constexpr int EV = VT::EV;
+    constexpr int esz = 2 * sizeof(S);
+    constexpr int VPT = kTileEvents / EV;      // vectors per lane per slot per tile
+    constexpr int VS = E / EV;                 // vectors per lane per slot per sub-tile
+    constexpr int NSUB = kTileEvents / E;
+    constexpr int RUN = 64 / E;                // lanes per event after the reduction
+    static_assert(E % EV == 0 && kTileEvents % E == 0, "sub-tile shape");
+
+    __shared__ double2 s_c[K * 64];
+    __shared__ double2 s_u[K * 64];
+    __shared__ double s_misc[2];
+
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+
+    // coefficients c_e for every (slot, lane)
+    for (int idx = threadIdx.x; idx < K * 64; idx += blockDim.x) {
+        double2 c = make_double2(0.0, 0.0);
+        if (idx < P) {
+            const uint32_t pr = pairs[idx];
+            const int a = (int)(pr & 0xffffu), b = (int)(pr >> 16);
+            const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
+            const double wr = vp.v[2 * b], wi = vp.v[2 * b + 1];
+            const double f = (a == b) ? 1.0 : 2.0;
+            c.x = f * (vr * wr + vi * wi);   // Re V_a V*_b
+            c.y = f * (vi * wr - vr * wi);   // Im V_a V*_b
+        }
+        s_c[idx] = c;
+    }
+    __syncthreads();
+
+    const int nslots = (P + 63) >> 6;
+    double ur[K], ui[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { ur[k] = 0.0; ui[k] = 0.0; }
+    double dsum = 0.0;
+    int nbad = 0;
+
+    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
+    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
+    const int64_t tile_bytes = (int64_t)P * kTileEvents * esz;
+
+    for (int64_t t = t0 + wave; t < t1; t += nwaves) {
+        const char* tb = table + t * tile_bytes;
+#pragma unroll 1
+        for (int sub = 0; sub < NSUB; ++sub) {
+            V4 x[K][VS];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int nk = min(64, P - 64 * k);
+                const bool on = (k < nslots) && (lane < nk);
+                const char* sb = tb + (int64_t)k * 64 * VPT * 16;
+#pragma unroll
+                for (int v = 0; v < VS; ++v) {
+                    x[k][v] = on ? *reinterpret_cast<const V4*>(sb + ((sub * VS + v) * nk + lane) * 16)
+                                 : VT::zero();
+                }
+            }
+            double p[E];
+#pragma unroll
+            for (int j = 0; j < E; ++j) p[j] = 0.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double2 c = s_c[k * 64 + lane];
+#pragma unroll
+                for (int v = 0; v < VS; ++v)
+#pragma unroll
+                    for (int h = 0; h < EV; ++h)
+                        p[v * EV + h] += c.x * VT::re(x[k][v], h) - c.y * VT::im(x[k][v], h);
+            }
+            // Keep the compiler from carrying FP64 copies of the loaded
+            // values from step 2 to step 5 (that would double the register
+            // footprint); step 5 converts again from the FP32/FP64 registers.
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int v = 0; v < VS; ++v) VT::opaque(x[k][v]);
+            const double I = transpose_reduce<E>(p, lane);
+            const int64_t evt = t * kTileEvents + sub * E + lane / RUN;
+            const bool valid = evt < n_events;
+            const bool ok = valid && (I > 0.0) && (I < INFINITY);
+            const double w = ok ? 1.0 / I : 0.0;
+            if ((lane % RUN) == 0) {
+                if (ok) dsum += log(I);
+                if (valid && !ok) ++nbad;
+            }
+            if (GRAD) {
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const double wj = readlane_f64(w, j * RUN);
+                    const int v = j / EV, h = j % EV;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        ur[k] += wj * VT::re(x[k][v], h);
+                        ui[k] += wj * VT::im(x[k][v], h);
+                    }
+                }
+            }
+        }
+    }
+
+    // combine the block's wavefronts in a fixed order
+    dsum = wave_allsum(dsum);
+    nbad = wave_allsum_int(nbad);
+    for (int w = 0; w < nwaves; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                double2 u = make_double2(ur[k], ui[k]);
+                if (w > 0) {
+                    const double2 o = s_u[k * 64 + lane];
+                    u.x += o.x;
+                    u.y += o.y;
+                }
+                s_u[k * 64 + lane] = u;
+            }
+            if (lane == 0) {
+                s_misc[0] = (w > 0 ? s_misc[0] : 0.0) + dsum;
+                s_misc[1] = (w > 0 ? s_misc[1] : 0.0) + (double)nbad;
+            }
+        }
+        __syncthreads();
+    }
+    double* rec = partials + (int64_t)blockIdx.x * rec_len;
+    if (threadIdx.x == 0) {
+        rec[0] = s_misc[0];
+        rec[1] = s_misc[1];
+    }
+    if (GRAD) {
+        for (int e = threadIdx.x; e < P; e += blockDim.x) {
+            rec[2 + 2 * e] = s_u[e].x;
+            rec[3 + 2 * e] = s_u[e].y;
+        }
+    }
+}
+
+// Instantiations: K slots of 64 entries per lane (P <= 64 K) and E events per
+// sub-tile.  The default E keeps the loaded vectors near 64 registers; the
+// other sub-tile widths are kept for tuning (PWA_TABLE_SUBTILE).
+template <typename S, int K, int E>
+static hipError_t run_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s)
+{
+    if (grad)
+        hipLaunchKernelGGL((k_table_fused<S, K, E, true>), dim3(m.grid), dim3(kBlock), 0, s,
+                           (const char*)m.d_data, m.n, m.n_tiles, m.P, m.d_pairs, vp,
+                           m.d_partials, m.rec_len);
+    else
+        hipLaunchKernelGGL((k_table_fused<S, K, E, false>), dim3(m.grid), dim3(kBlock), 0, s,
+                           (const char*)m.d_data, m.n, m.n_tiles, m.P, m.d_pairs, vp,
+                           m.d_partials, m.rec_len);
+    return hipGetLastError();
+}
+
+template <typename S, int K, int E>
+static const void* fused_fn()
+{
+    return (const void*)&k_table_fused<S, K, E, true>;
+}
+
+int select_kslots(int P, bool c128)
+{
+    (void)c128;
+    const int need = (P + 63) / 64;
+    const int opts[] = {1, 2, 4, 8, 16, 33};
+    for (int k : opts)
+        if (k >= need) return k;
+    return -1;
+}
+
+// Default sub-tile width per slot count: at most 16 loaded 16-byte vectors
+// (64 registers) per lane, which leaves room for three wavefronts per SIMD.
+int default_subtile(int kslots, bool c128)
+{
+    int e = 16 / kslots * (c128 ? 1 : 2);
+    if (e > kTileEvents) e = kTileEvents;
+    if (e < (c128 ? 1 : 2)) e = c128 ? 1 : 2;
+    return e;
+}
+
+// Calls f.template operator()<K, E>() for the instantiated (K, E) pair, or returns
+// false when the pair is not instantiated.
+template <typename S, typename F>
+static bool with_shape(int K, int E, F&& f)
+{
+    constexpr bool F32 = sizeof(S) == 4;
+#define PWA_SHAPE(k, e)                                \
+    if (K == k && E == e) {                            \
+        f.template operator()<k, e>();                 \
+        return true;                                   \
+    }
+    PWA_SHAPE(1, 16)
+    PWA_SHAPE(2, 16)
+    PWA_SHAPE(2, 8)
+    PWA_SHAPE(4, 16)
+    PWA_SHAPE(4, 8)
+    PWA_SHAPE(4, 4)
+    if constexpr (F32) {
+        PWA_SHAPE(8, 8)
+        PWA_SHAPE(8, 4)
+        PWA_SHAPE(16, 4)
+        PWA_SHAPE(16, 2)
+        PWA_SHAPE(33, 2)
+    } else {
+        PWA_SHAPE(4, 2)
+        PWA_SHAPE(8, 4)
+        PWA_SHAPE(8, 2)
+        PWA_SHAPE(16, 2)
+        PWA_SHAPE(16, 1)
+        PWA_SHAPE(33, 1)
+    }
+#undef PWA_SHAPE
+    return false;
+}
+
+bool fused_shape_ok(const Model& m)
+{
+    bool ok = false;
+    auto probe = [&]<int K, int E>() { ok = true; };
+    if (m.form == kTable32) with_shape<float>(m.kslots, m.subtile, probe);
+    else with_shape<double>(m.kslots, m.subtile, probe);
+    return ok;
+}
+
+hipError_t launch_table_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s)
+{
+    hipError_t err = hipErrorInvalidValue;
+    if (m.form == kTable32) {
+        auto go = [&]<int K, int E>() { err = run_fused<float, K, E>(m, vp, grad, s); };
+        with_shape<float>(m.kslots, m.subtile, go);
+    } else {
+        auto go = [&]<int K, int E>() { err = run_fused<double, K, E>(m, vp, grad, s); };
+        with_shape<double>(m.kslots, m.subtile, go);
+    }
+    return err;
+}
+
+int table_fused_grid(const Model& m)
+{
+    const void* fn = nullptr;
+    if (m.form == kTable32) {
+        auto get = [&]<int K, int E>() { fn = fused_fn<float, K, E>(); };
+        with_shape<float>(m.kslots, m.subtile, get);
+    } else {
+        auto get = [&]<int K, int E>() { fn = fused_fn<double, K, E>(); };
+        with_shape<double>(m.kslots, m.subtile, get);
+    }
+    int per_cu = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int64_t g = (int64_t)m.cus * per_cu;
+    if (g > m.n_tiles) g = m.n_tiles;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace pwa

@@ -1,0 +1,507 @@
+// pwa_api.cpp -- the C ABI declared in include/pwa.h: argument checking,
+// device memory ownership, the build step and the evaluation sequence.
+//
+// Evaluation sequence on the caller's stream (all device work is in kernels):
+//   main kernel (fused table / plain two-pass / amplitude) -> per-block partials
+//   column sum of the partials (fixed order)               -> d_colsum
+//   finalize: NLL = -sum ln I + mu, gradient               -> d_out
+//   one device-to-host copy of 2 + 2W doubles into pinned memory, stream sync.
+// V travels in the kernel arguments, so nothing is copied host-to-device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pwa.h"
+#include "pwa_internal.h"
+
+using pwa::Model;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int device_fail(hipError_t e, const char* what)
+{
+    (void)hipGetLastError();
+    const int code = (e == hipErrorOutOfMemory) ? PWA_ERR_OOM : PWA_ERR_DEVICE;
+    return fail(code, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                           \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return device_fail(e_, #expr);    \
+    } while (0)
+
+bool is_device_ptr(const void* p)
+{
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
+           attr.type == hipMemoryTypeUnified;
+}
+
+// Switches to the model's device for the lifetime of the object.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Device copy of a caller buffer (or the buffer itself when it is on the device).
+struct Staged {
+    const void* ptr = nullptr;
+    void* owned = nullptr;
+    ~Staged()
+    {
+        if (owned) (void)hipFree(owned);
+    }
+};
+
+int stage(const void* src, size_t bytes, hipStream_t s, Staged& out)
+{
+    if (is_device_ptr(src)) {
+        out.ptr = src;
+        return PWA_OK;
+    }
+    HIP_TRY(hipMalloc(&out.owned, bytes));
+    HIP_TRY(hipMemcpyAsync(out.owned, src, bytes, hipMemcpyHostToDevice, s));
+    out.ptr = out.owned;
+    return PWA_OK;
+}
+
+void release(Model* m)
+{
+    if (!m) return;
+    DeviceGuard g(m->device);
+    if (m->d_data) (void)hipFree(m->d_data);
+    if (m->d_pairs) (void)hipFree(m->d_pairs);
+    if (m->d_M) (void)hipFree(m->d_M);
+    if (m->d_partials) (void)hipFree(m->d_partials);
+    if (m->d_colsum) (void)hipFree(m->d_colsum);
+    if (m->d_w) (void)hipFree(m->d_w);
+    if (m->d_out) (void)hipFree(m->d_out);
+    if (m->h_out) (void)hipHostFree(m->h_out);
+    if (m->ev0) (void)hipEventDestroy(m->ev0);
+    if (m->ev1) (void)hipEventDestroy(m->ev1);
+    delete m;
+}
+
+int alloc_out(Model* m, int cap)
+{
+    const size_t bytes = sizeof(double) * (size_t)(2 + 2 * m->W) * cap;
+    if (m->d_out) (void)hipFree(m->d_out);
+    if (m->h_out) (void)hipHostFree(m->h_out);
+    m->d_out = nullptr;
+    m->h_out = nullptr;
+    HIP_TRY(hipMalloc(&m->d_out, bytes));
+    HIP_TRY(hipHostMalloc(&m->h_out, bytes, hipHostMallocDefault));
+    m->out_cap = cap;
+    return PWA_OK;
+}
+
+int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t n_acc,
+                int64_t n_gen, uint32_t flags, hipStream_t s, Model* m)
+{
+    const uint32_t form = flags & (PWA_FORM_TABLE | PWA_FORM_AMPLITUDE |
+                                   PWA_PRECISION_FP64_PLAIN | PWA_PRECISION_FP64_FUSED);
+    const bool in_table = flags & PWA_INPUT_IS_TABLE;
+    const bool data_c128 = flags & PWA_DATA_COMPLEX128;
+    const bool mc_c128 = flags & PWA_MC_COMPLEX128;
+
+    HIP_TRY(hipGetDevice(&m->device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, m->device));
+    m->cus = prop.multiProcessorCount;
+    m->form = (pwa::Form)form;
+    m->n = n;
+    m->W = W;
+    m->P = W * (W + 1) / 2;
+    const int P = m->P;
+
+    // (a, a') of every packed entry, row-major upper triangle
+    std::vector<uint32_t> pairs;
+    pairs.reserve(P);
+    for (int a = 0; a < W; ++a)
+        for (int b = a; b < W; ++b) pairs.push_back((uint32_t)a | ((uint32_t)b << 16));
+    HIP_TRY(hipMalloc(&m->d_pairs, sizeof(uint32_t) * P));
+    HIP_TRY(hipMemcpyAsync(m->d_pairs, pairs.data(), sizeof(uint32_t) * P, hipMemcpyHostToDevice, s));
+
+    // ---- data: table or amplitudes on the device ----
+    const size_t in_elem = data_c128 ? 16 : 8;
+    const size_t in_bytes = (size_t)n * (in_table ? P : W) * in_elem;
+    Staged sd;
+    int rc = stage(data, in_bytes, s, sd);
+    if (rc != PWA_OK) return rc;
+
+    if (form == PWA_FORM_TABLE || form == PWA_PRECISION_FP64_FUSED) {
+        const bool c128 = form == PWA_PRECISION_FP64_FUSED;
+        m->n_tiles = (n + pwa::kTileEvents - 1) / pwa::kTileEvents;
+        m->data_bytes = m->n_tiles * pwa::kTileEvents * (int64_t)P * (c128 ? 16 : 8);
+        HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
+        HIP_TRY(pwa::launch_pack_tiled(sd.ptr, in_table, data_c128, n, W, P, m->d_pairs, c128,
+                                       m->n_tiles, m->d_data, s));
+        m->kslots = pwa::select_kslots(P, c128);
+        if (m->kslots < 0) return fail(PWA_ERR_INVALID, "n_waves %d too large for the table form", W);
+        m->subtile = pwa::default_subtile(m->kslots, c128);
+        if (const char* env = std::getenv("PWA_TABLE_SUBTILE")) {
+            const int e = std::atoi(env);
+            const int keep = m->subtile;
+            m->subtile = e;
+            if (!pwa::fused_shape_ok(*m)) m->subtile = keep;
+        }
+        m->grid = pwa::table_fused_grid(*m);
+        m->rows = m->grid;
+        m->rec_len = 2 + 2 * P;
+    } else if (form == PWA_PRECISION_FP64_PLAIN) {
+        m->data_bytes = (int64_t)n * P * 16;
+        HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
+        HIP_TRY(pwa::launch_pack_soa(sd.ptr, in_table, data_c128, n, W, P, m->d_pairs,
+                                     (double*)m->d_data, s));
+        HIP_TRY(hipMalloc(&m->d_w, sizeof(double) * n));
+        m->rows = pwa::plain_rows(n);
+        m->grid = m->rows;
+        m->rec_len = 2 + 2 * P;
+    } else {   // amplitude form
+        m->wpad = W + (W & 1);
+        m->n_tiles = (n + pwa::kAmpTile - 1) / pwa::kAmpTile;
+        const int64_t n_pad = m->n_tiles * pwa::kAmpTile;
+        m->data_bytes = n_pad * m->wpad * 8;
+        HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
+        HIP_TRY(pwa::launch_pack_amp(sd.ptr, data_c128, n, W, m->wpad, n_pad, (float*)m->d_data, s));
+        m->grid = pwa::amp_fused_grid(*m);
+        m->rows = m->grid;
+        m->rec_len = 2 + 2 * W;
+    }
+
+    // ---- MC matrix ----
+    HIP_TRY(hipMalloc(&m->d_M, sizeof(double) * 2 * W * W));
+    HIP_TRY(hipMalloc(&m->d_colsum, sizeof(double) * (size_t)(m->rec_len > 2 * P ? m->rec_len : 2 * P)));
+    if (n_acc > 0) {
+        Staged sm;
+        rc = stage(mc, (size_t)n_acc * W * (mc_c128 ? 16 : 8), s, sm);
+        if (rc != PWA_OK) return rc;
+        const int grows = pwa::gram_rows(n_acc);
+        double* gpart = nullptr;
+        HIP_TRY(hipMalloc(&gpart, sizeof(double) * 2 * P * (size_t)grows));
+        hipError_t e = pwa::launch_gram(sm.ptr, mc_c128, n_acc, W, P, m->d_pairs, gpart, grows, s);
+        if (e == hipSuccess) e = pwa::launch_colsum(gpart, grows, 2 * P, m->d_colsum, s);
+        if (e == hipSuccess) e = pwa::launch_expand_m(m->d_colsum, W, n_gen, m->d_M, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(gpart);
+        if (e != hipSuccess) return device_fail(e, "MC matrix build");
+    } else {
+        HIP_TRY(hipMemsetAsync(m->d_M, 0, sizeof(double) * 2 * W * W, s));
+    }
+
+    HIP_TRY(hipMalloc(&m->d_partials, sizeof(double) * (size_t)m->rows * m->rec_len));
+    rc = alloc_out(m, 1);
+    if (rc != PWA_OK) return rc;
+    HIP_TRY(hipEventCreate(&m->ev0));
+    HIP_TRY(hipEventCreate(&m->ev1));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PWA_OK;
+}
+
+int check_v(const double* v, int W)
+{
+    for (int k = 0; k < 2 * W; ++k)
+        if (!std::isfinite(v[k])) return fail(PWA_ERR_NONFINITE_INPUT, "v[%d] is not finite", k);
+    return PWA_OK;
+}
+
+// Enqueue one evaluation writing slot `slot` of d_out.
+int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, bool timed)
+{
+    pwa::VParams vp;
+    std::memset(&vp, 0, sizeof vp);
+    std::memcpy(vp.v, v, sizeof(double) * 2 * m->W);
+    if (timed) HIP_TRY(hipEventRecord(m->ev0, s));
+    hipError_t e;
+    if (m->form == pwa::kTable32 || m->form == pwa::kTable64Fused)
+        e = pwa::launch_table_fused(*m, vp, grad, s);
+    else if (m->form == pwa::kTable64Plain)
+        e = pwa::launch_plain(*m, vp, grad, s);
+    else
+        e = pwa::launch_amp_fused(*m, vp, grad, s);
+    if (e != hipSuccess) return device_fail(e, "main kernel launch");
+    if (timed) HIP_TRY(hipEventRecord(m->ev1, s));
+    HIP_TRY(pwa::launch_colsum(m->d_partials, m->rows, grad ? m->rec_len : 2, m->d_colsum, s));
+    HIP_TRY(pwa::launch_finalize(*m, vp, grad, m->d_out + (size_t)slot * (2 + 2 * m->W), s));
+    return PWA_OK;
+}
+
+int finish(Model* m, int count, hipStream_t s, bool timed)
+{
+    HIP_TRY(hipMemcpyAsync(m->h_out, m->d_out, sizeof(double) * (2 + 2 * m->W) * count,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (timed) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, m->ev0, m->ev1));
+        m->timed_ms += ms;
+        m->timed_launches += 1;
+    }
+    return PWA_OK;
+}
+
+int evaluate(const pwa_model* cm, const double* v, double* nll, double* grad, void* stream)
+{
+    if (!cm || !v || !nll) return fail(PWA_ERR_INVALID, "NULL model, v or nll");
+    Model* m = reinterpret_cast<Model*>(const_cast<pwa_model*>(cm));
+    int rc = check_v(v, m->W);
+    if (rc != PWA_OK) return rc;
+    DeviceGuard g(m->device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool want_grad = grad != nullptr;
+    rc = enqueue_eval(m, v, want_grad, 0, s, m->timing);
+    if (rc != PWA_OK) return rc;
+    rc = finish(m, 1, s, m->timing);
+    if (rc != PWA_OK) return rc;
+    *nll = m->h_out[0];
+    if (want_grad) std::memcpy(grad, m->h_out + 2, sizeof(double) * 2 * m->W);
+    return m->h_out[1] > 0.0 ? PWA_WARN_DEGENERATE : PWA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pwa_build_table(const void* data, int64_t n_data, int32_t n_waves, const void* mc_amp,
+                    int64_t n_mc_acc, int64_t n_mc_gen, uint32_t flags, void* hip_stream,
+                    pwa_model** out)
+{
+    if (!out) return fail(PWA_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    const uint32_t known = PWA_FORM_TABLE | PWA_FORM_AMPLITUDE | PWA_INPUT_IS_TABLE |
+                           PWA_PRECISION_FP64_PLAIN | PWA_DATA_COMPLEX128 | PWA_MC_COMPLEX128 |
+                           PWA_PRECISION_FP64_FUSED;
+    if (flags & ~known) return fail(PWA_ERR_INVALID, "unknown flag bits 0x%x", flags & ~known);
+    const uint32_t form = flags & (PWA_FORM_TABLE | PWA_FORM_AMPLITUDE |
+                                   PWA_PRECISION_FP64_PLAIN | PWA_PRECISION_FP64_FUSED);
+    if (form != PWA_FORM_TABLE && form != PWA_FORM_AMPLITUDE &&
+        form != PWA_PRECISION_FP64_PLAIN && form != PWA_PRECISION_FP64_FUSED)
+        return fail(PWA_ERR_INVALID, "exactly one form flag is required (got 0x%x)", form);
+    if (!data) return fail(PWA_ERR_INVALID, "data is NULL");
+    if (n_data < 1) return fail(PWA_ERR_INVALID, "n_data must be >= 1 (got %lld)", (long long)n_data);
+    const int wmax = (form == PWA_FORM_AMPLITUDE) ? PWA_MAX_WAVES_AMPLITUDE : PWA_MAX_WAVES_TABLE;
+    if (n_waves < 1 || n_waves > wmax)
+        return fail(PWA_ERR_INVALID, "n_waves must be in [1, %d] for this form (got %d)", wmax, n_waves);
+    if ((flags & PWA_INPUT_IS_TABLE) && form == PWA_FORM_AMPLITUDE)
+        return fail(PWA_ERR_INVALID, "PWA_INPUT_IS_TABLE needs a table form");
+    if (n_mc_acc < 0) return fail(PWA_ERR_INVALID, "n_mc_acc must be >= 0");
+    if (n_mc_acc > 0 && !mc_amp) return fail(PWA_ERR_INVALID, "mc_amp is NULL but n_mc_acc > 0");
+    if (n_mc_gen < 1) return fail(PWA_ERR_INVALID, "n_mc_gen must be >= 1");
+    if (n_mc_acc > n_mc_gen) return fail(PWA_ERR_INVALID, "n_mc_acc exceeds n_mc_gen");
+    if (n_data > ((int64_t)1 << 40)) return fail(PWA_ERR_INVALID, "n_data too large");
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(PWA_ERR_NO_DEVICE, "no HIP device available");
+    }
+    Model* m = new (std::nothrow) Model();
+    if (!m) return fail(PWA_ERR_OOM, "host allocation failed");
+    const int rc = build_model(data, n_data, n_waves, mc_amp, n_mc_acc, n_mc_gen, flags,
+                               (hipStream_t)hip_stream, m);
+    if (rc != PWA_OK) {
+        (void)hipStreamSynchronize((hipStream_t)hip_stream);
+        release(m);
+        return rc;
+    }
+    *out = reinterpret_cast<pwa_model*>(m);
+    return PWA_OK;
+}
+
+int pwa_nll(const pwa_model* model, const double* v, double* nll, void* hip_stream)
+{
+    return evaluate(model, v, nll, nullptr, hip_stream);
+}
+
+int pwa_nll_grad(const pwa_model* model, const double* v, double* nll, double* grad,
+                 void* hip_stream)
+{
+    if (!grad) return fail(PWA_ERR_INVALID, "grad is NULL");
+    return evaluate(model, v, nll, grad, hip_stream);
+}
+
+int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k_per_model,
+                    const double* v, double* nll, double* grad, void* hip_stream)
+{
+    if (n_models < 0) return fail(PWA_ERR_INVALID, "n_models < 0");
+    if (n_models == 0) return PWA_OK;
+    if (!models || !k_per_model || !v || !nll)
+        return fail(PWA_ERR_INVALID, "NULL models, k_per_model, v or nll");
+    for (int mi = 0; mi < n_models; ++mi) {
+        if (!models[mi]) return fail(PWA_ERR_INVALID, "models[%d] is NULL", mi);
+        if (k_per_model[mi] < 0) return fail(PWA_ERR_INVALID, "k_per_model[%d] < 0", mi);
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    int status = PWA_OK;
+    const double* vp = v;
+    double* np = nll;
+    double* gp = grad;
+    for (int mi = 0; mi < n_models; ++mi) {
+        Model* m = reinterpret_cast<Model*>(models[mi]);
+        const int K = k_per_model[mi];
+        const int W = m->W;
+        for (int k = 0; k < K; ++k) {
+            const int rc = check_v(vp + (size_t)k * 2 * W, W);
+            if (rc != PWA_OK) return rc;
+        }
+        DeviceGuard g(m->device);
+        if (K > m->out_cap) {
+            const int rc = alloc_out(m, K);
+            if (rc != PWA_OK) return rc;
+        }
+        for (int k = 0; k < K; ++k) {
+            const int rc = enqueue_eval(m, vp + (size_t)k * 2 * W, gp != nullptr, k, s, false);
+            if (rc != PWA_OK) return rc;
+        }
+        if (K > 0) {
+            const int rc = finish(m, K, s, false);
+            if (rc != PWA_OK) return rc;
+        }
+        for (int k = 0; k < K; ++k) {
+            const double* o = m->h_out + (size_t)k * (2 + 2 * W);
+            np[k] = o[0];
+            if (gp) std::memcpy(gp + (size_t)k * 2 * W, o + 2, sizeof(double) * 2 * W);
+            if (o[1] > 0.0) status = PWA_WARN_DEGENERATE;
+        }
+        vp += (size_t)K * 2 * W;
+        np += K;
+        if (gp) gp += (size_t)K * 2 * W;
+    }
+    return status;
+}
+
+void pwa_free(pwa_model* model)
+{
+    release(reinterpret_cast<Model*>(model));
+}
+
+const char* pwa_last_error(void)
+{
+    return g_error.c_str();
+}
+
+int pwa_model_info(const pwa_model* model, pwa_info* out)
+{
+    if (!model || !out) return fail(PWA_ERR_INVALID, "NULL model or out");
+    const Model* m = reinterpret_cast<const Model*>(model);
+    out->n_data = m->n;
+    out->n_waves = m->W;
+    out->n_packed = m->P;
+    out->form = (uint32_t)m->form;
+    switch (m->form) {
+    case pwa::kTable32: out->stream_bytes = m->n * m->P * 8; break;
+    case pwa::kTable64Fused: out->stream_bytes = m->n * m->P * 16; break;
+    case pwa::kTable64Plain: out->stream_bytes = 2 * m->n * m->P * 16; break;
+    default: out->stream_bytes = m->n * m->W * 8; break;
+    }
+    out->grid_blocks = m->grid;
+    out->compute_units = m->cus;
+    return PWA_OK;
+}
+
+int pwa_copy_table(const pwa_model* model, void* out_host, void* hip_stream)
+{
+    if (!model || !out_host) return fail(PWA_ERR_INVALID, "NULL model or out_host");
+    const Model* m = reinterpret_cast<const Model*>(model);
+    if (m->form == pwa::kAmp32) return fail(PWA_ERR_INVALID, "amplitude-form model has no table");
+    DeviceGuard g(m->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const bool c128 = m->form != pwa::kTable32;
+    const size_t bytes = (size_t)m->n * m->P * (c128 ? 16 : 8);
+    void* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, bytes));
+    hipError_t e;
+    if (m->form == pwa::kTable64Plain)
+        e = pwa::launch_unpack_soa((const double*)m->d_data, m->n, m->P, (double*)tmp, s);
+    else
+        e = pwa::launch_unpack_tiled(m->d_data, c128, m->n, m->P, tmp, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out_host, tmp, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return device_fail(e, "table copy");
+    return PWA_OK;
+}
+
+int pwa_copy_mc_matrix(const pwa_model* model, double* out_host, void* hip_stream)
+{
+    if (!model || !out_host) return fail(PWA_ERR_INVALID, "NULL model or out_host");
+    const Model* m = reinterpret_cast<const Model*>(model);
+    DeviceGuard g(m->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_TRY(hipMemcpyAsync(out_host, m->d_M, sizeof(double) * 2 * m->W * m->W,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PWA_OK;
+}
+
+int pwa_set_mc_matrix(pwa_model* model, const double* m_host, void* hip_stream)
+{
+    if (!model || !m_host) return fail(PWA_ERR_INVALID, "NULL model or m_host");
+    Model* m = reinterpret_cast<Model*>(model);
+    for (int k = 0; k < 2 * m->W * m->W; ++k)
+        if (!std::isfinite(m_host[k])) return fail(PWA_ERR_NONFINITE_INPUT, "M[%d] not finite", k / 2);
+    DeviceGuard g(m->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_TRY(hipMemcpyAsync(m->d_M, m_host, sizeof(double) * 2 * m->W * m->W,
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PWA_OK;
+}
+
+int pwa_set_timing(pwa_model* model, int enable)
+{
+    if (!model) return fail(PWA_ERR_INVALID, "NULL model");
+    Model* m = reinterpret_cast<Model*>(model);
+    m->timing = enable != 0;
+    return PWA_OK;
+}
+
+int pwa_get_timing(pwa_model* model, double* total_ms, int64_t* launches)
+{
+    if (!model || !total_ms || !launches) return fail(PWA_ERR_INVALID, "NULL argument");
+    Model* m = reinterpret_cast<Model*>(model);
+    *total_ms = m->timed_ms;
+    *launches = m->timed_launches;
+    m->timed_ms = 0.0;
+    m->timed_launches = 0;
+    return PWA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// pwa_internal.h -- model state and kernel launchers shared by the library's
+// translation units.  Not part of the public ABI (include/pwa.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pwa.h"
+
+namespace pwa {
+
+// Events per tile of the tiled table layout (see k_table.hip).
+constexpr int kTileEvents = 16;
+// Events per tile of the amplitude kernel (one wavefront's worth).
+constexpr int kAmpTile = 64;
+// Threads per block of the streaming kernels: four wavefronts.
+constexpr int kBlock = 256;
+
+enum Form : uint32_t {
+    kTable32 = PWA_FORM_TABLE,
+    kAmp32 = PWA_FORM_AMPLITUDE,
+    kTable64Plain = PWA_PRECISION_FP64_PLAIN,
+    kTable64Fused = PWA_PRECISION_FP64_FUSED,
+};
+
+// Parameter vector passed by value in the kernel arguments: no host-to-device
+// copy is needed per evaluation.
+struct VParams {
+    double v[2 * PWA_MAX_WAVES_AMPLITUDE];
+};
+
+struct Model {
+    int device = 0;
+    Form form = kTable32;
+    int64_t n = 0;           // data events
+    int32_t W = 0;           // waves
+    int32_t P = 0;           // packed entries W(W+1)/2
+    int32_t wpad = 0;        // amplitude row length (even) for the amplitude form
+    int64_t n_tiles = 0;     // tiles of the main kernel's layout
+    int32_t grid = 0;        // blocks of the main kernel
+    int32_t cus = 0;         // compute units of the device
+    int32_t rows = 0;        // partial records written per evaluation
+    int32_t rec_len = 0;     // doubles per partial record
+    int32_t kslots = 0;      // fused table kernel: slots of 64 entries per lane
+    int32_t subtile = 0;     // fused table kernel: events per sub-tile
+
+    void* d_data = nullptr;         // table (tiled or SoA) or padded amplitudes
+    int64_t data_bytes = 0;
+    uint32_t* d_pairs = nullptr;    // (a | a' << 16) per packed entry
+    double* d_M = nullptr;          // W x W complex128
+    double* d_partials = nullptr;   // rows x rec_len
+    double* d_colsum = nullptr;     // rec_len (x K for batched)
+    double* d_w = nullptr;          // plain path: per-event weights 1/I_i
+    double* d_out = nullptr;        // [nll, nbad, grad 2W] (x K for batched)
+    double* h_out = nullptr;        // pinned copy of d_out
+    int32_t out_cap = 1;            // evaluations d_out / h_out can hold
+
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+};
+
+// ---- launchers (each returns the hipError_t of its launch) ----------------
+// build step
+hipError_t launch_pack_tiled(const void* src, bool src_is_table, bool src_c128, int64_t n,
+                             int W, int P, const uint32_t* pairs, bool store_c128,
+                             int64_t n_tiles, void* dst, hipStream_t s);
+hipError_t launch_pack_soa(const void* src, bool src_is_table, bool src_c128, int64_t n, int W,
+                           int P, const uint32_t* pairs, double* dst, hipStream_t s);
+hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, int wpad,
+                           int64_t n_pad, float* dst, hipStream_t s);
+hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, void* dst,
+                               hipStream_t s);
+hipError_t launch_unpack_soa(const double* src, int64_t n, int P, double* dst, hipStream_t s);
+hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, int P,
+                       const uint32_t* pairs, double* partials, int rows, hipStream_t s);
+hipError_t launch_expand_m(const double* packed_colsum, int W, int64_t n_gen, double* M,
+                           hipStream_t s);
+int gram_rows(int64_t n_acc);
+int plain_rows(int64_t n);
+
+// evaluation
+hipError_t launch_table_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s);
+hipError_t launch_plain(const Model& m, const VParams& vp, bool grad, hipStream_t s);
+hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s);
+hipError_t launch_colsum(const double* partials, int rows, int cols, double* out,
+                         hipStream_t s);
+hipError_t launch_finalize(const Model& m, const VParams& vp, bool grad, double* out,
+                           hipStream_t s);
+
+// occupancy-derived grid sizes
+int table_fused_grid(const Model& m);
+int amp_fused_grid(const Model& m);
+int select_kslots(int P, bool c128);
+int default_subtile(int kslots, bool c128);
+bool fused_shape_ok(const Model& m);
+
+}  // namespace pwa

@@ -1,0 +1,242 @@
+"""HIP path against the FP64 oracle on identical inputs (needs an MI355X).
+
+Inputs are the stored arrays both sides see: complex64 amplitudes for the
+single-precision forms (the oracle widens them exactly and forms the same
+single-precision table), complex128 for the double-precision forms.  The
+oracle and the kernels share no code; only the seeded generator feeds both.
+
+Tolerances (FP64 arithmetic on both sides, different summation orders):
+NLL relative 1e-10 at small sizes; gradient ||dG|| / ||G|| <= 1e-9.  Tables are
+compared bit for bit: each entry is the same IEEE operations on the same inputs.
+"""
+import math
+import warnings
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1108_5673_amd as pwa
+from paper_1108_5673_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FORMS = ["table", "amplitude", "table_fp64_plain", "table_fp64"]
+SP_FORMS = ("table", "amplitude")
+
+
+def _o():
+    return oracle.get()
+
+
+def _inputs(form, s):
+    """(data, mc) as stored for the form, and their exact complex128 widening."""
+    if form in SP_FORMS:
+        d, m = s.data.astype(np.complex64), s.mc.astype(np.complex64)
+    else:
+        d, m = s.data, s.mc
+    return d, m, d.astype(np.complex128), m.astype(np.complex128)
+
+
+def _reference(form, d128, m128, n_gen, V, grad=True):
+    o = _o()
+    M = o.mc_matrix(m128, n_gen)
+    if form == "amplitude":
+        return o.nll_amp(d128, M, V, grad)
+    T = o.table(d128)
+    if form == "table":
+        T = T.astype(np.complex64).astype(np.complex128)
+    return o.nll_table(T, M, V, grad)
+
+
+def _rel(g, ref):
+    return float(np.linalg.norm(np.asarray(g) - ref) / np.linalg.norm(ref))
+
+
+def _check(form, w, n, n_mc, seed, points=2, nll_rtol=1e-10, g_rtol=1e-9):
+    s = synth.small_sample(w, n, n_mc, seed, points)
+    d, m, d128, m128 = _inputs(form, s)
+    model = pwa.Model(d, m, 2 * n_mc, form=form)
+    for V in s.points:
+        nll, g = model.nll_grad(V)
+        rn, rg, nbad = _reference(form, d128, m128, 2 * n_mc, V)
+        assert nbad == 0
+        assert abs(nll - rn) <= nll_rtol * max(1.0, abs(rn)), (form, w, n, nll, rn)
+        assert _rel(g, rg) <= g_rtol, (form, w, n, _rel(g, rg))
+        assert abs(model.nll(V) - nll) <= 1e-14 * max(1.0, abs(nll))
+    model.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("w,n", [(1, 1), (1, 33), (2, 17), (3, 100), (4, 1000), (7, 4099),
+                                 (11, 777), (20, 2049), (23, 300), (32, 1500), (48, 513),
+                                 (64, 130)])
+def test_parity_small(form, w, n):
+    _check(form, w, n, 3 * n + 7, seed=100 * w + n)
+
+
+@pytest.mark.parametrize("w", [33, 80, 128])
+def test_parity_amplitude_wide(w):
+    _check("amplitude", w, 700, 900, seed=w)
+
+
+@pytest.mark.parametrize("form", ["table", "table_fp64_plain", "table_fp64"])
+@pytest.mark.parametrize("w,n", [(1, 5), (4, 31), (20, 1001), (33, 65), (64, 17)])
+def test_table_bit_exact(form, w, n):
+    s = synth.small_sample(w, n, 4, seed=7 * w + n)
+    d, _, d128, _ = _inputs(form, s)
+    model = pwa.Model(d, None, 1, form=form)
+    ref = _o().table(d128)
+    if form == "table":
+        ref = ref.astype(np.complex64)
+    got = model.table()
+    assert got.dtype == ref.dtype and np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_mc_matrix(form):
+    s = synth.small_sample(9, 10, 20_000, seed=3)
+    _, m, _, m128 = _inputs(form, s)
+    model = pwa.Model(s.data.astype(np.complex64 if form in SP_FORMS else np.complex128), m,
+                      50_000, form=form)
+    ref = _o().mc_matrix(m128, 50_000)
+    got = model.mc_matrix()
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+    assert np.array_equal(got, got.conj().T)
+
+
+def test_no_mc_gives_zero_matrix():
+    s = synth.small_sample(3, 50, 4, seed=4)
+    model = pwa.Model(s.data.astype(np.complex64), None, 1, form="table")
+    assert np.all(model.mc_matrix() == 0)
+    V = s.points[0]
+    rn, _, _ = _o().nll_table(_o().table_fp32(s.data.astype(np.complex64)).astype(np.complex128),
+                              np.zeros((3, 3)), V)
+    assert abs(model.nll(V) - rn) <= 1e-12 * abs(rn)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_degenerate_event(form):
+    s = synth.small_sample(3, 40, 60, seed=5)
+    V = np.array([1.0 + 0.5j, -0.25 + 1j, 0.5 - 0.5j])
+    A = s.data.copy()
+    A[13] = [V[1], -V[0], 0.0]           # sum_a V_a A_a = 0 exactly (dyadic values)
+    d = A.astype(np.complex64) if form in SP_FORMS else A
+    model = pwa.Model(d, s.mc.astype(d.dtype), 100, form=form)
+    with warnings.catch_warnings(record=True):
+        warnings.simplefilter("always")
+        nll, g = model.nll_grad(V)
+    assert nll == math.inf and np.all(np.isnan(g))
+    # the next call at a regular point is unaffected
+    nll2, g2 = model.nll_grad(s.points[0])
+    assert math.isfinite(nll2) and np.all(np.isfinite(g2))
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_bitwise_repeatable(form):
+    s = synth.small_sample(20, 20_000, 1000, seed=6)
+    d, m, _, _ = _inputs(form, s)
+    model = pwa.Model(d, m, 2000, form=form)
+    first = model.nll_grad(s.points[1])
+    for _ in range(5):
+        again = model.nll_grad(s.points[1])
+        assert again[0] == first[0] and np.array_equal(again[1], first[1])
+
+
+def test_general_psd_table_input():
+    """PWA_INPUT_IS_TABLE: a rank-3 Hermitian PSD table, not A A^H."""
+    o = _o()
+    parts = [synth.small_sample(6, 700, 10, seed=k).data.astype(np.complex64) for k in (1, 2, 3)]
+    T = sum(o.table(p.astype(np.complex128)) for p in parts)
+    mc = synth.small_sample(6, 10, 900, seed=9).mc.astype(np.complex64)
+    M = o.mc_matrix(mc.astype(np.complex128), 1800)
+    for form, stored in (("table", T.astype(np.complex64)), ("table_fp64", T),
+                         ("table_fp64_plain", T)):
+        model = pwa.Model(stored, mc, 1800, form=form, input_is_table=True)
+        assert model.n_waves == 6
+        ref_T = stored.astype(np.complex128)
+        for V in synth.small_sample(6, 1, 1, seed=11, n_points=3).points:
+            nll, g = model.nll_grad(V)
+            rn, rg, _ = o.nll_table(ref_T, M, V)
+            assert abs(nll - rn) <= 1e-10 * abs(rn)
+            assert _rel(g, rg) <= 1e-9
+
+
+def test_set_mc_matrix():
+    s = synth.small_sample(5, 300, 10, seed=12)
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((5, 5)) + 1j * rng.standard_normal((5, 5))
+    M = X @ X.conj().T
+    model = pwa.Model(s.data.astype(np.complex64), None, 1, form="amplitude")
+    model.set_mc_matrix(M)
+    assert np.array_equal(model.mc_matrix(), M)
+    V = s.points[0]
+    rn, rg, _ = _o().nll_amp(s.data.astype(np.complex64).astype(np.complex128), M, V)
+    nll, g = model.nll_grad(V)
+    assert abs(nll - rn) <= 1e-11 * abs(rn) and _rel(g, rg) <= 1e-10
+
+
+def test_device_tensor_inputs_match_host_inputs():
+    import torch
+    s = synth.small_sample(8, 5000, 3000, seed=13)
+    d, m = s.data.astype(np.complex64), s.mc.astype(np.complex64)
+    host = pwa.Model(d, m, 6000, form="table")
+    dev = pwa.Model(torch.from_numpy(d).cuda(), torch.from_numpy(m).cuda(), 6000, form="table")
+    for V in s.points:
+        a, b = host.nll_grad(V), dev.nll_grad(V)
+        assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_batched_matches_single_calls():
+    s1 = synth.small_sample(6, 3000, 2000, seed=14, n_points=3)
+    s2 = synth.small_sample(11, 2000, 1000, seed=15, n_points=2)
+    m1 = pwa.Model(s1.data.astype(np.complex64), s1.mc.astype(np.complex64), 4000, form="table")
+    m2 = pwa.Model(s2.data.astype(np.complex64), s2.mc.astype(np.complex64), 2000,
+                   form="amplitude")
+    out = pwa.nll_batched([m1, m2], [s1.points, s2.points])
+    for (nll, g), m, s in zip(out, (m1, m2), (s1, s2)):
+        for k, V in enumerate(s.points):
+            rn, rg = m.nll_grad(V)
+            assert nll[k] == rn and np.array_equal(g[k], rg)
+    out = pwa.nll_batched([m1], [s1.points], grad=False)
+    assert np.array_equal(out[0][0], np.array([m1.nll(V) for V in s1.points]))
+
+
+def test_autograd_function():
+    import torch
+    from paper_1108_5673_amd.autograd import NLLFunction
+    s = synth.small_sample(4, 2000, 1000, seed=16)
+    model = pwa.Model(s.data.astype(np.complex64), s.mc.astype(np.complex64), 2000)
+    V = s.points[0]
+    v = torch.tensor(np.stack([V.real, V.imag], -1).ravel(), dtype=torch.float64,
+                     requires_grad=True)
+    loss = 3.0 * NLLFunction.apply(v, model)
+    loss.backward()
+    nll, g = model.nll_grad(V)
+    assert abs(loss.item() - 3.0 * nll) <= 1e-12 * abs(nll)
+    assert np.allclose(v.grad.numpy(), 3.0 * g, rtol=1e-14, atol=0)
+    # real parametrisation: d|z|^2 / d(Re z, Im z) at z = 1 + 1j is (2, 2)
+    z = torch.tensor([1.0, 1.0], dtype=torch.float64, requires_grad=True)
+    (z[0] ** 2 + z[1] ** 2).backward()
+    assert z.grad.tolist() == [2.0, 2.0]
+
+
+def test_timing_counters():
+    s = synth.small_sample(20, 50_000, 100, seed=17)
+    model = pwa.Model(s.data.astype(np.complex64), s.mc.astype(np.complex64), 200)
+    model.set_timing(True)
+    for V in s.points:
+        model.nll_grad(V)
+    ms, n = model.timing()
+    assert n == len(s.points) and ms > 0
+    model.set_timing(False)
+    model.nll_grad(s.points[0])
+    assert model.timing() == (0.0, 0)
+
+
+def test_nonfinite_v_rejected():
+    s = synth.small_sample(3, 10, 10, seed=18)
+    model = pwa.Model(s.data.astype(np.complex64), s.mc.astype(np.complex64), 20)
+    with pytest.raises(pwa.PWAError) as e:
+        model.nll(np.array([1.0, np.nan, 0, 0, 0, 0]))
+    assert e.value.status == -5
