@@ -129,7 +129,8 @@ def main():
     log("built fused complex64 table in %.2f s" % (time.perf_counter() - t))
     info = fused.info()
     f = time_model(fused, pts, args.steps, args.warmup)
-    log("fused: %.1f evals/s, kernel %.1f us" % (f["evals_per_s"], 1e3 * f["kernel_ms"]))
+    log("fused: %.1f evals/s, kernel %.1f us, grid %d blocks on %d CUs"
+        % (f["evals_per_s"], 1e3 * f["kernel_ms"], info["grid_blocks"], info["compute_units"]))
 
     out = {}
     if not args.no_baselines:
@@ -172,7 +173,7 @@ def main():
         M = o.mc_matrix(mc32.astype(np.complex128), sample.n_gen)
         log("oracle table and MC matrix in %.1f s" % (time.perf_counter() - t))
         times, k, dn, dg = [], 0, [], []
-        while k < len(pts) and (k < 2 or sum(times) < args.cpu_seconds):
+        while k < min(len(pts), args.steps) and (k < 2 or sum(times) < args.cpu_seconds):
             t = time.perf_counter()
             rn, rg, _ = o.nll_table(T, M, pts[k])
             times.append(time.perf_counter() - t)

@@ -129,23 +129,25 @@ hipError_t launch_expand_m(const double* packed_colsum, int W, int64_t n_gen, do
     return hipGetLastError();
 }
 
-// one wavefront per column; lane l sums rows l, l + 64, ... in order
+// one wavefront per column; lane l sums rows l, l + 64, ... in order.  Rows
+// are `stride` doubles apart; the first `cols` columns are summed.
 __global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ partials, int rows,
-                                                int cols, double* __restrict__ out)
+                                                int cols, int stride, double* __restrict__ out)
 {
     const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (col >= cols) return;
     double s = 0.0;
-    for (int r = lane; r < rows; r += 64) s += partials[(int64_t)r * cols + col];
+    for (int r = lane; r < rows; r += 64) s += partials[(int64_t)r * stride + col];
     s = wave_allsum(s);
     if (lane == 0) out[col] = s;
 }
 
-hipError_t launch_colsum(const double* partials, int rows, int cols, double* out, hipStream_t s)
+hipError_t launch_colsum(const double* partials, int rows, int cols, int stride, double* out,
+                         hipStream_t s)
 {
     hipLaunchKernelGGL(k_colsum, dim3((cols + 3) / 4), dim3(256), 0, s, partials, rows, cols,
-                       out);
+                       stride, out);
     return hipGetLastError();
 }
 

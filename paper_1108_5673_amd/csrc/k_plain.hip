@@ -17,6 +17,16 @@ namespace pwa {
 
 constexpr int kPlainChunk = 4096;   // events per block of either pass
 
+// x conj(y) with separately rounded products (no fused multiply-add)
+__device__ inline double2 herm_product_soa(double xr, double xi, double yr, double yi)
+{
+#pragma clang fp contract(off)
+    double2 t;
+    t.x = xr * yr + xi * yi;
+    t.y = xi * yr - xr * yi;
+    return t;
+}
+
 __global__ void k_pack_soa(const void* __restrict__ src, bool src_is_table, bool src_c128,
                            int64_t n, int W, int P, const uint32_t* __restrict__ pairs,
                            double* __restrict__ dst)
@@ -46,8 +56,7 @@ __global__ void k_pack_soa(const void* __restrict__ src, bool src_is_table, bool
                 const float2 y = reinterpret_cast<const float2*>(src)[i * W + b];
                 xr = x.x; xi = x.y; yr = y.x; yi = y.y;
             }
-            t.x = __dadd_rn(__dmul_rn(xr, yr), __dmul_rn(xi, yi));
-            t.y = __dadd_rn(__dmul_rn(xi, yr), -__dmul_rn(xr, yi));
+            t = herm_product_soa(xr, xi, yr, yi);
         }
         reinterpret_cast<double2*>(dst)[(int64_t)e * n + i] = t;
     }

@@ -30,12 +30,14 @@ __host__ __device__ inline int64_t tiled_offset(int64_t i, int e, int P, int esz
            (int64_t)((j / ev) * nk + lane) * 16 + (j % ev) * esz;
 }
 
-// T = x conj(y), each product rounded separately (no fused multiply-add), in FP64
+// T = x conj(y) in FP64 with each product rounded separately (no fused
+// multiply-add), so that the table repeats a plain FP64 evaluation bit for bit.
 __device__ inline double2 herm_product(double xr, double xi, double yr, double yi)
 {
+#pragma clang fp contract(off)
     double2 t;
-    t.x = __dadd_rn(__dmul_rn(xr, yr), __dmul_rn(xi, yi));
-    t.y = __dadd_rn(__dmul_rn(xi, yr), -__dmul_rn(xr, yi));
+    t.x = xr * yr + xi * yi;
+    t.y = xi * yr - xr * yi;
     return t;
 }
 

@@ -216,7 +216,7 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         double* gpart = nullptr;
         HIP_TRY(hipMalloc(&gpart, sizeof(double) * 2 * P * (size_t)grows));
         hipError_t e = pwa::launch_gram(sm.ptr, mc_c128, n_acc, W, P, m->d_pairs, gpart, grows, s);
-        if (e == hipSuccess) e = pwa::launch_colsum(gpart, grows, 2 * P, m->d_colsum, s);
+        if (e == hipSuccess) e = pwa::launch_colsum(gpart, grows, 2 * P, 2 * P, m->d_colsum, s);
         if (e == hipSuccess) e = pwa::launch_expand_m(m->d_colsum, W, n_gen, m->d_M, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         (void)hipFree(gpart);
@@ -257,7 +257,8 @@ int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, 
         e = pwa::launch_amp_fused(*m, vp, grad, s);
     if (e != hipSuccess) return device_fail(e, "main kernel launch");
     if (timed) HIP_TRY(hipEventRecord(m->ev1, s));
-    HIP_TRY(pwa::launch_colsum(m->d_partials, m->rows, grad ? m->rec_len : 2, m->d_colsum, s));
+    HIP_TRY(pwa::launch_colsum(m->d_partials, m->rows, grad ? m->rec_len : 2, m->rec_len,
+                                m->d_colsum, s));
     HIP_TRY(pwa::launch_finalize(*m, vp, grad, m->d_out + (size_t)slot * (2 + 2 * m->W), s));
     return PWA_OK;
 }

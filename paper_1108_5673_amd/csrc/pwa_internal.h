@@ -85,7 +85,7 @@ int plain_rows(int64_t n);
 hipError_t launch_table_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s);
 hipError_t launch_plain(const Model& m, const VParams& vp, bool grad, hipStream_t s);
 hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s);
-hipError_t launch_colsum(const double* partials, int rows, int cols, double* out,
+hipError_t launch_colsum(const double* partials, int rows, int cols, int stride, double* out,
                          hipStream_t s);
 hipError_t launch_finalize(const Model& m, const VParams& vp, bool grad, double* out,
                            hipStream_t s);
