@@ -130,7 +130,8 @@ hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, voi
 //   3. reduces the E partials over the 64 lanes with one transposing
 //      butterfly (transpose_reduce), after which each run of 64/E lanes holds
 //      the full I_i of one event;
-//   4. forms ln I_i and w_i = 1/I_i in FP64 (invalid or padded events give 0);
+//   4. forms w_i = 1/I_i in FP64 (invalid or padded events give 0) and
+//      queues I_i for a batched ln (FusedState);
 //   5. broadcasts w_i through scalar registers and accumulates, from the
 //      registers loaded in step 1, U_e += w_i T_ie (FP64), the data part of
 //      the gradient; the table is read from memory exactly once.
@@ -155,20 +156,108 @@ template <> struct Vec16<double> {
     __device__ static void opaque(T&) {}
 };
 
+// One sub-tile's loaded vectors: lane l holds, for each slot k, the E events
+// of entry 64k + l as E / EV 16-byte vectors.
+template <typename S, int K, int E>
+struct SubTile {
+    using VT = Vec16<S>;
+    using V4 = typename VT::T;
+    static constexpr int EV = VT::EV;
+    static constexpr int VS = E / EV;
+    static constexpr int VPT = kTileEvents / EV;
+    V4 x[K][VS];
+
+    __device__ void load(const char* tb, int sub, int P, int nslots, int lane)
+    {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int nk = min(64, P - 64 * k);
+            const bool on = (k < nslots) && (lane < nk);
+            const char* sb = tb + (int64_t)k * 64 * VPT * 16;
+#pragma unroll
+            for (int v = 0; v < VS; ++v)
+                x[k][v] = on ? *reinterpret_cast<const V4*>(sb + ((sub * VS + v) * nk + lane) * 16)
+                             : VT::zero();
+        }
+    }
+};
+
+// Per-lane running state.  ln I is not taken per sub-tile: after each
+// sub-tile one lane of every run keeps its event's intensity in `held` (lane
+// l % RUN == u % RUN), so that after RUN sub-tiles the 64 lanes hold 64
+// different events and one logarithm per lane covers them all.
+struct FusedState {
+    double dsum;     // sum of ln I over this lane's flushed events
+    double held;     // intensity waiting for its logarithm (1 when none)
+    int nbad;        // invalid intensities seen by this lane (run leaders only)
+};
+
+// Steps 2-5 for one loaded sub-tile.
+template <typename S, int K, int E, bool GRAD>
+__device__ inline void process_subtile(SubTile<S, K, E>& st, const double2* s_c, int lane,
+                                       int64_t u, int64_t first_event, int64_t n_events,
+                                       double (&ur)[K], double (&ui)[K], FusedState& fs)
+{
+    using VT = Vec16<S>;
+    constexpr int EV = VT::EV;
+    constexpr int VS = E / EV;
+    constexpr int RUN = 64 / E;
+    double p[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) p[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double2 c = s_c[k * 64 + lane];
+#pragma unroll
+        for (int v = 0; v < VS; ++v)
+#pragma unroll
+            for (int h = 0; h < EV; ++h) {
+                double& pj = p[v * EV + h];
+                pj = __fma_rn(c.x, VT::re(st.x[k][v], h), pj);
+                pj = __fma_rn(-c.y, VT::im(st.x[k][v], h), pj);
+            }
+    }
+    // Keep the compiler from carrying FP64 copies of the loaded values from
+    // step 2 to step 5 (that would double the register footprint); step 5
+    // converts again from the loaded registers.
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int v = 0; v < VS; ++v) VT::opaque(st.x[k][v]);
+    const double I = transpose_reduce<E>(p, lane);
+    const int64_t evt = first_event + lane / RUN;
+    const bool valid = evt < n_events;
+    const bool ok = valid && (I > 0.0) && (I < INFINITY);
+    const double w = ok ? recip_f64(I) : 0.0;
+    if ((lane % RUN) == 0 && valid && !ok) ++fs.nbad;
+    if ((lane % RUN) == (int)(u % RUN) && ok) fs.held = I;
+    if ((int)(u % RUN) == RUN - 1) {
+        fs.dsum += log(fs.held);
+        fs.held = 1.0;
+    }
+    if (GRAD) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const double wj = readlane_f64(w, j * RUN);
+            const int v = j / EV, h = j % EV;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                ur[k] = __fma_rn(wj, VT::re(st.x[k][v], h), ur[k]);
+                ui[k] = __fma_rn(wj, VT::im(st.x[k][v], h), ui[k]);
+            }
+        }
+    }
+}
+
 template <typename S, int K, int E, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_table_fused(
     const char* __restrict__ table, int64_t n_events, int64_t n_tiles, int P,
     const uint32_t* __restrict__ pairs, VParams vp, double* __restrict__ partials, int rec_len)
 {
     using VT = Vec16<S>;
-    using V4 = typename VT::T;
-    constexpr int EV = VT::EV;
     constexpr int esz = 2 * sizeof(S);
-    constexpr int VPT = kTileEvents / EV;      // vectors per lane per slot per tile
-    constexpr int VS = E / EV;                 // vectors per lane per slot per sub-tile
     constexpr int NSUB = kTileEvents / E;
-    constexpr int RUN = 64 / E;                // lanes per event after the reduction
-    static_assert(E % EV == 0 && kTileEvents % E == 0, "sub-tile shape");
+    static_assert(E % VT::EV == 0 && kTileEvents % E == 0, "sub-tile shape");
 
     __shared__ double2 s_c[K * 64];
     __shared__ double2 s_u[K * 64];
@@ -198,75 +287,36 @@ __global__ __launch_bounds__(kBlock) void k_table_fused(
     double ur[K], ui[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) { ur[k] = 0.0; ui[k] = 0.0; }
-    double dsum = 0.0;
-    int nbad = 0;
+    FusedState fs{0.0, 1.0, 0};
 
+    // This wave's sub-tiles, in order: tiles t0 + wave, t0 + wave + nwaves, ...,
+    // each split into NSUB sub-tiles.  The next sub-tile is loaded while the
+    // current one is processed (two register buffers).
     const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
     const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
     const int64_t tile_bytes = (int64_t)P * kTileEvents * esz;
+    const int64_t my_tiles = (t1 - t0 > wave) ? (t1 - t0 - wave + nwaves - 1) / nwaves : 0;
+    const int64_t U = my_tiles * NSUB;
+    auto tile_of = [&](int64_t u) { return t0 + wave + nwaves * (u / NSUB); };
+    auto base_of = [&](int64_t u) { return table + tile_of(u) * tile_bytes; };
+    auto first_of = [&](int64_t u) { return tile_of(u) * kTileEvents + (u % NSUB) * E; };
 
-    for (int64_t t = t0 + wave; t < t1; t += nwaves) {
-        const char* tb = table + t * tile_bytes;
-#pragma unroll 1
-        for (int sub = 0; sub < NSUB; ++sub) {
-            V4 x[K][VS];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int nk = min(64, P - 64 * k);
-                const bool on = (k < nslots) && (lane < nk);
-                const char* sb = tb + (int64_t)k * 64 * VPT * 16;
-#pragma unroll
-                for (int v = 0; v < VS; ++v) {
-                    x[k][v] = on ? *reinterpret_cast<const V4*>(sb + ((sub * VS + v) * nk + lane) * 16)
-                                 : VT::zero();
-                }
-            }
-            double p[E];
-#pragma unroll
-            for (int j = 0; j < E; ++j) p[j] = 0.0;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const double2 c = s_c[k * 64 + lane];
-#pragma unroll
-                for (int v = 0; v < VS; ++v)
-#pragma unroll
-                    for (int h = 0; h < EV; ++h)
-                        p[v * EV + h] += c.x * VT::re(x[k][v], h) - c.y * VT::im(x[k][v], h);
-            }
-            // Keep the compiler from carrying FP64 copies of the loaded
-            // values from step 2 to step 5 (that would double the register
-            // footprint); step 5 converts again from the FP32/FP64 registers.
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-#pragma unroll
-                for (int v = 0; v < VS; ++v) VT::opaque(x[k][v]);
-            const double I = transpose_reduce<E>(p, lane);
-            const int64_t evt = t * kTileEvents + sub * E + lane / RUN;
-            const bool valid = evt < n_events;
-            const bool ok = valid && (I > 0.0) && (I < INFINITY);
-            const double w = ok ? 1.0 / I : 0.0;
-            if ((lane % RUN) == 0) {
-                if (ok) dsum += log(I);
-                if (valid && !ok) ++nbad;
-            }
-            if (GRAD) {
-#pragma unroll
-                for (int j = 0; j < E; ++j) {
-                    const double wj = readlane_f64(w, j * RUN);
-                    const int v = j / EV, h = j % EV;
-#pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        ur[k] += wj * VT::re(x[k][v], h);
-                        ui[k] += wj * VT::im(x[k][v], h);
-                    }
-                }
-            }
+    SubTile<S, K, E> a, b;
+    if (U > 0) a.load(base_of(0), 0, P, nslots, lane);
+    for (int64_t u = 0; u < U; u += 2) {
+        if (u + 1 < U) b.load(base_of(u + 1), (int)((u + 1) % NSUB), P, nslots, lane);
+        process_subtile<S, K, E, GRAD>(a, s_c, lane, u, first_of(u), n_events, ur, ui, fs);
+        if (u + 1 < U) {
+            if (u + 2 < U) a.load(base_of(u + 2), (int)((u + 2) % NSUB), P, nslots, lane);
+            process_subtile<S, K, E, GRAD>(b, s_c, lane, u + 1, first_of(u + 1), n_events, ur, ui, fs);
         }
     }
 
-    // combine the block's wavefronts in a fixed order
-    dsum = wave_allsum(dsum);
-    nbad = wave_allsum_int(nbad);
+    // logarithms of the intensities still held, then combine the block's
+    // wavefronts in a fixed order
+    fs.dsum += log(fs.held);
+    double dsum = wave_allsum(fs.dsum);
+    int nbad = wave_allsum_int(fs.nbad);
     for (int w = 0; w < nwaves; ++w) {
         if (wave == w) {
 #pragma unroll
@@ -332,11 +382,12 @@ int select_kslots(int P, bool c128)
     return -1;
 }
 
-// Default sub-tile width per slot count: at most 16 loaded 16-byte vectors
-// (64 registers) per lane, which leaves room for three wavefronts per SIMD.
+// Default sub-tile width per slot count: at most 8 loaded 16-byte vectors
+// (32 registers) per lane and buffer, which with the second buffer of the
+// software pipeline leaves room for three wavefronts per SIMD.
 int default_subtile(int kslots, bool c128)
 {
-    int e = 16 / kslots * (c128 ? 1 : 2);
+    int e = 8 / kslots * (c128 ? 1 : 2);
     if (e > kTileEvents) e = kTileEvents;
     if (e < (c128 ? 1 : 2)) e = c128 ? 1 : 2;
     return e;
@@ -353,23 +404,20 @@ static bool with_shape(int K, int E, F&& f)
         f.template operator()<k, e>();                 \
         return true;                                   \
     }
-    PWA_SHAPE(1, 16)
-    PWA_SHAPE(2, 16)
-    PWA_SHAPE(2, 8)
-    PWA_SHAPE(4, 16)
-    PWA_SHAPE(4, 8)
-    PWA_SHAPE(4, 4)
     if constexpr (F32) {
-        PWA_SHAPE(8, 8)
-        PWA_SHAPE(8, 4)
-        PWA_SHAPE(16, 4)
+        PWA_SHAPE(1, 16)
+        PWA_SHAPE(2, 8)
+        PWA_SHAPE(4, 4)
+        PWA_SHAPE(4, 8)
+        PWA_SHAPE(8, 2)
         PWA_SHAPE(16, 2)
         PWA_SHAPE(33, 2)
     } else {
+        PWA_SHAPE(1, 8)
+        PWA_SHAPE(2, 4)
         PWA_SHAPE(4, 2)
-        PWA_SHAPE(8, 4)
-        PWA_SHAPE(8, 2)
-        PWA_SHAPE(16, 2)
+        PWA_SHAPE(4, 4)
+        PWA_SHAPE(8, 1)
         PWA_SHAPE(16, 1)
         PWA_SHAPE(33, 1)
     }
