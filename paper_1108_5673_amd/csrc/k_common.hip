@@ -151,71 +151,122 @@ hipError_t launch_colsum(const double* partials, int rows, int cols, int stride,
     return hipGetLastError();
 }
 
-// NLL and gradient from the column sums; one block, thread b handles wave b.
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ colsum,
-                                                  const double2* __restrict__ M, int W,
-                                                  int rec_len, VParams vp, bool grad,
-                                                  bool amplitude, double* __restrict__ out)
+// NLL and gradient from the column sums, by the block that finishes last.
+//
+// Every block of k_reduce_finalize sums four columns of the partial records
+// (one wavefront per column, as k_colsum).  It then takes a ticket; the block
+// that draws the last ticket knows all column sums are written and assembles
+//   mu   = sum_b Re(conj(V_b) m_b),  m_b = sum_a V_a M_ab
+//   NLL  = -sum ln I + mu
+//   G_b  = 2 (m_b - u_b),  u_b = sum_a V_a U_ab   (table forms, U Hermitian packed)
+//   G_b  = 2 (m_b - g_b)                          (amplitude form)
+// with thread t working on wave b = t % W and the a-range t / W, partial sums
+// combined in LDS in a fixed order.  The result goes straight to `out`, a
+// pinned host buffer, and the ticket counter is reset for the next call.
+constexpr int kFinBlock = 256;
+
+__device__ inline void finalize_block(const double* __restrict__ colsum,
+                                      const double2* __restrict__ M, int W, const VParams& vp,
+                                      bool grad, bool amplitude, double* __restrict__ out)
 {
-    __shared__ double s_mu[PWA_MAX_WAVES_AMPLITUDE];
-    const double sum_ln = colsum[0];
-    const double nbad = colsum[1];
-    for (int b = threadIdx.x; b < W; b += blockDim.x) {
-        // m_b = sum_a V_a M_ab
-        double mr = 0.0, mi = 0.0;
-        for (int a = 0; a < W; ++a) {
+    __shared__ double s_part[4][kFinBlock];
+    __shared__ double s_mu[kFinBlock];
+    const int t = threadIdx.x;
+    const int groups = W <= kFinBlock ? kFinBlock / W : 1;   // a-ranges per wave
+    const int b = t % W;
+    const int g = t / W;
+    double mr = 0.0, mi = 0.0, ur = 0.0, ui = 0.0;
+    if (g < groups) {
+        for (int a = g; a < W; a += groups) {
             const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
             const double2 x = M[a * W + b];
             mr += vr * x.x - vi * x.y;
             mi += vr * x.y + vi * x.x;
+            if (grad && !amplitude) {
+                double xr, xi;
+                if (a <= b) {
+                    const int e = packed_index(W, a, b);
+                    xr = colsum[2 + 2 * e];
+                    xi = colsum[3 + 2 * e];
+                } else {
+                    const int e = packed_index(W, b, a);
+                    xr = colsum[2 + 2 * e];
+                    xi = -colsum[3 + 2 * e];
+                }
+                ur += vr * xr - vi * xi;
+                ui += vr * xi + vi * xr;
+            }
         }
-        // Re( conj(V_b) m_b )
-        s_mu[b] = vp.v[2 * b] * mr + vp.v[2 * b + 1] * mi;
+    }
+    s_part[0][t] = mr;
+    s_part[1][t] = mi;
+    s_part[2][t] = ur;
+    s_part[3][t] = ui;
+    __syncthreads();
+    const double nbad = colsum[1];
+    if (t < W) {
+        double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+        for (int gg = 0; gg < groups; ++gg) {
+            const int src = gg * W + t;
+            r0 += s_part[0][src];
+            r1 += s_part[1][src];
+            r2 += s_part[2][src];
+            r3 += s_part[3][src];
+        }
+        s_mu[t] = vp.v[2 * t] * r0 + vp.v[2 * t + 1] * r1;
         if (grad) {
             double gr, gi;
             if (amplitude) {
-                gr = 2.0 * (mr - colsum[2 + 2 * b]);
-                gi = 2.0 * (mi - colsum[3 + 2 * b]);
+                gr = 2.0 * (r0 - colsum[2 + 2 * t]);
+                gi = 2.0 * (r1 - colsum[3 + 2 * t]);
             } else {
-                // u_b = sum_a V_a U_ab, U Hermitian, stored packed (a <= b)
-                double ur = 0.0, ui = 0.0;
-                for (int a = 0; a < W; ++a) {
-                    double xr, xi;
-                    if (a <= b) {
-                        const int e = packed_index(W, a, b);
-                        xr = colsum[2 + 2 * e];
-                        xi = colsum[3 + 2 * e];
-                    } else {
-                        const int e = packed_index(W, b, a);
-                        xr = colsum[2 + 2 * e];
-                        xi = -colsum[3 + 2 * e];
-                    }
-                    const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
-                    ur += vr * xr - vi * xi;
-                    ui += vr * xi + vi * xr;
-                }
-                gr = 2.0 * (mr - ur);
-                gi = 2.0 * (mi - ui);
+                gr = 2.0 * (r0 - r2);
+                gi = 2.0 * (r1 - r3);
             }
-            out[2 + 2 * b] = nbad > 0.0 ? NAN : gr;
-            out[3 + 2 * b] = nbad > 0.0 ? NAN : gi;
+            out[2 + 2 * t] = nbad > 0.0 ? NAN : gr;
+            out[3 + 2 * t] = nbad > 0.0 ? NAN : gi;
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         double mu = 0.0;
-        for (int b = 0; b < W; ++b) mu += s_mu[b];
-        out[0] = nbad > 0.0 ? INFINITY : (-sum_ln + mu);
+        for (int bb = 0; bb < W; ++bb) mu += s_mu[bb];
+        out[0] = nbad > 0.0 ? INFINITY : (-colsum[0] + mu);
         out[1] = nbad;
     }
-    (void)rec_len;
 }
 
-hipError_t launch_finalize(const Model& m, const VParams& vp, bool grad, double* out,
-                           hipStream_t s)
+__global__ __launch_bounds__(kFinBlock) void k_reduce_finalize(
+    const double* __restrict__ partials, int rows, int cols, int stride, double* __restrict__ colsum,
+    unsigned int* __restrict__ ticket, const double2* __restrict__ M, int W, VParams vp, bool grad,
+    bool amplitude, double* __restrict__ out)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, m.d_colsum,
-                       (const double2*)m.d_M, m.W, m.rec_len, vp, grad, m.form == kAmp32, out);
+    __shared__ bool s_last;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (col < cols) {
+        double s = 0.0;
+        for (int r = lane; r < rows; r += 64) s += partials[(int64_t)r * stride + col];
+        s = wave_allsum(s);
+        if (lane == 0) colsum[col] = s;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    finalize_block(colsum, M, W, vp, grad, amplitude, out);
+    if (threadIdx.x == 0) atomicExch(ticket, 0u);
+}
+
+hipError_t launch_reduce_finalize(const Model& m, const VParams& vp, bool grad, double* out,
+                                  hipStream_t s)
+{
+    const int cols = grad ? m.rec_len : 2;
+    hipLaunchKernelGGL(k_reduce_finalize, dim3((cols + 3) / 4), dim3(kFinBlock), 0, s,
+                       m.d_partials, m.rows, cols, m.rec_len, m.d_colsum, m.d_ticket,
+                       (const double2*)m.d_M, m.W, vp, grad, m.form == kAmp32, out);
     return hipGetLastError();
 }
 

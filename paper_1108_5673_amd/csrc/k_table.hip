@@ -167,17 +167,29 @@ struct SubTile {
     static constexpr int VPT = kTileEvents / EV;
     V4 x[K][VS];
 
-    __device__ void load(const char* tb, int sub, int P, int nslots, int lane)
+    // tb is wave-uniform, so every address is a scalar base plus the lane's
+    // 16-byte offset.  Full slots load unconditionally; only the last,
+    // partly filled slot is predicated on the lane.
+    __device__ void load(const char* tb, int sub, int P, int lane)
     {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int nk = min(64, P - 64 * k);
-            const bool on = (k < nslots) && (lane < nk);
             const char* sb = tb + (int64_t)k * 64 * VPT * 16;
+            if (64 * (k + 1) <= P) {
 #pragma unroll
-            for (int v = 0; v < VS; ++v)
-                x[k][v] = on ? *reinterpret_cast<const V4*>(sb + ((sub * VS + v) * nk + lane) * 16)
-                             : VT::zero();
+                for (int v = 0; v < VS; ++v)
+                    x[k][v] = *reinterpret_cast<const V4*>(sb + ((sub * VS + v) * 64 + lane) * 16);
+            } else if (64 * k < P) {
+                const int nk = P - 64 * k;
+#pragma unroll
+                for (int v = 0; v < VS; ++v)
+                    x[k][v] = lane < nk
+                                  ? *reinterpret_cast<const V4*>(sb + ((sub * VS + v) * nk + lane) * 16)
+                                  : VT::zero();
+            } else {
+#pragma unroll
+                for (int v = 0; v < VS; ++v) x[k][v] = VT::zero();
+            }
         }
     }
 };
@@ -264,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_table_fused(
     __shared__ double s_misc[2];
 
     const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int nwaves = blockDim.x >> 6;
 
     // coefficients c_e for every (slot, lane)
@@ -283,7 +295,6 @@ __global__ __launch_bounds__(kBlock) void k_table_fused(
     }
     __syncthreads();
 
-    const int nslots = (P + 63) >> 6;
     double ur[K], ui[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) { ur[k] = 0.0; ui[k] = 0.0; }
@@ -302,12 +313,12 @@ __global__ __launch_bounds__(kBlock) void k_table_fused(
     auto first_of = [&](int64_t u) { return tile_of(u) * kTileEvents + (u % NSUB) * E; };
 
     SubTile<S, K, E> a, b;
-    if (U > 0) a.load(base_of(0), 0, P, nslots, lane);
+    if (U > 0) a.load(base_of(0), 0, P, lane);
     for (int64_t u = 0; u < U; u += 2) {
-        if (u + 1 < U) b.load(base_of(u + 1), (int)((u + 1) % NSUB), P, nslots, lane);
+        if (u + 1 < U) b.load(base_of(u + 1), (int)((u + 1) % NSUB), P, lane);
         process_subtile<S, K, E, GRAD>(a, s_c, lane, u, first_of(u), n_events, ur, ui, fs);
         if (u + 1 < U) {
-            if (u + 2 < U) a.load(base_of(u + 2), (int)((u + 2) % NSUB), P, nslots, lane);
+            if (u + 2 < U) a.load(base_of(u + 2), (int)((u + 2) % NSUB), P, lane);
             process_subtile<S, K, E, GRAD>(b, s_c, lane, u + 1, first_of(u + 1), n_events, ur, ui, fs);
         }
     }

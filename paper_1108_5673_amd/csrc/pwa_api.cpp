@@ -3,9 +3,9 @@
 //
 // Evaluation sequence on the caller's stream (all device work is in kernels):
 //   main kernel (fused table / plain two-pass / amplitude) -> per-block partials
-//   column sum of the partials (fixed order)               -> d_colsum
-//   finalize: NLL = -sum ln I + mu, gradient               -> d_out
-//   one device-to-host copy of 2 + 2W doubles into pinned memory, stream sync.
+//   column sums of the partials (fixed order), then in the last block to
+//   finish: NLL = -sum ln I + mu and the gradient -> pinned host memory
+//   stream sync; nothing is copied with a separate transfer.
 // V travels in the kernel arguments, so nothing is copied host-to-device.
 #include <hip/hip_runtime.h>
 
@@ -111,22 +111,21 @@ void release(Model* m)
     if (m->d_partials) (void)hipFree(m->d_partials);
     if (m->d_colsum) (void)hipFree(m->d_colsum);
     if (m->d_w) (void)hipFree(m->d_w);
-    if (m->d_out) (void)hipFree(m->d_out);
+    if (m->d_ticket) (void)hipFree(m->d_ticket);
     if (m->h_out) (void)hipHostFree(m->h_out);
     if (m->ev0) (void)hipEventDestroy(m->ev0);
     if (m->ev1) (void)hipEventDestroy(m->ev1);
     delete m;
 }
 
+// Pinned, device-visible, coherent host memory: the final kernel writes the
+// results there directly, so no device-to-host copy is queued.
 int alloc_out(Model* m, int cap)
 {
     const size_t bytes = sizeof(double) * (size_t)(2 + 2 * m->W) * cap;
-    if (m->d_out) (void)hipFree(m->d_out);
     if (m->h_out) (void)hipHostFree(m->h_out);
-    m->d_out = nullptr;
     m->h_out = nullptr;
-    HIP_TRY(hipMalloc(&m->d_out, bytes));
-    HIP_TRY(hipHostMalloc(&m->h_out, bytes, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&m->h_out, bytes, hipHostMallocCoherent | hipHostMallocMapped));
     m->out_cap = cap;
     return PWA_OK;
 }
@@ -226,6 +225,8 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
     }
 
     HIP_TRY(hipMalloc(&m->d_partials, sizeof(double) * (size_t)m->rows * m->rec_len));
+    HIP_TRY(hipMalloc(&m->d_ticket, sizeof(unsigned int)));
+    HIP_TRY(hipMemsetAsync(m->d_ticket, 0, sizeof(unsigned int), s));
     rc = alloc_out(m, 1);
     if (rc != PWA_OK) return rc;
     HIP_TRY(hipEventCreate(&m->ev0));
@@ -257,16 +258,12 @@ int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, 
         e = pwa::launch_amp_fused(*m, vp, grad, s);
     if (e != hipSuccess) return device_fail(e, "main kernel launch");
     if (timed) HIP_TRY(hipEventRecord(m->ev1, s));
-    HIP_TRY(pwa::launch_colsum(m->d_partials, m->rows, grad ? m->rec_len : 2, m->rec_len,
-                                m->d_colsum, s));
-    HIP_TRY(pwa::launch_finalize(*m, vp, grad, m->d_out + (size_t)slot * (2 + 2 * m->W), s));
+    HIP_TRY(pwa::launch_reduce_finalize(*m, vp, grad, m->h_out + (size_t)slot * (2 + 2 * m->W), s));
     return PWA_OK;
 }
 
-int finish(Model* m, int count, hipStream_t s, bool timed)
+int finish(Model* m, hipStream_t s, bool timed)
 {
-    HIP_TRY(hipMemcpyAsync(m->h_out, m->d_out, sizeof(double) * (2 + 2 * m->W) * count,
-                           hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (timed) {
         float ms = 0.f;
@@ -288,7 +285,7 @@ int evaluate(const pwa_model* cm, const double* v, double* nll, double* grad, vo
     const bool want_grad = grad != nullptr;
     rc = enqueue_eval(m, v, want_grad, 0, s, m->timing);
     if (rc != PWA_OK) return rc;
-    rc = finish(m, 1, s, m->timing);
+    rc = finish(m, s, m->timing);
     if (rc != PWA_OK) return rc;
     *nll = m->h_out[0];
     if (want_grad) std::memcpy(grad, m->h_out + 2, sizeof(double) * 2 * m->W);
@@ -392,7 +389,7 @@ int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k
             if (rc != PWA_OK) return rc;
         }
         if (K > 0) {
-            const int rc = finish(m, K, s, false);
+            const int rc = finish(m, s, false);
             if (rc != PWA_OK) return rc;
         }
         for (int k = 0; k < K; ++k) {

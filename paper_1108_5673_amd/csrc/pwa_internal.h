@@ -52,9 +52,9 @@ struct Model {
     double* d_partials = nullptr;   // rows x rec_len
     double* d_colsum = nullptr;     // rec_len (x K for batched)
     double* d_w = nullptr;          // plain path: per-event weights 1/I_i
-    double* d_out = nullptr;        // [nll, nbad, grad 2W] (x K for batched)
-    double* h_out = nullptr;        // pinned copy of d_out
-    int32_t out_cap = 1;            // evaluations d_out / h_out can hold
+    unsigned int* d_ticket = nullptr;   // last-block counter of the final reduction
+    double* h_out = nullptr;        // pinned host [nll, nbad, grad 2W] per evaluation
+    int32_t out_cap = 1;            // evaluations h_out can hold
 
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -87,8 +87,8 @@ hipError_t launch_plain(const Model& m, const VParams& vp, bool grad, hipStream_
 hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s);
 hipError_t launch_colsum(const double* partials, int rows, int cols, int stride, double* out,
                          hipStream_t s);
-hipError_t launch_finalize(const Model& m, const VParams& vp, bool grad, double* out,
-                           hipStream_t s);
+hipError_t launch_reduce_finalize(const Model& m, const VParams& vp, bool grad, double* out,
+                                  hipStream_t s);
 
 // occupancy-derived grid sizes
 int table_fused_grid(const Model& m);
