@@ -26,8 +26,9 @@
  *   - Complex numbers are interleaved (re, im) pairs; arrays are row-major.
  *   - V, nll and grad are host pointers.  V has 2W doubles (re, im per wave).
  *   - Each evaluation call is synchronous: it enqueues its work on hip_stream
- *     (a hipStream_t; NULL means the default stream), waits for that stream
- *     and returns with the results in host memory.
+ *     (a hipStream_t; NULL means the default stream) and returns once the
+ *     results are in host memory (the last kernel writes them to pinned host
+ *     memory; the call polls a completion word and reports stream errors).
  *   - No exception or abort crosses the ABI.  Every function returns a status
  *     (pwa_status); pwa_last_error() gives a message for the last non-OK
  *     status of the calling thread.
@@ -135,8 +136,8 @@ int pwa_nll_grad(const pwa_model* model, const double* v, double* nll, double* g
  *   grad         sum_m K_m x 2W_m doubles, or NULL for NLL only.
  *
  * Returns PWA_WARN_DEGENERATE if any evaluation is degenerate (those entries
- * are +INFINITY / NaN); other entries are valid.  Amplitude-form models
- * evaluate all their K_m sets in one pass over their events.
+ * are +INFINITY / NaN); other entries are valid.  The K_m evaluations of a
+ * model are queued back to back and waited for once.
  */
 int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k_per_model,
                     const double* v, double* nll, double* grad, void* hip_stream);

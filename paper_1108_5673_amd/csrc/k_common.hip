@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "pwa_internal.h"
+#include "tail.h"
 #include "wave_ops.h"
 
 namespace pwa {
@@ -151,122 +152,51 @@ hipError_t launch_colsum(const double* partials, int rows, int cols, int stride,
     return hipGetLastError();
 }
 
-// NLL and gradient from the column sums, by the block that finishes last.
-//
-// Every block of k_reduce_finalize sums four columns of the partial records
-// (one wavefront per column, as k_colsum).  It then takes a ticket; the block
-// that draws the last ticket knows all column sums are written and assembles
-//   mu   = sum_b Re(conj(V_b) m_b),  m_b = sum_a V_a M_ab
-//   NLL  = -sum ln I + mu
-//   G_b  = 2 (m_b - u_b),  u_b = sum_a V_a U_ab   (table forms, U Hermitian packed)
-//   G_b  = 2 (m_b - g_b)                          (amplitude form)
-// with thread t working on wave b = t % W and the a-range t / W, partial sums
-// combined in LDS in a fixed order.  The result goes straight to `out`, a
-// pinned host buffer, and the ticket counter is reset for the next call.
-constexpr int kFinBlock = 256;
-
-__device__ inline void finalize_block(const double* __restrict__ colsum,
-                                      const double2* __restrict__ M, int W, const VParams& vp,
-                                      bool grad, bool amplitude, double* __restrict__ out)
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_assemble(VParams vp, TailArgs ta)
 {
-    __shared__ double s_part[4][kFinBlock];
-    __shared__ double s_mu[kFinBlock];
-    const int t = threadIdx.x;
-    const int groups = W <= kFinBlock ? kFinBlock / W : 1;   // a-ranges per wave
-    const int b = t % W;
-    const int g = t / W;
-    double mr = 0.0, mi = 0.0, ur = 0.0, ui = 0.0;
-    if (g < groups) {
-        for (int a = g; a < W; a += groups) {
-            const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
-            const double2 x = M[a * W + b];
-            mr += vr * x.x - vi * x.y;
-            mi += vr * x.y + vi * x.x;
-            if (grad && !amplitude) {
-                double xr, xi;
-                if (a <= b) {
-                    const int e = packed_index(W, a, b);
-                    xr = colsum[2 + 2 * e];
-                    xi = colsum[3 + 2 * e];
-                } else {
-                    const int e = packed_index(W, b, a);
-                    xr = colsum[2 + 2 * e];
-                    xi = -colsum[3 + 2 * e];
-                }
-                ur += vr * xr - vi * xi;
-                ui += vr * xi + vi * xr;
-            }
-        }
-    }
-    s_part[0][t] = mr;
-    s_part[1][t] = mi;
-    s_part[2][t] = ur;
-    s_part[3][t] = ui;
-    __syncthreads();
-    const double nbad = colsum[1];
-    if (t < W) {
-        double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
-        for (int gg = 0; gg < groups; ++gg) {
-            const int src = gg * W + t;
-            r0 += s_part[0][src];
-            r1 += s_part[1][src];
-            r2 += s_part[2][src];
-            r3 += s_part[3][src];
-        }
-        s_mu[t] = vp.v[2 * t] * r0 + vp.v[2 * t + 1] * r1;
-        if (grad) {
-            double gr, gi;
-            if (amplitude) {
-                gr = 2.0 * (r0 - colsum[2 + 2 * t]);
-                gi = 2.0 * (r1 - colsum[3 + 2 * t]);
-            } else {
-                gr = 2.0 * (r0 - r2);
-                gi = 2.0 * (r1 - r3);
-            }
-            out[2 + 2 * t] = nbad > 0.0 ? NAN : gr;
-            out[3 + 2 * t] = nbad > 0.0 ? NAN : gi;
-        }
-    }
-    __syncthreads();
-    if (t == 0) {
-        double mu = 0.0;
-        for (int bb = 0; bb < W; ++bb) mu += s_mu[bb];
-        out[0] = nbad > 0.0 ? INFINITY : (-colsum[0] + mu);
-        out[1] = nbad;
-    }
-}
-
-__global__ __launch_bounds__(kFinBlock) void k_reduce_finalize(
-    const double* __restrict__ partials, int rows, int cols, int stride, double* __restrict__ colsum,
-    unsigned int* __restrict__ ticket, const double2* __restrict__ M, int W, VParams vp, bool grad,
-    bool amplitude, double* __restrict__ out)
-{
+    __shared__ double s_sum[16][kReduceCols];
+    __shared__ double s_scratch[tail_scratch_doubles(kReduceThreads)];
     __shared__ bool s_last;
-    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (col < cols) {
-        double s = 0.0;
-        for (int r = lane; r < rows; r += 64) s += partials[(int64_t)r * stride + col];
-        s = wave_allsum(s);
-        if (lane == 0) colsum[col] = s;
+    const int l = threadIdx.x & 63;
+    const int g = threadIdx.x >> 6;                 // row group 0..15
+    const int col = blockIdx.x * kReduceCols + l;
+    const int64_t stride = ta.rec_len;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (col < ta.cols) {
+        int r = g;
+        for (; r + 48 < ta.rows; r += 64) {
+            s0 += ta.partials[(int64_t)r * stride + col];
+            s1 += ta.partials[(int64_t)(r + 16) * stride + col];
+            s2 += ta.partials[(int64_t)(r + 32) * stride + col];
+            s3 += ta.partials[(int64_t)(r + 48) * stride + col];
+        }
+        for (; r < ta.rows; r += 16) s0 += ta.partials[(int64_t)r * stride + col];
     }
-    __threadfence();
+    s_sum[g][l] = (s0 + s1) + (s2 + s3);
     __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    finalize_block(colsum, M, W, vp, grad, amplitude, out);
-    if (threadIdx.x == 0) atomicExch(ticket, 0u);
+    if (g == 0 && col < ta.cols) {
+        double s = 0.0;
+        for (int k = 0; k < 16; ++k) s += s_sum[k][l];
+        ta.colsum[col] = s;
+    }
+    if (gridDim.x > 1) {
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = atomicAdd(ta.ticket, 1u) == gridDim.x - 1;
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+    } else {
+        __syncthreads();
+    }
+    tail_assemble(ta, vp, s_scratch);
+    if (threadIdx.x == 0 && gridDim.x > 1) atomicExch(ta.ticket, 0u);
 }
 
-hipError_t launch_reduce_finalize(const Model& m, const VParams& vp, bool grad, double* out,
-                                  hipStream_t s)
+hipError_t launch_reduce_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s)
 {
-    const int cols = grad ? m.rec_len : 2;
-    hipLaunchKernelGGL(k_reduce_finalize, dim3((cols + 3) / 4), dim3(kFinBlock), 0, s,
-                       m.d_partials, m.rows, cols, m.rec_len, m.d_colsum, m.d_ticket,
-                       (const double2*)m.d_M, m.W, vp, grad, m.form == kAmp32, out);
+    const int blocks = (ta.cols + kReduceCols - 1) / kReduceCols;
+    hipLaunchKernelGGL(k_reduce_assemble, dim3(blocks), dim3(kReduceThreads), 0, s, vp, ta);
     return hipGetLastError();
 }
 

@@ -3,12 +3,14 @@
 //
 // Evaluation sequence on the caller's stream (all device work is in kernels):
 //   main kernel (fused table / plain two-pass / amplitude) -> per-block partials
-//   column sums of the partials (fixed order), then in the last block to
-//   finish: NLL = -sum ln I + mu and the gradient -> pinned host memory
-//   stream sync; nothing is copied with a separate transfer.
+//   k_reduce_assemble: column sums of the partials (fixed order), then in its
+//   last block: NLL = -sum ln I + mu and the gradient -> pinned host memory
+//   the host polls a completion word in pinned memory; nothing is copied
+//   with a separate transfer.
 // V travels in the kernel arguments, so nothing is copied host-to-device.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -20,6 +22,7 @@
 
 #include "pwa.h"
 #include "pwa_internal.h"
+#include "tail.h"
 
 using pwa::Model;
 
@@ -113,6 +116,7 @@ void release(Model* m)
     if (m->d_w) (void)hipFree(m->d_w);
     if (m->d_ticket) (void)hipFree(m->d_ticket);
     if (m->h_out) (void)hipHostFree(m->h_out);
+    if (m->h_done) (void)hipHostFree(m->h_done);
     if (m->ev0) (void)hipEventDestroy(m->ev0);
     if (m->ev1) (void)hipEventDestroy(m->ev1);
     delete m;
@@ -227,6 +231,9 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
     HIP_TRY(hipMalloc(&m->d_partials, sizeof(double) * (size_t)m->rows * m->rec_len));
     HIP_TRY(hipMalloc(&m->d_ticket, sizeof(unsigned int)));
     HIP_TRY(hipMemsetAsync(m->d_ticket, 0, sizeof(unsigned int), s));
+    HIP_TRY(hipHostMalloc((void**)&m->h_done, sizeof(unsigned long long),
+                          hipHostMallocCoherent | hipHostMallocMapped));
+    *m->h_done = 0;
     rc = alloc_out(m, 1);
     if (rc != PWA_OK) return rc;
     HIP_TRY(hipEventCreate(&m->ev0));
@@ -242,12 +249,28 @@ int check_v(const double* v, int W)
     return PWA_OK;
 }
 
-// Enqueue one evaluation writing slot `slot` of d_out.
-int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, bool timed)
+// Enqueue one evaluation writing slot `slot` of h_out; returns the completion
+// value the last block will publish in h_done.
+int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, bool timed,
+                 unsigned long long* seq_out)
 {
     pwa::VParams vp;
     std::memset(&vp, 0, sizeof vp);
     std::memcpy(vp.v, v, sizeof(double) * 2 * m->W);
+    pwa::TailArgs ta;
+    ta.partials = m->d_partials;
+    ta.rows = m->rows;
+    ta.colsum = m->d_colsum;
+    ta.ticket = m->d_ticket;
+    ta.M = (const double2*)m->d_M;
+    ta.out = m->h_out + (size_t)slot * (2 + 2 * m->W);
+    ta.done = m->h_done;
+    ta.seq = ++m->seq;
+    ta.rec_len = m->rec_len;
+    ta.cols = grad ? m->rec_len : 2;
+    ta.W = m->W;
+    ta.grad = grad ? 1 : 0;
+    ta.amplitude = m->form == pwa::kAmp32 ? 1 : 0;
     if (timed) HIP_TRY(hipEventRecord(m->ev0, s));
     hipError_t e;
     if (m->form == pwa::kTable32 || m->form == pwa::kTable64Fused)
@@ -256,16 +279,34 @@ int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, 
         e = pwa::launch_plain(*m, vp, grad, s);
     else
         e = pwa::launch_amp_fused(*m, vp, grad, s);
-    if (e != hipSuccess) return device_fail(e, "main kernel launch");
+    if (e != hipSuccess) return device_fail(e, "kernel launch");
     if (timed) HIP_TRY(hipEventRecord(m->ev1, s));
-    HIP_TRY(pwa::launch_reduce_finalize(*m, vp, grad, m->h_out + (size_t)slot * (2 + 2 * m->W), s));
+    e = pwa::launch_reduce_assemble(vp, ta, s);
+    if (e != hipSuccess) return device_fail(e, "reduction launch");
+    *seq_out = ta.seq;
     return PWA_OK;
 }
 
-int finish(Model* m, hipStream_t s, bool timed)
+// Wait until the evaluation that publishes `seq` has written its results to
+// host memory.  The host polls the completion word; every few thousand polls
+// it asks the runtime whether the stream failed or finished without it.
+int wait_for(Model* m, unsigned long long seq, hipStream_t s, bool timed)
 {
-    HIP_TRY(hipStreamSynchronize(s));
+    volatile unsigned long long* done = m->h_done;
+    for (unsigned long it = 1;; ++it) {
+        if (*done == seq) break;
+        if ((it & 4095) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                if (*done == seq) break;
+                return fail(PWA_ERR_DEVICE, "evaluation finished without publishing its result");
+            }
+            if (e != hipErrorNotReady) return device_fail(e, "evaluation");
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
     if (timed) {
+        HIP_TRY(hipEventSynchronize(m->ev1));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, m->ev0, m->ev1));
         m->timed_ms += ms;
@@ -283,9 +324,10 @@ int evaluate(const pwa_model* cm, const double* v, double* nll, double* grad, vo
     DeviceGuard g(m->device);
     hipStream_t s = (hipStream_t)stream;
     const bool want_grad = grad != nullptr;
-    rc = enqueue_eval(m, v, want_grad, 0, s, m->timing);
+    unsigned long long seq = 0;
+    rc = enqueue_eval(m, v, want_grad, 0, s, m->timing, &seq);
     if (rc != PWA_OK) return rc;
-    rc = finish(m, s, m->timing);
+    rc = wait_for(m, seq, s, m->timing);
     if (rc != PWA_OK) return rc;
     *nll = m->h_out[0];
     if (want_grad) std::memcpy(grad, m->h_out + 2, sizeof(double) * 2 * m->W);
@@ -384,12 +426,13 @@ int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k
             const int rc = alloc_out(m, K);
             if (rc != PWA_OK) return rc;
         }
+        unsigned long long seq = 0;
         for (int k = 0; k < K; ++k) {
-            const int rc = enqueue_eval(m, vp + (size_t)k * 2 * W, gp != nullptr, k, s, false);
+            const int rc = enqueue_eval(m, vp + (size_t)k * 2 * W, gp != nullptr, k, s, false, &seq);
             if (rc != PWA_OK) return rc;
         }
         if (K > 0) {
-            const int rc = finish(m, s, false);
+            const int rc = wait_for(m, seq, s, false);
             if (rc != PWA_OK) return rc;
         }
         for (int k = 0; k < K; ++k) {

@@ -52,8 +52,10 @@ struct Model {
     double* d_partials = nullptr;   // rows x rec_len
     double* d_colsum = nullptr;     // rec_len (x K for batched)
     double* d_w = nullptr;          // plain path: per-event weights 1/I_i
-    unsigned int* d_ticket = nullptr;   // last-block counter of the final reduction
+    unsigned int* d_ticket = nullptr;   // last-block counter of the reduction (zero between calls)
     double* h_out = nullptr;        // pinned host [nll, nbad, grad 2W] per evaluation
+    unsigned long long* h_done = nullptr;   // pinned host completion word
+    unsigned long long seq = 0;     // last published completion value
     int32_t out_cap = 1;            // evaluations h_out can hold
 
     bool timing = false;
@@ -82,13 +84,13 @@ int gram_rows(int64_t n_acc);
 int plain_rows(int64_t n);
 
 // evaluation
+struct TailArgs;
 hipError_t launch_table_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s);
 hipError_t launch_plain(const Model& m, const VParams& vp, bool grad, hipStream_t s);
 hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s);
 hipError_t launch_colsum(const double* partials, int rows, int cols, int stride, double* out,
                          hipStream_t s);
-hipError_t launch_reduce_finalize(const Model& m, const VParams& vp, bool grad, double* out,
-                                  hipStream_t s);
+hipError_t launch_reduce_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s);
 
 // occupancy-derived grid sizes
 int table_fused_grid(const Model& m);
