@@ -4,7 +4,7 @@
 //
 // Amplitudes are stored complex64, row-major, each row padded to an even
 // number of waves wpad and the event count padded to a multiple of 64 with
-// zero rows.  One wavefront (block of 64 threads) handles a tile of 64 events:
+// zero rows.  A block has up to four wavefronts; each handles tiles of 64 events:
 //   1. coalesced 16-byte loads of the tile's contiguous 512*wpad bytes into LDS
 //      (rows padded in LDS so that the per-event reads below hit distinct banks);
 //   2. lane = event: S_i, I_i, ln I_i and c_i = S_i / I_i in FP64;
@@ -28,25 +28,44 @@ __host__ __device__ inline int amp_lds_stride_words(int wpad)
     return words + pad;
 }
 
-__host__ __device__ inline size_t amp_lds_bytes(int wpad)
+// LDS of one wavefront: its tile of kAmpTile rows and the per-event weights.
+__host__ __device__ inline size_t amp_wave_lds_bytes(int wpad)
 {
-    return (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4 + kAmpTile * 16 + (size_t)wpad * 16;
+    return (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4 + kAmpTile * 16;
+}
+
+__host__ __device__ inline size_t amp_lds_bytes(int wpad, int nwaves)
+{
+    const size_t main = (size_t)wpad * 16 + nwaves * amp_wave_lds_bytes(wpad);
+    const size_t combine = (size_t)wpad * 16 + 2 * 64 * 16 + 16;   // wave combine at the end
+    return main > combine ? main : combine;
+}
+
+// Wavefronts per block: four unless their tiles would not fit twice per CU.
+inline int amp_waves_per_block(int wpad)
+{
+    int w = 4;
+    while (w > 1 && amp_lds_bytes(wpad, w) > 80 * 1024) w >>= 1;
+    return w;
 }
 
 template <int KW, bool GRAD>
-__global__ __launch_bounds__(64) void k_amp_fused(const float4* __restrict__ amp, int64_t n_events,
-                                                  int64_t n_tiles, int W, int wpad, VParams vp,
-                                                  double* __restrict__ partials, int rec_len)
+__global__ __launch_bounds__(256) void k_amp_fused(const float4* __restrict__ amp, int64_t n_events,
+                                                   int64_t n_tiles, int W, int wpad, VParams vp,
+                                                   double* __restrict__ partials, int rec_len)
 {
-    extern __shared__ char lds[];
+    extern __shared__ double lds_d[];
+    char* lds = reinterpret_cast<char*>(lds_d);
     const int stride = amp_lds_stride_words(wpad) * 4;      // bytes per LDS row
-    char* tile = lds;
-    double2* s_cw = reinterpret_cast<double2*>(lds + kAmpTile * stride);
-    double2* s_v = s_cw + kAmpTile;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwaves = blockDim.x >> 6;
+    double2* s_v = reinterpret_cast<double2*>(lds);
+    char* tile = lds + (size_t)wpad * 16 + (size_t)wave * amp_wave_lds_bytes(wpad);
+    double2* s_cw = reinterpret_cast<double2*>(tile + kAmpTile * stride);
     const int h = wpad >> 1;                                 // 16-byte vectors per row
 
-    for (int a = lane; a < wpad; a += 64)
+    for (int a = threadIdx.x; a < wpad; a += blockDim.x)
         s_v[a] = (a < W) ? make_double2(vp.v[2 * a], vp.v[2 * a + 1]) : make_double2(0.0, 0.0);
     __syncthreads();
 
@@ -56,9 +75,11 @@ __global__ __launch_bounds__(64) void k_amp_fused(const float4* __restrict__ amp
     double dsum = 0.0;
     int nbad = 0;
 
+    // the block's tiles, interleaved over its wavefronts; each wavefront uses
+    // only its own LDS region, so it synchronises with itself only
     const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
     const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
-    for (int64_t t = t0; t < t1; ++t) {
+    for (int64_t t = t0 + wave; t < t1; t += nwaves) {
         const float4* src = amp + t * kAmpTile * h;
         for (int q = 0; q < h; ++q) {
             const int f = q * 64 + lane;
@@ -67,7 +88,7 @@ __global__ __launch_bounds__(64) void k_amp_fused(const float4* __restrict__ amp
             const int c = f - ev * h;
             *reinterpret_cast<float4*>(tile + ev * stride + c * 16) = val;
         }
-        __syncthreads();
+        wave_lds_sync();
 
         // lane = event
         const char* row = tile + lane * stride;
@@ -88,7 +109,7 @@ __global__ __launch_bounds__(64) void k_amp_fused(const float4* __restrict__ amp
         if (GRAD) {
             const double w = ok ? 1.0 / I : 0.0;
             s_cw[lane] = make_double2(w * sr, w * si);
-            __syncthreads();
+            wave_lds_sync();
             // lane = wave
             for (int l = 0; l < kAmpTile; ++l) {
                 const double2 c = s_cw[l];
@@ -104,24 +125,43 @@ __global__ __launch_bounds__(64) void k_amp_fused(const float4* __restrict__ amp
                 }
             }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 
+    // combine the block's wavefronts in a fixed order (reusing wave 0's tile)
     dsum = wave_allsum(dsum);
     nbad = wave_allsum_int(nbad);
+    __syncthreads();
+    double2* s_g = reinterpret_cast<double2*>(lds + (size_t)wpad * 16);
+    double* s_misc = reinterpret_cast<double*>(s_g + 2 * 64);   // after KW <= 2 slots of 64
+    for (int w = 0; w < nwaves; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int s = 0; s < KW; ++s) {
+                double2 g = make_double2(gr[s], gi[s]);
+                if (w > 0) {
+                    const double2 o = s_g[s * 64 + lane];
+                    g.x += o.x;
+                    g.y += o.y;
+                }
+                s_g[s * 64 + lane] = g;
+            }
+            if (lane == 0) {
+                s_misc[0] = (w > 0 ? s_misc[0] : 0.0) + dsum;
+                s_misc[1] = (w > 0 ? s_misc[1] : 0.0) + (double)nbad;
+            }
+        }
+        __syncthreads();
+    }
     double* rec = partials + (int64_t)blockIdx.x * rec_len;
-    if (lane == 0) {
-        rec[0] = dsum;
-        rec[1] = (double)nbad;
+    if (threadIdx.x == 0) {
+        rec[0] = s_misc[0];
+        rec[1] = s_misc[1];
     }
     if (GRAD) {
-#pragma unroll
-        for (int s = 0; s < KW; ++s) {
-            const int a = lane + 64 * s;
-            if (a < W) {
-                rec[2 + 2 * a] = gr[s];
-                rec[3 + 2 * a] = gi[s];
-            }
+        for (int a = threadIdx.x; a < W; a += blockDim.x) {
+            rec[2 + 2 * a] = s_g[a].x;
+            rec[3 + 2 * a] = s_g[a].y;
         }
     }
 }
@@ -132,43 +172,49 @@ static const void* amp_symbol()
     return (const void*)&k_amp_fused<KW, true>;
 }
 
-int amp_fused_grid(const Model& m)
+int amp_fused_grid(Model& m)
 {
+    const int nw = amp_waves_per_block(m.wpad);
+    m.amp_waves = nw;
     const void* fn = (m.wpad <= 64) ? amp_symbol<1>() : amp_symbol<2>();
-    const size_t lds = amp_lds_bytes(m.wpad);
+    const size_t lds = amp_lds_bytes(m.wpad, nw);
     if (lds > 65536) {
         // wide rows: allow more than the default 64 KB of dynamic LDS
-        const void* fns[] = {(const void*)&k_amp_fused<2, true>, (const void*)&k_amp_fused<2, false>};
+        const void* fns[] = {(const void*)&k_amp_fused<1, true>, (const void*)&k_amp_fused<1, false>,
+                             (const void*)&k_amp_fused<2, true>, (const void*)&k_amp_fused<2, false>};
         for (const void* f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     }
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * nw, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int64_t g = (int64_t)m.cus * per_cu;
-    if (g > m.n_tiles) g = m.n_tiles;
+    const int64_t max_blocks = (m.n_tiles + nw - 1) / nw;
+    if (g > max_blocks) g = max_blocks;
     return (int)(g < 1 ? 1 : g);
 }
 
 hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s)
 {
-    const size_t lds = amp_lds_bytes(m.wpad);
+    const int nw = m.amp_waves;
+    const size_t lds = amp_lds_bytes(m.wpad, nw);
     const float4* a = (const float4*)m.d_data;
+    const dim3 grid(m.grid), block(64 * nw);
     if (m.wpad <= 64) {
         if (grad)
-            hipLaunchKernelGGL((k_amp_fused<1, true>), dim3(m.grid), dim3(64), lds, s, a, m.n,
-                               m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
+            hipLaunchKernelGGL((k_amp_fused<1, true>), grid, block, lds, s, a, m.n, m.n_tiles, m.W,
+                               m.wpad, vp, m.d_partials, m.rec_len);
         else
-            hipLaunchKernelGGL((k_amp_fused<1, false>), dim3(m.grid), dim3(64), lds, s, a, m.n,
-                               m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
+            hipLaunchKernelGGL((k_amp_fused<1, false>), grid, block, lds, s, a, m.n, m.n_tiles,
+                               m.W, m.wpad, vp, m.d_partials, m.rec_len);
     } else {
         if (grad)
-            hipLaunchKernelGGL((k_amp_fused<2, true>), dim3(m.grid), dim3(64), lds, s, a, m.n,
-                               m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
+            hipLaunchKernelGGL((k_amp_fused<2, true>), grid, block, lds, s, a, m.n, m.n_tiles, m.W,
+                               m.wpad, vp, m.d_partials, m.rec_len);
         else
-            hipLaunchKernelGGL((k_amp_fused<2, false>), dim3(m.grid), dim3(64), lds, s, a, m.n,
-                               m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
+            hipLaunchKernelGGL((k_amp_fused<2, false>), grid, block, lds, s, a, m.n, m.n_tiles,
+                               m.W, m.wpad, vp, m.d_partials, m.rec_len);
     }
     return hipGetLastError();
 }

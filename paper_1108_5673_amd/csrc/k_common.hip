@@ -152,51 +152,160 @@ hipError_t launch_colsum(const double* partials, int rows, int cols, int stride,
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kReduceThreads) void k_reduce_assemble(VParams vp, TailArgs ta)
+// ---- end of an evaluation -------------------------------------------------
+// Every loop below issues its loads in explicit batches before using them:
+// an accumulate-as-you-load loop costs one memory round trip per element.
+constexpr int kBatch = 8;
+
+// Fixed-order LDS tree over the block (blockDim a power of two).
+__device__ inline double block_tree_sum(double x, double* s_red)
 {
-    __shared__ double s_sum[16][kReduceCols];
-    __shared__ double s_scratch[tail_scratch_doubles(kReduceThreads)];
-    __shared__ bool s_last;
-    const int l = threadIdx.x & 63;
-    const int g = threadIdx.x >> 6;                 // row group 0..15
-    const int col = blockIdx.x * kReduceCols + l;
-    const int64_t stride = ta.rec_len;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    if (col < ta.cols) {
-        int r = g;
-        for (; r + 48 < ta.rows; r += 64) {
-            s0 += ta.partials[(int64_t)r * stride + col];
-            s1 += ta.partials[(int64_t)(r + 16) * stride + col];
-            s2 += ta.partials[(int64_t)(r + 32) * stride + col];
-            s3 += ta.partials[(int64_t)(r + 48) * stride + col];
-        }
-        for (; r < ta.rows; r += 16) s0 += ta.partials[(int64_t)r * stride + col];
-    }
-    s_sum[g][l] = (s0 + s1) + (s2 + s3);
+    s_red[threadIdx.x] = x;
     __syncthreads();
-    if (g == 0 && col < ta.cols) {
-        double s = 0.0;
-        for (int k = 0; k < 16; ++k) s += s_sum[k][l];
-        ta.colsum[col] = s;
-    }
-    if (gridDim.x > 1) {
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) s_last = atomicAdd(ta.ticket, 1u) == gridDim.x - 1;
-        __syncthreads();
-        if (!s_last) return;
-        __threadfence();
-    } else {
+    for (int m = blockDim.x / 2; m >= 1; m >>= 1) {
+        if ((int)threadIdx.x < m) s_red[threadIdx.x] += s_red[threadIdx.x + m];
         __syncthreads();
     }
-    tail_assemble(ta, vp, s_scratch);
-    if (threadIdx.x == 0 && gridDim.x > 1) atomicExch(ta.ticket, 0u);
+    const double r = s_red[0];
+    __syncthreads();
+    return r;
 }
 
-hipError_t launch_reduce_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s)
+// Sum of column `col` over the records: thread t adds rows t, t + blockDim,
+// ... in order, then the block tree.
+__device__ inline double block_column_sum(const TailArgs& ta, int col, double* s_red)
 {
-    const int blocks = (ta.cols + kReduceCols - 1) / kReduceCols;
-    hipLaunchKernelGGL(k_reduce_assemble, dim3(blocks), dim3(kReduceThreads), 0, s, vp, ta);
+    double s = 0.0;
+    const int step = blockDim.x;
+    int r = threadIdx.x;
+    for (; r + (kBatch - 1) * step < ta.rows; r += kBatch * step) {
+        double x[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) x[k] = ta.rec[(int64_t)(r + k * step) * ta.rec_len + col];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) s += x[k];
+    }
+    for (; r < ta.rows; r += step) s += ta.rec[(int64_t)r * ta.rec_len + col];
+    return block_tree_sum(s, s_red);
+}
+
+__device__ inline void publish(const TailArgs& ta)
+{
+    wait_vm_complete();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(ta.done + blockIdx.x, ta.seq, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailArgs ta)
+{
+    __shared__ double s_red[kAssembleThreads];
+    __shared__ double2 s_acc[kAssembleThreads];
+    const int W = ta.W;
+    const double nbad = block_column_sum(ta, 1, s_red);
+    if (blockIdx.x == 0) {
+        const double dsum = block_column_sum(ta, 0, s_red);
+        // mu = sum_{a,b} Re(conj(V_b) V_a M_ab): pairs (a, b) over the threads
+        double mu_part = 0.0;
+        for (int k = threadIdx.x; k < W * W; k += blockDim.x) {
+            const int a = k / W, bb = k % W;
+            const double2 x = ta.M[k];
+            const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
+            const double tr = vr * x.x - vi * x.y, ti = vr * x.y + vi * x.x;   // V_a M_ab
+            mu_part += vp.v[2 * bb] * tr + vp.v[2 * bb + 1] * ti;             // Re(conj(V_b) .)
+        }
+        const double mu = block_tree_sum(mu_part, s_red);
+        if (threadIdx.x == 0) {
+            store_system(ta.out, nbad > 0.0 ? INFINITY : (-dsum + mu));
+            store_system(ta.out + 1, nbad);
+        }
+        publish(ta);
+        return;
+    }
+    const int b = blockIdx.x - 1;
+    // the entries this gradient component needs: U_ab for all a (packed row and
+    // column of b) or g_b; thread t works on entry a = t % nent over the record
+    // range t / nent, and the ranges are added in order
+    const int nent = ta.amplitude ? 1 : W;
+    const int chunks = kAssembleThreads / nent;
+    const int a = threadIdx.x % nent;
+    const int ch = threadIdx.x / nent;
+    double2 acc = make_double2(0.0, 0.0);
+    if (ch < chunks) {
+        int col;
+        double sgn = 1.0;
+        if (ta.amplitude) {
+            col = 2 + 2 * b;
+        } else if (a <= b) {
+            col = 2 + 2 * packed_index(W, a, b);
+        } else {
+            col = 2 + 2 * packed_index(W, b, a);   // U_ab = conj(U_ba)
+            sgn = -1.0;
+        }
+        const double* base = ta.rec + col;
+        int r = ch;
+        for (; r + (kBatch - 1) * chunks < ta.rows; r += kBatch * chunks) {
+            double2 x[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                x[k] = *reinterpret_cast<const double2*>(base + (int64_t)(r + k * chunks) * ta.rec_len);
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                acc.x += x[k].x;
+                acc.y += x[k].y;
+            }
+        }
+        for (; r < ta.rows; r += chunks) {
+            const double2 x = *reinterpret_cast<const double2*>(base + (int64_t)r * ta.rec_len);
+            acc.x += x.x;
+            acc.y += x.y;
+        }
+        acc.y *= sgn;
+    }
+    s_acc[threadIdx.x] = acc;
+    // m_b = sum_a V_a M_ab: thread a < W forms its term, added in order below
+    __shared__ double2 s_m[PWA_MAX_WAVES_AMPLITUDE];
+    for (int aa = threadIdx.x; aa < W; aa += blockDim.x) {
+        const double2 x = ta.M[aa * W + b];
+        const double vr = vp.v[2 * aa], vi = vp.v[2 * aa + 1];
+        s_m[aa] = make_double2(vr * x.x - vi * x.y, vr * x.y + vi * x.x);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ur = 0.0, ui = 0.0, mr = 0.0, mi = 0.0;
+        for (int aa = 0; aa < nent; ++aa) {
+            double xr = 0.0, xi = 0.0;
+            for (int c = 0; c < chunks; ++c) {
+                xr += s_acc[c * nent + aa].x;
+                xi += s_acc[c * nent + aa].y;
+            }
+            if (ta.amplitude) {
+                ur = xr;
+                ui = xi;
+            } else {
+                const double vr = vp.v[2 * aa], vi = vp.v[2 * aa + 1];
+                ur += vr * xr - vi * xi;
+                ui += vr * xi + vi * xr;
+            }
+        }
+        for (int aa = 0; aa < W; ++aa) {
+            mr += s_m[aa].x;
+            mi += s_m[aa].y;
+        }
+        const double gr = 2.0 * (mr - ur), gi = 2.0 * (mi - ui);
+        store_system(ta.out + 2 + 2 * b, nbad > 0.0 ? NAN : gr);
+        store_system(ta.out + 3 + 2 * b, nbad > 0.0 ? NAN : gi);
+    }
+    publish(ta);
+}
+
+int assemble_blocks(int W, bool grad) { return 1 + (grad ? W : 0); }
+
+hipError_t launch_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_assemble, dim3(assemble_blocks(ta.W, ta.grad != 0)),
+                       dim3(kAssembleThreads), 0, s, vp, ta);
     return hipGetLastError();
 }
 

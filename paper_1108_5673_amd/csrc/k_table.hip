@@ -135,8 +135,8 @@ hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, voi
 //   5. broadcasts w_i through scalar registers and accumulates, from the
 //      registers loaded in step 1, U_e += w_i T_ie (FP64), the data part of
 //      the gradient; the table is read from memory exactly once.
-// At the end the four wavefronts of a block are combined in LDS in a fixed
-// order and the block writes one partial record [sum ln I, n_bad, U_e...].
+// At the end the wavefronts of a block are combined in LDS in a fixed order
+// and the block writes one partial record [sum ln I, n_bad, U_e...].
 // ---------------------------------------------------------------------------
 template <typename S> struct Vec16;
 template <> struct Vec16<float> {
@@ -261,8 +261,19 @@ __device__ inline void process_subtile(SubTile<S, K, E>& st, const double2* s_c,
     }
 }
 
+// Block shape.  The shapes whose streaming loop fits in 128 registers (the
+// 20-wave shapes) run one block of sixteen wavefronts per CU, four per SIMD,
+// which also makes the per-block partial records few; the others run blocks
+// of four wavefronts.
+template <typename S, int K, int E>
+constexpr int fused_threads()
+{
+    if constexpr (sizeof(S) == 4) return (K == 4 && E == 4) ? 1024 : 256;
+    else return (K == 2 && E == 4) ? 1024 : 256;
+}
+
 template <typename S, int K, int E, bool GRAD>
-__global__ __launch_bounds__(kBlock) void k_table_fused(
+__global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
     const char* __restrict__ table, int64_t n_events, int64_t n_tiles, int P,
     const uint32_t* __restrict__ pairs, VParams vp, double* __restrict__ partials, int rec_len)
 {
@@ -366,12 +377,13 @@ __global__ __launch_bounds__(kBlock) void k_table_fused(
 template <typename S, int K, int E>
 static hipError_t run_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s)
 {
+    constexpr int NT = fused_threads<S, K, E>();
     if (grad)
-        hipLaunchKernelGGL((k_table_fused<S, K, E, true>), dim3(m.grid), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL((k_table_fused<S, K, E, true>), dim3(m.grid), dim3(NT), 0, s,
                            (const char*)m.d_data, m.n, m.n_tiles, m.P, m.d_pairs, vp,
                            m.d_partials, m.rec_len);
     else
-        hipLaunchKernelGGL((k_table_fused<S, K, E, false>), dim3(m.grid), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL((k_table_fused<S, K, E, false>), dim3(m.grid), dim3(NT), 0, s,
                            (const char*)m.d_data, m.n, m.n_tiles, m.P, m.d_pairs, vp,
                            m.d_partials, m.rec_len);
     return hipGetLastError();
@@ -461,19 +473,27 @@ hipError_t launch_table_fused(const Model& m, const VParams& vp, bool grad, hipS
 int table_fused_grid(const Model& m)
 {
     const void* fn = nullptr;
+    int nt = 256;
     if (m.form == kTable32) {
-        auto get = [&]<int K, int E>() { fn = fused_fn<float, K, E>(); };
+        auto get = [&]<int K, int E>() {
+            fn = fused_fn<float, K, E>();
+            nt = fused_threads<float, K, E>();
+        };
         with_shape<float>(m.kslots, m.subtile, get);
     } else {
-        auto get = [&]<int K, int E>() { fn = fused_fn<double, K, E>(); };
+        auto get = [&]<int K, int E>() {
+            fn = fused_fn<double, K, E>();
+            nt = fused_threads<double, K, E>();
+        };
         with_shape<double>(m.kslots, m.subtile, get);
     }
     int per_cu = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess ||
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int64_t g = (int64_t)m.cus * per_cu;
-    if (g > m.n_tiles) g = m.n_tiles;
+    const int64_t max_blocks = (m.n_tiles + nt / 64 - 1) / (nt / 64);
+    if (g > max_blocks) g = max_blocks;
     return (int)(g < 1 ? 1 : g);
 }
 

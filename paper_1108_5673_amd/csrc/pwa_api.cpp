@@ -3,8 +3,9 @@
 //
 // Evaluation sequence on the caller's stream (all device work is in kernels):
 //   main kernel (fused table / plain two-pass / amplitude) -> per-block partials
-//   k_reduce_assemble: column sums of the partials (fixed order), then in its
-//   last block: NLL = -sum ln I + mu and the gradient -> pinned host memory
+//   k_assemble: block 0 sums ln I and forms NLL = -sum ln I + mu, block 1 + b
+//   sums the entries gradient component b needs and forms it; results go to
+//   pinned host memory, each block then sets its completion word
 //   the host polls a completion word in pinned memory; nothing is copied
 //   with a separate transfer.
 // V travels in the kernel arguments, so nothing is copied host-to-device.
@@ -114,7 +115,7 @@ void release(Model* m)
     if (m->d_partials) (void)hipFree(m->d_partials);
     if (m->d_colsum) (void)hipFree(m->d_colsum);
     if (m->d_w) (void)hipFree(m->d_w);
-    if (m->d_ticket) (void)hipFree(m->d_ticket);
+
     if (m->h_out) (void)hipHostFree(m->h_out);
     if (m->h_done) (void)hipHostFree(m->h_done);
     if (m->ev0) (void)hipEventDestroy(m->ev0);
@@ -229,11 +230,11 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
     }
 
     HIP_TRY(hipMalloc(&m->d_partials, sizeof(double) * (size_t)m->rows * m->rec_len));
-    HIP_TRY(hipMalloc(&m->d_ticket, sizeof(unsigned int)));
-    HIP_TRY(hipMemsetAsync(m->d_ticket, 0, sizeof(unsigned int), s));
-    HIP_TRY(hipHostMalloc((void**)&m->h_done, sizeof(unsigned long long),
+
+    const int nblk = pwa::assemble_blocks(W, true);
+    HIP_TRY(hipHostMalloc((void**)&m->h_done, sizeof(unsigned long long) * nblk,
                           hipHostMallocCoherent | hipHostMallocMapped));
-    *m->h_done = 0;
+    for (int k = 0; k < nblk; ++k) m->h_done[k] = 0;
     rc = alloc_out(m, 1);
     if (rc != PWA_OK) return rc;
     HIP_TRY(hipEventCreate(&m->ev0));
@@ -252,22 +253,19 @@ int check_v(const double* v, int W)
 // Enqueue one evaluation writing slot `slot` of h_out; returns the completion
 // value the last block will publish in h_done.
 int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, bool timed,
-                 unsigned long long* seq_out)
+                 unsigned long long* seq_out, int* nblk_out)
 {
     pwa::VParams vp;
     std::memset(&vp, 0, sizeof vp);
     std::memcpy(vp.v, v, sizeof(double) * 2 * m->W);
     pwa::TailArgs ta;
-    ta.partials = m->d_partials;
+    ta.rec = m->d_partials;
     ta.rows = m->rows;
-    ta.colsum = m->d_colsum;
-    ta.ticket = m->d_ticket;
+    ta.rec_len = m->rec_len;
     ta.M = (const double2*)m->d_M;
     ta.out = m->h_out + (size_t)slot * (2 + 2 * m->W);
     ta.done = m->h_done;
     ta.seq = ++m->seq;
-    ta.rec_len = m->rec_len;
-    ta.cols = grad ? m->rec_len : 2;
     ta.W = m->W;
     ta.grad = grad ? 1 : 0;
     ta.amplitude = m->form == pwa::kAmp32 ? 1 : 0;
@@ -281,24 +279,31 @@ int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, 
         e = pwa::launch_amp_fused(*m, vp, grad, s);
     if (e != hipSuccess) return device_fail(e, "kernel launch");
     if (timed) HIP_TRY(hipEventRecord(m->ev1, s));
-    e = pwa::launch_reduce_assemble(vp, ta, s);
-    if (e != hipSuccess) return device_fail(e, "reduction launch");
+    e = pwa::launch_assemble(vp, ta, s);
+    if (e != hipSuccess) return device_fail(e, "assembly launch");
     *seq_out = ta.seq;
+    *nblk_out = pwa::assemble_blocks(m->W, grad);
     return PWA_OK;
 }
 
 // Wait until the evaluation that publishes `seq` has written its results to
-// host memory.  The host polls the completion word; every few thousand polls
-// it asks the runtime whether the stream failed or finished without it.
-int wait_for(Model* m, unsigned long long seq, hipStream_t s, bool timed)
+// host memory: every assembly block stores `seq` in its completion word after
+// its outputs.  The host polls the words; every few thousand polls it asks the
+// runtime whether the stream failed or finished without them.
+int wait_for(Model* m, unsigned long long seq, int nblk, hipStream_t s, bool timed)
 {
     volatile unsigned long long* done = m->h_done;
+    auto all_done = [&]() {
+        for (int k = 0; k < nblk; ++k)
+            if (done[k] != seq) return false;
+        return true;
+    };
     for (unsigned long it = 1;; ++it) {
-        if (*done == seq) break;
+        if (all_done()) break;
         if ((it & 4095) == 0) {
             const hipError_t e = hipStreamQuery(s);
             if (e == hipSuccess) {
-                if (*done == seq) break;
+                if (all_done()) break;
                 return fail(PWA_ERR_DEVICE, "evaluation finished without publishing its result");
             }
             if (e != hipErrorNotReady) return device_fail(e, "evaluation");
@@ -325,9 +330,10 @@ int evaluate(const pwa_model* cm, const double* v, double* nll, double* grad, vo
     hipStream_t s = (hipStream_t)stream;
     const bool want_grad = grad != nullptr;
     unsigned long long seq = 0;
-    rc = enqueue_eval(m, v, want_grad, 0, s, m->timing, &seq);
+    int nblk = 0;
+    rc = enqueue_eval(m, v, want_grad, 0, s, m->timing, &seq, &nblk);
     if (rc != PWA_OK) return rc;
-    rc = wait_for(m, seq, s, m->timing);
+    rc = wait_for(m, seq, nblk, s, m->timing);
     if (rc != PWA_OK) return rc;
     *nll = m->h_out[0];
     if (want_grad) std::memcpy(grad, m->h_out + 2, sizeof(double) * 2 * m->W);
@@ -427,12 +433,14 @@ int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k
             if (rc != PWA_OK) return rc;
         }
         unsigned long long seq = 0;
+        int nblk = 0;
         for (int k = 0; k < K; ++k) {
-            const int rc = enqueue_eval(m, vp + (size_t)k * 2 * W, gp != nullptr, k, s, false, &seq);
+            const int rc = enqueue_eval(m, vp + (size_t)k * 2 * W, gp != nullptr, k, s, false, &seq,
+                                        &nblk);
             if (rc != PWA_OK) return rc;
         }
         if (K > 0) {
-            const int rc = wait_for(m, seq, s, false);
+            const int rc = wait_for(m, seq, nblk, s, false);
             if (rc != PWA_OK) return rc;
         }
         for (int k = 0; k < K; ++k) {

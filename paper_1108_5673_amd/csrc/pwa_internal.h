@@ -14,8 +14,6 @@ namespace pwa {
 constexpr int kTileEvents = 16;
 // Events per tile of the amplitude kernel (one wavefront's worth).
 constexpr int kAmpTile = 64;
-// Threads per block of the streaming kernels: four wavefronts.
-constexpr int kBlock = 256;
 
 enum Form : uint32_t {
     kTable32 = PWA_FORM_TABLE,
@@ -44,6 +42,7 @@ struct Model {
     int32_t rec_len = 0;     // doubles per partial record
     int32_t kslots = 0;      // fused table kernel: slots of 64 entries per lane
     int32_t subtile = 0;     // fused table kernel: events per sub-tile
+    int32_t amp_waves = 1;   // amplitude kernel: wavefronts per block
 
     void* d_data = nullptr;         // table (tiled or SoA) or padded amplitudes
     int64_t data_bytes = 0;
@@ -52,9 +51,8 @@ struct Model {
     double* d_partials = nullptr;   // rows x rec_len
     double* d_colsum = nullptr;     // rec_len (x K for batched)
     double* d_w = nullptr;          // plain path: per-event weights 1/I_i
-    unsigned int* d_ticket = nullptr;   // last-block counter of the reduction (zero between calls)
     double* h_out = nullptr;        // pinned host [nll, nbad, grad 2W] per evaluation
-    unsigned long long* h_done = nullptr;   // pinned host completion word
+    unsigned long long* h_done = nullptr;   // pinned host completion words (one per assembly block)
     unsigned long long seq = 0;     // last published completion value
     int32_t out_cap = 1;            // evaluations h_out can hold
 
@@ -90,11 +88,12 @@ hipError_t launch_plain(const Model& m, const VParams& vp, bool grad, hipStream_
 hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s);
 hipError_t launch_colsum(const double* partials, int rows, int cols, int stride, double* out,
                          hipStream_t s);
-hipError_t launch_reduce_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s);
+hipError_t launch_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s);
+int assemble_blocks(int W, bool grad);
 
 // occupancy-derived grid sizes
 int table_fused_grid(const Model& m);
-int amp_fused_grid(const Model& m);
+int amp_fused_grid(Model& m);
 int select_kslots(int P, bool c128);
 int default_subtile(int kslots, bool c128);
 bool fused_shape_ok(const Model& m);
