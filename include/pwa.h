@@ -176,8 +176,10 @@ int pwa_copy_mc_matrix(const pwa_model* model, double* out_host, void* hip_strea
 int pwa_set_mc_matrix(pwa_model* model, const double* m_host, void* hip_stream);
 
 /*
- * Kernel timing: while enabled, every evaluation records HIP events on its
- * stream around the main (event-streaming) kernel; pwa_get_timing returns the
+ * Kernel timing: while enabled, every evaluation has the runtime stamp two HIP
+ * events with the begin and end of the main (event-streaming) kernel's
+ * dispatch on the evaluation's stream (for PWA_PRECISION_FP64_PLAIN, the begin
+ * of the first pass and the end of the second); pwa_get_timing returns the
  * accumulated device time of those kernels in milliseconds and the number of
  * launches timed, and resets both.
  */

@@ -195,26 +195,28 @@ int amp_fused_grid(Model& m)
     return (int)(g < 1 ? 1 : g);
 }
 
-hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s)
+hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s,
+                            const LaunchEvents& ev)
 {
     const int nw = m.amp_waves;
     const size_t lds = amp_lds_bytes(m.wpad, nw);
     const float4* a = (const float4*)m.d_data;
     const dim3 grid(m.grid), block(64 * nw);
+    const hipEvent_t t0 = ev.start, t1 = ev.stop;
     if (m.wpad <= 64) {
         if (grad)
-            hipLaunchKernelGGL((k_amp_fused<1, true>), grid, block, lds, s, a, m.n, m.n_tiles, m.W,
-                               m.wpad, vp, m.d_partials, m.rec_len);
+            hipExtLaunchKernelGGL((k_amp_fused<1, true>), grid, block, lds, s, t0, t1, 0, a, m.n,
+                                  m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
         else
-            hipLaunchKernelGGL((k_amp_fused<1, false>), grid, block, lds, s, a, m.n, m.n_tiles,
-                               m.W, m.wpad, vp, m.d_partials, m.rec_len);
+            hipExtLaunchKernelGGL((k_amp_fused<1, false>), grid, block, lds, s, t0, t1, 0, a, m.n,
+                                  m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
     } else {
         if (grad)
-            hipLaunchKernelGGL((k_amp_fused<2, true>), grid, block, lds, s, a, m.n, m.n_tiles, m.W,
-                               m.wpad, vp, m.d_partials, m.rec_len);
+            hipExtLaunchKernelGGL((k_amp_fused<2, true>), grid, block, lds, s, t0, t1, 0, a, m.n,
+                                  m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
         else
-            hipLaunchKernelGGL((k_amp_fused<2, false>), grid, block, lds, s, a, m.n, m.n_tiles,
-                               m.W, m.wpad, vp, m.d_partials, m.rec_len);
+            hipExtLaunchKernelGGL((k_amp_fused<2, false>), grid, block, lds, s, t0, t1, 0, a, m.n,
+                                  m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
     }
     return hipGetLastError();
 }

@@ -153,40 +153,47 @@ hipError_t launch_colsum(const double* partials, int rows, int cols, int stride,
 }
 
 // ---- end of an evaluation -------------------------------------------------
-// Every loop below issues its loads in explicit batches before using them:
-// an accumulate-as-you-load loop costs one memory round trip per element.
-constexpr int kBatch = 8;
+// Every loop below issues its loads in predicated batches before using any of
+// them: a loop that adds each value as it arrives costs one memory round trip
+// per element, and the records are few (one per block of the streaming
+// kernel), so one or two batches cover a thread's share.
+constexpr int kBatch = 16;
 
-// Fixed-order LDS tree over the block (blockDim a power of two).
-__device__ inline double block_tree_sum(double x, double* s_red)
+// Block sum in a fixed order: a butterfly inside each wavefront, then the
+// wavefront sums in wave order (blockDim a multiple of 64, at most 1024).
+__device__ inline double block_sum_fixed(double x, double* s_wave)
 {
-    s_red[threadIdx.x] = x;
+    x = wave_allsum(x);
+    const int waves = blockDim.x >> 6;
+    if (lane_id() == 0) s_wave[threadIdx.x >> 6] = x;
     __syncthreads();
-    for (int m = blockDim.x / 2; m >= 1; m >>= 1) {
-        if ((int)threadIdx.x < m) s_red[threadIdx.x] += s_red[threadIdx.x + m];
-        __syncthreads();
-    }
-    const double r = s_red[0];
+    double r = 0.0;
+    for (int w = 0; w < waves; ++w) r += s_wave[w];
     __syncthreads();
     return r;
 }
 
-// Sum of column `col` over the records: thread t adds rows t, t + blockDim,
-// ... in order, then the block tree.
-__device__ inline double block_column_sum(const TailArgs& ta, int col, double* s_red)
+// Sum over rows first, first + step, ... (< rows) of the double2 at `col` of
+// each record, added in row order.
+__device__ inline double2 strided_record_sum(const TailArgs& ta, int col, int first, int step)
 {
-    double s = 0.0;
-    const int step = blockDim.x;
-    int r = threadIdx.x;
-    for (; r + (kBatch - 1) * step < ta.rows; r += kBatch * step) {
-        double x[kBatch];
+    double2 acc = make_double2(0.0, 0.0);
+    const double* base = ta.rec + col;
+    for (int r = first; r < ta.rows; r += kBatch * step) {
+        double2 x[kBatch];
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) x[k] = ta.rec[(int64_t)(r + k * step) * ta.rec_len + col];
+        for (int k = 0; k < kBatch; ++k) {
+            const int row = r + k * step;
+            x[k] = row < ta.rows ? *reinterpret_cast<const double2*>(base + (int64_t)row * ta.rec_len)
+                                 : make_double2(0.0, 0.0);
+        }
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) s += x[k];
+        for (int k = 0; k < kBatch; ++k) {
+            acc.x += x[k].x;
+            acc.y += x[k].y;
+        }
     }
-    for (; r < ta.rows; r += step) s += ta.rec[(int64_t)r * ta.rec_len + col];
-    return block_tree_sum(s, s_red);
+    return acc;
 }
 
 __device__ inline void publish(const TailArgs& ta)
@@ -198,24 +205,32 @@ __device__ inline void publish(const TailArgs& ta)
                            __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// V_a M_ab
+__device__ inline double2 v_times_m(const VParams& vp, const double2* M, int W, int a, int b)
+{
+    const double2 x = M[a * W + b];
+    const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
+    return make_double2(vr * x.x - vi * x.y, vr * x.y + vi * x.x);
+}
+
 __global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailArgs ta)
 {
-    __shared__ double s_red[kAssembleThreads];
+    __shared__ double s_wave[kAssembleThreads / 64];
     __shared__ double2 s_acc[kAssembleThreads];
     const int W = ta.W;
-    const double nbad = block_column_sum(ta, 1, s_red);
+    // columns 0 and 1: sum ln I and the count of invalid intensities
+    const double2 head = strided_record_sum(ta, 0, threadIdx.x, blockDim.x);
+    const double nbad = block_sum_fixed(head.y, s_wave);
     if (blockIdx.x == 0) {
-        const double dsum = block_column_sum(ta, 0, s_red);
+        const double dsum = block_sum_fixed(head.x, s_wave);
         // mu = sum_{a,b} Re(conj(V_b) V_a M_ab): pairs (a, b) over the threads
         double mu_part = 0.0;
         for (int k = threadIdx.x; k < W * W; k += blockDim.x) {
             const int a = k / W, bb = k % W;
-            const double2 x = ta.M[k];
-            const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
-            const double tr = vr * x.x - vi * x.y, ti = vr * x.y + vi * x.x;   // V_a M_ab
-            mu_part += vp.v[2 * bb] * tr + vp.v[2 * bb + 1] * ti;             // Re(conj(V_b) .)
+            const double2 t = v_times_m(vp, ta.M, W, a, bb);
+            mu_part += vp.v[2 * bb] * t.x + vp.v[2 * bb + 1] * t.y;
         }
-        const double mu = block_tree_sum(mu_part, s_red);
+        const double mu = block_sum_fixed(mu_part, s_wave);
         if (threadIdx.x == 0) {
             store_system(ta.out, nbad > 0.0 ? INFINITY : (-dsum + mu));
             store_system(ta.out + 1, nbad);
@@ -243,59 +258,45 @@ __global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailA
             col = 2 + 2 * packed_index(W, b, a);   // U_ab = conj(U_ba)
             sgn = -1.0;
         }
-        const double* base = ta.rec + col;
-        int r = ch;
-        for (; r + (kBatch - 1) * chunks < ta.rows; r += kBatch * chunks) {
-            double2 x[kBatch];
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k)
-                x[k] = *reinterpret_cast<const double2*>(base + (int64_t)(r + k * chunks) * ta.rec_len);
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                acc.x += x[k].x;
-                acc.y += x[k].y;
-            }
-        }
-        for (; r < ta.rows; r += chunks) {
-            const double2 x = *reinterpret_cast<const double2*>(base + (int64_t)r * ta.rec_len);
-            acc.x += x.x;
-            acc.y += x.y;
-        }
+        acc = strided_record_sum(ta, col, ch, chunks);
         acc.y *= sgn;
     }
     s_acc[threadIdx.x] = acc;
-    // m_b = sum_a V_a M_ab: thread a < W forms its term, added in order below
-    __shared__ double2 s_m[PWA_MAX_WAVES_AMPLITUDE];
-    for (int aa = threadIdx.x; aa < W; aa += blockDim.x) {
-        const double2 x = ta.M[aa * W + b];
-        const double vr = vp.v[2 * aa], vi = vp.v[2 * aa + 1];
-        s_m[aa] = make_double2(vr * x.x - vi * x.y, vr * x.y + vi * x.x);
-    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
+        // lane l: u term of entry l (its chunk partials in chunk order) and the
+        // MC terms V_a M_ab of a = l, l + 64, ...; then fixed butterflies
+        const int l = threadIdx.x;
         double ur = 0.0, ui = 0.0, mr = 0.0, mi = 0.0;
-        for (int aa = 0; aa < nent; ++aa) {
+        if (l < nent) {
             double xr = 0.0, xi = 0.0;
             for (int c = 0; c < chunks; ++c) {
-                xr += s_acc[c * nent + aa].x;
-                xi += s_acc[c * nent + aa].y;
+                xr += s_acc[c * nent + l].x;
+                xi += s_acc[c * nent + l].y;
             }
             if (ta.amplitude) {
                 ur = xr;
                 ui = xi;
             } else {
-                const double vr = vp.v[2 * aa], vi = vp.v[2 * aa + 1];
-                ur += vr * xr - vi * xi;
-                ui += vr * xi + vi * xr;
+                const double vr = vp.v[2 * l], vi = vp.v[2 * l + 1];
+                ur = vr * xr - vi * xi;
+                ui = vr * xi + vi * xr;
             }
         }
-        for (int aa = 0; aa < W; ++aa) {
-            mr += s_m[aa].x;
-            mi += s_m[aa].y;
+        for (int aa = l; aa < W; aa += 64) {
+            const double2 t = v_times_m(vp, ta.M, W, aa, b);
+            mr += t.x;
+            mi += t.y;
         }
-        const double gr = 2.0 * (mr - ur), gi = 2.0 * (mi - ui);
-        store_system(ta.out + 2 + 2 * b, nbad > 0.0 ? NAN : gr);
-        store_system(ta.out + 3 + 2 * b, nbad > 0.0 ? NAN : gi);
+        ur = wave_allsum(ur);
+        ui = wave_allsum(ui);
+        mr = wave_allsum(mr);
+        mi = wave_allsum(mi);
+        if (l == 0) {
+            const double gr = 2.0 * (mr - ur), gi = 2.0 * (mi - ui);
+            store_system(ta.out + 2 + 2 * b, nbad > 0.0 ? NAN : gr);
+            store_system(ta.out + 3 + 2 * b, nbad > 0.0 ? NAN : gi);
+        }
     }
     publish(ta);
 }

@@ -179,16 +179,18 @@ __global__ __launch_bounds__(256) void k_plain_adjoint(const double2* __restrict
 
 int plain_rows(int64_t n) { return (int)((n + kPlainChunk - 1) / kPlainChunk); }
 
-hipError_t launch_plain(const Model& m, const VParams& vp, bool grad, hipStream_t s)
+hipError_t launch_plain(const Model& m, const VParams& vp, bool grad, hipStream_t s,
+                        const LaunchEvents& ev)
 {
     const int rows = plain_rows(m.n);
-    hipLaunchKernelGGL(k_plain_intensity, dim3(rows), dim3(256), sizeof(double2) * m.P, s,
-                       (const double2*)m.d_data, m.n, m.P, m.d_pairs, vp, m.d_w, m.d_partials,
-                       m.rec_len);
+    // timed from the start of the first pass to the end of the last one
+    hipExtLaunchKernelGGL(k_plain_intensity, dim3(rows), dim3(256), sizeof(double2) * m.P, s,
+                          ev.start, grad ? nullptr : ev.stop, 0, (const double2*)m.d_data, m.n,
+                          m.P, m.d_pairs, vp, m.d_w, m.d_partials, m.rec_len);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess || !grad) return err;
-    hipLaunchKernelGGL(k_plain_adjoint, dim3(rows, m.P), dim3(256), 0, s,
-                       (const double2*)m.d_data, m.n, m.d_w, m.d_partials, m.rec_len);
+    hipExtLaunchKernelGGL(k_plain_adjoint, dim3(rows, m.P), dim3(256), 0, s, nullptr, ev.stop, 0,
+                          (const double2*)m.d_data, m.n, m.d_w, m.d_partials, m.rec_len);
     return hipGetLastError();
 }
 

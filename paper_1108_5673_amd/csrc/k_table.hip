@@ -146,6 +146,12 @@ template <> struct Vec16<float> {
     __device__ static double re(const T& x, int h) { return h == 0 ? (double)x.x : (double)x.z; }
     __device__ static double im(const T& x, int h) { return h == 0 ? (double)x.y : (double)x.w; }
     __device__ static void opaque(T& x) { asm volatile("" : "+v"(x.x), "+v"(x.y), "+v"(x.z), "+v"(x.w)); }
+    __device__ static T load(const char* p)
+    {
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        const f4v t = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+        return make_float4(t.x, t.y, t.z, t.w);
+    }
 };
 template <> struct Vec16<double> {
     using T = double2;
@@ -154,6 +160,12 @@ template <> struct Vec16<double> {
     __device__ static double re(const T& x, int) { return x.x; }
     __device__ static double im(const T& x, int) { return x.y; }
     __device__ static void opaque(T&) {}
+    __device__ static T load(const char* p)
+    {
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        const d2v t = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+        return make_double2(t.x, t.y);
+    }
 };
 
 // One sub-tile's loaded vectors: lane l holds, for each slot k, the E events
@@ -169,7 +181,8 @@ struct SubTile {
 
     // tb is wave-uniform, so every address is a scalar base plus the lane's
     // 16-byte offset.  Full slots load unconditionally; only the last,
-    // partly filled slot is predicated on the lane.
+    // partly filled slot is predicated on the lane.  The table is read once
+    // per evaluation, so the loads are non-temporal.
     __device__ void load(const char* tb, int sub, int P, int lane)
     {
 #pragma unroll
@@ -178,13 +191,13 @@ struct SubTile {
             if (64 * (k + 1) <= P) {
 #pragma unroll
                 for (int v = 0; v < VS; ++v)
-                    x[k][v] = *reinterpret_cast<const V4*>(sb + ((sub * VS + v) * 64 + lane) * 16);
+                    x[k][v] = VT::load(sb + ((sub * VS + v) * 64 + lane) * 16);
             } else if (64 * k < P) {
                 const int nk = P - 64 * k;
 #pragma unroll
                 for (int v = 0; v < VS; ++v)
                     x[k][v] = lane < nk
-                                  ? *reinterpret_cast<const V4*>(sb + ((sub * VS + v) * nk + lane) * 16)
+                                  ? VT::load(sb + ((sub * VS + v) * nk + lane) * 16)
                                   : VT::zero();
             } else {
 #pragma unroll
@@ -375,16 +388,17 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
 // sub-tile.  The default E keeps the loaded vectors near 64 registers; the
 // other sub-tile widths are kept for tuning (PWA_TABLE_SUBTILE).
 template <typename S, int K, int E>
-static hipError_t run_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s)
+static hipError_t run_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s,
+                            const LaunchEvents& ev)
 {
     constexpr int NT = fused_threads<S, K, E>();
     if (grad)
-        hipLaunchKernelGGL((k_table_fused<S, K, E, true>), dim3(m.grid), dim3(NT), 0, s,
-                           (const char*)m.d_data, m.n, m.n_tiles, m.P, m.d_pairs, vp,
+        hipExtLaunchKernelGGL((k_table_fused<S, K, E, true>), dim3(m.grid), dim3(NT), 0, s,
+                              ev.start, ev.stop, 0, (const char*)m.d_data, m.n, m.n_tiles, m.P, m.d_pairs, vp,
                            m.d_partials, m.rec_len);
     else
-        hipLaunchKernelGGL((k_table_fused<S, K, E, false>), dim3(m.grid), dim3(NT), 0, s,
-                           (const char*)m.d_data, m.n, m.n_tiles, m.P, m.d_pairs, vp,
+        hipExtLaunchKernelGGL((k_table_fused<S, K, E, false>), dim3(m.grid), dim3(NT), 0, s,
+                              ev.start, ev.stop, 0, (const char*)m.d_data, m.n, m.n_tiles, m.P, m.d_pairs, vp,
                            m.d_partials, m.rec_len);
     return hipGetLastError();
 }
@@ -457,14 +471,15 @@ bool fused_shape_ok(const Model& m)
     return ok;
 }
 
-hipError_t launch_table_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s)
+hipError_t launch_table_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s,
+                              const LaunchEvents& ev)
 {
     hipError_t err = hipErrorInvalidValue;
     if (m.form == kTable32) {
-        auto go = [&]<int K, int E>() { err = run_fused<float, K, E>(m, vp, grad, s); };
+        auto go = [&]<int K, int E>() { err = run_fused<float, K, E>(m, vp, grad, s, ev); };
         with_shape<float>(m.kslots, m.subtile, go);
     } else {
-        auto go = [&]<int K, int E>() { err = run_fused<double, K, E>(m, vp, grad, s); };
+        auto go = [&]<int K, int E>() { err = run_fused<double, K, E>(m, vp, grad, s, ev); };
         with_shape<double>(m.kslots, m.subtile, go);
     }
     return err;

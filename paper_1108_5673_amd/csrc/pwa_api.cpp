@@ -269,16 +269,19 @@ int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, 
     ta.W = m->W;
     ta.grad = grad ? 1 : 0;
     ta.amplitude = m->form == pwa::kAmp32 ? 1 : 0;
-    if (timed) HIP_TRY(hipEventRecord(m->ev0, s));
+    pwa::LaunchEvents ev;
+    if (timed) {
+        ev.start = m->ev0;
+        ev.stop = m->ev1;
+    }
     hipError_t e;
     if (m->form == pwa::kTable32 || m->form == pwa::kTable64Fused)
-        e = pwa::launch_table_fused(*m, vp, grad, s);
+        e = pwa::launch_table_fused(*m, vp, grad, s, ev);
     else if (m->form == pwa::kTable64Plain)
-        e = pwa::launch_plain(*m, vp, grad, s);
+        e = pwa::launch_plain(*m, vp, grad, s, ev);
     else
-        e = pwa::launch_amp_fused(*m, vp, grad, s);
+        e = pwa::launch_amp_fused(*m, vp, grad, s, ev);
     if (e != hipSuccess) return device_fail(e, "kernel launch");
-    if (timed) HIP_TRY(hipEventRecord(m->ev1, s));
     e = pwa::launch_assemble(vp, ta, s);
     if (e != hipSuccess) return device_fail(e, "assembly launch");
     *seq_out = ta.seq;

@@ -2,6 +2,7 @@
 // translation units.  Not part of the public ABI (include/pwa.h is).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -26,6 +27,14 @@ enum Form : uint32_t {
 // copy is needed per evaluation.
 struct VParams {
     double v[2 * PWA_MAX_WAVES_AMPLITUDE];
+};
+
+// Optional timing of a launch: when non-null, the runtime stamps `start` and
+// `stop` with the begin and end times of the dispatch itself
+// (hipExtLaunchKernel), so the elapsed time excludes launch latency.
+struct LaunchEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
 };
 
 struct Model {
@@ -83,9 +92,12 @@ int plain_rows(int64_t n);
 
 // evaluation
 struct TailArgs;
-hipError_t launch_table_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s);
-hipError_t launch_plain(const Model& m, const VParams& vp, bool grad, hipStream_t s);
-hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s);
+hipError_t launch_table_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s,
+                   const LaunchEvents& ev);
+hipError_t launch_plain(const Model& m, const VParams& vp, bool grad, hipStream_t s,
+                   const LaunchEvents& ev);
+hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s,
+                   const LaunchEvents& ev);
 hipError_t launch_colsum(const double* partials, int rows, int cols, int stride, double* out,
                          hipStream_t s);
 hipError_t launch_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s);
