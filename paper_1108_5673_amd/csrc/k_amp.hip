@@ -107,7 +107,8 @@ __global__ __launch_bounds__(256) void k_amp_fused(const float4* __restrict__ am
         if (ok) dsum += log(I);
         if (valid && !ok) ++nbad;
         if (GRAD) {
-            const double w = ok ? 1.0 / I : 0.0;
+            // NaN for a degenerate event (the gradient becomes NaN), 0 for padding
+            const double w = ok ? 1.0 / I : (valid ? NAN : 0.0);
             s_cw[lane] = make_double2(w * sr, w * si);
             wave_lds_sync();
             // lane = wave

@@ -218,11 +218,11 @@ __global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailA
     __shared__ double s_wave[kAssembleThreads / 64];
     __shared__ double2 s_acc[kAssembleThreads];
     const int W = ta.W;
-    // columns 0 and 1: sum ln I and the count of invalid intensities
-    const double2 head = strided_record_sum(ta, 0, threadIdx.x, blockDim.x);
-    const double nbad = block_sum_fixed(head.y, s_wave);
     if (blockIdx.x == 0) {
+        // columns 0 and 1: sum ln I and the count of invalid intensities
+        const double2 head = strided_record_sum(ta, 0, threadIdx.x, blockDim.x);
         const double dsum = block_sum_fixed(head.x, s_wave);
+        const double nbad = block_sum_fixed(head.y, s_wave);
         // mu = sum_{a,b} Re(conj(V_b) V_a M_ab): pairs (a, b) over the threads
         double mu_part = 0.0;
         for (int k = threadIdx.x; k < W * W; k += blockDim.x) {
@@ -294,8 +294,9 @@ __global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailA
         mi = wave_allsum(mi);
         if (l == 0) {
             const double gr = 2.0 * (mr - ur), gi = 2.0 * (mi - ui);
-            store_system(ta.out + 2 + 2 * b, nbad > 0.0 ? NAN : gr);
-            store_system(ta.out + 3 + 2 * b, nbad > 0.0 ? NAN : gi);
+            // a degenerate event made its records' entries NaN, and so G_b
+            store_system(ta.out + 2 + 2 * b, gr);
+            store_system(ta.out + 3 + 2 * b, gi);
         }
     }
     publish(ta);

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_plain_intensity(const double2* __restri
         const bool ok = (I > 0.0) && (I < INFINITY);
         if (ok) dsum += log(I);
         else nbad += 1.0;
-        wout[i] = ok ? 1.0 / I : 0.0;
+        wout[i] = ok ? 1.0 / I : NAN;   // a degenerate event makes the gradient NaN
     }
     dsum = block_sum(dsum, s_red);
     nbad = block_sum(nbad, s_red);

@@ -253,7 +253,9 @@ __device__ inline void process_subtile(SubTile<S, K, E>& st, const double2* s_c,
     const int64_t evt = first_event + lane / RUN;
     const bool valid = evt < n_events;
     const bool ok = valid && (I > 0.0) && (I < INFINITY);
-    const double w = ok ? recip_f64(I) : 0.0;
+    // a degenerate event's weight is NaN, so that every gradient entry it
+    // reaches is NaN; padding events weigh nothing
+    const double w = ok ? recip_f64(I) : (valid ? NAN : 0.0);
     if ((lane % RUN) == 0 && valid && !ok) ++fs.nbad;
     if ((lane % RUN) == (int)(u % RUN) && ok) fs.held = I;
     if ((int)(u % RUN) == RUN - 1) {
@@ -295,23 +297,41 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
     constexpr int NSUB = kTileEvents / E;
     static_assert(E % VT::EV == 0 && kTileEvents % E == 0, "sub-tile shape");
 
+    constexpr int NW = fused_threads<S, K, E>() / 64;
+    constexpr bool kTree = (NW / 2 + 1) * K * 64 * 16 <= 65536;
     __shared__ double2 s_c[K * 64];
-    __shared__ double2 s_u[K * 64];
-    __shared__ double s_misc[2];
+    __shared__ double2 s_u[GRAD ? (kTree ? NW / 2 : 1) * K * 64 : 1];
+    __shared__ double s_misc[2 * NW];
 
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int nwaves = blockDim.x >> 6;
+
+    // This wave's sub-tiles, in order: tiles t0 + wave, t0 + wave + nwaves, ...,
+    // each split into NSUB sub-tiles.  The next sub-tile is loaded while the
+    // current one is processed (two register buffers); the first load is
+    // issued before the coefficients are formed.
+    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
+    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
+    const int64_t tile_bytes = (int64_t)P * kTileEvents * esz;
+    const int64_t my_tiles = (t1 - t0 > wave) ? (t1 - t0 - wave + nwaves - 1) / nwaves : 0;
+    const int64_t U = my_tiles * NSUB;
+    auto tile_of = [&](int64_t u) { return t0 + wave + nwaves * (u / NSUB); };
+    auto base_of = [&](int64_t u) { return table + tile_of(u) * tile_bytes; };
+    auto first_of = [&](int64_t u) { return tile_of(u) * kTileEvents + (u % NSUB) * E; };
+
+    SubTile<S, K, E> a, b;
+    if (U > 0) a.load(base_of(0), 0, P, lane);
 
     // coefficients c_e for every (slot, lane)
     for (int idx = threadIdx.x; idx < K * 64; idx += blockDim.x) {
         double2 c = make_double2(0.0, 0.0);
         if (idx < P) {
             const uint32_t pr = pairs[idx];
-            const int a = (int)(pr & 0xffffu), b = (int)(pr >> 16);
-            const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
-            const double wr = vp.v[2 * b], wi = vp.v[2 * b + 1];
-            const double f = (a == b) ? 1.0 : 2.0;
+            const int wa = (int)(pr & 0xffffu), wb = (int)(pr >> 16);
+            const double vr = vp.v[2 * wa], vi = vp.v[2 * wa + 1];
+            const double wr = vp.v[2 * wb], wi = vp.v[2 * wb + 1];
+            const double f = (wa == wb) ? 1.0 : 2.0;
             c.x = f * (vr * wr + vi * wi);   // Re V_a V*_b
             c.y = f * (vi * wr - vr * wi);   // Im V_a V*_b
         }
@@ -324,20 +344,6 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
     for (int k = 0; k < K; ++k) { ur[k] = 0.0; ui[k] = 0.0; }
     FusedState fs{0.0, 1.0, 0};
 
-    // This wave's sub-tiles, in order: tiles t0 + wave, t0 + wave + nwaves, ...,
-    // each split into NSUB sub-tiles.  The next sub-tile is loaded while the
-    // current one is processed (two register buffers).
-    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
-    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
-    const int64_t tile_bytes = (int64_t)P * kTileEvents * esz;
-    const int64_t my_tiles = (t1 - t0 > wave) ? (t1 - t0 - wave + nwaves - 1) / nwaves : 0;
-    const int64_t U = my_tiles * NSUB;
-    auto tile_of = [&](int64_t u) { return t0 + wave + nwaves * (u / NSUB); };
-    auto base_of = [&](int64_t u) { return table + tile_of(u) * tile_bytes; };
-    auto first_of = [&](int64_t u) { return tile_of(u) * kTileEvents + (u % NSUB) * E; };
-
-    SubTile<S, K, E> a, b;
-    if (U > 0) a.load(base_of(0), 0, P, lane);
     for (int64_t u = 0; u < U; u += 2) {
         if (u + 1 < U) b.load(base_of(u + 1), (int)((u + 1) % NSUB), P, lane);
         process_subtile<S, K, E, GRAD>(a, s_c, lane, u, first_of(u), n_events, ur, ui, fs);
@@ -347,40 +353,71 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
         }
     }
 
-    // logarithms of the intensities still held, then combine the block's
-    // wavefronts in a fixed order
+    // logarithms of the intensities still held, then the fixed-order combine
+    // of the block's wavefronts
     fs.dsum += log(fs.held);
-    double dsum = wave_allsum(fs.dsum);
-    int nbad = wave_allsum_int(fs.nbad);
-    for (int w = 0; w < nwaves; ++w) {
-        if (wave == w) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                double2 u = make_double2(ur[k], ui[k]);
-                if (w > 0) {
-                    const double2 o = s_u[k * 64 + lane];
-                    u.x += o.x;
-                    u.y += o.y;
-                }
-                s_u[k * 64 + lane] = u;
-            }
-            if (lane == 0) {
-                s_misc[0] = (w > 0 ? s_misc[0] : 0.0) + dsum;
-                s_misc[1] = (w > 0 ? s_misc[1] : 0.0) + (double)nbad;
-            }
-        }
-        __syncthreads();
+    const double dsum = wave_allsum(fs.dsum);
+    const int nbad = wave_allsum_int(fs.nbad);
+    if (lane == 0) {
+        s_misc[2 * wave] = dsum;
+        s_misc[2 * wave + 1] = (double)nbad;
     }
     double* rec = partials + (int64_t)blockIdx.x * rec_len;
-    if (threadIdx.x == 0) {
-        rec[0] = s_misc[0];
-        rec[1] = s_misc[1];
-    }
     if (GRAD) {
-        for (int e = threadIdx.x; e < P; e += blockDim.x) {
-            rec[2 + 2 * e] = s_u[e].x;
-            rec[3 + 2 * e] = s_u[e].y;
+        if constexpr (kTree) {
+            // pairwise tree: at half-width h, wave w + h hands its sums to wave w
+            for (int h = NW / 2; h >= 1; h >>= 1) {
+                if (wave >= h && wave < 2 * h) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        s_u[((wave - h) * K + k) * 64 + lane] = make_double2(ur[k], ui[k]);
+                }
+                __syncthreads();
+                if (wave < h) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const double2 o = s_u[(wave * K + k) * 64 + lane];
+                        ur[k] += o.x;
+                        ui[k] += o.y;
+                    }
+                }
+                __syncthreads();
+            }
+            if (wave == 0) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int e = k * 64 + lane;
+                    if (e < P)
+                        *reinterpret_cast<double2*>(rec + 2 + 2 * e) = make_double2(ur[k], ui[k]);
+                }
+            }
+        } else {
+            // one accumulator in LDS, the wavefronts adding in turn
+            for (int w = 0; w < NW; ++w) {
+                if (wave == w) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        double2 u = make_double2(ur[k], ui[k]);
+                        if (w > 0) {
+                            const double2 o = s_u[k * 64 + lane];
+                            u.x += o.x;
+                            u.y += o.y;
+                        }
+                        s_u[k * 64 + lane] = u;
+                    }
+                }
+                __syncthreads();
+            }
+            for (int e = threadIdx.x; e < P; e += blockDim.x)
+                *reinterpret_cast<double2*>(rec + 2 + 2 * e) = s_u[e];
         }
+    } else {
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) {
+        double x = 0.0;
+        for (int w = 0; w < NW; ++w) x += s_misc[2 * w + threadIdx.x];
+        rec[threadIdx.x] = x;
     }
 }
 

@@ -18,6 +18,9 @@
 //                Hermitian and stored packed, so block b reads only the W
 //                packed columns of its row and column), or
 //                G_b = 2 (m_b - g_b)  (amplitude form).
+// A degenerate event (I <= 0 or not finite) is counted in n_bad, which makes
+// the NLL +inf, and carries a NaN weight, which makes every U_ab or g_b of its
+// block's record, and so every G_b, NaN.
 // Every sum over records runs in a fixed order.  Each block writes its outputs
 // to pinned host memory with system-scope stores, waits for their completion
 // and then stores `seq` in its own completion word; the host waits for all of

@@ -1,0 +1,177 @@
+"""Parity on the named workloads at their full sizes (needs an MI355X).
+
+Workloads (seeded, synthetic J/psi -> gamma K+K- shaped samples):
+  w4_n10k   10k events, 4 waves, 10 random points: every form against the
+            oracle, 1e-9 relative.
+  w20_n1m   10^6 events, 20 waves, the complex64 table form in the launch
+            configuration the benchmark times, at 8 of the 200 walk points:
+            (a) against the oracle on the identical stored table, which isolates
+            the kernels' arithmetic, and (b) against the oracle on the complex128
+            amplitudes, which adds the single-precision storage: |dNLL| <= 1e-3
+            and ||dG|| / ||G|| <= 1e-5.  The complex128 forms against the oracle
+            on the complex128 table.
+  w32_n2m   2x10^6 events, 32 waves, amplitude form, 20 random points: NLL and
+            gradient against the oracle, and the gradient against Richardson-
+            extrapolated central differences of the kernels' own NLL.
+  w20_n1m_k256  256 random points on the 10^6-event table, one batched call:
+            every entry equal to the single call at the same point, a sample
+            against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1108_5673_amd as pwa
+from paper_1108_5673_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+WALK_SAMPLE = [0, 1, 37, 99, 100, 150, 198, 199]
+
+
+def _rel(g, ref):
+    return float(np.linalg.norm(np.asarray(g) - ref) / np.linalg.norm(ref))
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.get()
+
+
+@pytest.fixture(scope="module")
+def w20():
+    s = synth.make_sample("w20_n1m")
+    d32 = s.data.astype(np.complex64)
+    mc32 = s.mc.astype(np.complex64)
+    return s, d32, mc32
+
+
+def test_w4_n10k_all_forms(o):
+    s = synth.make_sample("w4_n10k")
+    assert s.data.shape == (10_000, 4) and s.mc.shape == (50_000, 4) and s.n_gen == 100_000
+    for form in ["table_fp64_plain", "table_fp64", "table", "amplitude"]:
+        sp = form in ("table", "amplitude")
+        d = s.data.astype(np.complex64) if sp else s.data
+        m = s.mc.astype(np.complex64) if sp else s.mc
+        d128, m128 = d.astype(np.complex128), m.astype(np.complex128)
+        M = o.mc_matrix(m128, s.n_gen)
+        if form == "amplitude":
+            ref = [o.nll_amp(d128, M, V) for V in s.points]
+        else:
+            T = o.table(d128)
+            if form == "table":
+                T = T.astype(np.complex64).astype(np.complex128)
+            ref = [o.nll_table(T, M, V) for V in s.points]
+        model = pwa.Model(d, m, s.n_gen, form=form)
+        for V, (rn, rg, nbad) in zip(s.points, ref):
+            nll, g = model.nll_grad(V)
+            assert nbad == 0
+            assert abs(nll - rn) <= 1e-9 * abs(rn), (form, nll, rn)
+            assert _rel(g, rg) <= 1e-9, (form, _rel(g, rg))
+        model.close()
+
+
+def test_w20_n1m_table_complex64(o, w20):
+    s, d32, mc32 = w20
+    model = pwa.Model(d32, mc32, s.n_gen, form="table")
+    info = model.info()
+    assert info["n_data"] == 1_000_000 and info["n_waves"] == 20 and info["n_packed"] == 210
+    assert info["stream_bytes"] == 1_000_000 * 210 * 8
+    got = {k: model.nll_grad(s.points[k]) for k in WALK_SAMPLE}
+    model.close()
+    # (a) the identical stored table
+    T = o.table(d32.astype(np.complex128)).astype(np.complex64).astype(np.complex128)
+    M32 = o.mc_matrix(mc32.astype(np.complex128), s.n_gen)
+    for k in WALK_SAMPLE:
+        rn, rg, nbad = o.nll_table(T, M32, s.points[k])
+        nll, g = got[k]
+        assert nbad == 0
+        assert abs(nll - rn) <= 1e-12 * max(abs(rn), 1e6), (k, nll, rn)
+        assert _rel(g, rg) <= 1e-10, (k, _rel(g, rg))
+    del T
+    # (b) the FP64 oracle on the complex128 amplitudes
+    M = o.mc_matrix(s.mc, s.n_gen)
+    for k in WALK_SAMPLE:
+        rn, rg, nbad = o.nll_amp(s.data, M, s.points[k])
+        nll, g = got[k]
+        assert abs(nll - rn) <= 1e-3, (k, nll, rn)
+        assert _rel(g, rg) <= 1e-5, (k, _rel(g, rg))
+
+
+@pytest.mark.parametrize("form", ["table_fp64_plain", "table_fp64"])
+def test_w20_n1m_table_complex128(o, w20, form):
+    s, _, _ = w20
+    model = pwa.Model(s.data, s.mc, s.n_gen, form=form)
+    pts = [0, 199]
+    got = {k: model.nll_grad(s.points[k]) for k in pts}
+    model.close()
+    T = o.table(s.data)
+    M = o.mc_matrix(s.mc, s.n_gen)
+    for k in pts:
+        rn, rg, _ = o.nll_table(T, M, s.points[k])
+        nll, g = got[k]
+        assert abs(nll - rn) <= 1e-12 * max(abs(rn), 1e6), (form, k, nll, rn)
+        assert _rel(g, rg) <= 1e-10, (form, k, _rel(g, rg))
+
+
+def test_w20_n1m_k256_batched(o):
+    k = synth.make_sample("w20_n1m_k256")
+    assert k.points.shape == (256, 20) and k.data.shape == (1_000_000, 20)
+    d, mc = k.data.astype(np.complex64), k.mc.astype(np.complex64)
+    model = pwa.Model(d, mc, k.n_gen, form="table")
+    [(nll_b, g_b)] = pwa.nll_batched([model], [k.points])
+    assert nll_b.shape == (256,) and g_b.shape == (256, 40)
+    for j in range(0, 256, 17):
+        nll, g = model.nll_grad(k.points[j])
+        assert nll == nll_b[j] and np.array_equal(g, g_b[j], equal_nan=True), j
+    model.close()
+    T = o.table(d.astype(np.complex128)).astype(np.complex64).astype(np.complex128)
+    M = o.mc_matrix(mc.astype(np.complex128), k.n_gen)
+    for j in [0, 85, 170, 255]:
+        rn, rg, nbad = o.nll_table(T, M, k.points[j])
+        if nbad:
+            assert np.isinf(nll_b[j])
+            continue
+        assert abs(nll_b[j] - rn) <= 1e-12 * max(abs(rn), 1e6), (j, nll_b[j], rn)
+        assert _rel(g_b[j], rg) <= 1e-10, (j, _rel(g_b[j], rg))
+
+
+@pytest.fixture(scope="module")
+def w32():
+    s = synth.make_sample("w32_n2m")
+    return s, s.data.astype(np.complex64), s.mc.astype(np.complex64)
+
+
+def test_w32_n2m_amplitude_parity(o, w32):
+    s, d32, mc32 = w32
+    model = pwa.Model(d32, mc32, s.n_gen, form="amplitude")
+    M = o.mc_matrix(mc32.astype(np.complex128), s.n_gen)
+    d128 = d32.astype(np.complex128)
+    for V in s.points:
+        nll, g = model.nll_grad(V)
+        rn, rg, nbad = o.nll_amp(d128, M, V)
+        assert nbad == 0
+        assert abs(nll - rn) <= 1e-12 * max(abs(rn), 2e6), (nll, rn)
+        assert _rel(g, rg) <= 1e-10, _rel(g, rg)
+    model.close()
+
+
+def test_w32_n2m_gradient_vs_differences(w32):
+    """Central differences of the kernels' NLL, h = 1e-4 and h / 2, combined by
+    Richardson extrapolation (error O(h^4))."""
+    s, d32, mc32 = w32
+    model = pwa.Model(d32, mc32, s.n_gen, form="amplitude")
+    h = 1e-4
+    for V in s.points[:4]:
+        x = np.ascontiguousarray(V.astype(np.complex128)).view(np.float64).copy()
+        _, g = model.nll_grad(x)
+
+        def cd(step, i):
+            xp, xm = x.copy(), x.copy()
+            xp[i] += step
+            xm[i] -= step
+            return (model.nll(xp) - model.nll(xm)) / (2 * step)
+
+        fd = np.array([(4 * cd(h / 2, i) - cd(h, i)) / 3 for i in range(x.size)])
+        assert _rel(g, fd) <= 1e-6, _rel(g, fd)
+    model.close()
