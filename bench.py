@@ -12,8 +12,11 @@ host memory, with the table already resident in HBM.
 Timed paths: the fused one-pass kernel over the packed complex64 table (the
 reported value), the plain two-pass FP64 table kernels (the baseline), and the
 fused kernel over a complex128 table (ablation).  The main kernel's device time
-is taken with HIP events on its own stream inside the timed region and turned
-into achieved bandwidth from the algorithmic bytes (1680 B per event).  The CPU
+is taken inside the timed region with two HIP events per launch, on the stream
+the kernel runs on, which the runtime stamps with the dispatch's own begin and
+end; it is turned into achieved bandwidth from the algorithmic bytes (1680 B per
+event).  Per-call latency percentiles are host wall-clock times of the
+synchronous call.  The CPU
 oracle is timed on a bounded sample of the same walk on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -22,7 +25,6 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -36,21 +38,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "table_fused_w20_n1m_traffic.json")
-KERNEL_SOURCES = ["paper_1108_5673_amd/csrc/k_table.hip", "paper_1108_5673_amd/csrc/wave_ops.h",
-                  "paper_1108_5673_amd/csrc/pwa_internal.h"]
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
+    from paper_1108_5673_amd.profiling import kernel_source_hash
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -72,19 +65,24 @@ def time_model(model, points, steps, warmup):
     torch.cuda.synchronize()
     model.set_timing(True)
     model.timing()
-    results = []
+    results, lat = [], []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
+        a = time.perf_counter()
         results.append(model.nll_grad(points[k % len(points)]))
+        lat.append(time.perf_counter() - a)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kernel_ms, launches = model.timing()
     model.set_timing(False)
+    q = np.percentile(np.array(lat) * 1e6, [10, 50, 90])
     return {
         "seconds": t1 - t0,
         "evals_per_s": steps / (t1 - t0),
         "ms_per_step": 1e3 * (t1 - t0) / steps,
         "kernel_ms": kernel_ms / max(1, launches),
+        "latency_us": {"p10": q[0], "p50": q[1], "p90": q[2]},
         "results": results,
     }
 
@@ -211,6 +209,7 @@ def main():
                    "n_events": sample.data.shape[0], "n_waves": 20, "n_mc_acc": sample.mc.shape[0],
                    "n_mc_gen": sample.n_gen, "points": len(pts)},
         "events_iter_per_s": f["evals_per_s"] * sample.data.shape[0],
+        "latency_us": f["latency_us"],
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
