@@ -126,9 +126,27 @@ def main():
     torch.cuda.synchronize()
     log("built fused complex64 table in %.2f s" % (time.perf_counter() - t))
     info = fused.info()
+    prefit = fused.build_timing()
+    log("build steps on the device: table %.2f ms, MC integral %.2f ms"
+        % (prefit["table_ms"], prefit["mc_ms"]))
     f = time_model(fused, pts, args.steps, args.warmup)
     log("fused: %.1f evals/s, kernel %.1f us, grid %d blocks on %d CUs"
         % (f["evals_per_s"], 1e3 * f["kernel_ms"], info["grid_blocks"], info["compute_units"]))
+
+    # a full fit on the same model from a random start (L-BFGS in the library,
+    # one pwa_nll_grad per objective call)
+    from paper_1108_5673_amd import fit as pwa_fit
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([11085673, 20, 1])))
+    v0 = synth.random_v(rng, 20)
+    t = time.perf_counter()
+    v_fit, fres = pwa_fit.fit_lbfgs(fused, v0)
+    fit_s = time.perf_counter() - t
+    fit_info = {"start": "Re, Im V ~ N(0, 1)", "status": fres["message"],
+                "iterations": fres["iterations"], "evaluations": fres["evaluations"],
+                "seconds": fit_s, "evals_per_s": fres["evaluations"] / fit_s,
+                "nll": fres["f"], "grad_norm": fres["grad_norm"]}
+    log("fit from a random start: %s after %d iterations, %d evaluations, %.3f s"
+        % (fres["message"], fres["iterations"], fres["evaluations"], fit_s))
 
     out = {}
     if not args.no_baselines:
@@ -168,8 +186,12 @@ def main():
         o = oracle.get()
         t = time.perf_counter()
         T = o.table(d32.astype(np.complex128)).astype(np.complex64).astype(np.complex128)
+        prefit["oracle_table_s"] = time.perf_counter() - t
+        t = time.perf_counter()
         M = o.mc_matrix(mc32.astype(np.complex128), sample.n_gen)
-        log("oracle table and MC matrix in %.1f s" % (time.perf_counter() - t))
+        prefit["oracle_mc_s"] = time.perf_counter() - t
+        log("oracle table %.2f s, MC matrix %.2f s"
+            % (prefit["oracle_table_s"], prefit["oracle_mc_s"]))
         times, k, dn, dg = [], 0, [], []
         while k < min(len(pts), args.steps) and (k < 2 or sum(times) < args.cpu_seconds):
             t = time.perf_counter()
@@ -210,6 +232,8 @@ def main():
                    "n_mc_gen": sample.n_gen, "points": len(pts)},
         "events_iter_per_s": f["evals_per_s"] * sample.data.shape[0],
         "latency_us": f["latency_us"],
+        "prefit": prefit,
+        "fit": fit_info,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,

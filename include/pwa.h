@@ -186,6 +186,77 @@ int pwa_set_mc_matrix(pwa_model* model, const double* m_host, void* hip_stream);
 int pwa_set_timing(pwa_model* model, int enable);
 int pwa_get_timing(pwa_model* model, double* total_ms, int64_t* launches);
 
+/*
+ * Device time of the two build steps that bracket the fit (Sec. 5, Table 1:
+ * the MC integral and the lookup-table creation), measured with HIP events
+ * when the model was built, in milliseconds: table_ms covers the preparation
+ * of the table (or the amplitude copy) from the device-resident input, mc_ms
+ * the MC integral M (0 when n_mc_acc == 0).  Staging host inputs to the device
+ * is not included.
+ */
+int pwa_build_timing(const pwa_model* model, double* table_ms, double* mc_ms);
+
+/*
+ * ---- Fit driver: limited-memory BFGS ---------------------------------------
+ *
+ * The fits of Sec. 2 minimise Eq. 3 with analytic derivatives, repeated from
+ * several starting points.  pwa_lbfgs_minimize is a general minimiser (the
+ * two-loop L-BFGS recursion with a strong Wolfe line search, Nocedal and
+ * Wright, Numerical Optimization, Algorithms 7.4, 3.5 and 3.6) over a caller
+ * objective; pwa_fit_lbfgs drives it with pwa_nll_grad on a model.
+ *
+ * pwa_objective: fills *f and g[n] at x[n]; returns 0, or a negative status
+ * to abort the minimisation (returned unchanged).  A non-finite *f is taken as
+ * a point outside the domain: the line search shortens the step.
+ */
+typedef int (*pwa_objective)(void* ctx, const double* x, double* f, double* g);
+
+typedef struct pwa_lbfgs_options {
+    int32_t max_iterations;  /* default 2000                                           */
+    int32_t history;         /* correction pairs kept, default 10                      */
+    double grad_tol;         /* stop when ||g||_2 <= grad_tol * max(1, |f|); 1e-9      */
+    double rel_f_tol;        /* stop after 3 iterations each lowering f by at most
+                                rel_f_tol * max(1, |f|); default 1e-15; 0 = off        */
+    int32_t fixed_index;     /* coordinate held at its start value, or -1 (default)    */
+} pwa_lbfgs_options;
+
+enum {
+    PWA_LBFGS_CONVERGED_GRADIENT = 0,
+    PWA_LBFGS_CONVERGED_VALUE = 1,
+    PWA_LBFGS_MAX_ITERATIONS = 2,
+    PWA_LBFGS_LINE_SEARCH_FAILED = 3
+};
+
+typedef struct pwa_lbfgs_result {
+    int32_t status;          /* PWA_LBFGS_*                                            */
+    int32_t iterations;
+    int32_t evaluations;     /* objective calls, line-search trials included           */
+    double f;                /* objective at the returned x                            */
+    double grad_norm;        /* ||g||_2 there (fixed coordinate excluded)              */
+} pwa_lbfgs_result;
+
+/* Fill `opt` with the defaults above. */
+void pwa_lbfgs_default_options(pwa_lbfgs_options* opt);
+
+/*
+ * Minimise fn from x (n values, overwritten with the result).  options may be
+ * NULL for the defaults.  Returns PWA_OK (then res->status says how it
+ * stopped), PWA_WARN_DEGENERATE if f is not finite at the start,
+ * PWA_ERR_INVALID for bad arguments, or the objective's negative status.
+ */
+int pwa_lbfgs_minimize(int32_t n, double* x, pwa_objective fn, void* ctx,
+                       const pwa_lbfgs_options* options, pwa_lbfgs_result* res);
+
+/*
+ * Fit V on a model: minimise NLL(V) from v (2W doubles, host, overwritten with
+ * the fitted V).  The NLL is invariant under a global phase of V, so the start
+ * is first rotated to make V_0 real and non-negative and Im V_0 is then held
+ * at zero (options->fixed_index is ignored); Re V_0 may change sign.  Each objective call is one
+ * pwa_nll_grad on hip_stream.
+ */
+int pwa_fit_lbfgs(const pwa_model* model, double* v, const pwa_lbfgs_options* options,
+                  pwa_lbfgs_result* res, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -195,6 +195,14 @@ class Model:
                                                    ctypes.byref(n)))
         return ms.value, n.value
 
+    def build_timing(self) -> dict:
+        """Device milliseconds of the table preparation and of the MC integral."""
+        t = ctypes.c_double(0.0)
+        mc = ctypes.c_double(0.0)
+        _native.check(_native.lib().pwa_build_timing(self._handle(), ctypes.byref(t),
+                                                     ctypes.byref(mc)))
+        return {"table_ms": t.value, "mc_ms": mc.value}
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             _native.lib().pwa_free(self._h)

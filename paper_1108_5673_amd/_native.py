@@ -29,8 +29,38 @@ PWA_MAX_WAVES_AMPLITUDE = 128
 EXPORTED = (
     "pwa_build_table", "pwa_nll", "pwa_nll_grad", "pwa_nll_batched", "pwa_free",
     "pwa_last_error", "pwa_model_info", "pwa_copy_table", "pwa_copy_mc_matrix",
-    "pwa_set_mc_matrix", "pwa_set_timing", "pwa_get_timing",
+    "pwa_set_mc_matrix", "pwa_set_timing", "pwa_get_timing", "pwa_build_timing",
+    "pwa_lbfgs_default_options", "pwa_lbfgs_minimize", "pwa_fit_lbfgs",
 )
+
+PWA_LBFGS_CONVERGED_GRADIENT = 0
+PWA_LBFGS_CONVERGED_VALUE = 1
+PWA_LBFGS_MAX_ITERATIONS = 2
+PWA_LBFGS_LINE_SEARCH_FAILED = 3
+
+# int (*)(void* ctx, const double* x, double* f, double* g)
+OBJECTIVE = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+
+
+class LbfgsOptions(ctypes.Structure):
+    _fields_ = [
+        ("max_iterations", ctypes.c_int32),
+        ("history", ctypes.c_int32),
+        ("grad_tol", ctypes.c_double),
+        ("rel_f_tol", ctypes.c_double),
+        ("fixed_index", ctypes.c_int32),
+    ]
+
+
+class LbfgsResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("evaluations", ctypes.c_int32),
+        ("f", ctypes.c_double),
+        ("grad_norm", ctypes.c_double),
+    ]
 
 
 class Info(ctypes.Structure):
@@ -83,8 +113,14 @@ def _declare(L):
     L.pwa_set_mc_matrix.argtypes = [p, p, p]
     L.pwa_set_timing.argtypes = [p, ctypes.c_int]
     L.pwa_get_timing.argtypes = [p, dp, ctypes.POINTER(i64)]
+    L.pwa_build_timing.argtypes = [p, dp, dp]
+    L.pwa_lbfgs_default_options.argtypes = [ctypes.POINTER(LbfgsOptions)]
+    L.pwa_lbfgs_default_options.restype = None
+    L.pwa_lbfgs_minimize.argtypes = [i32, dp, OBJECTIVE, p, ctypes.POINTER(LbfgsOptions),
+                                     ctypes.POINTER(LbfgsResult)]
+    L.pwa_fit_lbfgs.argtypes = [p, dp, ctypes.POINTER(LbfgsOptions), ctypes.POINTER(LbfgsResult), p]
     for name in EXPORTED:
-        if name not in ("pwa_free", "pwa_last_error"):
+        if name not in ("pwa_free", "pwa_last_error", "pwa_lbfgs_default_options"):
             getattr(L, name).restype = ctypes.c_int
     return L
 

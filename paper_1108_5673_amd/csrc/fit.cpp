@@ -1,0 +1,323 @@
+// fit.cpp -- fit drivers on the host: limited-memory BFGS over the NLL and its
+// analytic gradient.
+//
+// The paper's fits repeat a minimisation of Eq. 3 with analytic derivatives
+// (Sec. 2, Sec. 4).  This file provides the minimiser: the two-loop recursion
+// of limited-memory BFGS for the search direction and a line search that
+// enforces the strong Wolfe conditions (bracketing, then zoom with safeguarded
+// cubic interpolation), as published in Nocedal and Wright, Numerical
+// Optimization, 2nd ed., Algorithms 7.4, 3.5 and 3.6, with the approximate
+// Wolfe test of Hager and Zhang (SIAM J. Optim. 16, 2005) once the decrease of
+// f is below its rounding.  Each objective call on a
+// model is one pwa_nll_grad evaluation on the GPU; the minimiser itself is a
+// few vector operations over 2W numbers.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pwa.h"
+
+namespace {
+
+double dot(const std::vector<double>& a, const std::vector<double>& b)
+{
+    double s = 0.0;
+    for (size_t k = 0; k < a.size(); ++k) s += a[k] * b[k];
+    return s;
+}
+
+double norm2(const std::vector<double>& a) { return std::sqrt(dot(a, a)); }
+
+// Minimiser of the cubic through (a, fa, ga) and (b, fb, gb), kept inside the
+// interval shrunk by 10 % at both ends; bisection when the cubic has no usable
+// minimiser.
+double cubic_step(double a, double fa, double ga, double b, double fb, double gb)
+{
+    const double lo = std::min(a, b), hi = std::max(a, b);
+    const double d1 = ga + gb - 3.0 * (fa - fb) / (a - b);
+    const double disc = d1 * d1 - ga * gb;
+    double t = 0.5 * (a + b);
+    if (disc >= 0.0 && std::isfinite(disc)) {
+        const double d2 = std::copysign(std::sqrt(disc), b - a);
+        const double den = gb - ga + 2.0 * d2;
+        if (den != 0.0) {
+            const double c = b - (b - a) * (gb + d2 - d1) / den;
+            if (std::isfinite(c)) t = c;
+        }
+    }
+    const double margin = 0.1 * (hi - lo);
+    if (!(t > lo + margin && t < hi - margin)) t = 0.5 * (a + b);
+    return t;
+}
+
+struct Objective {
+    pwa_objective fn;
+    void* ctx;
+    int fixed;
+    int evaluations = 0;
+
+    // f and g at x; the gauge coordinate's derivative is dropped so that the
+    // minimiser never moves it
+    int operator()(const std::vector<double>& x, double& f, std::vector<double>& g)
+    {
+        ++evaluations;
+        const int rc = fn(ctx, x.data(), &f, g.data());
+        if (fixed >= 0) g[fixed] = 0.0;
+        if (rc < 0) return rc;
+        if (!std::isfinite(f)) f = INFINITY;
+        return 0;
+    }
+};
+
+// Strong Wolfe line search along d from x (value f0, slope d0 < 0).  On success
+// x, f, g hold the accepted point.  Returns 0 on success, 1 if no acceptable
+// step was found, < 0 on an objective error.
+int wolfe_search(Objective& obj, std::vector<double>& x, double& f, std::vector<double>& g,
+                 const std::vector<double>& d, double step0)
+{
+    const double c1 = 1e-4, c2 = 0.9;
+    const double f0 = f, d0 = dot(g, d);
+    const std::vector<double> x0 = x;
+    std::vector<double> xt(x.size()), gt(x.size());
+    auto eval = [&](double a, double& fa, double& da) {
+        for (size_t k = 0; k < x.size(); ++k) xt[k] = x0[k] + a * d[k];
+        const int rc = obj(xt, fa, gt);
+        da = std::isfinite(fa) ? dot(gt, d) : NAN;
+        return rc;
+    };
+    auto accept = [&](double fa) {
+        x = xt;
+        f = fa;
+        g = gt;
+        return 0;
+    };
+    // Near a minimiser the decrease of f along d falls below the rounding of
+    // f itself while the slope is still accurate; a step is then also taken
+    // when f has not grown beyond that rounding and the slope has the
+    // approximate Wolfe bracket of Hager and Zhang (c2 d0 <= da <= (1 - 2 c1) |d0|).
+    const double f_noise = 1e-14 * std::fabs(f0);
+    auto approx_ok = [&](double fa, double da) {
+        return std::isfinite(fa) && fa <= f0 + f_noise && da >= c2 * d0 &&
+               da <= (1.0 - 2.0 * c1) * (-d0);
+    };
+    auto zoom = [&](double lo, double flo, double dlo, double hi, double fhi, double dhi) {
+        for (int it = 0; it < 30; ++it) {
+            double a;
+            if (std::isfinite(fhi) && std::isfinite(dhi)) a = cubic_step(lo, flo, dlo, hi, fhi, dhi);
+            else a = 0.5 * (lo + hi);
+            double fa, da;
+            const int rc = eval(a, fa, da);
+            if (rc < 0) return rc;
+            if (approx_ok(fa, da) && !(fa <= f0 + c1 * a * d0)) return accept(fa);
+            if (!std::isfinite(fa) || fa > f0 + c1 * a * d0 || fa >= flo) {
+                hi = a;
+                fhi = fa;
+                dhi = da;
+            } else {
+                if (std::fabs(da) <= -c2 * d0) return accept(fa);
+                if (da * (hi - lo) >= 0.0) {
+                    hi = lo;
+                    fhi = flo;
+                    dhi = dlo;
+                }
+                lo = a;
+                flo = fa;
+                dlo = da;
+            }
+            if (std::fabs(hi - lo) <= 1e-16 * std::max(1.0, std::fabs(lo))) break;
+        }
+        // no step met the curvature condition: keep the best sufficient decrease
+        if (lo > 0.0 && flo < f0) {
+            double fa, da;
+            const int rc = eval(lo, fa, da);
+            if (rc < 0) return rc;
+            return accept(fa);
+        }
+        return 1;
+    };
+
+    double a_prev = 0.0, f_prev = f0, d_prev = d0;
+    double a = step0;
+    for (int it = 0; it < 40; ++it) {
+        double fa, da;
+        const int rc = eval(a, fa, da);
+        if (rc < 0) return rc;
+        if (approx_ok(fa, da) && !(fa <= f0 + c1 * a * d0)) return accept(fa);
+        if (!std::isfinite(fa) || fa > f0 + c1 * a * d0 || (it > 0 && fa >= f_prev))
+            return zoom(a_prev, f_prev, d_prev, a, fa, da);
+        if (std::fabs(da) <= -c2 * d0) return accept(fa);
+        if (da >= 0.0) return zoom(a, fa, da, a_prev, f_prev, d_prev);
+        a_prev = a;
+        f_prev = fa;
+        d_prev = da;
+        a *= 2.0;
+    }
+    return 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pwa_lbfgs_default_options(pwa_lbfgs_options* opt)
+{
+    if (!opt) return;
+    opt->max_iterations = 2000;
+    opt->history = 10;
+    opt->grad_tol = 1e-9;
+    opt->rel_f_tol = 1e-15;
+    opt->fixed_index = -1;
+}
+
+int pwa_lbfgs_minimize(int32_t n, double* x_io, pwa_objective fn, void* ctx,
+                       const pwa_lbfgs_options* options, pwa_lbfgs_result* res)
+{
+    if (n < 1 || !x_io || !fn || !res) return PWA_ERR_INVALID;
+    pwa_lbfgs_options opt;
+    pwa_lbfgs_default_options(&opt);
+    if (options) opt = *options;
+    if (opt.history < 1 || opt.max_iterations < 0 || opt.fixed_index >= n) return PWA_ERR_INVALID;
+    std::memset(res, 0, sizeof *res);
+
+    Objective obj{fn, ctx, opt.fixed_index};
+    std::vector<double> x(x_io, x_io + n), g(n), d(n), q(n);
+    double f = 0.0;
+    int rc = obj(x, f, g);
+    if (rc < 0) return rc;
+    if (!std::isfinite(f)) return PWA_WARN_DEGENERATE;
+
+    const int m = opt.history;
+    std::vector<std::vector<double>> S(m, std::vector<double>(n)), Y(m, std::vector<double>(n));
+    std::vector<double> rho(m), alpha(m);
+    int stored = 0, head = 0;   // ring buffer of the last `stored` pairs, newest at head - 1
+    int status = PWA_LBFGS_MAX_ITERATIONS;
+    int iter = 0;
+    int small_steps = 0;
+    for (; iter < opt.max_iterations; ++iter) {
+        const double gn = norm2(g);
+        if (gn <= opt.grad_tol * std::max(1.0, std::fabs(f))) {
+            status = PWA_LBFGS_CONVERGED_GRADIENT;
+            break;
+        }
+        // two-loop recursion: d = -H g with H0 = (s'y / y'y) I
+        q = g;
+        for (int j = 0; j < stored; ++j) {
+            const int k = (head - 1 - j + m) % m;
+            alpha[k] = rho[k] * dot(S[k], q);
+            for (int i = 0; i < n; ++i) q[i] -= alpha[k] * Y[k][i];
+        }
+        double gamma = 1.0;
+        if (stored > 0) {
+            const int k = (head - 1 + m) % m;
+            gamma = dot(S[k], Y[k]) / dot(Y[k], Y[k]);
+        }
+        for (int i = 0; i < n; ++i) q[i] *= gamma;
+        for (int j = stored - 1; j >= 0; --j) {
+            const int k = (head - 1 - j + m) % m;
+            const double beta = rho[k] * dot(Y[k], q);
+            for (int i = 0; i < n; ++i) q[i] += (alpha[k] - beta) * S[k][i];
+        }
+        for (int i = 0; i < n; ++i) d[i] = -q[i];
+        if (opt.fixed_index >= 0) d[opt.fixed_index] = 0.0;
+        double slope = dot(g, d);
+        if (!(slope < 0.0)) {   // not a descent direction: restart from steepest descent
+            stored = 0;
+            for (int i = 0; i < n; ++i) d[i] = -g[i];
+            slope = -gn * gn;
+        }
+        const double step0 = stored == 0 ? std::min(1.0, 1.0 / gn) : 1.0;
+
+        const std::vector<double> x_old = x, g_old = g;
+        const double f_old = f;
+        rc = wolfe_search(obj, x, f, g, d, step0);
+        if (rc < 0) return rc;
+        if (rc == 1) {
+            if (stored > 0) {   // drop the curvature memory once and retry
+                stored = 0;
+                continue;
+            }
+            status = PWA_LBFGS_LINE_SEARCH_FAILED;
+            break;
+        }
+        // curvature pair
+        std::vector<double>& s = S[head];
+        std::vector<double>& y = Y[head];
+        for (int i = 0; i < n; ++i) {
+            s[i] = x[i] - x_old[i];
+            y[i] = g[i] - g_old[i];
+        }
+        const double sy = dot(s, y);
+        if (sy > 1e-300) {
+            rho[head] = 1.0 / sy;
+            head = (head + 1) % m;
+            stored = std::min(stored + 1, m);
+        }
+        if (opt.rel_f_tol > 0.0 && f_old - f <= opt.rel_f_tol * std::max(1.0, std::fabs(f))) {
+            if (++small_steps >= 3) {
+                status = PWA_LBFGS_CONVERGED_VALUE;
+                ++iter;
+                break;
+            }
+        } else {
+            small_steps = 0;
+        }
+    }
+    std::memcpy(x_io, x.data(), sizeof(double) * n);
+    res->status = status;
+    res->iterations = iter;
+    res->evaluations = obj.evaluations;
+    res->f = f;
+    res->grad_norm = norm2(g);
+    return PWA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct ModelCtx {
+    const pwa_model* model;
+    void* stream;
+};
+
+int model_objective(void* ctx, const double* x, double* f, double* g)
+{
+    const ModelCtx* c = static_cast<const ModelCtx*>(ctx);
+    const int rc = pwa_nll_grad(c->model, x, f, g, c->stream);
+    if (rc == PWA_WARN_DEGENERATE) {
+        *f = INFINITY;
+        return 0;
+    }
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int pwa_fit_lbfgs(const pwa_model* model, double* v, const pwa_lbfgs_options* options,
+                             pwa_lbfgs_result* res, void* hip_stream)
+{
+    if (!model || !v || !res) return PWA_ERR_INVALID;
+    pwa_info info;
+    int rc = pwa_model_info(model, &info);
+    if (rc != PWA_OK) return rc;
+    const int W = info.n_waves;
+    pwa_lbfgs_options opt;
+    pwa_lbfgs_default_options(&opt);
+    if (options) opt = *options;
+    // gauge: the NLL does not depend on a global phase of V, so V_0 is
+    // rotated onto the positive real axis and Im V_0 is held at zero
+    const double r = std::hypot(v[0], v[1]);
+    if (r > 0.0) {
+        const double c = v[0] / r, s = -v[1] / r;   // multiply by exp(-i arg V_0)
+        for (int a = 0; a < W; ++a) {
+            const double re = v[2 * a], im = v[2 * a + 1];
+            v[2 * a] = re * c - im * s;
+            v[2 * a + 1] = re * s + im * c;
+        }
+        v[1] = 0.0;
+    }
+    opt.fixed_index = 1;
+    ModelCtx ctx{model, hip_stream};
+    return pwa_lbfgs_minimize(2 * W, v, model_objective, &ctx, &opt, res);
+}

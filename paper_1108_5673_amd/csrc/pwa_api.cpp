@@ -162,6 +162,21 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
     HIP_TRY(hipMalloc(&m->d_pairs, sizeof(uint32_t) * P));
     HIP_TRY(hipMemcpyAsync(m->d_pairs, pairs.data(), sizeof(uint32_t) * P, hipMemcpyHostToDevice, s));
 
+    // build-step timing: events around the table preparation and the MC
+    // integral kernels (the inputs are already on the device by then)
+    HIP_TRY(hipEventCreate(&m->ev0));
+    HIP_TRY(hipEventCreate(&m->ev1));
+    hipEvent_t bt[4] = {nullptr, nullptr, nullptr, nullptr};
+    struct EventsGuard {
+        hipEvent_t* e;
+        ~EventsGuard()
+        {
+            for (int k = 0; k < 4; ++k)
+                if (e[k]) (void)hipEventDestroy(e[k]);
+        }
+    } bt_guard{bt};
+    for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&bt[k]));
+
     // ---- data: table or amplitudes on the device ----
     const size_t in_elem = data_c128 ? 16 : 8;
     const size_t in_bytes = (size_t)n * (in_table ? P : W) * in_elem;
@@ -174,8 +189,10 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         m->n_tiles = (n + pwa::kTileEvents - 1) / pwa::kTileEvents;
         m->data_bytes = m->n_tiles * pwa::kTileEvents * (int64_t)P * (c128 ? 16 : 8);
         HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
+        HIP_TRY(hipEventRecord(bt[0], s));
         HIP_TRY(pwa::launch_pack_tiled(sd.ptr, in_table, data_c128, n, W, P, m->d_pairs, c128,
                                        m->n_tiles, m->d_data, s));
+        HIP_TRY(hipEventRecord(bt[1], s));
         m->kslots = pwa::select_kslots(P, c128);
         if (m->kslots < 0) return fail(PWA_ERR_INVALID, "n_waves %d too large for the table form", W);
         m->subtile = pwa::default_subtile(m->kslots, c128);
@@ -191,8 +208,10 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
     } else if (form == PWA_PRECISION_FP64_PLAIN) {
         m->data_bytes = (int64_t)n * P * 16;
         HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
+        HIP_TRY(hipEventRecord(bt[0], s));
         HIP_TRY(pwa::launch_pack_soa(sd.ptr, in_table, data_c128, n, W, P, m->d_pairs,
                                      (double*)m->d_data, s));
+        HIP_TRY(hipEventRecord(bt[1], s));
         HIP_TRY(hipMalloc(&m->d_w, sizeof(double) * n));
         m->rows = pwa::plain_rows(n);
         m->grid = m->rows;
@@ -203,7 +222,9 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         const int64_t n_pad = m->n_tiles * pwa::kAmpTile;
         m->data_bytes = n_pad * m->wpad * 8;
         HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
+        HIP_TRY(hipEventRecord(bt[0], s));
         HIP_TRY(pwa::launch_pack_amp(sd.ptr, data_c128, n, W, m->wpad, n_pad, (float*)m->d_data, s));
+        HIP_TRY(hipEventRecord(bt[1], s));
         m->grid = pwa::amp_fused_grid(*m);
         m->rows = m->grid;
         m->rec_len = 2 + 2 * W;
@@ -219,10 +240,16 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         const int grows = pwa::gram_rows(n_acc);
         double* gpart = nullptr;
         HIP_TRY(hipMalloc(&gpart, sizeof(double) * 2 * P * (size_t)grows));
-        hipError_t e = pwa::launch_gram(sm.ptr, mc_c128, n_acc, W, P, m->d_pairs, gpart, grows, s);
+        hipError_t e = hipStreamSynchronize(s);   // the MC input staged
+        if (e == hipSuccess) e = hipEventRecord(bt[2], s);
+        if (e == hipSuccess) e = pwa::launch_gram(sm.ptr, mc_c128, n_acc, W, P, m->d_pairs, gpart, grows, s);
         if (e == hipSuccess) e = pwa::launch_colsum(gpart, grows, 2 * P, 2 * P, m->d_colsum, s);
         if (e == hipSuccess) e = pwa::launch_expand_m(m->d_colsum, W, n_gen, m->d_M, s);
+        if (e == hipSuccess) e = hipEventRecord(bt[3], s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, bt[2], bt[3]);
+        m->build_mc_ms = ms;
         (void)hipFree(gpart);
         if (e != hipSuccess) return device_fail(e, "MC matrix build");
     } else {
@@ -237,9 +264,10 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
     for (int k = 0; k < nblk; ++k) m->h_done[k] = 0;
     rc = alloc_out(m, 1);
     if (rc != PWA_OK) return rc;
-    HIP_TRY(hipEventCreate(&m->ev0));
-    HIP_TRY(hipEventCreate(&m->ev1));
     HIP_TRY(hipStreamSynchronize(s));
+    float tms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&tms, bt[0], bt[1]));
+    m->build_table_ms = tms;
     return PWA_OK;
 }
 
@@ -542,6 +570,15 @@ int pwa_set_timing(pwa_model* model, int enable)
     if (!model) return fail(PWA_ERR_INVALID, "NULL model");
     Model* m = reinterpret_cast<Model*>(model);
     m->timing = enable != 0;
+    return PWA_OK;
+}
+
+int pwa_build_timing(const pwa_model* model, double* table_ms, double* mc_ms)
+{
+    if (!model || !table_ms || !mc_ms) return fail(PWA_ERR_INVALID, "NULL argument");
+    const Model* m = reinterpret_cast<const Model*>(model);
+    *table_ms = m->build_table_ms;
+    *mc_ms = m->build_mc_ms;
     return PWA_OK;
 }
 

@@ -69,6 +69,8 @@ struct Model {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
+    double build_table_ms = 0.0;   // device time of the table (or amplitude) preparation
+    double build_mc_ms = 0.0;      // device time of the MC integral M
 };
 
 // ---- launchers (each returns the hipError_t of its launch) ----------------

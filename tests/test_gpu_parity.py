@@ -240,3 +240,15 @@ def test_nonfinite_v_rejected():
     with pytest.raises(pwa.PWAError) as e:
         model.nll(np.array([1.0, np.nan, 0, 0, 0, 0]))
     assert e.value.status == -5
+
+
+def test_build_timing():
+    s = synth.small_sample(8, 5000, 20000, seed=3)
+    m = pwa.Model(s.data.astype(np.complex64), s.mc.astype(np.complex64), 20000, form="table")
+    t = m.build_timing()
+    assert t["table_ms"] > 0.0 and t["mc_ms"] > 0.0
+    m.close()
+    m = pwa.Model(s.data.astype(np.complex64), None, 1, form="amplitude")
+    t = m.build_timing()
+    assert t["table_ms"] > 0.0 and t["mc_ms"] == 0.0
+    m.close()

@@ -175,3 +175,29 @@ def test_w32_n2m_gradient_vs_differences(w32):
         fd = np.array([(4 * cd(h / 2, i) - cd(h, i)) / 3 for i in range(x.size)])
         assert _rel(g, fd) <= 1e-6, _rel(g, fd)
     model.close()
+
+
+def test_w32_n2m_lbfgs_fit_from_random_start(o, w32):
+    """A full fit (L-BFGS, gauge Im V_0 = 0) from a random start: it reaches
+    its gradient test, the extended likelihood's stationarity then fixes mu = N
+    (|mu - N| <= ||G|| ||V|| / 2 by the scale identity), and the fitted NLL
+    agrees with the oracle at the fitted V."""
+    from paper_1108_5673_amd import fit
+    s, d32, mc32 = w32
+    model = pwa.Model(d32, mc32, s.n_gen, form="amplitude")
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([11085673, 32, 1])))
+    v0 = synth.random_v(rng, 32)
+    nll0 = model.nll(v0)
+    # the value test off: the fit must reach a gradient of 1e-12 |NLL|
+    V, res = fit.fit_lbfgs(model, v0, grad_tol=1e-12, rel_f_tol=0.0)
+    assert res["status"] == 0, res
+    assert V[0].imag == 0.0
+    nll, g = model.nll_grad(V)
+    assert nll == res["f"] and nll < nll0
+    M = o.mc_matrix(mc32.astype(np.complex128), s.n_gen)
+    rn, rg, _ = o.nll_amp(d32.astype(np.complex128), M, V)
+    assert abs(nll - rn) <= 1e-12 * max(abs(rn), 2e6)
+    mu, _ = o.mc_term(M, V)
+    n = d32.shape[0]
+    assert abs(mu - n) <= 1e-6 * n, (mu, n)
+    model.close()
