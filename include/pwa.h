@@ -60,11 +60,14 @@ typedef enum pwa_status {
 } pwa_status;
 
 typedef enum pwa_flags {
-    /* Evaluation form (exactly one of the four must be given). */
+    /* Evaluation form (exactly one of the six must be given). */
     PWA_FORM_TABLE = 1,              /* complex64 packed table, fused one-pass NLL+gradient kernel */
     PWA_FORM_AMPLITUDE = 2,          /* complex64 amplitudes, S_i = sum_a V_a A_ia per event (Eq. 1) */
     PWA_PRECISION_FP64_PLAIN = 8,    /* complex128 packed table, plain two-pass FP64 kernels       */
     PWA_PRECISION_FP64_FUSED = 64,   /* complex128 packed table, fused one-pass kernel            */
+    PWA_FORM_AMPLITUDE_BF16 = 128,   /* amplitudes stored in bfloat16, matrix-core kernel that
+                                        evaluates any number of V together (S = A V as a GEMM)  */
+    PWA_FORM_AMPLITUDE_FP16 = 256,   /* the same with amplitudes stored in float16               */
     /* Input description. */
     PWA_INPUT_IS_TABLE = 4,          /* `data` is an N x P packed Hermitian table, P = W(W+1)/2,
                                         entries (a, a') with a <= a' in row-major order of the
@@ -78,6 +81,7 @@ typedef enum pwa_flags {
 /* Largest wave count per form. */
 #define PWA_MAX_WAVES_TABLE 64
 #define PWA_MAX_WAVES_AMPLITUDE 128
+#define PWA_MAX_WAVES_MATRIX 64      /* PWA_FORM_AMPLITUDE_BF16 / _FP16 */
 
 /*
  * pwa_build_table -- build a model: the per-event table (or the device copy
@@ -89,8 +93,9 @@ typedef enum pwa_flags {
  *             memory (detected).  Copied: the caller keeps ownership and may
  *             free it when the call returns.
  *   n_data    N >= 1.
- *   n_waves   W, 1 <= W <= PWA_MAX_WAVES_TABLE (table forms) or
- *             PWA_MAX_WAVES_AMPLITUDE (amplitude form).
+ *   n_waves   W, 1 <= W <= PWA_MAX_WAVES_TABLE (table forms),
+ *             PWA_MAX_WAVES_AMPLITUDE (amplitude form) or PWA_MAX_WAVES_MATRIX
+ *             (16-bit amplitude forms).
  *   mc_amp    N_acc x W accepted MC amplitudes B_ja (complex64 unless
  *             PWA_MC_COMPLEX128), host or device; copied.  May be NULL only
  *             when n_mc_acc == 0, which gives M = 0.
@@ -104,7 +109,13 @@ typedef enum pwa_flags {
  * formed with a separately rounded multiply and add) and store it at the
  * form's precision, rounded to nearest.  M is accumulated in FP64.  The
  * amplitude form keeps the amplitudes in complex64 (complex128 input is
- * rounded to nearest).
+ * rounded to nearest).  The 16-bit amplitude forms store the real and
+ * imaginary parts in bfloat16 or float16, rounded to nearest from complex64
+ * (complex128 input is rounded to float first; float16 results below 2^-14 in
+ * magnitude are stored as zero); they evaluate through the
+ * matrix cores: each call, single or batched, runs one pass over the events
+ * for all its vectors, with V split into 16-bit parts (three for bfloat16, two
+ * for float16), FP32 products and FP64 sums across events.
  */
 int pwa_build_table(const void* data, int64_t n_data, int32_t n_waves,
                     const void* mc_amp, int64_t n_mc_acc, int64_t n_mc_gen,
@@ -166,7 +177,9 @@ typedef struct pwa_info {
 int pwa_model_info(const pwa_model* model, pwa_info* out);
 
 /* Copy the model's table back in the canonical packed N x P layout (complex64
- * for PWA_FORM_TABLE, complex128 for the FP64 forms).  Table forms only. */
+ * for PWA_FORM_TABLE, complex128 for the FP64 forms); for the 16-bit amplitude
+ * forms, the stored amplitudes widened to complex64 (N x W).  Not for
+ * PWA_FORM_AMPLITUDE. */
 int pwa_copy_table(const pwa_model* model, void* out_host, void* hip_stream);
 
 /* Copy M (W x W complex128, row-major) to host memory. */

@@ -27,6 +27,8 @@ FORMS = {
     "amplitude": _native.PWA_FORM_AMPLITUDE,            # complex64 amplitudes
     "table_fp64_plain": _native.PWA_PRECISION_FP64_PLAIN,   # complex128 table, two passes
     "table_fp64": _native.PWA_PRECISION_FP64_FUSED,     # complex128 table, fused kernel
+    "amplitude_bf16": _native.PWA_FORM_AMPLITUDE_BF16,  # bfloat16 amplitudes, matrix cores
+    "amplitude_fp16": _native.PWA_FORM_AMPLITUDE_FP16,  # float16 amplitudes, matrix cores
 }
 
 
@@ -165,9 +167,13 @@ class Model:
         return {k: getattr(inf, k) for k, _ in _native.Info._fields_}
 
     def table(self) -> np.ndarray:
-        """The stored table in canonical packed (N, P) layout."""
-        dt = np.complex64 if self.form == "table" else np.complex128
-        out = np.zeros((self.n_data, self.n_packed), dt)
+        """The stored table in canonical packed (N, P) layout; for the 16-bit
+        amplitude forms the stored amplitudes as complex64 (N, W)."""
+        if self.form in ("amplitude_bf16", "amplitude_fp16"):
+            out = np.zeros((self.n_data, self.n_waves), np.complex64)
+        else:
+            dt = np.complex64 if self.form == "table" else np.complex128
+            out = np.zeros((self.n_data, self.n_packed), dt)
         _native.check(_native.lib().pwa_copy_table(self._handle(), out.ctypes.data, self._stream))
         return out
 

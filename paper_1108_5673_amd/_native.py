@@ -21,9 +21,12 @@ PWA_PRECISION_FP64_PLAIN = 8
 PWA_DATA_COMPLEX128 = 16
 PWA_MC_COMPLEX128 = 32
 PWA_PRECISION_FP64_FUSED = 64
+PWA_FORM_AMPLITUDE_BF16 = 128
+PWA_FORM_AMPLITUDE_FP16 = 256
 
 PWA_MAX_WAVES_TABLE = 64
 PWA_MAX_WAVES_AMPLITUDE = 128
+PWA_MAX_WAVES_MATRIX = 64
 
 # every symbol include/pwa.h declares
 EXPORTED = (

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIBRARY = os.path.join(PKG, "libpwa.so")
 
-SOURCES = ["pwa_api.cpp", "fit.cpp", "k_table.hip", "k_plain.hip", "k_amp.hip", "k_common.hip"]
+SOURCES = ["pwa_api.cpp", "fit.cpp", "k_table.hip", "k_plain.hip", "k_amp.hip", "k_common.hip",
+           "k_mfma.hip"]
 HEADERS = ["pwa_internal.h", "wave_ops.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

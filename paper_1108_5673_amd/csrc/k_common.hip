@@ -159,20 +159,6 @@ hipError_t launch_colsum(const double* partials, int rows, int cols, int stride,
 // kernel), so one or two batches cover a thread's share.
 constexpr int kBatch = 16;
 
-// Block sum in a fixed order: a butterfly inside each wavefront, then the
-// wavefront sums in wave order (blockDim a multiple of 64, at most 1024).
-__device__ inline double block_sum_fixed(double x, double* s_wave)
-{
-    x = wave_allsum(x);
-    const int waves = blockDim.x >> 6;
-    if (lane_id() == 0) s_wave[threadIdx.x >> 6] = x;
-    __syncthreads();
-    double r = 0.0;
-    for (int w = 0; w < waves; ++w) r += s_wave[w];
-    __syncthreads();
-    return r;
-}
-
 // Sum over rows first, first + step, ... (< rows) of the double2 at `col` of
 // each record, added in row order.
 __device__ inline double2 strided_record_sum(const TailArgs& ta, int col, int first, int step)

@@ -1,0 +1,643 @@
+// k_mfma.hip -- the amplitude form for many parameter vectors at once, on the
+// matrix cores (Eq. 1 and Eq. 3 for K vectors V_1..V_K in one pass).
+//
+// The fits of Sec. 2 are repeated from many starting points; evaluating K of
+// them together turns S_ik = sum_a A_ia V_ak into a matrix product.  In real
+// arithmetic, with event row x_i = [Re A_i0 .. Re A_i,W-1, Im A_i0 .. Im A_i,W-1]
+// (padded to KD = 16 * NS) and two columns per vector,
+//     Re S_ik = x_i . [Re V_k ; -Im V_k],   Im S_ik = x_i . [Im V_k ; Re V_k],
+// S = X B is an (events x KD) by (KD x 2K) product.  The adjoint needs
+// g_bk = sum_i c_ik conj(A_ib) with c_ik = S_ik / I_ik, another product
+// G = X^T C (KD x 2K) over events, whose four real blocks give
+//     Re g_bk = G[Re b][Re k] + G[Im b][Im k],  Im g_bk = G[Re b][Im k] - G[Im b][Re k].
+//
+// Both products run on the 32x32x16 16-bit MFMA with FP32 accumulation:
+//   * forward: A operand = 32 events x 16 of KD (lane l: event l % 32, KD
+//     8 (l / 32) .. + 7), B operand = the vector matrix (lane l: column l % 32);
+//     the accumulator gives lane l column l % 32 and events 8 j + 4 (l / 32) + i
+//     in register 4 j + i;
+//   * epilogue in registers: the Re and Im columns of a vector sit in
+//     neighbouring lanes, exchanged with one DPP move; I = Re^2 + Im^2, ln I
+//     (each (event, vector) pair's logarithm taken by one of its two lanes),
+//     w = 1 / I and this lane's part of c = S w;
+//   * adjoint: registers 8 s .. 8 s + 7 of the accumulator are exactly the B
+//     operand of an MFMA whose 16 k-slots are events {8 j + 4 h + i} with j in
+//     {2 s, 2 s + 1}; the A operand (lane l: KD row l % 32, the same 8 event
+//     slots) comes from a second copy of the tile stored in that event order.
+//     So S never leaves the registers.
+// Scale: each vector enters as V_k / s_k with s_k the power of two nearest
+// ||V_k||_2, so S, I and c = S / I stay near unit magnitude whatever the size of
+// V (float16 has a narrow exponent range); the assembly undoes it exactly:
+// ln I = ln I' + 2 ln s_k and g = g' / s_k.
+// Accuracy: the amplitudes are stored in the 16-bit type (the input of this
+// form).  V is split into 16-bit parts (three for bf16, two for fp16: about
+// 24 and 22 significant bits) whose products are accumulated, so that the
+// parameters, which every event shares, add no coherent 16-bit rounding; the
+// weights c are split into two parts (see Split below).  ln I is summed in FP64 per lane, and all
+// cross-block sums are FP64.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <type_traits>
+#include <hip/hip_fp16.h>
+
+#include "pwa_internal.h"
+#include "tail.h"
+#include "wave_ops.h"
+
+namespace pwa {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Splitting a value into 16-bit parts.  bf16 has the exponent range of FP32,
+// so its parts (three for V, two for c) are plain successive remainders,
+// accumulated together.  fp16 would make the low part subnormal for values
+// below about 0.125, and subnormal fp16 inputs do not reliably survive the
+// conversion and the matrix product, so an fp16 split keeps every part normal:
+// the high part is zero below 2^-14, the low part is stored multiplied by 2^11
+// and accumulated on its own, and the two accumulators are recombined exactly.
+template <typename T> struct Split;
+template <> struct Split<__bf16> {
+    static constexpr int kVParts = 3;
+    static constexpr bool kScaledLow = false;
+};
+template <> struct Split<_Float16> {
+    static constexpr int kVParts = 2;
+    static constexpr bool kScaledLow = true;
+};
+template <typename T> constexpr int mfma_v_parts() { return Split<T>::kVParts; }
+constexpr float kLowScale = 2048.0f;          // 2^11
+constexpr float kLowUnscale = 1.0f / 2048.0f;
+constexpr float kHalfNormalMin = 6.103515625e-05f;   // 2^-14
+
+template <typename T> struct H16;
+template <> struct H16<__bf16> {
+    typedef __bf16 V8 __attribute__((ext_vector_type(8)));
+    __device__ static f32x16 mfma(V8 a, V8 b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct H16<_Float16> {
+    typedef _Float16 V8 __attribute__((ext_vector_type(8)));
+    __device__ static f32x16 mfma(V8 a, V8 b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// float -> 16-bit, round to nearest even
+__device__ inline __bf16 to16(float x, __bf16*) { return (__bf16)x; }
+__device__ inline _Float16 to16(float x, _Float16*) { return (_Float16)x; }
+template <typename T> __device__ inline T round16(float x) { return to16(x, (T*)nullptr); }
+
+// high part of a two-part split: the rounded value, or zero where fp16 would
+// be subnormal
+template <typename T> __device__ inline T split_hi(float x)
+{
+    if constexpr (Split<T>::kScaledLow)
+        if (fabsf(x) < kHalfNormalMin) return round16<T>(0.f);
+    return round16<T>(x);
+}
+// low part: the remainder, times 2^11 for fp16
+template <typename T> __device__ inline T split_lo(float x, T hi)
+{
+    const float r = x - (float)hi;
+    return round16<T>(Split<T>::kScaledLow ? r * kLowScale : r);
+}
+
+// ---- build: the two copies of the event tiles -------------------------------
+// af: [tile][32 events][KD]            (forward A operand)
+// at: [tile][RB * 32 rows][32 slots]   (adjoint A operand; slot 16 s + 8 h + t
+//                                       holds event 8 (2 s + t / 4) + 4 h + t % 4)
+template <typename T>
+__global__ void k_pack_mfma(const void* __restrict__ src, bool c128, int64_t n, int W, int KD,
+                            int RB, int64_t n_tiles, T* __restrict__ af, T* __restrict__ at)
+{
+    const int64_t total = n_tiles * 32 * (int64_t)KD;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ev = g / KD;       // global event (padded)
+        const int kd = (int)(g % KD);
+        float x = 0.f;
+        if (ev < n && kd < 2 * W) {
+            const int a = kd < W ? kd : kd - W;
+            if (c128) {
+                const double2 v = reinterpret_cast<const double2*>(src)[ev * W + a];
+                x = (float)(kd < W ? v.x : v.y);
+            } else {
+                const float2 v = reinterpret_cast<const float2*>(src)[ev * W + a];
+                x = kd < W ? v.x : v.y;
+            }
+        }
+        T y = round16<T>(x);
+        // fp16 storage holds no subnormals: they are stored as zero, the value
+        // the matrix product is certain to use
+        if constexpr (Split<T>::kScaledLow)
+            if (fabsf((float)y) < kHalfNormalMin) y = round16<T>(0.f);
+        af[g] = y;
+        const int64_t tile = ev / 32;
+        const int e = (int)(ev % 32);
+        const int j = e / 8, h = (e / 4) % 2, i = e % 4;
+        const int slot = 16 * (j / 2) + 8 * h + 4 * (j % 2) + i;
+        at[(tile * RB * 32 + kd) * 32 + slot] = y;
+    }
+}
+
+// ---- per call: the vector matrix, split into NP 16-bit parts --------------
+// part p at vm + p * part_elems, element [((cb * NS + s) * 2 + h) * 32 + c][8]:
+// column 32 cb + c, KD rows 16 s + 8 h .. + 7
+// power of two nearest ||V_k||_2 (1 for V_k = 0)
+__device__ inline double vector_scale(const double* vk, int W)
+{
+    double nn = 0.0;
+    for (int a = 0; a < 2 * W; ++a) nn += vk[a] * vk[a];
+    if (!(nn > 0.0)) return 1.0;
+    return ldexp(1.0, (int)rint(0.5 * log2(nn)));
+}
+
+template <typename T>
+__global__ void k_prep_vmat16(const double* __restrict__ v, int K, int W, int NS, int n_cb,
+                              int NP, T* __restrict__ vm, double* __restrict__ vscale)
+{
+    const int part_elems = n_cb * NS * 2 * 32 * 8;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < part_elems;
+         g += gridDim.x * blockDim.x) {
+        const int t = g % 8;
+        const int c = (g / 8) % 32;
+        const int h = (g / 256) % 2;
+        const int s = (g / 512) % NS;
+        const int cb = g / (512 * NS);
+        const int col = 32 * cb + c;
+        const int k = col / 2, part = col % 2;
+        const int kd = 16 * s + 8 * h + t;
+        double x = 0.0;
+        if (k < K && kd < 2 * W) {
+            const double sk = vector_scale(v + (size_t)k * 2 * W, W);
+            if (part == 0 && kd == 0) vscale[k] = sk;
+            const int a = kd < W ? kd : kd - W;
+            const double vr = v[(size_t)k * 2 * W + 2 * a] / sk;
+            const double vi = v[(size_t)k * 2 * W + 2 * a + 1] / sk;
+            if (kd < W) x = part == 0 ? vr : vi;     // multiplies Re A_a
+            else x = part == 0 ? -vi : vr;           // multiplies Im A_a
+        }
+        if constexpr (Split<T>::kScaledLow) {
+            const T hi = split_hi<T>((float)x);
+            vm[g] = hi;
+            vm[(size_t)part_elems + g] = round16<T>((float)((x - (double)(float)hi) * kLowScale));
+        } else {
+            // successive remainders, each rounded to the 16-bit type
+            for (int p = 0; p < NP; ++p) {
+                const T y = round16<T>((float)x);
+                vm[(size_t)p * part_elems + g] = y;
+                x -= (double)(float)y;
+            }
+        }
+    }
+}
+
+// exchange with the neighbouring lane (l ^ 1)
+__device__ inline float swap_pair(float x)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
+// ---- the fused forward + epilogue + adjoint kernel -------------------------
+// grid (chunks, ceil(n_cb / B)), blocks of B = min(n_cb, mfma_waves) wavefronts:
+// wavefront w of a block takes column block cb = B blockIdx.y + w (16 vectors)
+// over every event tile of
+// the block's chunk, so the wavefronts of a block read the same tiles at about
+// the same time and all but the first find them in cache.  Records per
+// (chunk, cb, column): rec_d = [sum ln I, n_bad] (FP64; n_bad counts the
+// column's lane sums that met a degenerate event, so it is non-zero exactly when
+// one did) and rec_g = G[0 .. KD) of the column (the wavefront's FP32 sums).
+// Up to 8 wavefronts per block (two per SIMD, 256 registers each); the wider
+// row lengths (NS > 4) need more registers and run 4 (one per SIMD).
+template <int NS> constexpr int mfma_waves() { return NS <= 4 ? 8 : 4; }
+
+template <typename T, int NS, int NP>
+__global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
+    const T* __restrict__ af, const T* __restrict__ at, const T* __restrict__ vm,
+    int64_t n_events, int64_t n_tiles, int n_cols, int n_cb, int chunks,
+    double* __restrict__ rec_d, float* __restrict__ rec_g)
+{
+    constexpr int KD = 16 * NS;
+    constexpr int RB = (NS + 1) / 2;
+    using V8 = typename H16<T>::V8;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 5, c = lane & 31;
+    const int cb = (int)(blockDim.x >> 6) * blockIdx.y + wave;
+    if (cb >= n_cb) return;   // no barrier follows
+    const int col = 32 * cb + c;
+    const bool col_active = col < n_cols;
+    const bool odd = (c & 1) != 0;
+
+    const size_t part_elems = (size_t)n_cb * NS * 2 * 32 * 8;
+    V8 vp[NP][NS];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            vp[p][s] = *reinterpret_cast<const V8*>(
+                vm + p * part_elems + ((size_t)((cb * NS + s) * 2 + h) * 32 + c) * 8);
+    constexpr bool SL = Split<T>::kScaledLow;
+    f32x16 g[RB], gl[SL ? RB : 1];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) g[rb] = f32x16{};
+#pragma unroll
+    for (int rb = 0; rb < (SL ? RB : 1); ++rb) gl[rb] = f32x16{};
+    double dsum = 0.0;
+
+    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / chunks;
+    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / chunks;
+    // operands of one tile: forward rows (event x KD) and adjoint rows (KD x
+    // event slots); the next tile's are loaded while this one is processed
+    struct Ops {
+        V8 a[NS];
+        V8 b[RB][2];
+    };
+    auto load = [&](Ops& o, int64_t t) {
+        const T* ta = af + t * 32 * KD;
+        const T* tt = at + t * RB * 32 * 32;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) o.a[s] = *reinterpret_cast<const V8*>(ta + c * KD + 16 * s + 8 * h);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+                o.b[rb][s2] = *reinterpret_cast<const V8*>(tt + (rb * 32 + c) * 32 + 16 * s2 + 8 * h);
+    };
+    auto process = [&](const Ops& o, int64_t t, auto fast_tag) {
+        constexpr bool fast = decltype(fast_tag)::value;
+        f32x16 acc = f32x16{};
+        if constexpr (SL) {
+            f32x16 acc_lo = f32x16{};
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                acc = H16<T>::mfma(o.a[s], vp[0][s], acc);
+                acc_lo = H16<T>::mfma(o.a[s], vp[1][s], acc_lo);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] = fmaf(acc_lo[q], kLowUnscale, acc[q]);
+        } else {
+#pragma unroll
+            for (int p = NP - 1; p >= 0; --p)   // smallest parts first
+#pragma unroll
+                for (int s = 0; s < NS; ++s) acc = H16<T>::mfma(o.a[s], vp[p][s], acc);
+        }
+
+        // Epilogue and adjoint, in two halves of 8 registers (the adjoint MFMA
+        // of half s2 takes registers 8 s2 .. 8 s2 + 7).  The two lanes of a
+        // vector (columns 2k, 2k + 1) hold the same I: of each register pair
+        // (q, q + 1) the even lane takes the logarithm of q, the odd lane that
+        // of q + 1.  A full tile whose columns all carry vectors needs no
+        // validity test: a degenerate event (I not positive and finite) only
+        // has to be counted (its NLL is +inf whatever the sum, and its weight
+        // 0 * inf or x * NaN is NaN); the last tile and the padding columns
+        // take the general path.
+        const int nvalid = (int)min<int64_t>(32, n_events - t * 32);
+        float lsum = 0.f;
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            float cp[8];
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+                float Ipair[2];
+                bool vp2[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int q = 8 * s2 + u + e;
+                    const float x = acc[q];
+                    const float y = swap_pair(x);
+                    const float I = x * x + y * y;
+                    const float w = __builtin_amdgcn_rcpf(I);
+                    if constexpr (fast) {
+                        cp[u + e] = x * w;
+                        vp2[e] = true;
+                    } else {
+                        const int ev = 8 * (q >> 2) + 4 * h + (q & 3);
+                        const bool valid = col_active && ev < nvalid;
+                        // positive normal or subnormal: not 0, negative, inf or NaN
+                        const bool ok = __builtin_amdgcn_classf(I, 0x180);
+                        cp[u + e] = valid ? (ok ? x * w : NAN) : 0.f;
+                        vp2[e] = valid;
+                    }
+                    Ipair[e] = I;
+                }
+                const float Iq = odd ? Ipair[1] : Ipair[0];
+                // a degenerate I (0, negative, inf or NaN) makes log2 I and so
+                // this lane's sum non-finite: that is how it is detected
+                if constexpr (fast) {
+                    lsum += __builtin_amdgcn_logf(Iq);
+                } else {
+                    const bool vq = odd ? vp2[1] : vp2[0];
+                    lsum += vq ? __builtin_amdgcn_logf(Iq) : 0.f;
+                }
+            }
+            V8 chi, clo;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const T hi = split_hi<T>(cp[u]);
+                chi[u] = hi;
+                clo[u] = split_lo<T>(cp[u], hi);
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                g[rb] = H16<T>::mfma(o.b[rb][s2], chi, g[rb]);
+                if constexpr (SL) gl[rb] = H16<T>::mfma(o.b[rb][s2], clo, gl[rb]);
+                else g[rb] = H16<T>::mfma(o.b[rb][s2], clo, g[rb]);
+            }
+        }
+        dsum += (double)lsum * 0.69314718055994530942;   // log2 -> ln
+    };
+
+    // the fast path: tiles below the last one, when every column carries a vector
+    const int64_t t_full = 32 * cb + 32 <= n_cols ? n_events / 32 : 0;
+    auto run = [&](const Ops& o, int64_t t) {
+        if (t < t_full) process(o, t, std::true_type{});
+        else process(o, t, std::false_type{});
+    };
+    Ops A, B;
+    int64_t t = t0;
+    if (t < t1) load(A, t);
+    for (; t < t1; t += 2) {
+        if (t + 1 < t1) load(B, t + 1);
+        run(A, t);
+        if (t + 1 < t1) {
+            if (t + 2 < t1) load(A, t + 2);
+            run(B, t + 1);
+        }
+    }
+
+    if constexpr (SL) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) g[rb][q] = fmaf(gl[rb][q], kLowUnscale, g[rb][q]);
+    }
+    // records of this wavefront: G column c, rows 8 j + 4 h + i of each row
+    // block, and the column's sum ln I (lanes c and c + 32)
+    const size_t rec_idx = ((size_t)blockIdx.x * n_cb + cb) * 32 + c;
+    float* gcol = rec_g + rec_idx * KD;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = rb * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
+            if (r < KD) gcol[r] = g[rb][q];
+        }
+    const double other = __shfl_xor(dsum, 32);
+    if (h == 0) {
+        rec_d[2 * rec_idx] = dsum + other;
+        rec_d[2 * rec_idx + 1] = (isfinite(dsum) ? 0.0 : 1.0) + (isfinite(other) ? 0.0 : 1.0);
+    }
+}
+
+// ---- assembly: one block per vector k ---------------------------------------
+struct BatchTail {
+    const double* rec_d;   // chunks x n_cb x 32 x 2
+    const float* rec_g;    // chunks x n_cb x 32 x KD
+    int chunks, n_cb, KD, W, K;
+    int64_t n_events;
+    const double* v;       // K x 2W (device)
+    const double* vscale;  // K scales s_k (device)
+    const double2* M;      // W x W
+    double* out;           // K x (2 + 2W) (pinned host memory)
+    unsigned long long* done;   // K completion words (pinned host memory)
+    unsigned long long seq;
+};
+
+constexpr int kBatchAsmThreads = 256;
+
+// One block per vector k.  Every loop issues its loads in batches before
+// using them (a loop that adds each value as it arrives waits one memory round
+// trip per value).
+__global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt)
+{
+    __shared__ double s_wave[kBatchAsmThreads / 64];
+    __shared__ double s_v[2 * PWA_MAX_WAVES_MATRIX];
+    __shared__ double2 s_m[PWA_MAX_WAVES_MATRIX];
+    __shared__ double s_part[kBatchAsmThreads];
+    const int k = blockIdx.x;
+    const int W = bt.W;
+    const int cb = (2 * k) / 32, c0 = (2 * k) % 32;
+    const double* vk = bt.v + (size_t)k * 2 * W;
+    auto ridx = [&](int ch, int cc) { return ((size_t)ch * bt.n_cb + cb) * 32 + cc; };
+    for (int a = threadIdx.x; a < 2 * W; a += blockDim.x) s_v[a] = vk[a];
+    // sum ln I and n_bad over chunks (both columns of the vector)
+    double d = 0.0, nb = 0.0;
+    for (int ch = threadIdx.x; ch < bt.chunks; ch += blockDim.x) {
+        const double2 p0 = *reinterpret_cast<const double2*>(bt.rec_d + 2 * ridx(ch, c0));
+        const double2 p1 = *reinterpret_cast<const double2*>(bt.rec_d + 2 * ridx(ch, c0 + 1));
+        d += p0.x + p1.x;
+        nb += p0.y + p1.y;
+    }
+    __syncthreads();   // s_v
+    const double sk = bt.vscale[k];
+    const double dsum = block_sum_fixed(d, s_wave) + 2.0 * (double)bt.n_events * log(sk);
+    const double nbad = block_sum_fixed(nb, s_wave);
+    // m_b = sum_a V_a M_ab, column b of M loaded in batches
+    for (int b = threadIdx.x; b < W; b += blockDim.x) {
+        double mr = 0.0, mi = 0.0;
+        constexpr int kB = 16;
+        for (int a0 = 0; a0 < W; a0 += kB) {
+            double2 x[kB];
+#pragma unroll
+            for (int j = 0; j < kB; ++j)
+                x[j] = a0 + j < W ? bt.M[(a0 + j) * W + b] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                const int a = a0 + j < W ? a0 + j : 0;
+                const double vr = s_v[2 * a], vi = s_v[2 * a + 1];
+                mr += vr * x[j].x - vi * x[j].y;
+                mi += vr * x[j].y + vi * x[j].x;
+            }
+        }
+        s_m[b] = make_double2(mr, mi);
+    }
+    __syncthreads();
+    double mu_part = 0.0;
+    for (int b = threadIdx.x; b < W; b += blockDim.x)
+        mu_part += s_v[2 * b] * s_m[b].x + s_v[2 * b + 1] * s_m[b].y;
+    const double mu = block_sum_fixed(mu_part, s_wave);
+    // gradient: output o = 2 b + part over R chunk ranges (thread o + 2W r
+    // takes chunks r, r + R, ...); the R partial sums are added in order
+    //   part 0: G[Re b][Re c] + G[Im b][Im c],  part 1: G[Re b][Im c] - G[Im b][Re c]
+    const int nout = 2 * W;
+    const int R = kBatchAsmThreads / nout;
+    const int o = threadIdx.x % nout, r = threadIdx.x / nout;
+    if (r < R) {
+        const int b = o / 2, part = o % 2;
+        const int c1 = part == 0 ? c0 : c0 + 1, c2 = part == 0 ? c0 + 1 : c0;
+        const double sg = part == 0 ? 1.0 : -1.0;
+        double x = 0.0;
+        constexpr int kB = 16;
+        for (int ch0 = r; ch0 < bt.chunks; ch0 += kB * R) {
+            float u1[kB], u2[kB];
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                const int ch = ch0 + j * R;
+                u1[j] = ch < bt.chunks ? bt.rec_g[ridx(ch, c1) * bt.KD + b] : 0.f;
+                u2[j] = ch < bt.chunks ? bt.rec_g[ridx(ch, c2) * bt.KD + W + b] : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < kB; ++j) x += (double)u1[j] + sg * (double)u2[j];
+        }
+        s_part[threadIdx.x] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < nout) {
+        double x = 0.0;
+        for (int rr = 0; rr < R; ++rr) x += s_part[rr * nout + threadIdx.x];
+        x /= sk;
+        const int b = threadIdx.x / 2, part = threadIdx.x % 2;
+        const double m = part == 0 ? s_m[b].x : s_m[b].y;
+        store_system(bt.out + (size_t)k * (2 + 2 * W) + 2 + threadIdx.x, 2.0 * (m - x));
+    }
+    if (threadIdx.x == 0) {
+        store_system(bt.out + (size_t)k * (2 + 2 * W), nbad > 0.0 ? INFINITY : (-dsum + mu));
+        store_system(bt.out + (size_t)k * (2 + 2 * W) + 1, nbad);
+    }
+    wait_vm_complete();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(bt.done + k, bt.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// ---- launchers --------------------------------------------------------------
+static int grid_for(int64_t total, int block)
+{
+    int64_t g = (total + block - 1) / block;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_pack_mfma(const void* src, bool c128, int64_t n, int W, bool bf,
+                            const Model& m, hipStream_t s)
+{
+    const int64_t total = m.n_tiles * 32 * (int64_t)m.kd;
+    if (bf)
+        hipLaunchKernelGGL(k_pack_mfma<__bf16>, dim3(grid_for(total, 256)), dim3(256), 0, s, src,
+                           c128, n, W, m.kd, m.rb, m.n_tiles, (__bf16*)m.d_data, (__bf16*)m.d_at);
+    else
+        hipLaunchKernelGGL(k_pack_mfma<_Float16>, dim3(grid_for(total, 256)), dim3(256), 0, s,
+                           src, c128, n, W, m.kd, m.rb, m.n_tiles, (_Float16*)m.d_data,
+                           (_Float16*)m.d_at);
+    return hipGetLastError();
+}
+
+// chunks: about 2048 wavefronts in all (two per SIMD), each with at least a
+// few tiles
+int mfma_chunks(const Model& m, int n_cb)
+{
+    int64_t c = (2048 + n_cb - 1) / n_cb;
+    const int64_t cap = (m.n_tiles + 3) / 4;
+    if (c > cap) c = cap;
+    return (int)(c < 1 ? 1 : c);
+}
+
+template <typename T, int NS>
+static void launch_main(const Model& m, const MfmaBatch& b, hipStream_t s, const LaunchEvents& ev)
+{
+    constexpr int NP = mfma_v_parts<T>();
+    const int wpb = b.n_cb < mfma_waves<NS>() ? b.n_cb : mfma_waves<NS>();
+    const int gy = (b.n_cb + wpb - 1) / wpb;
+    hipExtLaunchKernelGGL((k_amp_mfma<T, NS, NP>), dim3(b.chunks, gy), dim3(64 * wpb), 0,
+                          s, ev.start, ev.stop, 0, (const T*)m.d_data, (const T*)m.d_at,
+                          (const T*)b.vm, m.n, m.n_tiles, 2 * b.K, b.n_cb, b.chunks, b.rec_d,
+                          b.rec_g);
+}
+
+template <typename T>
+static hipError_t dispatch_ns(const Model& m, const MfmaBatch& b, hipStream_t s,
+                              const LaunchEvents& ev)
+{
+    switch (m.kd / 16) {
+    case 1: launch_main<T, 1>(m, b, s, ev); break;
+    case 2: launch_main<T, 2>(m, b, s, ev); break;
+    case 3: launch_main<T, 3>(m, b, s, ev); break;
+    case 4: launch_main<T, 4>(m, b, s, ev); break;
+    case 5: launch_main<T, 5>(m, b, s, ev); break;
+    case 6: launch_main<T, 6>(m, b, s, ev); break;
+    case 7: launch_main<T, 7>(m, b, s, ev); break;
+    case 8: launch_main<T, 8>(m, b, s, ev); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t run_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
+                            const LaunchEvents& ev)
+{
+    const int NS = m.kd / 16;
+    const int part_elems = b.n_cb * NS * 2 * 32 * 8;
+    hipLaunchKernelGGL(k_prep_vmat16<T>, dim3(grid_for(part_elems, 256)), dim3(256), 0, s, b.v,
+                       b.K, m.W, NS, b.n_cb, mfma_v_parts<T>(), (T*)b.vm, b.vscale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return dispatch_ns<T>(m, b, s, ev);
+}
+
+size_t mfma_vm_bytes(const Model& m, int n_cb)
+{
+    const size_t part = (size_t)n_cb * (m.kd / 16) * 2 * 32 * 8 * 2;
+    return part * (m.form == kAmpBF16 ? mfma_v_parts<__bf16>() : mfma_v_parts<_Float16>());
+}
+
+hipError_t launch_mfma_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
+                             const LaunchEvents& ev)
+{
+    hipError_t e = m.form == kAmpBF16 ? run_batch<__bf16>(m, b, s, ev)
+                                      : run_batch<_Float16>(m, b, s, ev);
+    if (e != hipSuccess) return e;
+    BatchTail bt;
+    bt.rec_d = b.rec_d;
+    bt.rec_g = b.rec_g;
+    bt.chunks = b.chunks;
+    bt.n_cb = b.n_cb;
+    bt.KD = m.kd;
+    bt.W = m.W;
+    bt.K = b.K;
+    bt.v = b.v;
+    bt.vscale = b.vscale;
+    bt.n_events = m.n;
+    bt.M = (const double2*)m.d_M;
+    bt.out = b.out;
+    bt.done = b.done;
+    bt.seq = b.seq;
+    hipLaunchKernelGGL(k_assemble_mfma, dim3(b.K), dim3(kBatchAsmThreads), 0, s, bt);
+    return hipGetLastError();
+}
+
+// copy of the stored 16-bit amplitudes, widened to complex64 (N x W)
+__global__ void k_unpack_mfma(const void* __restrict__ af, bool bf, int64_t n, int W, int KD,
+                              float2* __restrict__ dst)
+{
+    const int64_t total = n * W;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = g / W;
+        const int a = (int)(g % W);
+        float re, im;
+        if (bf) {
+            re = (float)reinterpret_cast<const __bf16*>(af)[i * KD + a];
+            im = (float)reinterpret_cast<const __bf16*>(af)[i * KD + W + a];
+        } else {
+            re = (float)reinterpret_cast<const _Float16*>(af)[i * KD + a];
+            im = (float)reinterpret_cast<const _Float16*>(af)[i * KD + W + a];
+        }
+        dst[g] = make_float2(re, im);
+    }
+}
+
+hipError_t launch_unpack_mfma(const Model& m, float* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_unpack_mfma, dim3(grid_for(m.n * m.W, 256)), dim3(256), 0, s, m.d_data,
+                       m.form == kAmpBF16, m.n, m.W, m.kd, (float2*)dst);
+    return hipGetLastError();
+}
+
+}  // namespace pwa

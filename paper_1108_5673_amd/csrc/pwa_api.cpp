@@ -29,6 +29,10 @@ using pwa::Model;
 
 namespace {
 
+constexpr uint32_t kFormBits = PWA_FORM_TABLE | PWA_FORM_AMPLITUDE | PWA_PRECISION_FP64_PLAIN |
+                               PWA_PRECISION_FP64_FUSED | PWA_FORM_AMPLITUDE_BF16 |
+                               PWA_FORM_AMPLITUDE_FP16;
+
 thread_local std::string g_error;
 
 int fail(int code, const char* fmt, ...)
@@ -115,6 +119,11 @@ void release(Model* m)
     if (m->d_partials) (void)hipFree(m->d_partials);
     if (m->d_colsum) (void)hipFree(m->d_colsum);
     if (m->d_w) (void)hipFree(m->d_w);
+    if (m->d_at) (void)hipFree(m->d_at);
+    if (m->d_vb) (void)hipFree(m->d_vb);
+    if (m->d_vm) (void)hipFree(m->d_vm);
+    if (m->d_brec) (void)hipFree(m->d_brec);
+    if (m->h_vstage) (void)hipHostFree(m->h_vstage);
 
     if (m->h_out) (void)hipHostFree(m->h_out);
     if (m->h_done) (void)hipHostFree(m->h_done);
@@ -138,8 +147,7 @@ int alloc_out(Model* m, int cap)
 int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t n_acc,
                 int64_t n_gen, uint32_t flags, hipStream_t s, Model* m)
 {
-    const uint32_t form = flags & (PWA_FORM_TABLE | PWA_FORM_AMPLITUDE |
-                                   PWA_PRECISION_FP64_PLAIN | PWA_PRECISION_FP64_FUSED);
+    const uint32_t form = flags & kFormBits;
     const bool in_table = flags & PWA_INPUT_IS_TABLE;
     const bool data_c128 = flags & PWA_DATA_COMPLEX128;
     const bool mc_c128 = flags & PWA_MC_COMPLEX128;
@@ -216,6 +224,21 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         m->rows = pwa::plain_rows(n);
         m->grid = m->rows;
         m->rec_len = 2 + 2 * P;
+    } else if (form == PWA_FORM_AMPLITUDE_BF16 || form == PWA_FORM_AMPLITUDE_FP16) {
+        m->kd = (2 * W + 15) / 16 * 16;
+        m->rb = (m->kd + 31) / 32;
+        m->n_tiles = (n + 31) / 32;
+        m->data_bytes = m->n_tiles * 32 * (int64_t)m->kd * 2;
+        const size_t at_bytes = (size_t)m->n_tiles * m->rb * 32 * 32 * 2;
+        HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
+        HIP_TRY(hipMalloc(&m->d_at, at_bytes));
+        HIP_TRY(hipMemsetAsync(m->d_at, 0, at_bytes, s));   // rows kd .. 32 rb stay zero
+        HIP_TRY(hipEventRecord(bt[0], s));
+        HIP_TRY(pwa::launch_pack_mfma(sd.ptr, data_c128, n, W, form == PWA_FORM_AMPLITUDE_BF16, *m,
+                                      s));
+        HIP_TRY(hipEventRecord(bt[1], s));
+        m->rows = 0;
+        m->rec_len = 2 + 2 * W;
     } else {   // amplitude form
         m->wpad = W + (W & 1);
         m->n_tiles = (n + pwa::kAmpTile - 1) / pwa::kAmpTile;
@@ -256,12 +279,14 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         HIP_TRY(hipMemsetAsync(m->d_M, 0, sizeof(double) * 2 * W * W, s));
     }
 
-    HIP_TRY(hipMalloc(&m->d_partials, sizeof(double) * (size_t)m->rows * m->rec_len));
+    if (m->rows > 0)
+        HIP_TRY(hipMalloc(&m->d_partials, sizeof(double) * (size_t)m->rows * m->rec_len));
 
     const int nblk = pwa::assemble_blocks(W, true);
     HIP_TRY(hipHostMalloc((void**)&m->h_done, sizeof(unsigned long long) * nblk,
                           hipHostMallocCoherent | hipHostMallocMapped));
     for (int k = 0; k < nblk; ++k) m->h_done[k] = 0;
+    m->done_cap = nblk;
     rc = alloc_out(m, 1);
     if (rc != PWA_OK) return rc;
     HIP_TRY(hipStreamSynchronize(s));
@@ -351,6 +376,90 @@ int wait_for(Model* m, unsigned long long seq, int nblk, hipStream_t s, bool tim
     return PWA_OK;
 }
 
+bool is_mfma(const Model* m) { return m->form == pwa::kAmpBF16 || m->form == pwa::kAmpFP16; }
+
+// Per-call buffers of the matrix-core path, grown to hold K vectors.
+int mfma_reserve(Model* m, int K, int n_cb, int chunks)
+{
+    const int W = m->W;
+    if (K > m->vec_cap) {
+        const int cap = (K + 15) / 16 * 16;
+        if (m->d_vb) (void)hipFree(m->d_vb);
+        if (m->h_vstage) (void)hipHostFree(m->h_vstage);
+        if (m->d_vm) (void)hipFree(m->d_vm);
+        if (m->d_brec) (void)hipFree(m->d_brec);
+        m->d_vb = nullptr;
+        m->h_vstage = nullptr;
+        m->d_vm = nullptr;
+        m->d_brec = nullptr;
+        m->vec_cap = 0;
+        const int cb_cap = cap / 16;
+        HIP_TRY(hipMalloc(&m->d_vb, sizeof(double) * (2 * W + 1) * (size_t)cap));
+        HIP_TRY(hipHostMalloc((void**)&m->h_vstage, sizeof(double) * 2 * W * (size_t)cap,
+                              hipHostMallocDefault));
+        HIP_TRY(hipMalloc(&m->d_vm, pwa::mfma_vm_bytes(*m, cb_cap)));
+        // chunks x column blocks stays near 2048 (or below) for every K up to cap
+        size_t rec_rows = 0;
+        for (int cb = 1; cb <= cb_cap; ++cb) {
+            const size_t r = (size_t)pwa::mfma_chunks(*m, cb) * cb;
+            if (r > rec_rows) rec_rows = r;
+        }
+        HIP_TRY(hipMalloc(&m->d_brec, rec_rows * 32 * (2 * sizeof(double) + sizeof(float) * m->kd)));
+        m->brec_rows = rec_rows;
+        m->vec_cap = cap;
+    }
+    (void)n_cb;
+    (void)chunks;
+    if (K > m->out_cap) {
+        const int rc = alloc_out(m, K);
+        if (rc != PWA_OK) return rc;
+    }
+    if (K > m->done_cap) {
+        if (m->h_done) (void)hipHostFree(m->h_done);
+        m->h_done = nullptr;
+        m->done_cap = 0;
+        HIP_TRY(hipHostMalloc((void**)&m->h_done, sizeof(unsigned long long) * K,
+                              hipHostMallocCoherent | hipHostMallocMapped));
+        for (int k = 0; k < K; ++k) m->h_done[k] = 0;
+        m->done_cap = K;
+    }
+    return PWA_OK;
+}
+
+// K evaluations on a 16-bit amplitude model in one pass; results in
+// h_out[k * (2 + 2W)].
+int eval_mfma(Model* m, const double* v, int K, hipStream_t s, bool timed)
+{
+    const int W = m->W;
+    const int n_cb = (2 * K + 31) / 32;
+    const int chunks = pwa::mfma_chunks(*m, n_cb);
+    int rc = mfma_reserve(m, K, n_cb, chunks);
+    if (rc != PWA_OK) return rc;
+    std::memcpy(m->h_vstage, v, sizeof(double) * 2 * W * (size_t)K);
+    HIP_TRY(hipMemcpyAsync(m->d_vb, m->h_vstage, sizeof(double) * 2 * W * (size_t)K,
+                           hipMemcpyHostToDevice, s));
+    pwa::MfmaBatch b;
+    b.v = m->d_vb;
+    b.vscale = m->d_vb + (size_t)2 * W * m->vec_cap;
+    b.vm = m->d_vm;
+    b.rec_d = m->d_brec;
+    b.rec_g = (float*)(m->d_brec + 2 * 32 * m->brec_rows);
+    b.out = m->h_out;
+    b.done = m->h_done;
+    b.seq = ++m->seq;
+    b.K = K;
+    b.n_cb = n_cb;
+    b.chunks = chunks;
+    pwa::LaunchEvents ev;
+    if (timed) {
+        ev.start = m->ev0;
+        ev.stop = m->ev1;
+    }
+    const hipError_t e = pwa::launch_mfma_batch(*m, b, s, ev);
+    if (e != hipSuccess) return device_fail(e, "matrix-core evaluation launch");
+    return wait_for(m, b.seq, K, s, timed);
+}
+
 int evaluate(const pwa_model* cm, const double* v, double* nll, double* grad, void* stream)
 {
     if (!cm || !v || !nll) return fail(PWA_ERR_INVALID, "NULL model, v or nll");
@@ -360,11 +469,15 @@ int evaluate(const pwa_model* cm, const double* v, double* nll, double* grad, vo
     DeviceGuard g(m->device);
     hipStream_t s = (hipStream_t)stream;
     const bool want_grad = grad != nullptr;
-    unsigned long long seq = 0;
-    int nblk = 0;
-    rc = enqueue_eval(m, v, want_grad, 0, s, m->timing, &seq, &nblk);
-    if (rc != PWA_OK) return rc;
-    rc = wait_for(m, seq, nblk, s, m->timing);
+    if (is_mfma(m)) {
+        rc = eval_mfma(m, v, 1, s, m->timing);
+    } else {
+        unsigned long long seq = 0;
+        int nblk = 0;
+        rc = enqueue_eval(m, v, want_grad, 0, s, m->timing, &seq, &nblk);
+        if (rc != PWA_OK) return rc;
+        rc = wait_for(m, seq, nblk, s, m->timing);
+    }
     if (rc != PWA_OK) return rc;
     *nll = m->h_out[0];
     if (want_grad) std::memcpy(grad, m->h_out + 2, sizeof(double) * 2 * m->W);
@@ -381,21 +494,21 @@ int pwa_build_table(const void* data, int64_t n_data, int32_t n_waves, const voi
 {
     if (!out) return fail(PWA_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    const uint32_t known = PWA_FORM_TABLE | PWA_FORM_AMPLITUDE | PWA_INPUT_IS_TABLE |
-                           PWA_PRECISION_FP64_PLAIN | PWA_DATA_COMPLEX128 | PWA_MC_COMPLEX128 |
-                           PWA_PRECISION_FP64_FUSED;
+    const uint32_t known = kFormBits | PWA_INPUT_IS_TABLE | PWA_DATA_COMPLEX128 | PWA_MC_COMPLEX128;
     if (flags & ~known) return fail(PWA_ERR_INVALID, "unknown flag bits 0x%x", flags & ~known);
-    const uint32_t form = flags & (PWA_FORM_TABLE | PWA_FORM_AMPLITUDE |
-                                   PWA_PRECISION_FP64_PLAIN | PWA_PRECISION_FP64_FUSED);
-    if (form != PWA_FORM_TABLE && form != PWA_FORM_AMPLITUDE &&
-        form != PWA_PRECISION_FP64_PLAIN && form != PWA_PRECISION_FP64_FUSED)
+    const uint32_t form = flags & kFormBits;
+    if (form == 0 || (form & (form - 1)) != 0)
         return fail(PWA_ERR_INVALID, "exactly one form flag is required (got 0x%x)", form);
+    const bool amp_form = form == PWA_FORM_AMPLITUDE || form == PWA_FORM_AMPLITUDE_BF16 ||
+                          form == PWA_FORM_AMPLITUDE_FP16;
     if (!data) return fail(PWA_ERR_INVALID, "data is NULL");
     if (n_data < 1) return fail(PWA_ERR_INVALID, "n_data must be >= 1 (got %lld)", (long long)n_data);
-    const int wmax = (form == PWA_FORM_AMPLITUDE) ? PWA_MAX_WAVES_AMPLITUDE : PWA_MAX_WAVES_TABLE;
+    const int wmax = form == PWA_FORM_AMPLITUDE ? PWA_MAX_WAVES_AMPLITUDE
+                     : amp_form             ? PWA_MAX_WAVES_MATRIX
+                                            : PWA_MAX_WAVES_TABLE;
     if (n_waves < 1 || n_waves > wmax)
         return fail(PWA_ERR_INVALID, "n_waves must be in [1, %d] for this form (got %d)", wmax, n_waves);
-    if ((flags & PWA_INPUT_IS_TABLE) && form == PWA_FORM_AMPLITUDE)
+    if ((flags & PWA_INPUT_IS_TABLE) && amp_form)
         return fail(PWA_ERR_INVALID, "PWA_INPUT_IS_TABLE needs a table form");
     if (n_mc_acc < 0) return fail(PWA_ERR_INVALID, "n_mc_acc must be >= 0");
     if (n_mc_acc > 0 && !mc_amp) return fail(PWA_ERR_INVALID, "mc_amp is NULL but n_mc_acc > 0");
@@ -459,20 +572,27 @@ int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k
             if (rc != PWA_OK) return rc;
         }
         DeviceGuard g(m->device);
-        if (K > m->out_cap) {
-            const int rc = alloc_out(m, K);
-            if (rc != PWA_OK) return rc;
-        }
-        unsigned long long seq = 0;
-        int nblk = 0;
-        for (int k = 0; k < K; ++k) {
-            const int rc = enqueue_eval(m, vp + (size_t)k * 2 * W, gp != nullptr, k, s, false, &seq,
-                                        &nblk);
-            if (rc != PWA_OK) return rc;
-        }
-        if (K > 0) {
-            const int rc = wait_for(m, seq, nblk, s, false);
-            if (rc != PWA_OK) return rc;
+        if (is_mfma(m)) {
+            if (K > 0) {
+                const int rc = eval_mfma(m, vp, K, s, m->timing);
+                if (rc != PWA_OK) return rc;
+            }
+        } else {
+            if (K > m->out_cap) {
+                const int rc = alloc_out(m, K);
+                if (rc != PWA_OK) return rc;
+            }
+            unsigned long long seq = 0;
+            int nblk = 0;
+            for (int k = 0; k < K; ++k) {
+                const int rc = enqueue_eval(m, vp + (size_t)k * 2 * W, gp != nullptr, k, s, false,
+                                            &seq, &nblk);
+                if (rc != PWA_OK) return rc;
+            }
+            if (K > 0) {
+                const int rc = wait_for(m, seq, nblk, s, false);
+                if (rc != PWA_OK) return rc;
+            }
         }
         for (int k = 0; k < K; ++k) {
             const double* o = m->h_out + (size_t)k * (2 + 2 * W);
@@ -509,6 +629,10 @@ int pwa_model_info(const pwa_model* model, pwa_info* out)
     case pwa::kTable32: out->stream_bytes = m->n * m->P * 8; break;
     case pwa::kTable64Fused: out->stream_bytes = m->n * m->P * 16; break;
     case pwa::kTable64Plain: out->stream_bytes = 2 * m->n * m->P * 16; break;
+    case pwa::kAmpBF16:
+    case pwa::kAmpFP16:
+        out->stream_bytes = m->n_tiles * 32 * (int64_t)(m->kd + 32 * m->rb) * 2;
+        break;
     default: out->stream_bytes = m->n * m->W * 8; break;
     }
     out->grid_blocks = m->grid;
@@ -523,6 +647,17 @@ int pwa_copy_table(const pwa_model* model, void* out_host, void* hip_stream)
     if (m->form == pwa::kAmp32) return fail(PWA_ERR_INVALID, "amplitude-form model has no table");
     DeviceGuard g(m->device);
     hipStream_t s = (hipStream_t)hip_stream;
+    if (is_mfma(m)) {   // the stored 16-bit amplitudes, widened to complex64
+        const size_t bytes = (size_t)m->n * m->W * 8;
+        void* tmp = nullptr;
+        HIP_TRY(hipMalloc(&tmp, bytes));
+        hipError_t e = pwa::launch_unpack_mfma(*m, (float*)tmp, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(out_host, tmp, bytes, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return device_fail(e, "amplitude copy");
+        return PWA_OK;
+    }
     const bool c128 = m->form != pwa::kTable32;
     const size_t bytes = (size_t)m->n * m->P * (c128 ? 16 : 8);
     void* tmp = nullptr;

@@ -21,6 +21,8 @@ enum Form : uint32_t {
     kAmp32 = PWA_FORM_AMPLITUDE,
     kTable64Plain = PWA_PRECISION_FP64_PLAIN,
     kTable64Fused = PWA_PRECISION_FP64_FUSED,
+    kAmpBF16 = PWA_FORM_AMPLITUDE_BF16,
+    kAmpFP16 = PWA_FORM_AMPLITUDE_FP16,
 };
 
 // Parameter vector passed by value in the kernel arguments: no host-to-device
@@ -71,6 +73,33 @@ struct Model {
     int64_t timed_launches = 0;
     double build_table_ms = 0.0;   // device time of the table (or amplitude) preparation
     double build_mc_ms = 0.0;      // device time of the MC integral M
+
+    // 16-bit amplitude forms (matrix-core kernel, any number of vectors)
+    void* d_at = nullptr;           // second copy of the event tiles (adjoint operand order)
+    int32_t kd = 0;                 // row length 2W padded to a multiple of 16
+    int32_t rb = 0;                 // adjoint row blocks of 32 (ceil(kd / 32))
+    int32_t vec_cap = 0;            // vectors the per-call buffers below can hold
+    double* d_vb = nullptr;         // vec_cap x 2W parameter vectors, then vec_cap scales (device)
+    double* h_vstage = nullptr;     // vec_cap x 2W pinned staging for d_vb
+    void* d_vm = nullptr;           // split vector matrix
+    double* d_brec = nullptr;       // per-(chunk, column) records: FP64 sums, then FP32 G
+    size_t brec_rows = 0;           // (chunk, column block) pairs d_brec can hold
+    int32_t done_cap = 0;           // completion words h_done can hold
+};
+
+// One call of the matrix-core path: K vectors, device buffers and outputs.
+struct MfmaBatch {
+    const double* v;            // K x 2W (device)
+    double* vscale;             // K power-of-two scales of the vectors (device)
+    void* vm;                   // split vector matrix (device)
+    double* rec_d;              // chunks x n_cb x 32 x 2: sum ln I, n_bad (device)
+    float* rec_g;               // chunks x n_cb x 32 x kd: G columns (device)
+    double* out;                // K x (2 + 2W) (pinned host)
+    unsigned long long* done;   // K completion words (pinned host)
+    unsigned long long seq;
+    int K;
+    int n_cb;                   // column blocks of 32 (16 vectors each)
+    int chunks;                 // event chunks
 };
 
 // ---- launchers (each returns the hipError_t of its launch) ----------------
@@ -102,6 +131,13 @@ hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStr
                    const LaunchEvents& ev);
 hipError_t launch_colsum(const double* partials, int rows, int cols, int stride, double* out,
                          hipStream_t s);
+hipError_t launch_pack_mfma(const void* src, bool c128, int64_t n, int W, bool bf,
+                            const Model& m, hipStream_t s);
+hipError_t launch_unpack_mfma(const Model& m, float* dst, hipStream_t s);
+hipError_t launch_mfma_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
+                             const LaunchEvents& ev);
+int mfma_chunks(const Model& m, int n_cb);
+size_t mfma_vm_bytes(const Model& m, int n_cb);
 hipError_t launch_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s);
 int assemble_blocks(int W, bool grad);
 

@@ -54,6 +54,20 @@ __device__ inline void store_system(double* p, double v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Block sum in a fixed order: a butterfly inside each wavefront, then the
+// wavefront sums in wave order (blockDim a multiple of 64, at most 1024).
+__device__ inline double block_sum_fixed(double x, double* s_wave)
+{
+    x = wave_allsum(x);
+    const int waves = blockDim.x >> 6;
+    if (lane_id() == 0) s_wave[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < waves; ++w) r += s_wave[w];
+    __syncthreads();
+    return r;
+}
+
 // Wait until this thread's outstanding vector-memory operations completed.
 __device__ inline void wait_vm_complete()
 {

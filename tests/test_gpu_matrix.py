@@ -1,0 +1,118 @@
+"""The 16-bit amplitude forms on the matrix cores (needs an MI355X).
+
+Inputs both sides see: the amplitudes rounded to bfloat16 or float16 on the
+host (torch's and numpy's round-to-nearest-even conversions from complex64;
+float16 results below the smallest normal stored as zero), which the library
+must store bit for bit; the oracle then evaluates Eq. 3 in
+FP64 on those rounded amplitudes.
+
+Tolerances, from the arithmetic of the kernel.  S_i = sum_a A_ia V_a is
+accumulated in FP32 over n_t = 2W x (parts of V) exact 16-bit products, so
+|dS_i| <= e_i = n_t 2^-24 sum_a |A_ia||V_a| (V itself carried to 22-24 bits);
+an event whose S_i nearly cancels has a large relative error, which enters
+ln I_i as 2 e_i / |S_i| and the adjoint weight c_i = 1 / conj(S_i) as
+e_i / |S_i|^2.  Per point:
+  |dNLL|   <= 4 sum_i 2 e_i / |S_i|  + 1e-6 N + 1e-9 |NLL|
+              (the second term: FP32 logarithms and the scale of the sums),
+  ||dG||_2 <= 4 * 2 sqrt(2) || sum_i |A_i| e_i / |S_i|^2 ||_2 + r ||G||_2,
+with r the weight split's relative precision (1e-5 for bfloat16, whose two
+parts carry 16 bits, 1e-6 for float16 with 22 bits).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1108_5673_amd as pwa
+from paper_1108_5673_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FORMS = ["amplitude_bf16", "amplitude_fp16"]
+G_REL = {"amplitude_bf16": 1e-5, "amplitude_fp16": 1e-6}
+V_PARTS = {"amplitude_bf16": 3, "amplitude_fp16": 2}
+
+
+def _round16(a: np.ndarray, form: str) -> np.ndarray:
+    """complex64 -> the stored 16-bit parts, widened back to complex128."""
+    a = np.ascontiguousarray(a, np.complex64)
+    re, im = a.real.astype(np.float32), a.imag.astype(np.float32)
+    if form == "amplitude_fp16":
+        # round to nearest even, then subnormal results stored as zero
+        r, i = re.astype(np.float16).astype(np.float64), im.astype(np.float16).astype(np.float64)
+        r[np.abs(r) < 2.0 ** -14] = 0.0
+        i[np.abs(i) < 2.0 ** -14] = 0.0
+    else:
+        import torch
+        r = torch.from_numpy(re).to(torch.bfloat16).to(torch.float64).numpy()
+        i = torch.from_numpy(im).to(torch.bfloat16).to(torch.float64).numpy()
+    return r + 1j * i
+
+
+def _rel(g, ref):
+    return float(np.linalg.norm(np.asarray(g) - ref) / np.linalg.norm(ref))
+
+
+def _bounds(A, V, form, nll_ref, g_ref):
+    """(|dNLL| bound, ||dG|| bound) of the derivation above."""
+    n, w = A.shape
+    S = A @ V
+    e = 2 * w * V_PARTS[form] * 2.0 ** -24 * (np.abs(A) @ np.abs(V))
+    b_nll = 4 * np.sum(2 * e / np.abs(S)) + 1e-6 * n + 1e-9 * abs(nll_ref)
+    du = np.abs(A).T @ (e / np.abs(S) ** 2)
+    b_g = 4 * 2 * np.sqrt(2) * np.linalg.norm(du) + G_REL[form] * np.linalg.norm(g_ref)
+    return b_nll, b_g
+
+
+def _check(form, w, n, n_mc, seed, k):
+    o = oracle.get()
+    s = synth.small_sample(w, n, n_mc, seed, n_points=k)
+    d32 = s.data.astype(np.complex64)
+    mc32 = s.mc.astype(np.complex64)
+    model = pwa.Model(d32, mc32, n_mc, form=form)
+    A = _round16(d32, form)
+    assert np.array_equal(model.table().astype(np.complex128), A)
+    M = o.mc_matrix(mc32.astype(np.complex128), n_mc)
+    [(nll_b, g_b)] = pwa.nll_batched([model], [s.points])
+    for j, V in enumerate(s.points):
+        rn, rg, nbad = o.nll_amp(A, M, V)
+        assert nbad == 0
+        b_nll, b_g = _bounds(A, V, form, rn, rg)
+        assert abs(nll_b[j] - rn) <= b_nll, (form, w, n, k, j, nll_b[j], rn, b_nll)
+        dg = float(np.linalg.norm(g_b[j] - rg))
+        assert dg <= b_g, (form, w, n, k, j, dg, b_g, _rel(g_b[j], rg))
+    # a single call agrees with the oracle within the same bounds
+    nll1, g1 = model.nll_grad(s.points[0])
+    rn, rg, _ = o.nll_amp(A, M, s.points[0])
+    b_nll, b_g = _bounds(A, s.points[0], form, rn, rg)
+    assert abs(nll1 - rn) <= b_nll
+    assert np.linalg.norm(g1 - rg) <= b_g
+    model.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("w,n,k", [(1, 1, 1), (2, 33, 3), (4, 1000, 16), (7, 4099, 17),
+                                   (20, 5000, 37), (24, 777, 64), (33, 300, 5), (64, 2000, 20)])
+def test_matrix_parity(form, w, n, k):
+    _check(form, w, n, 3 * n + 11, seed=1000 * w + n + k, k=k)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_matrix_degenerate_event(form):
+    s = synth.small_sample(6, 500, 800, seed=77, n_points=3)
+    d = s.data.astype(np.complex64)
+    d[123] = 0.0                          # I = 0 for every V
+    model = pwa.Model(d, s.mc.astype(np.complex64), 800, form=form)
+    with pytest.warns(UserWarning):
+        [(nll, g)] = pwa.nll_batched([model], [s.points])
+    assert np.all(np.isinf(nll)) and np.all(np.isnan(g))
+    model.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_matrix_repeatable(form):
+    s = synth.small_sample(12, 3000, 4000, seed=5, n_points=40)
+    model = pwa.Model(s.data.astype(np.complex64), s.mc.astype(np.complex64), 4000, form=form)
+    a = pwa.nll_batched([model], [s.points])[0]
+    b = pwa.nll_batched([model], [s.points])[0]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    model.close()
