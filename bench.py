@@ -87,6 +87,65 @@ def time_model(model, points, steps, warmup):
     }
 
 
+def mfma_flops(n_events, n_waves, k, v_parts):
+    """Matrix-core FLOPs of one batched pass as the kernel issues them: per
+    32-event tile and 16 vectors, the forward product (16-wide KD steps x V
+    parts) and the adjoint (32-row blocks x 2 event steps x 2 weight parts),
+    each a 32x32x16 MFMA of 32768 FLOP."""
+    kd = (2 * n_waves + 15) // 16 * 16
+    rb = (kd + 31) // 32
+    tiles = (n_events + 31) // 32
+    col_blocks = (2 * k + 31) // 32
+    per = (kd // 16) * v_parts + rb * 2 * 2
+    return tiles * col_blocks * per * 32768
+
+
+def bench_batched(args):
+    """The 256 random starting points of w20_n1m_k256 in one pass of the
+    matrix-core amplitude forms (bf16 and fp16 amplitudes)."""
+    import torch
+    import paper_1108_5673_amd as pwa
+    from paper_1108_5673_amd import synth
+    s = synth.make_sample("w20_n1m_k256")
+    d32, mc32 = s.data.astype(np.complex64), s.mc.astype(np.complex64)
+    out = {"workload": "w20_n1m_k256: 1M events x 20 waves, K = 256 vectors Re, Im ~ N(0, 1), "
+                       "amplitude form on the matrix cores", "K": 256}
+    ref = None
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.get()
+        M64 = o.mc_matrix(s.mc, s.n_gen)
+        ref = {j: o.nll_amp(s.data, M64, s.points[j]) for j in (0, 85, 170, 255)}
+    for form, parts in (("amplitude_bf16", 3), ("amplitude_fp16", 2)):
+        m = pwa.Model(d32, mc32, s.n_gen, form=form)
+        for _ in range(2):
+            pwa.nll_batched([m], [s.points])
+        torch.cuda.synchronize()
+        m.set_timing(True)
+        m.timing()
+        reps = 10
+        t = time.perf_counter()
+        for _ in range(reps):
+            [(nll, g)] = pwa.nll_batched([m], [s.points])
+        dt = (time.perf_counter() - t) / reps
+        ms, n = m.timing()
+        kus = 1e3 * ms / max(1, n)
+        fl = mfma_flops(s.data.shape[0], 20, 256, parts)
+        r = {"evals_per_s": 256 / dt, "batch_us": 1e6 * dt, "kernel_us": kus,
+             "mfma_tflops": fl / (kus * 1e-6) / 1e12, "mfma_peak_tflops": 2500.0,
+             "mfma_frac": fl / (kus * 1e-6) / 2.5e15,
+             "events_iter_per_s": 256 / dt * s.data.shape[0]}
+        if ref is not None:
+            r["max_abs_dnll_vs_fp64_amplitudes"] = max(abs(nll[j] - ref[j][0]) for j in ref)
+            r["max_rel_grad_vs_fp64_amplitudes"] = max(
+                float(np.linalg.norm(g[j] - ref[j][1]) / np.linalg.norm(ref[j][1])) for j in ref)
+        out[form] = r
+        log("batched %s: %.0f evals/s, kernel %.1f us (%.0f TFLOP/s on the matrix cores)"
+            % (form, r["evals_per_s"], kus, r["mfma_tflops"]))
+        m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +155,8 @@ def main():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baselines", action="store_true", help="time only the fused kernel")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 256-vector matrix-core measurement")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -172,6 +233,10 @@ def main():
         }
         out["speedup_vs_plain_fp64"] = f["evals_per_s"] / p["evals_per_s"]
 
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(args)
+
     achieved = info["stream_bytes"] / (f["kernel_ms"] * 1e-3) / 1e9
     traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -234,6 +299,7 @@ def main():
         "latency_us": f["latency_us"],
         "prefit": prefit,
         "fit": fit_info,
+        "batched_k256": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
