@@ -49,10 +49,12 @@ inline int amp_waves_per_block(int wpad)
     return w;
 }
 
+// One block's share: tiles [t0, t1) of one evaluation, V (2W doubles) from
+// `v`, one record [sum ln I, n_bad, g_0, ..., g_{W-1}] to `rec`.
 template <int KW, bool GRAD>
-__global__ __launch_bounds__(256) void k_amp_fused(const float4* __restrict__ amp, int64_t n_events,
-                                                   int64_t n_tiles, int W, int wpad, VParams vp,
-                                                   double* __restrict__ partials, int rec_len)
+__device__ void amp_block(const float4* __restrict__ amp, int64_t n_events, int64_t t0,
+                          int64_t t1, int W, int wpad, const double* __restrict__ v,
+                          double* __restrict__ rec)
 {
     extern __shared__ double lds_d[];
     char* lds = reinterpret_cast<char*>(lds_d);
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_amp_fused(const float4* __restrict__ am
     const int h = wpad >> 1;                                 // 16-byte vectors per row
 
     for (int a = threadIdx.x; a < wpad; a += blockDim.x)
-        s_v[a] = (a < W) ? make_double2(vp.v[2 * a], vp.v[2 * a + 1]) : make_double2(0.0, 0.0);
+        s_v[a] = (a < W) ? make_double2(v[2 * a], v[2 * a + 1]) : make_double2(0.0, 0.0);
     __syncthreads();
 
     double gr[KW], gi[KW];
@@ -77,8 +79,6 @@ __global__ __launch_bounds__(256) void k_amp_fused(const float4* __restrict__ am
 
     // the block's tiles, interleaved over its wavefronts; each wavefront uses
     // only its own LDS region, so it synchronises with itself only
-    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
-    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
     for (int64_t t = t0 + wave; t < t1; t += nwaves) {
         const float4* src = amp + t * kAmpTile * h;
         for (int q = 0; q < h; ++q) {
@@ -154,7 +154,6 @@ __global__ __launch_bounds__(256) void k_amp_fused(const float4* __restrict__ am
         }
         __syncthreads();
     }
-    double* rec = partials + (int64_t)blockIdx.x * rec_len;
     if (threadIdx.x == 0) {
         rec[0] = s_misc[0];
         rec[1] = s_misc[1];
@@ -165,6 +164,63 @@ __global__ __launch_bounds__(256) void k_amp_fused(const float4* __restrict__ am
             rec[3 + 2 * a] = s_g[a].y;
         }
     }
+}
+
+template <int KW, bool GRAD>
+__global__ __launch_bounds__(256) void k_amp_fused(const float4* __restrict__ amp, int64_t n_events,
+                                                   int64_t n_tiles, int W, int wpad, VParams vp,
+                                                   double* __restrict__ partials, int rec_len)
+{
+    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
+    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
+    amp_block<KW, GRAD>(amp, n_events, t0, t1, W, wpad, vp.v,
+                        partials + (int64_t)blockIdx.x * rec_len);
+}
+
+// ---- many evaluations, possibly of different models, in one launch --------
+// Block u takes work unit u: tiles [t0, t1) of job units[u].job, whose V is at
+// params + job.v_off; its record is record u (stride rec_stride doubles).
+template <int KW>
+__global__ __launch_bounds__(256) void k_amp_multi(const MultiJob* __restrict__ jobs,
+                                                   const MultiUnit* __restrict__ units,
+                                                   const double* __restrict__ params,
+                                                   double* __restrict__ recs, int rec_stride)
+{
+    const MultiUnit u = units[blockIdx.x];
+    const MultiJob j = jobs[u.job];
+    amp_block<KW, true>((const float4*)j.amp, j.n_events, u.t0, u.t1, j.W, j.wpad,
+                        params + j.v_off, recs + (int64_t)blockIdx.x * rec_stride);
+}
+
+hipError_t launch_amp_multi(const MultiLaunch& ml, hipStream_t s)
+{
+    const size_t lds = amp_lds_bytes(ml.wpad_max, ml.waves);
+    const dim3 grid(ml.n_units), block(64 * ml.waves);
+    if (ml.wpad_max <= 64)
+        hipLaunchKernelGGL((k_amp_multi<1>), grid, block, lds, s, ml.jobs, ml.units, ml.params,
+                           ml.recs, ml.rec_stride);
+    else
+        hipLaunchKernelGGL((k_amp_multi<2>), grid, block, lds, s, ml.jobs, ml.units, ml.params,
+                           ml.recs, ml.rec_stride);
+    return hipGetLastError();
+}
+
+int amp_multi_waves(int wpad_max) { return amp_waves_per_block(wpad_max); }
+
+size_t amp_multi_lds(int wpad_max) { return amp_lds_bytes(wpad_max, amp_waves_per_block(wpad_max)); }
+
+hipError_t amp_multi_prepare(int wpad_max)
+{
+    const size_t lds = amp_multi_lds(wpad_max);
+    if (lds > 65536) {
+        const void* fns[] = {(const void*)&k_amp_multi<1>, (const void*)&k_amp_multi<2>};
+        for (const void* f : fns) {
+            const hipError_t e =
+                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 template <int KW>

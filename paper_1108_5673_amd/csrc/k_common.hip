@@ -182,29 +182,33 @@ __device__ inline double2 strided_record_sum(const TailArgs& ta, int col, int fi
     return acc;
 }
 
-__device__ inline void publish(const TailArgs& ta)
+// All of this block's result stores have completed: publish `seq` in its
+// completion word.
+__device__ inline void publish(unsigned long long* word, unsigned long long seq)
 {
     wait_vm_complete();
     __syncthreads();
     if (threadIdx.x == 0)
-        __hip_atomic_store(ta.done + blockIdx.x, ta.seq, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(word, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // V_a M_ab
-__device__ inline double2 v_times_m(const VParams& vp, const double2* M, int W, int a, int b)
+__device__ inline double2 v_times_m(const double* v, const double2* M, int W, int a, int b)
 {
     const double2 x = M[a * W + b];
-    const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
+    const double vr = v[2 * a], vi = v[2 * a + 1];
     return make_double2(vr * x.x - vi * x.y, vr * x.y + vi * x.x);
 }
 
-__global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailArgs ta)
+// One assembly block: role 0 forms the NLL, role 1 + b the gradient component
+// b; V (2W doubles) at v; ends by publishing in `word`.
+__device__ void assemble_role(const double* v, const TailArgs& ta, int role,
+                              unsigned long long* word)
 {
     __shared__ double s_wave[kAssembleThreads / 64];
     __shared__ double2 s_acc[kAssembleThreads];
     const int W = ta.W;
-    if (blockIdx.x == 0) {
+    if (role == 0) {
         // columns 0 and 1: sum ln I and the count of invalid intensities
         const double2 head = strided_record_sum(ta, 0, threadIdx.x, blockDim.x);
         const double dsum = block_sum_fixed(head.x, s_wave);
@@ -213,18 +217,18 @@ __global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailA
         double mu_part = 0.0;
         for (int k = threadIdx.x; k < W * W; k += blockDim.x) {
             const int a = k / W, bb = k % W;
-            const double2 t = v_times_m(vp, ta.M, W, a, bb);
-            mu_part += vp.v[2 * bb] * t.x + vp.v[2 * bb + 1] * t.y;
+            const double2 t = v_times_m(v, ta.M, W, a, bb);
+            mu_part += v[2 * bb] * t.x + v[2 * bb + 1] * t.y;
         }
         const double mu = block_sum_fixed(mu_part, s_wave);
         if (threadIdx.x == 0) {
             store_system(ta.out, nbad > 0.0 ? INFINITY : (-dsum + mu));
             store_system(ta.out + 1, nbad);
         }
-        publish(ta);
+        publish(word, ta.seq);
         return;
     }
-    const int b = blockIdx.x - 1;
+    const int b = role - 1;
     // the entries this gradient component needs: U_ab for all a (packed row and
     // column of b) or g_b; thread t works on entry a = t % nent over the record
     // range t / nent, and the ranges are added in order
@@ -264,13 +268,13 @@ __global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailA
                 ur = xr;
                 ui = xi;
             } else {
-                const double vr = vp.v[2 * l], vi = vp.v[2 * l + 1];
+                const double vr = v[2 * l], vi = v[2 * l + 1];
                 ur = vr * xr - vi * xi;
                 ui = vr * xi + vi * xr;
             }
         }
         for (int aa = l; aa < W; aa += 64) {
-            const double2 t = v_times_m(vp, ta.M, W, aa, b);
+            const double2 t = v_times_m(v, ta.M, W, aa, b);
             mr += t.x;
             mi += t.y;
         }
@@ -285,7 +289,44 @@ __global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailA
             store_system(ta.out + 3 + 2 * b, gi);
         }
     }
-    publish(ta);
+    publish(word, ta.seq);
+}
+
+__global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailArgs ta)
+{
+    assemble_role(vp.v, ta, blockIdx.x, ta.done + blockIdx.x);
+}
+
+// The assembly of many evaluations in one launch: block i is role
+// blocks[i].role of job blocks[i].job.  The completion value is read from the
+// head of the parameter buffer, so that a captured graph can replay the launch
+// with new parameters and a new value.
+__global__ __launch_bounds__(kAssembleThreads) void k_assemble_multi(
+    const MultiJob* __restrict__ jobs, const AsmBlock* __restrict__ blocks,
+    const double* __restrict__ params, const double* __restrict__ recs, int rec_stride,
+    double* out, unsigned long long* done)
+{
+    const AsmBlock ab = blocks[blockIdx.x];
+    const MultiJob j = jobs[ab.job];
+    TailArgs ta;
+    ta.rec = recs + (int64_t)j.rec0 * rec_stride;
+    ta.rows = j.nrec;
+    ta.rec_len = rec_stride;
+    ta.M = j.M;
+    ta.out = out + j.out_off;
+    ta.done = done;
+    ta.seq = *reinterpret_cast<const unsigned long long*>(params);
+    ta.W = j.W;
+    ta.grad = 1;
+    ta.amplitude = 1;
+    assemble_role(params + j.v_off, ta, ab.role, done + j.done_off + ab.role);
+}
+
+hipError_t launch_assemble_multi(const MultiLaunch& ml, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_assemble_multi, dim3(ml.n_asm), dim3(kAssembleThreads), 0, s, ml.jobs,
+                       ml.asm_blocks, ml.params, ml.recs, ml.rec_stride, ml.out, ml.done);
+    return hipGetLastError();
 }
 
 int assemble_blocks(int W, bool grad) { return 1 + (grad ? W : 0); }

@@ -11,8 +11,10 @@
 // V travels in the kernel arguments, so nothing is copied host-to-device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -378,6 +380,252 @@ int wait_for(Model* m, unsigned long long seq, int nblk, hipStream_t s, bool tim
 
 bool is_mfma(const Model* m) { return m->form == pwa::kAmpBF16 || m->form == pwa::kAmpFP16; }
 
+// ---- many evaluations of FP32 amplitude models in one launch ---------------
+// A plan holds the work list of one set of (model, vector count) pairs, its
+// device tables, the pinned parameter staging and a graph captured once:
+// [copy parameters to the device, amplitude kernel over all work units,
+// assembly of all evaluations].  Each call writes the new parameters and
+// completion value into the staging buffer and replays the graph.  The last
+// plan is kept for the next call with the same pairs; freeing one of its
+// models discards it.
+struct MultiPlan {
+    std::vector<std::pair<const Model*, int>> key;
+    int device = 0;
+    int n_jobs = 0;
+    std::vector<int32_t> job_w, out_off, v_off;
+    void* d_tables = nullptr;
+    double* d_params = nullptr;
+    double* h_params = nullptr;
+    size_t params_bytes = 0;
+    double* d_recs = nullptr;
+    double* h_out = nullptr;
+    unsigned long long* h_done = nullptr;
+    int n_done = 0;
+    pwa::MultiLaunch ml{};
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long seq = 0;
+};
+
+std::mutex g_plan_mu;
+MultiPlan* g_plan = nullptr;
+
+void destroy_plan(MultiPlan* p)
+{
+    if (!p) return;
+    DeviceGuard g(p->device);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->d_tables) (void)hipFree(p->d_tables);
+    if (p->d_params) (void)hipFree(p->d_params);
+    if (p->d_recs) (void)hipFree(p->d_recs);
+    if (p->h_params) (void)hipHostFree(p->h_params);
+    if (p->h_out) (void)hipHostFree(p->h_out);
+    if (p->h_done) (void)hipHostFree(p->h_done);
+    delete p;
+}
+
+bool multi_eligible(pwa_model* const* models, int n_models, const int32_t* k_per_model)
+{
+    int jobs = 0;
+    int dev = -1;
+    for (int mi = 0; mi < n_models; ++mi) {
+        const Model* m = reinterpret_cast<const Model*>(models[mi]);
+        if (m->form != pwa::kAmp32) return false;
+        if (dev >= 0 && m->device != dev) return false;
+        dev = m->device;
+        jobs += k_per_model[mi];
+    }
+    return jobs >= 2;
+}
+
+int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_model, MultiPlan** out)
+{
+    MultiPlan* p = new (std::nothrow) MultiPlan();
+    if (!p) return fail(PWA_ERR_OOM, "host allocation failed");
+    struct Guard {
+        MultiPlan*& p;
+        ~Guard() { destroy_plan(p); }
+    } guard{p};
+    std::vector<pwa::MultiJob> jobs;
+    std::vector<pwa::MultiUnit> units;
+    std::vector<pwa::AsmBlock> asmb;
+    int wmax = 1, wpad_max = 2;
+    int64_t total_tiles = 0;
+    int32_t out_off = 0, done_off = 0, v_off = 1;   // the completion value comes first
+    for (int mi = 0; mi < n_models; ++mi) {
+        const Model* m = reinterpret_cast<const Model*>(models[mi]);
+        p->key.emplace_back(m, k_per_model[mi]);
+        p->device = m->device;
+        for (int k = 0; k < k_per_model[mi]; ++k) {
+            pwa::MultiJob j{};
+            j.amp = m->d_data;
+            j.n_events = m->n;
+            j.W = m->W;
+            j.wpad = m->wpad;
+            j.v_off = v_off;
+            j.out_off = out_off;
+            j.done_off = done_off;
+            j.M = (const double2*)m->d_M;
+            jobs.push_back(j);
+            p->job_w.push_back(m->W);
+            p->out_off.push_back(out_off);
+            p->v_off.push_back(v_off);
+            v_off += 2 * m->W;
+            out_off += 2 + 2 * m->W;
+            done_off += 1 + m->W;
+            wmax = std::max<int>(wmax, m->W);
+            wpad_max = std::max<int>(wpad_max, m->wpad);
+            total_tiles += m->n_tiles;
+        }
+    }
+    p->n_jobs = (int)jobs.size();
+    const int waves = pwa::amp_multi_waves(wpad_max);
+    const int64_t tpu = std::max<int64_t>(2 * waves, (total_tiles + 2047) / 2048);
+    for (int ji = 0; ji < p->n_jobs; ++ji) {
+        const Model* m = nullptr;
+        {
+            int acc = 0;
+            for (int mi = 0; mi < n_models; ++mi) {
+                if (ji < acc + k_per_model[mi]) {
+                    m = reinterpret_cast<const Model*>(models[mi]);
+                    break;
+                }
+                acc += k_per_model[mi];
+            }
+        }
+        const int64_t nt = m->n_tiles;
+        const int64_t nu = std::max<int64_t>(1, (nt + tpu - 1) / tpu);
+        jobs[ji].rec0 = (int32_t)units.size();
+        jobs[ji].nrec = (int32_t)nu;
+        for (int64_t u = 0; u < nu; ++u) {
+            pwa::MultiUnit mu{};
+            mu.job = ji;
+            mu.t0 = u * nt / nu;
+            mu.t1 = (u + 1) * nt / nu;
+            units.push_back(mu);
+        }
+        for (int r = 0; r <= jobs[ji].W; ++r) asmb.push_back(pwa::AsmBlock{ji, r});
+    }
+    DeviceGuard g(p->device);
+    const size_t jb = sizeof(pwa::MultiJob) * jobs.size();
+    const size_t ub = sizeof(pwa::MultiUnit) * units.size();
+    const size_t ab = sizeof(pwa::AsmBlock) * asmb.size();
+    HIP_TRY(hipMalloc(&p->d_tables, jb + ub + ab));
+    char* t = (char*)p->d_tables;
+    HIP_TRY(hipMemcpy(t, jobs.data(), jb, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t + jb, units.data(), ub, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t + jb + ub, asmb.data(), ab, hipMemcpyHostToDevice));
+    p->params_bytes = sizeof(double) * (size_t)v_off;
+    HIP_TRY(hipMalloc(&p->d_params, p->params_bytes));
+    HIP_TRY(hipHostMalloc((void**)&p->h_params, p->params_bytes, hipHostMallocDefault));
+    const int rec_stride = 2 + 2 * wmax;
+    HIP_TRY(hipMalloc(&p->d_recs, sizeof(double) * rec_stride * units.size()));
+    HIP_TRY(hipHostMalloc((void**)&p->h_out, sizeof(double) * out_off,
+                          hipHostMallocCoherent | hipHostMallocMapped));
+    HIP_TRY(hipHostMalloc((void**)&p->h_done, sizeof(unsigned long long) * done_off,
+                          hipHostMallocCoherent | hipHostMallocMapped));
+    for (int k = 0; k < done_off; ++k) p->h_done[k] = 0;
+    p->n_done = done_off;
+    pwa::MultiLaunch& ml = p->ml;
+    ml.jobs = (const pwa::MultiJob*)t;
+    ml.units = (const pwa::MultiUnit*)(t + jb);
+    ml.asm_blocks = (const pwa::AsmBlock*)(t + jb + ub);
+    ml.params = p->d_params;
+    ml.recs = p->d_recs;
+    ml.out = p->h_out;
+    ml.done = p->h_done;
+    ml.rec_stride = rec_stride;
+    ml.n_units = (int)units.size();
+    ml.n_asm = (int)asmb.size();
+    ml.wpad_max = wpad_max;
+    ml.waves = waves;
+    HIP_TRY(pwa::amp_multi_prepare(wpad_max));
+    // capture [parameter copy, amplitude kernel, assembly] once
+    HIP_TRY(hipStreamCreate(&p->cap));
+    HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipMemcpyAsync(p->d_params, p->h_params, p->params_bytes, hipMemcpyHostToDevice,
+                                  p->cap);
+    if (e == hipSuccess) e = pwa::launch_amp_multi(ml, p->cap);
+    if (e == hipSuccess) e = pwa::launch_assemble_multi(ml, p->cap);
+    const hipError_t e2 = hipStreamEndCapture(p->cap, &p->graph);
+    if (e != hipSuccess) return device_fail(e, "multi-evaluation capture");
+    if (e2 != hipSuccess) return device_fail(e2, "multi-evaluation capture");
+    HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    *out = p;
+    p = nullptr;   // the guard releases nothing
+    return PWA_OK;
+}
+
+// Run every (model, vector) evaluation of the call through the cached plan.
+int eval_multi(pwa_model* const* models, int n_models, const int32_t* k_per_model,
+               const double* v, double* nll, double* grad, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    bool same = g_plan && (int)g_plan->key.size() == n_models;
+    for (int mi = 0; same && mi < n_models; ++mi)
+        same = g_plan->key[mi].first == reinterpret_cast<const Model*>(models[mi]) &&
+               g_plan->key[mi].second == k_per_model[mi];
+    if (!same) {
+        destroy_plan(g_plan);
+        g_plan = nullptr;
+        const int rc = build_plan(models, n_models, k_per_model, &g_plan);
+        if (rc != PWA_OK) return rc;
+    }
+    MultiPlan* p = g_plan;
+    DeviceGuard g(p->device);
+    const unsigned long long seq = ++p->seq;
+    std::memcpy(p->h_params, &seq, sizeof seq);
+    size_t vpos = 0;
+    for (int j = 0; j < p->n_jobs; ++j) {
+        std::memcpy(p->h_params + p->v_off[j], v + vpos, sizeof(double) * 2 * p->job_w[j]);
+        vpos += 2 * p->job_w[j];
+    }
+    HIP_TRY(hipGraphLaunch(p->exec, s));
+    volatile unsigned long long* done = p->h_done;
+    for (unsigned long it = 1;; ++it) {
+        bool all = true;
+        for (int k = 0; k < p->n_done && all; ++k) all = done[k] == seq;
+        if (all) break;
+        if ((it & 4095) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                bool again = true;
+                for (int k = 0; k < p->n_done && again; ++k) again = done[k] == seq;
+                if (again) break;
+                return fail(PWA_ERR_DEVICE, "evaluation finished without publishing its result");
+            }
+            if (e != hipErrorNotReady) return device_fail(e, "multi-model evaluation");
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    int status = PWA_OK;
+    size_t gpos = 0;
+    for (int j = 0; j < p->n_jobs; ++j) {
+        const double* o = p->h_out + p->out_off[j];
+        nll[j] = o[0];
+        if (grad) std::memcpy(grad + gpos, o + 2, sizeof(double) * 2 * p->job_w[j]);
+        gpos += 2 * p->job_w[j];
+        if (o[1] > 0.0) status = PWA_WARN_DEGENERATE;
+    }
+    return status;
+}
+
+// Discard the cached plan if it refers to model m.
+void forget_model(const Model* m)
+{
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    if (!g_plan) return;
+    for (const auto& kv : g_plan->key)
+        if (kv.first == m) {
+            destroy_plan(g_plan);
+            g_plan = nullptr;
+            return;
+        }
+}
+
 // Per-call buffers of the matrix-core path, grown to hold K vectors.
 int mfma_reserve(Model* m, int K, int n_cb, int chunks)
 {
@@ -559,6 +807,17 @@ int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k
         if (k_per_model[mi] < 0) return fail(PWA_ERR_INVALID, "k_per_model[%d] < 0", mi);
     }
     hipStream_t s = (hipStream_t)hip_stream;
+    if (multi_eligible(models, n_models, k_per_model)) {
+        const double* vq = v;
+        for (int mi = 0; mi < n_models; ++mi) {
+            const int W = reinterpret_cast<const Model*>(models[mi])->W;
+            for (int k = 0; k < k_per_model[mi]; ++k, vq += 2 * W) {
+                const int rc = check_v(vq, W);
+                if (rc != PWA_OK) return rc;
+            }
+        }
+        return eval_multi(models, n_models, k_per_model, v, nll, grad, s);
+    }
     int status = PWA_OK;
     const double* vp = v;
     double* np = nll;
@@ -609,6 +868,8 @@ int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k
 
 void pwa_free(pwa_model* model)
 {
+    if (!model) return;
+    forget_model(reinterpret_cast<const Model*>(model));
     release(reinterpret_cast<Model*>(model));
 }
 

@@ -87,6 +87,39 @@ struct Model {
     int32_t done_cap = 0;           // completion words h_done can hold
 };
 
+// Many evaluations (jobs), possibly of different FP32 amplitude models, in one
+// launch of the amplitude kernel and one of the assembly.  All tables live in
+// device memory; the parameter buffer starts with the completion value (one
+// 8-byte word) followed by each job's V.
+struct MultiJob {
+    const void* amp;            // the model's padded complex64 amplitudes
+    int64_t n_events;
+    int32_t W, wpad;
+    int32_t v_off;              // offset of V in the parameter buffer (doubles)
+    int32_t rec0, nrec;         // the job's records: units rec0 .. rec0 + nrec - 1
+    int32_t out_off;            // offset of [nll, n_bad, grad] in the output (doubles)
+    int32_t done_off;           // first of the job's 1 + W completion words
+    int32_t pad;
+    const double2* M;
+};
+struct MultiUnit {
+    int32_t job, pad;
+    int64_t t0, t1;             // tiles of 64 events
+};
+struct AsmBlock {
+    int32_t job, role;          // role 0: NLL; 1 + b: gradient component b
+};
+struct MultiLaunch {
+    const MultiJob* jobs;
+    const MultiUnit* units;
+    const AsmBlock* asm_blocks;
+    const double* params;
+    double* recs;
+    double* out;                // pinned host
+    unsigned long long* done;   // pinned host
+    int rec_stride, n_units, n_asm, wpad_max, waves;
+};
+
 // One call of the matrix-core path: K vectors, device buffers and outputs.
 struct MfmaBatch {
     const double* v;            // K x 2W (device)
@@ -139,6 +172,10 @@ hipError_t launch_mfma_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
 int mfma_chunks(const Model& m, int n_cb);
 size_t mfma_vm_bytes(const Model& m, int n_cb);
 hipError_t launch_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s);
+hipError_t launch_amp_multi(const MultiLaunch& ml, hipStream_t s);
+hipError_t launch_assemble_multi(const MultiLaunch& ml, hipStream_t s);
+int amp_multi_waves(int wpad_max);
+hipError_t amp_multi_prepare(int wpad_max);
 int assemble_blocks(int W, bool grad);
 
 // occupancy-derived grid sizes
