@@ -146,6 +146,79 @@ def bench_batched(args):
     return out
 
 
+def bench_multi(args):
+    """64 amplitude-form models of uneven size (W uniform in 8..48, N log-uniform
+    in 1e5..4e6, 2N accepted MC each), one NLL+gradient of every model per
+    iteration through one pwa_nll_batched call (one amplitude launch and one
+    assembly, replayed from a captured graph), 500 iterations along a random
+    walk per model; and the same iterations as 64 separate calls."""
+    import torch
+    import paper_1108_5673_amd as pwa
+    from paper_1108_5673_amd import synth
+    sizes = synth.uneven_sizes()
+    t = time.perf_counter()
+    models, keep, v0 = [], {}, []
+    small = sorted(range(len(sizes)), key=lambda i: sizes[i][1])[:2]
+    for i, um in enumerate(synth.uneven_models(sizes)):
+        models.append(pwa.Model(um.data, um.mc, 2 * um.n_acc, form="amplitude"))
+        if i in small and not args.no_cpu_baseline:
+            keep[i] = (um.data.cpu().numpy(), um.mc.cpu().numpy(), 2 * um.n_acc)
+        v0.append(um.v0)
+        del um
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log("built 64 uneven models in %.1f s" % (time.perf_counter() - t))
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([11085673, 64, 2])))
+    iters = 500
+    walk = []
+    cur = [v.copy() for v in v0]
+    for _ in range(iters):
+        cur = [c + 0.01 * (rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape))
+               for c in cur]
+        walk.append(cur)
+    for k in range(5):
+        pwa.nll_batched(models, [w[None, :] for w in walk[k]])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(iters):
+        res = pwa.nll_batched(models, [w[None, :] for w in walk[k]])
+    dt = (time.perf_counter() - t) / iters
+    seq_iters = 50
+    t = time.perf_counter()
+    for k in range(seq_iters):
+        for m, w in zip(models, walk[k]):
+            m.nll_grad(w)
+    dt_seq = (time.perf_counter() - t) / seq_iters
+    n_tot = sum(n for w, n in sizes)
+    bytes_it = sum(m.info()["stream_bytes"] for m in models)
+    out = {"workload": "64 models: W uniform 8..48, N log-uniform 1e5..4e6 (%d events in all), "
+                       "2N accepted MC each, flat synthetic amplitudes; 500 iterations" % n_tot,
+           "iteration_ms": 1e3 * dt, "evals_per_s": 64 / dt,
+           "events_iter_per_s": n_tot / dt, "achieved_gbs": bytes_it / dt / 1e9,
+           "frac_of_8tbs": bytes_it / dt / 8e12, "separate_calls_iteration_ms": 1e3 * dt_seq,
+           "speedup_vs_separate_calls": dt_seq / dt}
+    if keep:
+        import oracle
+        o = oracle.get()
+        last = walk[iters - 1]
+        worst_n, worst_g = 0.0, 0.0
+        for i, (d, mc, n_gen) in keep.items():
+            M = o.mc_matrix(mc.astype(np.complex128), n_gen)
+            rn, rg, _ = o.nll_amp(d.astype(np.complex128), M, last[i])
+            nll, g = res[i][0][0], res[i][1][0]
+            dn = abs(nll - rn) / max(1.0, abs(rn))
+            dg = float(np.linalg.norm(g - rg) / np.linalg.norm(rg))
+            worst_n = max(worst_n, dn if np.isfinite(dn) else np.inf)
+            worst_g = max(worst_g, dg if np.isfinite(dg) else np.inf)
+        out["parity"] = {"models": sorted(keep), "max_rel_dnll": worst_n, "max_rel_grad": worst_g,
+                         "reference": "oracle on the same complex64 amplitudes"}
+    log("multi-model: %.2f ms per iteration of 64 models (%.0f GB/s); separate calls %.2f ms"
+        % (1e3 * dt, bytes_it / dt / 1e9, 1e3 * dt_seq))
+    for m in models:
+        m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +230,8 @@ def main():
     ap.add_argument("--no-baselines", action="store_true", help="time only the fused kernel")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-vector matrix-core measurement")
+    ap.add_argument("--no-multi", action="store_true",
+                    help="skip the 64-model batch measurement")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -236,6 +311,9 @@ def main():
     batched = None
     if not args.no_batched:
         batched = bench_batched(args)
+    multi = None
+    if not args.no_multi:
+        multi = bench_multi(args)
 
     achieved = info["stream_bytes"] / (f["kernel_ms"] * 1e-3) / 1e9
     traffic = measured_traffic()
@@ -300,6 +378,7 @@ def main():
         "prefit": prefit,
         "fit": fit_info,
         "batched_k256": batched,
+        "multi_model_64": multi,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -8,8 +8,11 @@
 //   1. coalesced 16-byte loads of the tile's contiguous 512*wpad bytes into LDS
 //      (rows padded in LDS so that the per-event reads below hit distinct banks);
 //   2. lane = event: S_i, I_i, ln I_i and c_i = S_i / I_i in FP64;
-//   3. lane = wave a: g_a += c_i conj(A_ia) over the tile's 64 events, reading
-//      the tile from LDS, so the amplitudes leave HBM once per evaluation.
+//   3. g_a += c_i conj(A_ia) over the tile's 64 events, reading the tile from
+//      LDS (so the amplitudes leave HBM once per evaluation): for W <= 64 the
+//      lanes are G = 64 / W groups of W, group q taking events q, q + G, ...,
+//      and the groups are added in order at the end; beyond 64 waves,
+//      lane = wave.
 // Each block writes one partial record [sum ln I, n_bad, g_0, ..., g_{W-1}];
 // the gradient is G_b = 2 sum_a V_a M_ab - 2 g_b.
 #include <hip/hip_runtime.h>
@@ -76,6 +79,10 @@ __device__ void amp_block(const float4* __restrict__ amp, int64_t n_events, int6
     for (int s = 0; s < KW; ++s) { gr[s] = 0.0; gi[s] = 0.0; }
     double dsum = 0.0;
     int nbad = 0;
+    // adjoint lane mapping for W <= 64: G = 64 / W event groups of W lanes
+    const int G = KW == 1 ? 64 / W : 1;
+    const int a_lane = KW == 1 ? lane % W : lane;
+    const int grp = KW == 1 ? lane / W : 0;
 
     // the block's tiles, interleaved over its wavefronts; each wavefront uses
     // only its own LDS region, so it synchronises with itself only
@@ -111,17 +118,46 @@ __device__ void amp_block(const float4* __restrict__ amp, int64_t n_events, int6
             const double w = ok ? 1.0 / I : (valid ? NAN : 0.0);
             s_cw[lane] = make_double2(w * sr, w * si);
             wave_lds_sync();
-            // lane = wave
-            for (int l = 0; l < kAmpTile; ++l) {
-                const double2 c = s_cw[l];
-                const float2* rl = reinterpret_cast<const float2*>(tile + l * stride);
+            if (KW == 1) {
+                // lane = (wave a, event group grp): events grp, grp + G, ...,
+                // four at a time with separate partial sums so that the LDS
+                // reads are in flight together
+                if (grp < G) {   // the 64 - G W lanes beyond the groups idle
+                    double pr[4] = {0.0, 0.0, 0.0, 0.0}, pi[4] = {0.0, 0.0, 0.0, 0.0};
+                    int l = grp;
+                    for (; l + 3 * G < kAmpTile; l += 4 * G) {
 #pragma unroll
-                for (int s = 0; s < KW; ++s) {
-                    const int a = lane + 64 * s;
-                    if (a < W) {
-                        const float2 x = rl[a];
-                        gr[s] += c.x * (double)x.x + c.y * (double)x.y;
-                        gi[s] += c.y * (double)x.x - c.x * (double)x.y;
+                        for (int q = 0; q < 4; ++q) {
+                            const double2 c = s_cw[l + q * G];
+                            const float2 x = *reinterpret_cast<const float2*>(
+                                tile + (l + q * G) * stride + a_lane * 8);
+                            pr[q] += c.x * (double)x.x + c.y * (double)x.y;
+                            pi[q] += c.y * (double)x.x - c.x * (double)x.y;
+                        }
+                    }
+                    for (; l < kAmpTile; l += G) {
+                        const double2 c = s_cw[l];
+                        const float2 x =
+                            *reinterpret_cast<const float2*>(tile + l * stride + a_lane * 8);
+                        pr[0] += c.x * (double)x.x + c.y * (double)x.y;
+                        pi[0] += c.y * (double)x.x - c.x * (double)x.y;
+                    }
+                    gr[0] += (pr[0] + pr[1]) + (pr[2] + pr[3]);
+                    gi[0] += (pi[0] + pi[1]) + (pi[2] + pi[3]);
+                }
+            } else {
+                // lane = wave (two per lane beyond 64 waves)
+                for (int l = 0; l < kAmpTile; ++l) {
+                    const double2 c = s_cw[l];
+                    const float2* rl = reinterpret_cast<const float2*>(tile + l * stride);
+#pragma unroll
+                    for (int s = 0; s < KW; ++s) {
+                        const int a = lane + 64 * s;
+                        if (a < W) {
+                            const float2 x = rl[a];
+                            gr[s] += c.x * (double)x.x + c.y * (double)x.y;
+                            gi[s] += c.y * (double)x.x - c.x * (double)x.y;
+                        }
                     }
                 }
             }
@@ -132,6 +168,27 @@ __device__ void amp_block(const float4* __restrict__ amp, int64_t n_events, int6
     // combine the block's wavefronts in a fixed order (reusing wave 0's tile)
     dsum = wave_allsum(dsum);
     nbad = wave_allsum_int(nbad);
+    if (KW == 1 && GRAD) {
+        // fold the event groups of each wave a into lane a, in group order,
+        // through this wavefront's own tile region
+        double2* s_fold = reinterpret_cast<double2*>(tile);
+        wave_lds_sync();
+        s_fold[lane] = make_double2(gr[0], gi[0]);
+        wave_lds_sync();
+        if (lane < W) {
+            double xr = 0.0, xi = 0.0;
+            for (int q = 0; q < G; ++q) {
+                xr += s_fold[q * W + lane].x;
+                xi += s_fold[q * W + lane].y;
+            }
+            gr[0] = xr;
+            gi[0] = xi;
+        } else {
+            gr[0] = 0.0;
+            gi[0] = 0.0;
+        }
+        wave_lds_sync();
+    }
     __syncthreads();
     double2* s_g = reinterpret_cast<double2*>(lds + (size_t)wpad * 16);
     double* s_misc = reinterpret_cast<double*>(s_g + 2 * 64);   // after KW <= 2 slots of 64
@@ -184,34 +241,47 @@ template <int KW>
 __global__ __launch_bounds__(256) void k_amp_multi(const MultiJob* __restrict__ jobs,
                                                    const MultiUnit* __restrict__ units,
                                                    const double* __restrict__ params,
-                                                   double* __restrict__ recs, int rec_stride)
+                                                   double* __restrict__ recs, int rec_stride,
+                                                   int unit_off)
 {
-    const MultiUnit u = units[blockIdx.x];
+    const int u_idx = unit_off + blockIdx.x;
+    const MultiUnit u = units[u_idx];
     const MultiJob j = jobs[u.job];
     amp_block<KW, true>((const float4*)j.amp, j.n_events, u.t0, u.t1, j.W, j.wpad,
-                        params + j.v_off, recs + (int64_t)blockIdx.x * rec_stride);
+                        params + j.v_off, recs + (int64_t)u_idx * rec_stride);
+}
+
+// width classes: rows of at most 16, 32, 48, 64 and 128 waves
+int amp_multi_class(int wpad)
+{
+    return wpad <= 16 ? 0 : wpad <= 32 ? 1 : wpad <= 48 ? 2 : wpad <= 64 ? 3 : 4;
 }
 
 hipError_t launch_amp_multi(const MultiLaunch& ml, hipStream_t s)
 {
-    const size_t lds = amp_lds_bytes(ml.wpad_max, ml.waves);
-    const dim3 grid(ml.n_units), block(64 * ml.waves);
-    if (ml.wpad_max <= 64)
-        hipLaunchKernelGGL((k_amp_multi<1>), grid, block, lds, s, ml.jobs, ml.units, ml.params,
-                           ml.recs, ml.rec_stride);
-    else
-        hipLaunchKernelGGL((k_amp_multi<2>), grid, block, lds, s, ml.jobs, ml.units, ml.params,
-                           ml.recs, ml.rec_stride);
-    return hipGetLastError();
+    for (int c = 0; c < ml.n_classes; ++c) {
+        const MultiClass& k = ml.cls[c];
+        if (k.n_units == 0) continue;
+        const int waves = amp_waves_per_block(k.wpad);
+        const size_t lds = amp_lds_bytes(k.wpad, waves);
+        const dim3 grid(k.n_units), block(64 * waves);
+        if (k.wpad <= 64)
+            hipLaunchKernelGGL((k_amp_multi<1>), grid, block, lds, s, ml.jobs, ml.units, ml.params,
+                               ml.recs, ml.rec_stride, k.unit_off);
+        else
+            hipLaunchKernelGGL((k_amp_multi<2>), grid, block, lds, s, ml.jobs, ml.units, ml.params,
+                               ml.recs, ml.rec_stride, k.unit_off);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-int amp_multi_waves(int wpad_max) { return amp_waves_per_block(wpad_max); }
+int amp_multi_waves(int wpad) { return amp_waves_per_block(wpad); }
 
-size_t amp_multi_lds(int wpad_max) { return amp_lds_bytes(wpad_max, amp_waves_per_block(wpad_max)); }
-
-hipError_t amp_multi_prepare(int wpad_max)
+hipError_t amp_multi_prepare(int wpad)
 {
-    const size_t lds = amp_multi_lds(wpad_max);
+    const size_t lds = amp_lds_bytes(wpad, amp_waves_per_block(wpad));
     if (lds > 65536) {
         const void* fns[] = {(const void*)&k_amp_multi<1>, (const void*)&k_amp_multi<2>};
         for (const void* f : fns) {

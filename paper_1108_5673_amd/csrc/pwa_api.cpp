@@ -482,8 +482,9 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
         }
     }
     p->n_jobs = (int)jobs.size();
-    const int waves = pwa::amp_multi_waves(wpad_max);
-    const int64_t tpu = std::max<int64_t>(2 * waves, (total_tiles + 2047) / 2048);
+    const int64_t tpu = std::max<int64_t>(8, (total_tiles + 2047) / 2048);
+    // units grouped by width class: class c's units are contiguous
+    std::vector<std::vector<pwa::MultiUnit>> by_class(pwa::kMultiClasses);
     for (int ji = 0; ji < p->n_jobs; ++ji) {
         const Model* m = nullptr;
         {
@@ -498,16 +499,36 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
         }
         const int64_t nt = m->n_tiles;
         const int64_t nu = std::max<int64_t>(1, (nt + tpu - 1) / tpu);
-        jobs[ji].rec0 = (int32_t)units.size();
+        std::vector<pwa::MultiUnit>& cu = by_class[pwa::amp_multi_class(m->wpad)];
+        jobs[ji].rec0 = (int32_t)cu.size();   // offset within its class for now
         jobs[ji].nrec = (int32_t)nu;
         for (int64_t u = 0; u < nu; ++u) {
             pwa::MultiUnit mu{};
             mu.job = ji;
             mu.t0 = u * nt / nu;
             mu.t1 = (u + 1) * nt / nu;
-            units.push_back(mu);
+            cu.push_back(mu);
         }
         for (int r = 0; r <= jobs[ji].W; ++r) asmb.push_back(pwa::AsmBlock{ji, r});
+    }
+    pwa::MultiLaunch& ml = p->ml;
+    ml.n_classes = pwa::kMultiClasses;
+    std::vector<int> class_off(pwa::kMultiClasses, 0);
+    for (int c = 0; c < pwa::kMultiClasses; ++c) {
+        class_off[c] = (int)units.size();
+        int wpc = 2;
+        for (const auto& mu : by_class[c]) wpc = std::max<int>(wpc, jobs[mu.job].wpad);
+        ml.cls[c] = pwa::MultiClass{(int)units.size(), (int)by_class[c].size(), wpc};
+        units.insert(units.end(), by_class[c].begin(), by_class[c].end());
+    }
+    for (int ji = 0; ji < p->n_jobs; ++ji) {
+        int w = 0;
+        for (int mi = 0, acc = 0; mi < n_models; acc += k_per_model[mi], ++mi)
+            if (ji < acc + k_per_model[mi]) {
+                w = reinterpret_cast<const Model*>(models[mi])->wpad;
+                break;
+            }
+        jobs[ji].rec0 += class_off[pwa::amp_multi_class(w)];
     }
     DeviceGuard g(p->device);
     const size_t jb = sizeof(pwa::MultiJob) * jobs.size();
@@ -529,7 +550,6 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
                           hipHostMallocCoherent | hipHostMallocMapped));
     for (int k = 0; k < done_off; ++k) p->h_done[k] = 0;
     p->n_done = done_off;
-    pwa::MultiLaunch& ml = p->ml;
     ml.jobs = (const pwa::MultiJob*)t;
     ml.units = (const pwa::MultiUnit*)(t + jb);
     ml.asm_blocks = (const pwa::AsmBlock*)(t + jb + ub);
@@ -540,9 +560,8 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
     ml.rec_stride = rec_stride;
     ml.n_units = (int)units.size();
     ml.n_asm = (int)asmb.size();
-    ml.wpad_max = wpad_max;
-    ml.waves = waves;
-    HIP_TRY(pwa::amp_multi_prepare(wpad_max));
+    for (int c = 0; c < ml.n_classes; ++c)
+        if (ml.cls[c].n_units > 0) HIP_TRY(pwa::amp_multi_prepare(ml.cls[c].wpad));
     // capture [parameter copy, amplitude kernel, assembly] once
     HIP_TRY(hipStreamCreate(&p->cap));
     HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));

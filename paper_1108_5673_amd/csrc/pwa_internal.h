@@ -109,6 +109,12 @@ struct MultiUnit {
 struct AsmBlock {
     int32_t job, role;          // role 0: NLL; 1 + b: gradient component b
 };
+// Units are grouped by row width so that each group's launch sizes its LDS
+// (and so its occupancy) for its own rows.
+constexpr int kMultiClasses = 5;
+struct MultiClass {
+    int unit_off, n_units, wpad;
+};
 struct MultiLaunch {
     const MultiJob* jobs;
     const MultiUnit* units;
@@ -117,7 +123,9 @@ struct MultiLaunch {
     double* recs;
     double* out;                // pinned host
     unsigned long long* done;   // pinned host
-    int rec_stride, n_units, n_asm, wpad_max, waves;
+    int rec_stride, n_units, n_asm;
+    int n_classes;
+    MultiClass cls[kMultiClasses];
 };
 
 // One call of the matrix-core path: K vectors, device buffers and outputs.
@@ -174,8 +182,9 @@ size_t mfma_vm_bytes(const Model& m, int n_cb);
 hipError_t launch_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s);
 hipError_t launch_amp_multi(const MultiLaunch& ml, hipStream_t s);
 hipError_t launch_assemble_multi(const MultiLaunch& ml, hipStream_t s);
-int amp_multi_waves(int wpad_max);
-hipError_t amp_multi_prepare(int wpad_max);
+int amp_multi_waves(int wpad);
+hipError_t amp_multi_prepare(int wpad);
+int amp_multi_class(int wpad);
 int assemble_blocks(int W, bool grad);
 
 // occupancy-derived grid sizes

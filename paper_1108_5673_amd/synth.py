@@ -239,3 +239,62 @@ def small_sample(n_waves: int, n_data: int, n_mc: int, seed: int, n_points: int 
     pts = random_v(rng, n_waves, n_points)
     wl = Workload("small", -1, n_waves, n_data, n_mc, n_mc, n_points, "random", ws)
     return Sample(wl, pts[0].copy(), data, mc, n_mc, pts)
+
+
+# ---- the uneven multi-model batch ---------------------------------------------
+@dataclasses.dataclass
+class UnevenModel:
+    n_waves: int
+    n_data: int
+    n_acc: int
+    data: object               # (n_data, W) complex64, torch tensor on the device
+    mc: object                 # (n_acc, W) complex64, torch tensor on the device
+    v0: np.ndarray             # (W,) complex128 starting point
+
+
+def uneven_sizes(n_models: int = 64, seed: int = 4, w_range=(8, 48), n_range=(100_000, 4_000_000)):
+    """(W, N) of each model: W uniform on the integers of w_range, N
+    log-uniform on n_range (seeded)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE, seed])))
+    ws = rng.integers(w_range[0], w_range[1] + 1, n_models)
+    ns = np.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1]), n_models)).astype(np.int64)
+    return [(int(w), int(n)) for w, n in zip(ws, ns)]
+
+
+def amplitudes_torch(m, cos_g, cos_k, waves: WaveSet):
+    """`amplitudes` for torch float64 kinematics (any device), complex64 out;
+    spins 0 and 2."""
+    import torch
+    photon = torch.sqrt((1.0 + cos_g * cos_g) / 2.0)
+    ang = {0: photon, 2: (1.5 * cos_k * cos_k - 0.5) * photon}
+    out = torch.empty((m.shape[0], waves.n_waves), dtype=torch.complex64, device=m.device)
+    for a, (mass, width, spin) in enumerate(zip(waves.masses, waves.widths, waves.spins)):
+        den = torch.complex(mass * mass - m * m, torch.full_like(m, -mass * width))
+        out[:, a] = (ang[spin] / den).to(torch.complex64)
+    return out
+
+
+def _amplitudes_torch(n: int, waves: WaveSet, gen, device):
+    """Amplitudes of n flat events drawn with the torch generator `gen`."""
+    import torch
+    u = torch.rand((3, n), generator=gen, device=device, dtype=torch.float64)
+    m = M_RANGE[0] + (M_RANGE[1] - M_RANGE[0]) * u[0]
+    return amplitudes_torch(m, 2.0 * u[1] - 1.0, 2.0 * u[2] - 1.0, waves)
+
+
+def uneven_models(sizes, mc_per_event: float = 2.0, seed: int = 4, device="cuda"):
+    """Flat synthetic samples for the multi-model batch, one model at a time
+    (a generator, so that only one model's MC is held at once): model k has W_k waves
+    (the wave-list rule), N_k data events and mc_per_event * N_k accepted MC
+    events, all drawn on the device with a seeded torch generator (the data
+    are flat in phase space, not accept-reject: only their shape matters for a
+    throughput measurement).  Spin factors are the Legendre P_0 = 1 and P_2."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(SEED_BASE + 1000 * seed)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE, seed, 1])))
+    for w, n in sizes:
+        ws = wave_set(w)
+        n_acc = int(mc_per_event * n)
+        yield UnevenModel(w, n, n_acc, _amplitudes_torch(n, ws, gen, device),
+                          _amplitudes_torch(n_acc, ws, gen, device), random_v(rng, w))

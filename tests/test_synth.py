@@ -63,3 +63,24 @@ def test_random_walk_steps():
     assert np.array_equal(walk[0], v0)
     step = np.abs(np.diff(walk, axis=0))
     assert 0.003 < step.mean() < 0.03
+
+
+def test_torch_amplitudes_match_numpy():
+    import torch
+    rng = np.random.default_rng(8)
+    m, cg, ck = synth.phase_space(rng, 500)
+    for w in (1, 8, 21):
+        ws = synth.wave_set(w)
+        a_np = synth.amplitudes((m, cg, ck), ws)
+        a_t = synth.amplitudes_torch(torch.from_numpy(m), torch.from_numpy(cg),
+                                     torch.from_numpy(ck), ws).numpy()
+        np.testing.assert_allclose(a_t, a_np.astype(np.complex64), rtol=2e-7, atol=1e-7)
+
+
+def test_uneven_sizes():
+    sizes = synth.uneven_sizes()
+    assert len(sizes) == 64
+    ws = np.array([w for w, n in sizes])
+    ns = np.array([n for w, n in sizes])
+    assert ws.min() >= 8 and ws.max() <= 48 and ns.min() >= 100_000 and ns.max() <= 4_000_000
+    assert sizes == synth.uneven_sizes()          # seeded
