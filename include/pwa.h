@@ -153,6 +153,22 @@ int pwa_nll_grad(const pwa_model* model, const double* v, double* nll, double* g
 int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k_per_model,
                     const double* v, double* nll, double* grad, void* hip_stream);
 
+/*
+ * pwa_nll_grad_hess -- NLL, gradient and the FUMILI second-derivative matrix
+ * in one call (the paper's fits use FUMILI with analytic derivatives and ship
+ * likelihood, gradient and this matrix per iteration, Sec. 5).  Amplitude form
+ * (PWA_FORM_AMPLITUDE) only.
+ *
+ *   hess  2W x 2W doubles, row-major, over theta = (Re V_0, Im V_0, Re V_1, ...):
+ *         H = sum_i J_i J_i^T + d2mu/dtheta2, with J_i = grad_theta ln I_i (the
+ *         outer-product form FUMILI uses for the data term, in FP64) and the
+ *         exact Hessian of the MC term mu, a quadratic form: for waves a, a'
+ *         the 2 x 2 block is 2 [[Re M_aa', Im M_aa'], [-Im M_aa', Re M_aa']].
+ * Degenerate events: as pwa_nll_grad, and hess is NaN.
+ */
+int pwa_nll_grad_hess(const pwa_model* model, const double* v, double* nll, double* grad,
+                      double* hess, void* hip_stream);
+
 /* pwa_free -- release a model and all device memory it owns.  NULL is ignored. */
 void pwa_free(pwa_model* model);
 

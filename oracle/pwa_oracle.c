@@ -323,3 +323,72 @@ int64_t oracle_nll_amp(const double* Ari, int64_t N, int32_t W, const double* Mr
     free(dpart); free(gpart); free(bad);
     return nbad;
 }
+
+/* ---- FUMILI-style second derivatives ---------------------------------
+ * The paper's fits use FUMILI with analytic gradients and Hessian (Sec. 5).
+ * For a likelihood, FUMILI replaces the Hessian of -ln L by the sum of outer
+ * products of the per-event gradients of ln f (the second-derivative terms of
+ * f are dropped); the normalisation term of the extended likelihood, mu, is a
+ * quadratic form and enters with its exact Hessian.  With theta = (Re V_0,
+ * Im V_0, Re V_1, ...):
+ *   dI_i/dRe V_b = 2 Re(conj(S_i) A_ib),  dI_i/dIm V_b = -2 Im(conj(S_i) A_ib)
+ *   J_i = grad_theta ln I_i = grad_theta I_i / I_i
+ *   H_D = sum_i J_i J_i^T
+ *   mu  = sum_a,a' (x_a x_a' + y_a y_a') Re M_aa' + 2 sum_a,a' x_a y_a' Im M_aa'
+ *         (V_a = x_a + i y_a), so d2mu/dtheta2 = 2 Q with
+ *         Q[(a,re),(a',re)] = Q[(a,im),(a',im)] = Re M_aa',
+ *         Q[(a,re),(a',im)] = Q[(a',im),(a,re)] = Im M_aa'.
+ * oracle_fumili_amp fills H (2W x 2W, row-major) with H_D + 2 Q and returns
+ * the number of degenerate events (then H is NaN).  Per chunk and entry the
+ * event sums are compensated, chunks added in order.
+ */
+int64_t oracle_fumili_amp(const double* Ari, int64_t N, int32_t W, const double* Mri,
+                          const double* Vri, double* H)
+{
+    const cplx* A = (const cplx*)Ari;
+    const cplx* V = (const cplx*)Vri;
+    const cplx* M = (const cplx*)Mri;
+    const int32_t P = 2 * W;
+    const int64_t nc = n_chunks(N);
+    nsum* hpart = calloc((size_t)(nc > 0 ? nc : 1) * P * P, sizeof(nsum));
+    int64_t* bad = calloc((size_t)(nc > 0 ? nc : 1), sizeof(int64_t));
+
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t i1 = (c + 1) * ORACLE_CHUNK < N ? (c + 1) * ORACLE_CHUNK : N;
+        double* J = malloc(sizeof(double) * P);
+        nsum* h = hpart + c * P * P;
+        for (int64_t i = c * ORACLE_CHUNK; i < i1; ++i) {
+            cplx s = 0;
+            for (int32_t a = 0; a < W; ++a) s += V[a] * A[i * W + a];
+            double Ii = creal(s) * creal(s) + cimag(s) * cimag(s);
+            if (!(Ii > 0.0) || !isfinite(Ii)) { bad[c]++; continue; }
+            for (int32_t b = 0; b < W; ++b) {
+                cplx z = conj(s) * A[i * W + b];
+                J[2 * b] = 2.0 * creal(z) / Ii;
+                J[2 * b + 1] = -2.0 * cimag(z) / Ii;
+            }
+            for (int32_t p = 0; p < P; ++p)
+                for (int32_t q = 0; q < P; ++q) nsum_add(&h[p * P + q], J[p] * J[q]);
+        }
+        free(J);
+    }
+    int64_t nbad = 0;
+    for (int64_t c = 0; c < nc; ++c) nbad += bad[c];
+    for (int32_t p = 0; p < P; ++p)
+        for (int32_t q = 0; q < P; ++q) {
+            nsum t = {0, 0};
+            for (int64_t c = 0; c < nc; ++c) nsum_add(&t, nsum_value(&hpart[c * P * P + p * P + q]));
+            /* the exact Hessian of mu */
+            const int32_t a = p / 2, ap = q / 2;
+            const int pim = p % 2, qim = q % 2;
+            double Qpq;
+            if (pim == qim) Qpq = creal(M[a * W + ap]);
+            else if (pim == 0) Qpq = cimag(M[a * W + ap]);     /* (a,re),(a',im) */
+            else Qpq = cimag(M[ap * W + a]);                    /* (a,im),(a',re) */
+            H[p * P + q] = nbad > 0 ? NAN : nsum_value(&t) + 2.0 * Qpq;
+        }
+    free(hpart);
+    free(bad);
+    return nbad;
+}

@@ -161,6 +161,19 @@ class Model:
         return out.value, g
 
     # -- inspection ---------------------------------------------------------
+    def nll_grad_hess(self, v):
+        """(NLL, gradient (2W,), FUMILI matrix (2W, 2W)); amplitude form."""
+        va = _v_array(v, self.n_waves)
+        out = ctypes.c_double(0.0)
+        g = np.zeros(2 * self.n_waves, np.float64)
+        h = np.zeros((2 * self.n_waves, 2 * self.n_waves), np.float64)
+        st = _native.check(_native.lib().pwa_nll_grad_hess(self._handle(), va.ctypes.data,
+                                                           ctypes.byref(out), g.ctypes.data,
+                                                           h.ctypes.data, self._stream))
+        if st == _native.PWA_WARN_DEGENERATE:
+            warnings.warn("degenerate event (I <= 0): NLL is +inf, gradient and matrix NaN")
+        return out.value, g, h
+
     def info(self) -> dict:
         inf = _native.Info()
         _native.check(_native.lib().pwa_model_info(self._handle(), ctypes.byref(inf)))

@@ -33,7 +33,7 @@ EXPORTED = (
     "pwa_build_table", "pwa_nll", "pwa_nll_grad", "pwa_nll_batched", "pwa_free",
     "pwa_last_error", "pwa_model_info", "pwa_copy_table", "pwa_copy_mc_matrix",
     "pwa_set_mc_matrix", "pwa_set_timing", "pwa_get_timing", "pwa_build_timing",
-    "pwa_lbfgs_default_options", "pwa_lbfgs_minimize", "pwa_fit_lbfgs",
+    "pwa_lbfgs_default_options", "pwa_lbfgs_minimize", "pwa_fit_lbfgs", "pwa_nll_grad_hess",
 )
 
 PWA_LBFGS_CONVERGED_GRADIENT = 0
@@ -105,6 +105,7 @@ def _declare(L):
     L.pwa_build_table.argtypes = [p, i64, i32, p, i64, i64, u32, p, ctypes.POINTER(p)]
     L.pwa_nll.argtypes = [p, p, dp, p]
     L.pwa_nll_grad.argtypes = [p, p, dp, p, p]
+    L.pwa_nll_grad_hess.argtypes = [p, p, dp, p, p, p]
     L.pwa_nll_batched.argtypes = [p, i32, p, p, p, p, p]
     L.pwa_free.argtypes = [p]
     L.pwa_free.restype = None

@@ -17,7 +17,10 @@
 // the gradient is G_b = 2 sum_a V_a M_ab - 2 g_b.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "pwa_internal.h"
+#include "tail.h"
 #include "wave_ops.h"
 
 namespace pwa {
@@ -377,6 +380,249 @@ hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, int
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_pack_amp, dim3((int)g), dim3(256), 0, s, src, src_c128, n, W, wpad,
                        total, (float2*)dst);
+    return hipGetLastError();
+}
+
+}  // namespace pwa
+
+namespace pwa {
+
+// ---- FUMILI second derivatives (amplitude form) ----------------------------
+// H_D = sum_i J_i J_i^T over theta = (Re V_0, Im V_0, Re V_1, ...), with
+// J_i = grad_theta ln I_i = 2 [Re z_ib, -Im z_ib]_b / I_i and z_ib = conj(S_i) A_ib
+// (the derivative of Eq. 1).  Per block, tiles of 64 events:
+//   1. the tile's amplitudes into LDS (coalesced 16-byte loads);
+//   2. wavefront 0, lane = event: S_i and w_i = 1 / I_i in FP64;
+//   3. all threads: J_i into LDS as a 64 x PJ array (PJ = 2W rounded up to 4);
+//   4. thread t: the 4 x 4 blocks (bp, bq), bp <= bq, numbered t % npair, over
+//      the events of its split t / npair (splits of the 64 events when fewer
+//      than 256 pairs), 16 FP64 accumulators per block.
+// Record per block: [n_bad, then 16 doubles per block pair].
+constexpr int kHessThreads = 256;
+
+__host__ __device__ inline int hess_pj(int W) { return (2 * W + 3) / 4 * 4; }
+__host__ __device__ inline int hess_npair(int W)
+{
+    const int nb = hess_pj(W) / 4;
+    return nb * (nb + 1) / 2;
+}
+__host__ __device__ inline int hess_rec_len(int W) { return 1 + 16 * hess_npair(W); }
+__host__ __device__ inline size_t hess_lds_bytes(int wpad)
+{
+    const int W = wpad;   // upper bound of the wave count
+    const size_t main = (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4   // amplitude tile
+                        + (size_t)kAmpTile * hess_pj(W) * 8                  // J
+                        + (size_t)kAmpTile * 16 + (size_t)kAmpTile * 8       // S, w
+                        + 16;                                                // n_bad
+    const size_t combine = (size_t)kHessThreads * 16 * 8;   // partial blocks at the end
+    return (main > combine ? main : combine) + 16;
+}
+
+__global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __restrict__ amp,
+                                                              int64_t n_events, int64_t n_tiles,
+                                                              int W, int wpad, VParams vp,
+                                                              double* __restrict__ recs)
+{
+    extern __shared__ double lds_d[];
+    char* lds = reinterpret_cast<char*>(lds_d);
+    const int stride = amp_lds_stride_words(wpad) * 4;
+    const int PJ = hess_pj(W);
+    const int nb = PJ / 4;
+    const int npair = nb * (nb + 1) / 2;
+    char* tile = lds;
+    double* s_J = reinterpret_cast<double*>(tile + (size_t)kAmpTile * stride);
+    double2* s_S = reinterpret_cast<double2*>(s_J + (size_t)kAmpTile * PJ);
+    double* s_w = reinterpret_cast<double*>(s_S + kAmpTile);
+    // the count sits past both the tile data and the combine area
+    int* s_bad = reinterpret_cast<int*>(lds + hess_lds_bytes(wpad) - 16);
+    const int h = wpad >> 1;
+    const int tid = threadIdx.x;
+
+    // this thread's block pairs and event split
+    const int splits = npair >= kHessThreads ? 1 : kHessThreads / npair;
+    const int split = tid / (npair < kHessThreads ? npair : kHessThreads);
+    const int pair0 = tid % (npair < kHessThreads ? npair : kHessThreads);
+    const bool active = split < splits;
+    constexpr int kMaxPairs = 3;   // pairs per thread: npair <= 3 * 256 (W <= 64)
+    double acc[kMaxPairs][16];
+    int bp[kMaxPairs], bq[kMaxPairs];
+#pragma unroll
+    for (int r = 0; r < kMaxPairs; ++r) {
+        const int pr = pair0 + r * kHessThreads;
+        bp[r] = bq[r] = -1;
+        if (active && (r == 0 || npair > kHessThreads) && pr < npair) {
+            // pair index -> (bp, bq), row-major upper triangle
+            int rem = pr, row = 0;
+            while (rem >= nb - row) {
+                rem -= nb - row;
+                ++row;
+            }
+            bp[r] = row;
+            bq[r] = row + rem;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[r][k] = 0.0;
+    }
+    if (tid == 0) *s_bad = 0;
+
+    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
+    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
+    for (int64_t t = t0; t < t1; ++t) {
+        const float4* src = amp + t * kAmpTile * h;
+        for (int f = tid; f < kAmpTile * h; f += blockDim.x) {
+            const int ev = f / h, c = f - ev * h;
+            *reinterpret_cast<float4*>(tile + ev * stride + c * 16) = src[f];
+        }
+        __syncthreads();
+        if (tid < kAmpTile) {
+            const char* row = tile + tid * stride;
+            double sr = 0.0, si = 0.0;
+            for (int a = 0; a < W; ++a) {
+                const float2 x = *reinterpret_cast<const float2*>(row + a * 8);
+                const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
+                sr += vr * (double)x.x - vi * (double)x.y;
+                si += vr * (double)x.y + vi * (double)x.x;
+            }
+            const double I = sr * sr + si * si;
+            const bool valid = t * kAmpTile + tid < n_events;
+            const bool ok = valid && (I > 0.0) && (I < INFINITY);
+            if (valid && !ok) atomicAdd(s_bad, 1);   // LDS count, order-free
+            s_S[tid] = make_double2(sr, si);
+            // NaN for a degenerate event (its J, and so H, become NaN), 0 for padding
+            s_w[tid] = ok ? 2.0 / I : (valid ? NAN : 0.0);
+        }
+        __syncthreads();
+        for (int f = tid; f < kAmpTile * PJ; f += blockDim.x) {
+            const int ev = f / PJ, p = f - ev * PJ;
+            double j = 0.0;
+            if (p < 2 * W) {
+                const int b = p >> 1;
+                const float2 x = *reinterpret_cast<const float2*>(tile + ev * stride + b * 8);
+                const double2 S = s_S[ev];
+                // z = conj(S) A_b
+                const double zr = S.x * (double)x.x + S.y * (double)x.y;
+                const double zi = S.x * (double)x.y - S.y * (double)x.x;
+                j = s_w[ev] * ((p & 1) ? -zi : zr);
+            }
+            s_J[f] = j;
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int r = 0; r < kMaxPairs; ++r) {
+                if (bp[r] < 0) continue;
+                for (int ev = split; ev < kAmpTile; ev += splits) {
+                    const double* Jr = s_J + ev * PJ;
+                    const double2 a01 = *reinterpret_cast<const double2*>(Jr + 4 * bp[r]);
+                    const double2 a23 = *reinterpret_cast<const double2*>(Jr + 4 * bp[r] + 2);
+                    const double2 b01 = *reinterpret_cast<const double2*>(Jr + 4 * bq[r]);
+                    const double2 b23 = *reinterpret_cast<const double2*>(Jr + 4 * bq[r] + 2);
+                    const double ai[4] = {a01.x, a01.y, a23.x, a23.y};
+                    const double bj[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) acc[r][4 * i + j] += ai[i] * bj[j];
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // combine the event splits of each pair in split order, write the record
+    double* rec = recs + (int64_t)blockIdx.x * hess_rec_len(W);
+    double* s_part = reinterpret_cast<double*>(lds);   // reuses the tile area
+    for (int r = 0; r < kMaxPairs; ++r) {
+        if (r > 0 && npair <= kHessThreads) break;
+        __syncthreads();
+        if (active && bp[r] >= 0)
+            for (int k = 0; k < 16; ++k) s_part[(size_t)tid * 16 + k] = acc[r][k];
+        __syncthreads();
+        const int base = r * kHessThreads;
+        const int np_here = min(npair - base, kHessThreads);
+        for (int e = tid; e < np_here * 16; e += blockDim.x) {
+            const int pr = e / 16, k = e % 16;
+            double x = 0.0;
+            for (int sp = 0; sp < splits; ++sp) x += s_part[(size_t)(sp * npair + pr) * 16 + k];
+            rec[1 + (size_t)(base + pr) * 16 + k] = x;
+        }
+    }
+    if (tid == 0) rec[0] = (double)*s_bad;
+}
+
+// Sum of the block records and the exact MC part 2 Q; one thread per entry of
+// the 2W x 2W matrix (full, row-major), written to pinned host memory.
+__global__ __launch_bounds__(256) void k_hess_assemble(const double* __restrict__ recs, int rows,
+                                                       int W, const double2* __restrict__ M,
+                                                       double* out, unsigned long long* done,
+                                                       unsigned long long seq)
+{
+    const int P = 2 * W;
+    const int rl = hess_rec_len(W);
+    const int nb = hess_pj(W) / 4;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < P * P) {
+        int p = e / P, q = e % P;
+        const int a = p / 2, ap = q / 2, pim = p % 2, qim = q % 2;
+        double Qpq;
+        if (pim == qim) Qpq = M[a * W + ap].x;
+        else if (pim == 0) Qpq = M[a * W + ap].y;
+        else Qpq = M[ap * W + a].y;
+        int i = p / 4, j = q / 4;
+        int pp = p % 4, qq = q % 4;
+        if (i > j) {   // the lower triangle mirrors the upper
+            const int ti = i, tp = pp;
+            i = j;
+            pp = qq;
+            j = ti;
+            qq = tp;
+        }
+        const int pair = i * nb - i * (i - 1) / 2 + (j - i);
+        const int col = 1 + pair * 16 + 4 * pp + qq;
+        double x = 0.0, bad = 0.0;
+        constexpr int kB = 16;
+        for (int r0 = 0; r0 < rows; r0 += kB) {
+            double v[kB], bv[kB];
+#pragma unroll
+            for (int k = 0; k < kB; ++k) {
+                v[k] = r0 + k < rows ? recs[(int64_t)(r0 + k) * rl + col] : 0.0;
+                bv[k] = r0 + k < rows ? recs[(int64_t)(r0 + k) * rl] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < kB; ++k) {
+                x += v[k];
+                bad += bv[k];
+            }
+        }
+        store_system(out + e, bad > 0.0 ? NAN : x + 2.0 * Qpq);
+    }
+    wait_vm_complete();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(done + blockIdx.x, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+int hess_grid(const Model& m) { return (int)std::min<int64_t>(2 * m.cus, std::max<int64_t>(1, m.n_tiles)); }
+int hess_rows(const Model& m) { return hess_grid(m); }
+int hess_rec_doubles(int W) { return hess_rec_len(W); }
+int hess_assemble_blocks(int W) { return (4 * W * W + 255) / 256; }
+
+hipError_t launch_hessian(const Model& m, const VParams& vp, double* recs, double* out,
+                          unsigned long long* done, unsigned long long seq, hipStream_t s)
+{
+    const size_t lds = hess_lds_bytes(m.wpad);
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void*)&k_amp_hessian,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_amp_hessian, dim3(hess_grid(m)), dim3(kHessThreads), lds, s,
+                       (const float4*)m.d_data, m.n, m.n_tiles, m.W, m.wpad, vp, recs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hess_assemble, dim3(hess_assemble_blocks(m.W)), dim3(256), 0, s, recs,
+                       hess_rows(m), m.W, (const double2*)m.d_M, out, done, seq);
     return hipGetLastError();
 }
 

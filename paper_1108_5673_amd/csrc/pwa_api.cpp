@@ -126,6 +126,9 @@ void release(Model* m)
     if (m->d_vm) (void)hipFree(m->d_vm);
     if (m->d_brec) (void)hipFree(m->d_brec);
     if (m->h_vstage) (void)hipHostFree(m->h_vstage);
+    if (m->d_hrec) (void)hipFree(m->d_hrec);
+    if (m->h_hout) (void)hipHostFree(m->h_hout);
+    if (m->h_hdone) (void)hipHostFree(m->h_hdone);
 
     if (m->h_out) (void)hipHostFree(m->h_out);
     if (m->h_done) (void)hipHostFree(m->h_done);
@@ -727,6 +730,29 @@ int eval_mfma(Model* m, const double* v, int K, hipStream_t s, bool timed)
     return wait_for(m, b.seq, K, s, timed);
 }
 
+// Wait until all n words hold seq (see wait_for).
+int poll_words(volatile unsigned long long* words, int n, unsigned long long seq, hipStream_t s)
+{
+    auto all_done = [&]() {
+        for (int k = 0; k < n; ++k)
+            if (words[k] != seq) return false;
+        return true;
+    };
+    for (unsigned long it = 1;; ++it) {
+        if (all_done()) break;
+        if ((it & 4095) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                if (all_done()) break;
+                return fail(PWA_ERR_DEVICE, "evaluation finished without publishing its result");
+            }
+            if (e != hipErrorNotReady) return device_fail(e, "evaluation");
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return PWA_OK;
+}
+
 int evaluate(const pwa_model* cm, const double* v, double* nll, double* grad, void* stream)
 {
     if (!cm || !v || !nll) return fail(PWA_ERR_INVALID, "NULL model, v or nll");
@@ -800,6 +826,49 @@ int pwa_build_table(const void* data, int64_t n_data, int32_t n_waves, const voi
     }
     *out = reinterpret_cast<pwa_model*>(m);
     return PWA_OK;
+}
+
+int pwa_nll_grad_hess(const pwa_model* model, const double* v, double* nll, double* grad,
+                      double* hess, void* hip_stream)
+{
+    if (!model || !v || !nll || !grad || !hess)
+        return fail(PWA_ERR_INVALID, "NULL model, v, nll, grad or hess");
+    Model* m = reinterpret_cast<Model*>(const_cast<pwa_model*>(model));
+    if (m->form != pwa::kAmp32)
+        return fail(PWA_ERR_INVALID, "the FUMILI matrix is computed for PWA_FORM_AMPLITUDE models");
+    int rc = check_v(v, m->W);
+    if (rc != PWA_OK) return rc;
+    DeviceGuard g(m->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int W = m->W;
+    const int nh = pwa::hess_assemble_blocks(W);
+    if (!m->d_hrec) {
+        HIP_TRY(hipMalloc(&m->d_hrec, sizeof(double) * (size_t)pwa::hess_rows(*m) *
+                                          pwa::hess_rec_doubles(W)));
+        HIP_TRY(hipHostMalloc((void**)&m->h_hout, sizeof(double) * 4 * W * W,
+                              hipHostMallocCoherent | hipHostMallocMapped));
+        HIP_TRY(hipHostMalloc((void**)&m->h_hdone, sizeof(unsigned long long) * nh,
+                              hipHostMallocCoherent | hipHostMallocMapped));
+        for (int k = 0; k < nh; ++k) m->h_hdone[k] = 0;
+    }
+    unsigned long long seq = 0;
+    int nblk = 0;
+    rc = enqueue_eval(m, v, true, 0, s, false, &seq, &nblk);
+    if (rc != PWA_OK) return rc;
+    pwa::VParams vp;
+    std::memset(&vp, 0, sizeof vp);
+    std::memcpy(vp.v, v, sizeof(double) * 2 * W);
+    const unsigned long long hseq = ++m->seq;
+    const hipError_t e = pwa::launch_hessian(*m, vp, m->d_hrec, m->h_hout, m->h_hdone, hseq, s);
+    if (e != hipSuccess) return device_fail(e, "second-derivative launch");
+    rc = poll_words(m->h_done, nblk, seq, s);
+    if (rc != PWA_OK) return rc;
+    rc = poll_words(m->h_hdone, nh, hseq, s);
+    if (rc != PWA_OK) return rc;
+    *nll = m->h_out[0];
+    std::memcpy(grad, m->h_out + 2, sizeof(double) * 2 * W);
+    std::memcpy(hess, m->h_hout, sizeof(double) * 4 * W * W);
+    return m->h_out[1] > 0.0 ? PWA_WARN_DEGENERATE : PWA_OK;
 }
 
 int pwa_nll(const pwa_model* model, const double* v, double* nll, void* hip_stream)

@@ -82,6 +82,9 @@ struct Model {
     double* d_vb = nullptr;         // vec_cap x 2W parameter vectors, then vec_cap scales (device)
     double* h_vstage = nullptr;     // vec_cap x 2W pinned staging for d_vb
     void* d_vm = nullptr;           // split vector matrix
+    double* d_hrec = nullptr;       // FUMILI matrix: per-block records
+    double* h_hout = nullptr;       // FUMILI matrix: 2W x 2W result (pinned host)
+    unsigned long long* h_hdone = nullptr;   // its completion words (pinned host)
     double* d_brec = nullptr;       // per-(chunk, column) records: FP64 sums, then FP32 G
     size_t brec_rows = 0;           // (chunk, column block) pairs d_brec can hold
     int32_t done_cap = 0;           // completion words h_done can hold
@@ -185,6 +188,11 @@ hipError_t launch_assemble_multi(const MultiLaunch& ml, hipStream_t s);
 int amp_multi_waves(int wpad);
 hipError_t amp_multi_prepare(int wpad);
 int amp_multi_class(int wpad);
+hipError_t launch_hessian(const Model& m, const VParams& vp, double* recs, double* out,
+                          unsigned long long* done, unsigned long long seq, hipStream_t s);
+int hess_rows(const Model& m);
+int hess_rec_doubles(int W);
+int hess_assemble_blocks(int W);
 int assemble_blocks(int W, bool grad);
 
 // occupancy-derived grid sizes

@@ -11,7 +11,10 @@ disagrees with something the paper or the mathematics fixes:
   * the MC term against the event-by-event sum it abbreviates (fixes the
     conjugation convention of M);
   * the packed table against numpy's own products in triu order;
-  * central finite differences (Richardson-extrapolated) of the oracle's NLL.
+  * central finite differences (Richardson-extrapolated) of the oracle's NLL;
+  * for the FUMILI matrix: the scale identity theta^T H_D theta = 4N, the phase
+    null vector, one-event brute force by differences, and the MC part against
+    second differences of mu.
 
 ``ALL_PINS`` lists them; ``tests/test_oracle_mutations.py`` checks that a
 plausible mistake planted anywhere in the oracle fails at least one.
@@ -307,9 +310,92 @@ def pin_thread_independence(o):
     assert res[0][0] == res[1][0] and np.array_equal(res[0][1], res[1][1])
 
 
+# ---------------------------------------------- FUMILI second derivatives
+def _theta(V):
+    return np.ascontiguousarray(np.asarray(V, np.complex128)).view(np.float64)
+
+
+def pin_fumili_scale_identity(o):
+    """I_i is homogeneous of degree 2 in theta, so theta . grad ln I_i = 2 for
+    every event and theta^T (sum_i J_i J_i^T) theta = 4 N exactly; mu is a
+    quadratic form, theta^T (2Q) theta = 2 mu."""
+    s = _sample(5, 3000, 4000, 41)
+    M = o.mc_matrix(s.mc, 4000)
+    for V in s.points:
+        H, nbad = o.fumili_amp(s.data, M, V)
+        assert nbad == 0
+        th = _theta(V)
+        mu, _ = o.mc_term(M, V)
+        assert abs(th @ H @ th - (4 * 3000 + 2 * mu)) <= 1e-10 * (4 * 3000 + 2 * mu)
+        assert np.array_equal(H, H.T) or _rel(H, H.T) < 1e-14
+
+
+def pin_fumili_phase_null_vector(o):
+    """A global phase does not change I_i: theta' = i V (as reals) is a null
+    vector of the data part (no MC term here), and the matrix is PSD."""
+    s = _sample(4, 2000, 10, 42)
+    M = np.zeros((4, 4), np.complex128)
+    V = s.points[0]
+    H, _ = o.fumili_amp(s.data, M, V)
+    phi = _theta(1j * V)
+    assert np.linalg.norm(H @ phi) <= 1e-11 * np.linalg.norm(H) * np.linalg.norm(phi)
+    assert np.linalg.eigvalsh(H).min() >= -1e-10 * np.abs(H).max()
+
+
+def pin_fumili_one_event_brute_force(o):
+    """One event: the data part is J J^T with J the gradient of ln I, here
+    taken by Richardson-extrapolated central differences of |sum_a V_a A_a|^2."""
+    rng = np.random.default_rng(43)
+    W = 3
+    A = rng.standard_normal((1, W)) + 1j * rng.standard_normal((1, W))
+    V = rng.standard_normal(W) + 1j * rng.standard_normal(W)
+    th = _theta(V).copy()
+
+    def lnI(t):
+        v = t.view(np.complex128)
+        s_ = np.sum(v * A[0])
+        return math.log(s_.real ** 2 + s_.imag ** 2)
+
+    J = np.zeros(2 * W)
+    for k in range(2 * W):
+        e = np.zeros(2 * W)
+        e[k] = 1.0
+
+        def cd(h):
+            return (lnI(th + h * e) - lnI(th - h * e)) / (2 * h)
+        J[k] = (4.0 * cd(1e-4) - cd(2e-4)) / 3.0
+    H, _ = o.fumili_amp(A, np.zeros((W, W), np.complex128), V)
+    assert _rel(H, np.outer(J, J)) < 1e-8, (H, np.outer(J, J))
+
+
+def pin_fumili_mc_part(o):
+    """With no events the matrix is the Hessian of mu alone; mu is quadratic,
+    so central differences of mu reproduce it up to rounding."""
+    s = _sample(4, 10, 5000, 44)
+    M = o.mc_matrix(s.mc, 7000)
+    V = s.points[0]
+    H, _ = o.fumili_amp(np.zeros((0, 4), np.complex128), M, V)
+    th = _theta(V).copy()
+
+    def mu(t):
+        return o.mc_term(M, t.view(np.complex128))[0]
+
+    n = th.size
+    fd = np.zeros((n, n))
+    h = 0.5
+    for p in range(n):
+        for q in range(n):
+            ep, eq = np.zeros(n), np.zeros(n)
+            ep[p] = h
+            eq[q] = h
+            fd[p, q] = (mu(th + ep + eq) - mu(th + ep - eq) - mu(th - ep + eq) + mu(th - ep - eq)) / (4 * h * h)
+    assert _rel(H, fd) < 1e-9, (H, fd)
+
+
 ALL_PINS = [
     pin_hand_example, pin_w1_closed_form, pin_exact_one_event, pin_mc_term_is_event_sum,
     pin_table_layout, pin_forms_agree, pin_phase_invariance, pin_scale_identity,
     pin_nonnegative, pin_additivity_permutation, pin_degenerate, pin_finite_differences,
-    pin_thread_independence,
+    pin_thread_independence, pin_fumili_scale_identity, pin_fumili_phase_null_vector,
+    pin_fumili_one_event_brute_force, pin_fumili_mc_part,
 ]

@@ -49,6 +49,14 @@ MUTATIONS = [
     ("degenerate_clamped",
      "if (!(Ii > 0.0) || !isfinite(Ii)) { bad[c]++; continue; }\n            nsum_add(&dpart[c], log(Ii));\n            if (!gpart)",
      "if (!(Ii > 0.0) || !isfinite(Ii)) { Ii = 1e-300; }\n            nsum_add(&dpart[c], log(Ii));\n            if (!gpart)"),
+    ("fumili_im_sign",
+     "J[2 * b + 1] = -2.0 * cimag(z) / Ii;", "J[2 * b + 1] = 2.0 * cimag(z) / Ii;"),
+    ("fumili_drops_conj",
+     "cplx z = conj(s) * A[i * W + b];", "cplx z = s * A[i * W + b];"),
+    ("fumili_mc_cross_block_transposed",
+     "else if (pim == 0) Qpq = cimag(M[a * W + ap]);", "else if (pim == 0) Qpq = cimag(M[ap * W + a]);"),
+    ("fumili_mc_factor",
+     "nsum_value(&t) + 2.0 * Qpq;", "nsum_value(&t) + Qpq;"),
     ("chunk_partials_dropped",
      "for (int64_t c = 0; c < nc; ++c) { nsum_add(&d, nsum_value(&dpart[c])); nbad += bad[c]; }\n    cplx* U",
      "for (int64_t c = 0; c + 1 < nc; ++c) { nsum_add(&d, nsum_value(&dpart[c])); nbad += bad[c]; }\n    cplx* U"),
