@@ -283,6 +283,18 @@ def main():
                 "nll": fres["f"], "grad_norm": fres["grad_norm"]}
     log("fit from a random start: %s after %d iterations, %d evaluations, %.3f s"
         % (fres["message"], fres["iterations"], fres["evaluations"], fit_s))
+    # the same start with FUMILI steps (NLL, gradient and FUMILI matrix per
+    # iteration) on the amplitude form of the same sample
+    amp = pwa.Model(d32, mc32, sample.n_gen, form="amplitude")
+    t = time.perf_counter()
+    v_fu, fu = pwa_fit.fit_fumili(amp, v0)
+    fu_s = time.perf_counter() - t
+    amp.close()
+    fit_info["fumili"] = {"status": fu["message"], "iterations": fu["iterations"],
+                          "evaluations": fu["evaluations"], "seconds": fu_s, "nll": fu["f"],
+                          "grad_norm": fu["grad_norm"], "form": "amplitude (complex64)"}
+    log("FUMILI fit from the same start: %s after %d iterations, %.3f s"
+        % (fu["message"], fu["iterations"], fu_s))
 
     out = {}
     if not args.no_baselines:

@@ -160,10 +160,13 @@ int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k
  * (PWA_FORM_AMPLITUDE) only.
  *
  *   hess  2W x 2W doubles, row-major, over theta = (Re V_0, Im V_0, Re V_1, ...):
- *         H = sum_i J_i J_i^T + d2mu/dtheta2, with J_i = grad_theta ln I_i (the
- *         outer-product form FUMILI uses for the data term, in FP64) and the
- *         exact Hessian of the MC term mu, a quadratic form: for waves a, a'
- *         the 2 x 2 block is 2 [[Re M_aa', Im M_aa'], [-Im M_aa', Re M_aa']].
+ *         H = sum_i J_i J_i^T with J_i = grad_theta ln I_i, in FP64.  FUMILI
+ *         replaces the Hessian of -ln L by these outer products, dropping the
+ *         second derivatives of I_i; for the extended likelihood of Eq. 3 the
+ *         dropped terms cancel the Hessian of the MC term on average over
+ *         samples drawn from the model, so neither appears (H is the observed
+ *         information, positive semidefinite, with the global-phase direction
+ *         i V in its null space).
  * Degenerate events: as pwa_nll_grad, and hess is NaN.
  */
 int pwa_nll_grad_hess(const pwa_model* model, const double* v, double* nll, double* grad,
@@ -285,6 +288,26 @@ int pwa_lbfgs_minimize(int32_t n, double* x, pwa_objective fn, void* ctx,
  */
 int pwa_fit_lbfgs(const pwa_model* model, double* v, const pwa_lbfgs_options* options,
                   pwa_lbfgs_result* res, void* hip_stream);
+
+/*
+ * ---- Fit driver: damped Newton steps on the FUMILI matrix ------------------
+ *
+ * pwa_objective_hess fills *f, g[n] and H[n x n] (row-major) at x[n]; returns
+ * 0 or a negative status.  pwa_newton_minimize solves (H + lambda diag H) d = -g
+ * by Cholesky, raising lambda until H + lambda diag H is positive definite,
+ * halves the step until f decreases sufficiently, and lowers lambda after full
+ * steps (Levenberg-Marquardt damping of the Gauss-Newton steps that FUMILI
+ * takes).  Options and result as for L-BFGS (history is unused).
+ * pwa_fit_fumili fits V on an amplitude-form model with pwa_nll_grad_hess,
+ * with the gauge of pwa_fit_lbfgs.
+ */
+typedef int (*pwa_objective_hess)(void* ctx, const double* x, double* f, double* g, double* H);
+
+int pwa_newton_minimize(int32_t n, double* x, pwa_objective_hess fn, void* ctx,
+                        const pwa_lbfgs_options* options, pwa_lbfgs_result* res);
+
+int pwa_fit_fumili(const pwa_model* model, double* v, const pwa_lbfgs_options* options,
+                   pwa_lbfgs_result* res, void* hip_stream);
 
 #ifdef __cplusplus
 }

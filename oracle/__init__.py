@@ -51,7 +51,7 @@ def _bind(lib):
     lib.oracle_nll_amp.argtypes = [p, i64, i32, p, p, p, p]
     lib.oracle_nll_amp.restype = i64
     if hasattr(lib, "oracle_fumili_amp"):
-        lib.oracle_fumili_amp.argtypes = [p, i64, i32, p, p, p]
+        lib.oracle_fumili_amp.argtypes = [p, i64, i32, p, p]
         lib.oracle_fumili_amp.restype = i64
     return lib
 
@@ -162,16 +162,14 @@ class Oracle:
         return self._nll(self.lib.oracle_nll_amp, A, A.shape[0], A.shape[1], M, V, grad)
 
 
-    def fumili_amp(self, A, M, V):
-        """(H, n_degenerate): the FUMILI second-derivative matrix (2W x 2W over
-        theta = (Re V_0, Im V_0, ...)): the sum over events of J_i J_i^T with
-        J_i = grad ln I_i, plus the exact Hessian of the MC term."""
+    def fumili_amp(self, A, V):
+        """(H, n_degenerate): the FUMILI matrix (2W x 2W over theta = (Re V_0,
+        Im V_0, ...)): the sum over events of J_i J_i^T, J_i = grad ln I_i."""
         A = _c128(A)
-        M = _c128(M)
         V = _c128(V)
         W = A.shape[1]
         H = np.zeros((2 * W, 2 * W), np.float64)
-        nbad = self.lib.oracle_fumili_amp(_ptr(A), A.shape[0], W, _ptr(M), _ptr(V), _ptr(H))
+        nbad = self.lib.oracle_fumili_amp(_ptr(A), A.shape[0], W, _ptr(V), _ptr(H))
         return H, int(nbad)
 
 

@@ -324,30 +324,25 @@ int64_t oracle_nll_amp(const double* Ari, int64_t N, int32_t W, const double* Mr
     return nbad;
 }
 
-/* ---- FUMILI-style second derivatives ---------------------------------
+/* ---- FUMILI second derivatives --------------------------------------
  * The paper's fits use FUMILI with analytic gradients and Hessian (Sec. 5).
- * For a likelihood, FUMILI replaces the Hessian of -ln L by the sum of outer
- * products of the per-event gradients of ln f (the second-derivative terms of
- * f are dropped); the normalisation term of the extended likelihood, mu, is a
- * quadratic form and enters with its exact Hessian.  With theta = (Re V_0,
- * Im V_0, Re V_1, ...):
- *   dI_i/dRe V_b = 2 Re(conj(S_i) A_ib),  dI_i/dIm V_b = -2 Im(conj(S_i) A_ib)
- *   J_i = grad_theta ln I_i = grad_theta I_i / I_i
- *   H_D = sum_i J_i J_i^T
- *   mu  = sum_a,a' (x_a x_a' + y_a y_a') Re M_aa' + 2 sum_a,a' x_a y_a' Im M_aa'
- *         (V_a = x_a + i y_a), so d2mu/dtheta2 = 2 Q with
- *         Q[(a,re),(a',re)] = Q[(a,im),(a',im)] = Re M_aa',
- *         Q[(a,re),(a',im)] = Q[(a',im),(a,re)] = Im M_aa'.
- * oracle_fumili_amp fills H (2W x 2W, row-major) with H_D + 2 Q and returns
- * the number of degenerate events (then H is NaN).  Per chunk and entry the
- * event sums are compensated, chunks added in order.
+ * FUMILI replaces the Hessian of -ln L by the sum over events of the outer
+ * products of the gradients of ln f, dropping the second derivatives of f.
+ * For the extended likelihood of Eq. 3 the dropped part of the data term,
+ * -sum_i (d2 I_i / dtheta2) / I_i, has the expectation -d2 mu / dtheta2 over
+ * samples drawn from the model, so it cancels the Hessian of the MC term on
+ * average and the matrix is the data sum alone (the observed information):
+ *   theta = (Re V_0, Im V_0, Re V_1, ...),
+ *   dI_i/dRe V_b = 2 Re(conj(S_i) A_ib),  dI_i/dIm V_b = -2 Im(conj(S_i) A_ib),
+ *   J_i = grad_theta ln I_i = grad_theta I_i / I_i,   H = sum_i J_i J_i^T.
+ * oracle_fumili_amp fills H (2W x 2W, row-major) and returns the number of
+ * degenerate events (then H is NaN).  Per chunk and entry the event sums are
+ * compensated, chunks added in order.
  */
-int64_t oracle_fumili_amp(const double* Ari, int64_t N, int32_t W, const double* Mri,
-                          const double* Vri, double* H)
+int64_t oracle_fumili_amp(const double* Ari, int64_t N, int32_t W, const double* Vri, double* H)
 {
     const cplx* A = (const cplx*)Ari;
     const cplx* V = (const cplx*)Vri;
-    const cplx* M = (const cplx*)Mri;
     const int32_t P = 2 * W;
     const int64_t nc = n_chunks(N);
     nsum* hpart = calloc((size_t)(nc > 0 ? nc : 1) * P * P, sizeof(nsum));
@@ -379,14 +374,7 @@ int64_t oracle_fumili_amp(const double* Ari, int64_t N, int32_t W, const double*
         for (int32_t q = 0; q < P; ++q) {
             nsum t = {0, 0};
             for (int64_t c = 0; c < nc; ++c) nsum_add(&t, nsum_value(&hpart[c * P * P + p * P + q]));
-            /* the exact Hessian of mu */
-            const int32_t a = p / 2, ap = q / 2;
-            const int pim = p % 2, qim = q % 2;
-            double Qpq;
-            if (pim == qim) Qpq = creal(M[a * W + ap]);
-            else if (pim == 0) Qpq = cimag(M[a * W + ap]);     /* (a,re),(a',im) */
-            else Qpq = cimag(M[ap * W + a]);                    /* (a,im),(a',re) */
-            H[p * P + q] = nbad > 0 ? NAN : nsum_value(&t) + 2.0 * Qpq;
+            H[p * P + q] = nbad > 0 ? NAN : nsum_value(&t);
         }
     free(hpart);
     free(bad);

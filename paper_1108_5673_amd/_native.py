@@ -34,6 +34,7 @@ EXPORTED = (
     "pwa_last_error", "pwa_model_info", "pwa_copy_table", "pwa_copy_mc_matrix",
     "pwa_set_mc_matrix", "pwa_set_timing", "pwa_get_timing", "pwa_build_timing",
     "pwa_lbfgs_default_options", "pwa_lbfgs_minimize", "pwa_fit_lbfgs", "pwa_nll_grad_hess",
+    "pwa_newton_minimize", "pwa_fit_fumili",
 )
 
 PWA_LBFGS_CONVERGED_GRADIENT = 0
@@ -44,6 +45,12 @@ PWA_LBFGS_LINE_SEARCH_FAILED = 3
 # int (*)(void* ctx, const double* x, double* f, double* g)
 OBJECTIVE = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+
+
+# int (*)(void* ctx, const double* x, double* f, double* g, double* H)
+OBJECTIVE_HESS = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double))
 
 
 class LbfgsOptions(ctypes.Structure):
@@ -123,6 +130,9 @@ def _declare(L):
     L.pwa_lbfgs_minimize.argtypes = [i32, dp, OBJECTIVE, p, ctypes.POINTER(LbfgsOptions),
                                      ctypes.POINTER(LbfgsResult)]
     L.pwa_fit_lbfgs.argtypes = [p, dp, ctypes.POINTER(LbfgsOptions), ctypes.POINTER(LbfgsResult), p]
+    L.pwa_newton_minimize.argtypes = [i32, dp, OBJECTIVE_HESS, p, ctypes.POINTER(LbfgsOptions),
+                                      ctypes.POINTER(LbfgsResult)]
+    L.pwa_fit_fumili.argtypes = [p, dp, ctypes.POINTER(LbfgsOptions), ctypes.POINTER(LbfgsResult), p]
     for name in EXPORTED:
         if name not in ("pwa_free", "pwa_last_error", "pwa_lbfgs_default_options"):
             getattr(L, name).restype = ctypes.c_int

@@ -281,6 +281,22 @@ struct ModelCtx {
     void* stream;
 };
 
+// Gauge: the NLL does not depend on a global phase of V, so V_0 is rotated
+// onto the positive real axis (the fits then hold Im V_0 at zero).
+void gauge_rotate(double* v, int W)
+{
+    const double r = std::hypot(v[0], v[1]);
+    if (r > 0.0) {
+        const double c = v[0] / r, s = -v[1] / r;   // multiply by exp(-i arg V_0)
+        for (int a = 0; a < W; ++a) {
+            const double re = v[2 * a], im = v[2 * a + 1];
+            v[2 * a] = re * c - im * s;
+            v[2 * a + 1] = re * s + im * c;
+        }
+        v[1] = 0.0;
+    }
+}
+
 int model_objective(void* ctx, const double* x, double* f, double* g)
 {
     const ModelCtx* c = static_cast<const ModelCtx*>(ctx);
@@ -305,19 +321,180 @@ extern "C" int pwa_fit_lbfgs(const pwa_model* model, double* v, const pwa_lbfgs_
     pwa_lbfgs_options opt;
     pwa_lbfgs_default_options(&opt);
     if (options) opt = *options;
-    // gauge: the NLL does not depend on a global phase of V, so V_0 is
-    // rotated onto the positive real axis and Im V_0 is held at zero
-    const double r = std::hypot(v[0], v[1]);
-    if (r > 0.0) {
-        const double c = v[0] / r, s = -v[1] / r;   // multiply by exp(-i arg V_0)
-        for (int a = 0; a < W; ++a) {
-            const double re = v[2 * a], im = v[2 * a + 1];
-            v[2 * a] = re * c - im * s;
-            v[2 * a + 1] = re * s + im * c;
-        }
-        v[1] = 0.0;
-    }
+    gauge_rotate(v, W);
     opt.fixed_index = 1;
     ModelCtx ctx{model, hip_stream};
     return pwa_lbfgs_minimize(2 * W, v, model_objective, &ctx, &opt, res);
+}
+
+// ---- FUMILI-style fit: damped Newton steps on the FUMILI matrix ------------
+// With f, g and the FUMILI matrix H at x: solve (H + lambda D) d = -g by
+// Cholesky (D the diagonal of H, lambda raised until the factorisation
+// succeeds), then halve the step until the sufficient-decrease condition
+// holds.  lambda shrinks after a full step and grows after a shortened one
+// (the Levenberg-Marquardt damping of Gauss-Newton steps; FUMILI is the
+// Gauss-Newton method of likelihood fits).
+namespace {
+
+// In-place Cholesky of the n x n row-major A (lower factor); false if A is not
+// positive definite.
+bool cholesky(std::vector<double>& A, int n)
+{
+    for (int j = 0; j < n; ++j) {
+        double d = A[j * n + j];
+        for (int k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+        if (!(d > 0.0) || !std::isfinite(d)) return false;
+        d = std::sqrt(d);
+        A[j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double x = A[i * n + j];
+            for (int k = 0; k < j; ++k) x -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = x / d;
+        }
+    }
+    return true;
+}
+
+void cholesky_solve(const std::vector<double>& L, int n, std::vector<double>& b)
+{
+    for (int i = 0; i < n; ++i) {
+        double x = b[i];
+        for (int k = 0; k < i; ++k) x -= L[i * n + k] * b[k];
+        b[i] = x / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double x = b[i];
+        for (int k = i + 1; k < n; ++k) x -= L[k * n + i] * b[k];
+        b[i] = x / L[i * n + i];
+    }
+}
+
+}  // namespace
+
+extern "C" int pwa_newton_minimize(int32_t n, double* x_io, pwa_objective_hess fn, void* ctx,
+                                   const pwa_lbfgs_options* options, pwa_lbfgs_result* res)
+{
+    if (n < 1 || !x_io || !fn || !res) return PWA_ERR_INVALID;
+    pwa_lbfgs_options opt;
+    pwa_lbfgs_default_options(&opt);
+    if (options) opt = *options;
+    if (opt.max_iterations < 0 || opt.fixed_index >= n) return PWA_ERR_INVALID;
+    std::memset(res, 0, sizeof *res);
+    std::vector<double> x(x_io, x_io + n), g(n), H((size_t)n * n), L((size_t)n * n), d(n),
+        xt(n), gt(n), Ht((size_t)n * n);
+    int evals = 0;
+    auto eval = [&](const std::vector<double>& xx, double& f, std::vector<double>& gg,
+                    std::vector<double>& HH) {
+        ++evals;
+        const int rc = fn(ctx, xx.data(), &f, gg.data(), HH.data());
+        if (rc < 0) return rc;
+        if (!std::isfinite(f)) f = INFINITY;
+        const int k = opt.fixed_index;
+        if (k >= 0) {   // the fixed coordinate: zero gradient, unit diagonal, no coupling
+            gg[k] = 0.0;
+            for (int i = 0; i < n; ++i) HH[(size_t)i * n + k] = HH[(size_t)k * n + i] = 0.0;
+            HH[(size_t)k * n + k] = 1.0;
+        }
+        return 0;
+    };
+    double f = 0.0;
+    int rc = eval(x, f, g, H);
+    if (rc < 0) return rc;
+    if (!std::isfinite(f)) return PWA_WARN_DEGENERATE;
+    double lambda = 1e-8;
+    int status = PWA_LBFGS_MAX_ITERATIONS;
+    int iter = 0, small_steps = 0;
+    for (; iter < opt.max_iterations; ++iter) {
+        const double gn = norm2(g);
+        if (gn <= opt.grad_tol * std::max(1.0, std::fabs(f))) {
+            status = PWA_LBFGS_CONVERGED_GRADIENT;
+            break;
+        }
+        // damped system, damping raised until positive definite
+        bool ok = false;
+        for (int tries = 0; tries < 60 && !ok; ++tries) {
+            L = H;
+            for (int i = 0; i < n; ++i) L[(size_t)i * n + i] += lambda * std::max(H[(size_t)i * n + i], 1e-300);
+            ok = cholesky(L, n);
+            if (!ok) lambda = std::max(lambda * 10.0, 1e-8);
+        }
+        if (!ok) {
+            status = PWA_LBFGS_LINE_SEARCH_FAILED;
+            break;
+        }
+        for (int i = 0; i < n; ++i) d[i] = -g[i];
+        cholesky_solve(L, n, d);
+        const double slope = dot(g, d);
+        double a = 1.0, ft = 0.0;
+        bool accepted = false;
+        for (int ls = 0; ls < 40; ++ls) {
+            for (int i = 0; i < n; ++i) xt[i] = x[i] + a * d[i];
+            rc = eval(xt, ft, gt, Ht);
+            if (rc < 0) return rc;
+            const double noise = 1e-14 * std::fabs(f);
+            if (std::isfinite(ft) && (ft <= f + 1e-4 * a * slope || (ft <= f + noise && a < 1.0))) {
+                accepted = true;
+                break;
+            }
+            a *= 0.5;
+        }
+        if (!accepted) {
+            status = PWA_LBFGS_LINE_SEARCH_FAILED;
+            break;
+        }
+        lambda = a == 1.0 ? std::max(lambda * 0.1, 1e-12) : lambda * 4.0;
+        const double f_old = f;
+        x = xt;
+        f = ft;
+        g = gt;
+        H = Ht;
+        if (opt.rel_f_tol > 0.0 && f_old - f <= opt.rel_f_tol * std::max(1.0, std::fabs(f))) {
+            if (++small_steps >= 3) {
+                status = PWA_LBFGS_CONVERGED_VALUE;
+                ++iter;
+                break;
+            }
+        } else {
+            small_steps = 0;
+        }
+    }
+    std::memcpy(x_io, x.data(), sizeof(double) * n);
+    res->status = status;
+    res->iterations = iter;
+    res->evaluations = evals;
+    res->f = f;
+    res->grad_norm = norm2(g);
+    return PWA_OK;
+}
+
+namespace {
+
+int model_objective_hess(void* ctx, const double* x, double* f, double* g, double* H)
+{
+    const ModelCtx* c = static_cast<const ModelCtx*>(ctx);
+    const int rc = pwa_nll_grad_hess(c->model, x, f, g, H, c->stream);
+    if (rc == PWA_WARN_DEGENERATE) {
+        *f = INFINITY;
+        return 0;
+    }
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int pwa_fit_fumili(const pwa_model* model, double* v, const pwa_lbfgs_options* options,
+                              pwa_lbfgs_result* res, void* hip_stream)
+{
+    if (!model || !v || !res) return PWA_ERR_INVALID;
+    pwa_info info;
+    int rc = pwa_model_info(model, &info);
+    if (rc != PWA_OK) return rc;
+    const int W = info.n_waves;
+    pwa_lbfgs_options opt;
+    pwa_lbfgs_default_options(&opt);
+    if (options) opt = *options;
+    gauge_rotate(v, W);
+    opt.fixed_index = 1;
+    ModelCtx ctx{model, hip_stream};
+    return pwa_newton_minimize(2 * W, v, model_objective_hess, &ctx, &opt, res);
 }

@@ -388,7 +388,11 @@ hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, int
 namespace pwa {
 
 // ---- FUMILI second derivatives (amplitude form) ----------------------------
-// H_D = sum_i J_i J_i^T over theta = (Re V_0, Im V_0, Re V_1, ...), with
+// FUMILI takes, for the Hessian of -ln L, the sum over events of the outer
+// products of the gradients of ln f; for the extended likelihood of Eq. 3 the
+// dropped second derivatives of the data term cancel the MC term's Hessian on
+// average, so the matrix is the data sum alone:
+// H = sum_i J_i J_i^T over theta = (Re V_0, Im V_0, Re V_1, ...), with
 // J_i = grad_theta ln I_i = 2 [Re z_ib, -Im z_ib]_b / I_i and z_ib = conj(S_i) A_ib
 // (the derivative of Eq. 1).  Per block, tiles of 64 events:
 //   1. the tile's amplitudes into LDS (coalesced 16-byte loads);
@@ -550,11 +554,11 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
     if (tid == 0) rec[0] = (double)*s_bad;
 }
 
-// Sum of the block records and the exact MC part 2 Q; one thread per entry of
-// the 2W x 2W matrix (full, row-major), written to pinned host memory.
+// Sum of the block records in block order; one thread per entry of the
+// 2W x 2W matrix (full, row-major), written to pinned host memory.
 __global__ __launch_bounds__(256) void k_hess_assemble(const double* __restrict__ recs, int rows,
-                                                       int W, const double2* __restrict__ M,
-                                                       double* out, unsigned long long* done,
+                                                       int W, double* out,
+                                                       unsigned long long* done,
                                                        unsigned long long seq)
 {
     const int P = 2 * W;
@@ -562,12 +566,7 @@ __global__ __launch_bounds__(256) void k_hess_assemble(const double* __restrict_
     const int nb = hess_pj(W) / 4;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < P * P) {
-        int p = e / P, q = e % P;
-        const int a = p / 2, ap = q / 2, pim = p % 2, qim = q % 2;
-        double Qpq;
-        if (pim == qim) Qpq = M[a * W + ap].x;
-        else if (pim == 0) Qpq = M[a * W + ap].y;
-        else Qpq = M[ap * W + a].y;
+        const int p = e / P, q = e % P;
         int i = p / 4, j = q / 4;
         int pp = p % 4, qq = q % 4;
         if (i > j) {   // the lower triangle mirrors the upper
@@ -594,7 +593,7 @@ __global__ __launch_bounds__(256) void k_hess_assemble(const double* __restrict_
                 bad += bv[k];
             }
         }
-        store_system(out + e, bad > 0.0 ? NAN : x + 2.0 * Qpq);
+        store_system(out + e, bad > 0.0 ? NAN : x);
     }
     wait_vm_complete();
     __syncthreads();
@@ -622,7 +621,7 @@ hipError_t launch_hessian(const Model& m, const VParams& vp, double* recs, doubl
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hess_assemble, dim3(hess_assemble_blocks(m.W)), dim3(256), 0, s, recs,
-                       hess_rows(m), m.W, (const double2*)m.d_M, out, done, seq);
+                       hess_rows(m), m.W, out, done, seq);
     return hipGetLastError();
 }
 

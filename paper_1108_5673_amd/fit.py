@@ -2,7 +2,9 @@
 
     from paper_1108_5673_amd import fit
     v, res = fit.fit_lbfgs(model, v0)              # NLL(V) on the GPU, gauge Im V_0 = 0
+    v, res = fit.fit_fumili(model, v0)             # damped Newton on the FUMILI matrix
     x, res = fit.minimize_lbfgs(fun, x0)           # fun(x) -> (f, g), any objective
+    x, res = fit.minimize_newton(fun, x0)          # fun(x) -> (f, g, H)
 
 The minimiser runs in the library (include/pwa.h, pwa_lbfgs_minimize); this
 module only marshals arguments and wraps a Python objective as a C callback.
@@ -83,5 +85,53 @@ def fit_lbfgs(model, v0, stream=None, **options):
     status = _native.lib().pwa_fit_lbfgs(model._handle(),
                                          x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                          ctypes.byref(opt), ctypes.byref(res), st)
+    _native.check(status)
+    return x.view(np.complex128).copy(), _result(res)
+
+
+def minimize_newton(fun, x0, **options):
+    """Minimise fun (x -> (f, g, H)) from x0 with damped Newton steps; returns
+    (x, result dict)."""
+    x = np.ascontiguousarray(np.asarray(x0, dtype=np.float64).ravel().copy())
+    n = x.size
+    err = []
+
+    def cb(_ctx, xp, fp, gp, hp):
+        try:
+            f, g, H = fun(np.ctypeslib.as_array(xp, shape=(n,)).copy())
+            fp[0] = float(f)
+            np.ctypeslib.as_array(gp, shape=(n,))[:] = np.asarray(g, dtype=np.float64).ravel()
+            np.ctypeslib.as_array(hp, shape=(n * n,))[:] = np.asarray(H, dtype=np.float64).ravel()
+            return 0
+        except Exception as e:          # reported after the call returns
+            err.append(e)
+            return _native.PWA_ERR_INVALID
+
+    c_cb = _native.OBJECTIVE_HESS(cb)
+    res = _native.LbfgsResult()
+    opt = _options(**options)
+    status = _native.lib().pwa_newton_minimize(n, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               c_cb, None, ctypes.byref(opt), ctypes.byref(res))
+    if err:
+        raise err[0]
+    _native.check(status)
+    return x, _result(res)
+
+
+def fit_fumili(model, v0, stream=None, **options):
+    """Fit V on an amplitude-form model with damped Newton steps on the FUMILI
+    matrix; returns (V as (W,) complex128, result dict)."""
+    a = np.asarray(v0)
+    if np.iscomplexobj(a):
+        a = a.astype(np.complex128).view(np.float64)
+    x = np.ascontiguousarray(a, dtype=np.float64).ravel().copy()
+    if x.size != 2 * model.n_waves:
+        raise ValueError("expected %d waves" % model.n_waves)
+    res = _native.LbfgsResult()
+    opt = _options(**options)
+    st = stream if stream is not None else model._stream
+    status = _native.lib().pwa_fit_fumili(model._handle(),
+                                          x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          ctypes.byref(opt), ctypes.byref(res), st)
     _native.check(status)
     return x.view(np.complex128).copy(), _result(res)

@@ -113,3 +113,57 @@ def test_pwa_fit_matches_scipy_and_scale_identity():
     mu = o.mc_term(M, V)
     mu = mu[0] if isinstance(mu, tuple) else mu
     assert abs(mu - A.shape[0]) <= 1e-6 * A.shape[0], (mu, A.shape[0])
+
+
+def test_newton_quadratic_one_step():
+    rng = np.random.default_rng(9)
+    n = 12
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.standard_normal(n)
+    x, res = fit.minimize_newton(lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b, A), np.zeros(n),
+                                 grad_tol=1e-12, rel_f_tol=0.0)
+    assert res["status"] == 0 and res["iterations"] <= 3, res
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-10, atol=1e-12)
+
+
+def test_newton_rosenbrock():
+    def f(x):
+        v = 100.0 * (x[1] - x[0] ** 2) ** 2 + (1 - x[0]) ** 2
+        g = np.array([-400.0 * x[0] * (x[1] - x[0] ** 2) - 2.0 * (1 - x[0]), 200.0 * (x[1] - x[0] ** 2)])
+        H = np.array([[1200.0 * x[0] ** 2 - 400.0 * x[1] + 2.0, -400.0 * x[0]], [-400.0 * x[0], 200.0]])
+        return v, g, H
+
+    x, res = fit.minimize_newton(f, np.array([-1.2, 1.0]), grad_tol=1e-12, max_iterations=500)
+    assert res["status"] in (0, 1), res
+    np.testing.assert_allclose(x, [1.0, 1.0], atol=1e-8)
+
+
+def test_fumili_fit_matches_lbfgs_minimum():
+    """FUMILI steps on the oracle's NLL, gradient and FUMILI matrix reach the
+    same minimum as L-BFGS, in few iterations (the paper's fits take 5-10)."""
+    o = oracle.get()
+    s = synth.make_sample("w4_n10k", n_data=3000, n_gen=20000, n_acc=10000, n_points=1)
+    A, M = s.data, o.mc_matrix(s.mc, s.n_gen)
+
+    def fgh(x):
+        V = x.view(np.complex128)
+        f, g, nbad = o.nll_amp(A, M, V)
+        H, _ = o.fumili_amp(A, V)
+        return (np.inf if nbad else f), g, H
+
+    rng = np.random.default_rng(11)
+    W = A.shape[1]
+    # start in the basin of the generating point: its direction, slightly
+    # perturbed, scaled so that mu = N (the extended likelihood's scale);
+    # both methods then find the same minimum
+    v0 = s.v_true * np.exp(0.7j) + 0.05 * (rng.standard_normal(W) + 1j * rng.standard_normal(W))
+    v0 = v0 * np.exp(-1j * np.angle(v0[0]))
+    v0 = v0 * np.sqrt(A.shape[0] / o.mc_term(M, v0)[0])
+    x0 = np.ascontiguousarray(v0).view(np.float64).copy()
+    x0[1] = 0.0
+    xn, rn = fit.minimize_newton(fgh, x0, fixed_index=1, grad_tol=1e-10)
+    xl, rl = fit.minimize_lbfgs(lambda x: fgh(x)[:2], x0, fixed_index=1, grad_tol=1e-10)
+    assert rn["status"] in (0, 1) and rl["status"] in (0, 1), (rn, rl)
+    assert rn["iterations"] < rl["iterations"], (rn, rl)
+    assert abs(rn["f"] - rl["f"]) <= 1e-9 * abs(rl["f"])

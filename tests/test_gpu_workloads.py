@@ -201,3 +201,24 @@ def test_w32_n2m_lbfgs_fit_from_random_start(o, w32):
     n = d32.shape[0]
     assert abs(mu - n) <= 1e-6 * n, (mu, n)
     model.close()
+
+
+def test_w32_n2m_fumili_fit(o, w32):
+    """The FUMILI fit (damped Newton on pwa_nll_grad_hess) from a random start
+    scaled to mu = N: converged, mu = N at the end, NLL matching the oracle."""
+    from paper_1108_5673_amd import fit
+    s, d32, mc32 = w32
+    model = pwa.Model(d32, mc32, s.n_gen, form="amplitude")
+    M = o.mc_matrix(mc32.astype(np.complex128), s.n_gen)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([11085673, 32, 2])))
+    v0 = synth.random_v(rng, 32)
+    n = d32.shape[0]
+    v0 = v0 * np.sqrt(n / o.mc_term(M, v0)[0])
+    V, res = fit.fit_fumili(model, v0, grad_tol=1e-12, rel_f_tol=0.0, max_iterations=200)
+    assert res["status"] == 0, res
+    nll, g = model.nll_grad(V)
+    rn, rg, _ = o.nll_amp(d32.astype(np.complex128), M, V)
+    assert abs(nll - rn) <= 1e-12 * max(abs(rn), 2e6)
+    mu, _ = o.mc_term(M, V)
+    assert abs(mu - n) <= 1e-6 * n, (mu, n)
+    model.close()

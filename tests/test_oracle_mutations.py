@@ -53,10 +53,11 @@ MUTATIONS = [
      "J[2 * b + 1] = -2.0 * cimag(z) / Ii;", "J[2 * b + 1] = 2.0 * cimag(z) / Ii;"),
     ("fumili_drops_conj",
      "cplx z = conj(s) * A[i * W + b];", "cplx z = s * A[i * W + b];"),
-    ("fumili_mc_cross_block_transposed",
-     "else if (pim == 0) Qpq = cimag(M[a * W + ap]);", "else if (pim == 0) Qpq = cimag(M[ap * W + a]);"),
-    ("fumili_mc_factor",
-     "nsum_value(&t) + 2.0 * Qpq;", "nsum_value(&t) + Qpq;"),
+    ("fumili_factor_two",
+     "J[2 * b] = 2.0 * creal(z) / Ii;", "J[2 * b] = creal(z) / Ii;"),
+    ("fumili_drops_last_chunk",
+     "for (int64_t c = 0; c < nc; ++c) nsum_add(&t, nsum_value(&hpart[c * P * P + p * P + q]));",
+     "for (int64_t c = 0; c + 1 < nc; ++c) nsum_add(&t, nsum_value(&hpart[c * P * P + p * P + q]));"),
     ("chunk_partials_dropped",
      "for (int64_t c = 0; c < nc; ++c) { nsum_add(&d, nsum_value(&dpart[c])); nbad += bad[c]; }\n    cplx* U",
      "for (int64_t c = 0; c + 1 < nc; ++c) { nsum_add(&d, nsum_value(&dpart[c])); nbad += bad[c]; }\n    cplx* U"),
