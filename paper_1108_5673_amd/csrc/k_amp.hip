@@ -2,19 +2,26 @@
 // per-event work is S_i = sum_a V_a A_ia and I_i = |S_i|^2, so only N x W
 // amplitudes are streamed instead of the N x W(W+1)/2 table.
 //
-// Amplitudes are stored complex64, row-major, each row padded to an even
-// number of waves wpad and the event count padded to a multiple of 64 with
-// zero rows.  A block has up to four wavefronts; each handles tiles of 64 events:
-//   1. coalesced 16-byte loads of the tile's contiguous 512*wpad bytes into LDS
-//      (rows padded in LDS so that the per-event reads below hit distinct banks);
-//   2. lane = event: S_i, I_i, ln I_i and c_i = S_i / I_i in FP64;
-//   3. g_a += c_i conj(A_ia) over the tile's 64 events, reading the tile from
-//      LDS (so the amplitudes leave HBM once per evaluation): for W <= 64 the
-//      lanes are G = 64 / W groups of W, group q taking events q, q + G, ...,
-//      and the groups are added in order at the end; beyond 64 waves,
-//      lane = wave.
-// Each block writes one partial record [sum ln I, n_bad, g_0, ..., g_{W-1}];
-// the gradient is G_b = 2 sum_a V_a M_ab - 2 g_b.
+// Layout (lane-split).  An event is held by q = 2^lq neighbouring lanes, each
+// with wl (even) of its waves, so rows are q wl >= W waves long (the extra
+// waves are zero; shape per W in amp_shape).  The events form steps of
+// R = 64 / q: in step k, lane l takes event k R + (l >> lq) and the waves
+// (l & (q - 1)) wl ... + wl - 1 as wl / 2 vectors of two complex64, stored
+// [k][vector][lane], so that every load of a wavefront reads 1 KB contiguous.
+// Events are padded with zero rows to a multiple of 64.
+//
+// A wavefront streams a contiguous range of steps through registers
+// (non-temporal loads into two register buffers: the next step is in flight
+// while the current one is processed):
+//   1. S over the lane's waves in FP64, summed over the q lanes of the event
+//      by an xor butterfly (every lane of the event ends with the same bits);
+//   2. I = |S|^2; in each run of q steps one lane of every event keeps I, so
+//      that one logarithm per lane covers the 64 events of the run;
+//   3. c = S / I (reciprocal refined in FP64), and per lane, in FP64 registers,
+//      g_a += c conj(A_a) over its own waves.
+// At the end the lanes that share waves are summed through LDS in lane order,
+// the block's wavefronts in wavefront order, and the block writes one record
+// [sum ln I, n_bad, g_0, ..., g_{W-1}]; G_b = 2 sum_a V_a M_ab - 2 g_b.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,239 +32,224 @@
 
 namespace pwa {
 
-__host__ __device__ inline int amp_lds_stride_words(int wpad)
+constexpr int kAmpBlockWaves = 4;
+
+template <int WL>
+struct AmpRegs {
+    float4 x[WL / 2];
+};
+
+// The lane's vectors of one step; p points at the step's first vector + lane.
+template <int WL>
+__device__ inline void amp_load(AmpRegs<WL>& r, const float4* __restrict__ p)
 {
-    // 16-byte aligned rows whose word stride is 4 (mod 32): eight consecutive
-    // lanes reading 16 bytes each cover all 32 banks.
-    int words = 2 * wpad;
-    int pad = ((4 - words) % 32 + 32) % 32;
-    return words + pad;
+    typedef float f4v __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int j = 0; j < WL / 2; ++j) {
+        const f4v t = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p + j * 64));
+        r.x[j] = make_float4(t.x, t.y, t.z, t.w);
+    }
 }
 
-// LDS of one wavefront: its tile of kAmpTile rows and the per-event weights.
-__host__ __device__ inline size_t amp_wave_lds_bytes(int wpad)
+// Sum over the 2^lq lanes of an event (xor butterfly; lq is wave-uniform).
+__device__ inline double event_lanes_sum(double x, int lq)
 {
-    return (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4 + kAmpTile * 16;
+    if (lq > 0) x += xor_lane_f64<1>(x);
+    if (lq > 1) x += xor_lane_f64<2>(x);
+    if (lq > 2) x += xor_lane_f64<4>(x);
+    if (lq > 3) x += xor_lane_f64<8>(x);
+    return x;
 }
 
-__host__ __device__ inline size_t amp_lds_bytes(int wpad, int nwaves)
+template <int WL>
+struct AmpLane {
+    const double2* v;        // V of this lane's waves (LDS)
+    double gr[WL], gi[WL];   // sum over its events of c conj(A_a)
+    double dsum;             // ln I of the events whose logarithm it has taken
+    double held;             // intensity waiting for its logarithm (1 when none)
+    int nbad;                // invalid intensities (counted by one lane per event)
+};
+
+template <int WL, bool GRAD>
+__device__ inline void amp_step(AmpRegs<WL>& r, AmpLane<WL>& st, int64_t evt, int64_t n_events,
+                                int lq, int sub, int u)
 {
-    const size_t main = (size_t)wpad * 16 + nwaves * amp_wave_lds_bytes(wpad);
-    const size_t combine = (size_t)wpad * 16 + 2 * 64 * 16 + 16;   // wave combine at the end
-    return main > combine ? main : combine;
+    // V is read from LDS at every step rather than held in registers
+    asm volatile("" ::: "memory");
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int j = 0; j < WL / 2; ++j) {
+        const float4 x = r.x[j];
+        const double2 v0 = st.v[2 * j], v1 = st.v[2 * j + 1];
+        sr += v0.x * (double)x.x - v0.y * (double)x.y;
+        si += v0.x * (double)x.y + v0.y * (double)x.x;
+        sr += v1.x * (double)x.z - v1.y * (double)x.w;
+        si += v1.x * (double)x.w + v1.y * (double)x.z;
+    }
+    if (GRAD) {
+        // convert again for step 3 instead of keeping FP64 copies alive
+#pragma unroll
+        for (int j = 0; j < WL / 2; ++j)
+            asm volatile("" : "+v"(r.x[j].x), "+v"(r.x[j].y), "+v"(r.x[j].z), "+v"(r.x[j].w));
+    }
+    sr = event_lanes_sum(sr, lq);
+    si = event_lanes_sum(si, lq);
+    const double I = sr * sr + si * si;
+    const bool valid = evt < n_events;
+    const bool ok = valid && (I > 0.0) && (I < INFINITY);
+    if (sub == 0 && valid && !ok) ++st.nbad;
+    if (sub == u && ok) st.held = I;
+    if (u == (1 << lq) - 1) {
+        st.dsum += log(st.held);
+        st.held = 1.0;
+    }
+    if (GRAD) {
+        // NaN for a degenerate event (the gradient becomes NaN), 0 for padding
+        const double w = ok ? recip_f64(I) : (valid ? NAN : 0.0);
+        const double cr = sr * w, ci = si * w;
+#pragma unroll
+        for (int j = 0; j < WL / 2; ++j) {
+            const float4 x = r.x[j];
+            st.gr[2 * j] += cr * (double)x.x + ci * (double)x.y;
+            st.gi[2 * j] += ci * (double)x.x - cr * (double)x.y;
+            st.gr[2 * j + 1] += cr * (double)x.z + ci * (double)x.w;
+            st.gi[2 * j + 1] += ci * (double)x.z - cr * (double)x.w;
+        }
+    }
 }
 
-// Wavefronts per block: four unless their tiles would not fit twice per CU.
-inline int amp_waves_per_block(int wpad)
+// One block's share of one evaluation: steps [k0, k1) of the amplitudes at
+// `amp` (shape lq, WL), V (2W doubles) at `v`; one record to `rec`.
+template <int WL, bool GRAD>
+__device__ __attribute__((always_inline)) void amp_block(const float4* __restrict__ amp,
+                                                      int64_t n_events, int64_t k0, int64_t k1,
+                          int W, int lq, const double* __restrict__ v, double* __restrict__ rec)
 {
-    int w = 4;
-    while (w > 1 && amp_lds_bytes(wpad, w) > 80 * 1024) w >>= 1;
-    return w;
-}
-
-// One block's share: tiles [t0, t1) of one evaluation, V (2W doubles) from
-// `v`, one record [sum ln I, n_bad, g_0, ..., g_{W-1}] to `rec`.
-template <int KW, bool GRAD>
-__device__ void amp_block(const float4* __restrict__ amp, int64_t n_events, int64_t t0,
-                          int64_t t1, int W, int wpad, const double* __restrict__ v,
-                          double* __restrict__ rec)
-{
-    extern __shared__ double lds_d[];
-    char* lds = reinterpret_cast<char*>(lds_d);
-    const int stride = amp_lds_stride_words(wpad) * 4;      // bytes per LDS row
+    __shared__ double s_red[kAmpBlockWaves][64 * (WL + 1)];
+    __shared__ double s_tot[kAmpBlockWaves][2 * 16 * WL];
+    __shared__ double s_misc[kAmpBlockWaves][2];
+    __shared__ double2 s_v[16 * WL];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
-    double2* s_v = reinterpret_cast<double2*>(lds);
-    char* tile = lds + (size_t)wpad * 16 + (size_t)wave * amp_wave_lds_bytes(wpad);
-    double2* s_cw = reinterpret_cast<double2*>(tile + kAmpTile * stride);
-    const int h = wpad >> 1;                                 // 16-byte vectors per row
+    const int q = 1 << lq;
+    const int sub = lane & (q - 1);
 
-    for (int a = threadIdx.x; a < wpad; a += blockDim.x)
-        s_v[a] = (a < W) ? make_double2(v[2 * a], v[2 * a + 1]) : make_double2(0.0, 0.0);
+    for (int a = threadIdx.x; a < (WL << lq); a += blockDim.x)
+        s_v[a] = a < W ? make_double2(v[2 * a], v[2 * a + 1]) : make_double2(0.0, 0.0);
     __syncthreads();
-
-    double gr[KW], gi[KW];
+    AmpLane<WL> st;
+    st.v = s_v + sub * WL;
 #pragma unroll
-    for (int s = 0; s < KW; ++s) { gr[s] = 0.0; gi[s] = 0.0; }
-    double dsum = 0.0;
-    int nbad = 0;
-    // adjoint lane mapping for W <= 64: G = 64 / W event groups of W lanes
-    const int G = KW == 1 ? 64 / W : 1;
-    const int a_lane = KW == 1 ? lane % W : lane;
-    const int grp = KW == 1 ? lane / W : 0;
+    for (int k = 0; k < WL; ++k) {
+        st.gr[k] = 0.0;
+        st.gi[k] = 0.0;
+    }
+    st.dsum = 0.0;
+    st.held = 1.0;
+    st.nbad = 0;
 
-    // the block's tiles, interleaved over its wavefronts; each wavefront uses
-    // only its own LDS region, so it synchronises with itself only
-    for (int64_t t = t0 + wave; t < t1; t += nwaves) {
-        const float4* src = amp + t * kAmpTile * h;
-        for (int q = 0; q < h; ++q) {
-            const int f = q * 64 + lane;
-            const float4 val = src[f];
-            const int ev = f / h;
-            const int c = f - ev * h;
-            *reinterpret_cast<float4*>(tile + ev * stride + c * 16) = val;
+    // this wavefront's contiguous part of the block's steps
+    const int64_t n_steps = k1 - k0;
+    const int64_t ka = k0 + n_steps * wave / nwaves;
+    const int64_t kb = k0 + n_steps * (wave + 1) / nwaves;
+    if (ka < kb) {
+        constexpr int64_t kStepVecs = 32 * WL;   // 64 lanes x WL / 2 vectors
+        const float4* base = amp + lane;
+        const int R_shift = 6 - lq;
+        AmpRegs<WL> ra, rb;
+        amp_load(ra, base + ka * kStepVecs);
+        for (int64_t k = ka; k < kb; k += 2) {
+            const bool has_b = k + 1 < kb;
+            if (has_b) amp_load(rb, base + (k + 1) * kStepVecs);
+            amp_step<WL, GRAD>(ra, st, (k << R_shift) + (lane >> lq), n_events, lq, sub,
+                               (int)(k & (q - 1)));
+            if (k + 2 < kb) amp_load(ra, base + (k + 2) * kStepVecs);
+            if (has_b)
+                amp_step<WL, GRAD>(rb, st, ((k + 1) << R_shift) + (lane >> lq), n_events, lq, sub,
+                                   (int)((k + 1) & (q - 1)));
         }
-        wave_lds_sync();
-
-        // lane = event
-        const char* row = tile + lane * stride;
-        double sr = 0.0, si = 0.0;
-        for (int c = 0; c < h; ++c) {
-            const float4 x = *reinterpret_cast<const float4*>(row + c * 16);
-            const double2 v0 = s_v[2 * c], v1 = s_v[2 * c + 1];
-            sr += v0.x * (double)x.x - v0.y * (double)x.y;
-            si += v0.x * (double)x.y + v0.y * (double)x.x;
-            sr += v1.x * (double)x.z - v1.y * (double)x.w;
-            si += v1.x * (double)x.w + v1.y * (double)x.z;
-        }
-        const double I = sr * sr + si * si;
-        const bool valid = t * kAmpTile + lane < n_events;
-        const bool ok = valid && (I > 0.0) && (I < INFINITY);
-        if (ok) dsum += log(I);
-        if (valid && !ok) ++nbad;
-        if (GRAD) {
-            // NaN for a degenerate event (the gradient becomes NaN), 0 for padding
-            const double w = ok ? 1.0 / I : (valid ? NAN : 0.0);
-            s_cw[lane] = make_double2(w * sr, w * si);
-            wave_lds_sync();
-            if (KW == 1) {
-                // lane = (wave a, event group grp): events grp, grp + G, ...,
-                // four at a time with separate partial sums so that the LDS
-                // reads are in flight together
-                if (grp < G) {   // the 64 - G W lanes beyond the groups idle
-                    double pr[4] = {0.0, 0.0, 0.0, 0.0}, pi[4] = {0.0, 0.0, 0.0, 0.0};
-                    int l = grp;
-                    for (; l + 3 * G < kAmpTile; l += 4 * G) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const double2 c = s_cw[l + q * G];
-                            const float2 x = *reinterpret_cast<const float2*>(
-                                tile + (l + q * G) * stride + a_lane * 8);
-                            pr[q] += c.x * (double)x.x + c.y * (double)x.y;
-                            pi[q] += c.y * (double)x.x - c.x * (double)x.y;
-                        }
-                    }
-                    for (; l < kAmpTile; l += G) {
-                        const double2 c = s_cw[l];
-                        const float2 x =
-                            *reinterpret_cast<const float2*>(tile + l * stride + a_lane * 8);
-                        pr[0] += c.x * (double)x.x + c.y * (double)x.y;
-                        pi[0] += c.y * (double)x.x - c.x * (double)x.y;
-                    }
-                    gr[0] += (pr[0] + pr[1]) + (pr[2] + pr[3]);
-                    gi[0] += (pi[0] + pi[1]) + (pi[2] + pi[3]);
-                }
-            } else {
-                // lane = wave (two per lane beyond 64 waves)
-                for (int l = 0; l < kAmpTile; ++l) {
-                    const double2 c = s_cw[l];
-                    const float2* rl = reinterpret_cast<const float2*>(tile + l * stride);
-#pragma unroll
-                    for (int s = 0; s < KW; ++s) {
-                        const int a = lane + 64 * s;
-                        if (a < W) {
-                            const float2 x = rl[a];
-                            gr[s] += c.x * (double)x.x + c.y * (double)x.y;
-                            gi[s] += c.y * (double)x.x - c.x * (double)x.y;
-                        }
-                    }
-                }
-            }
-        }
-        wave_lds_sync();
+        st.dsum += log(st.held);   // a run cut short by the end of the range
     }
 
-    // combine the block's wavefronts in a fixed order (reusing wave 0's tile)
-    dsum = wave_allsum(dsum);
-    nbad = wave_allsum_int(nbad);
-    if (KW == 1 && GRAD) {
-        // fold the event groups of each wave a into lane a, in group order,
-        // through this wavefront's own tile region
-        double2* s_fold = reinterpret_cast<double2*>(tile);
-        wave_lds_sync();
-        s_fold[lane] = make_double2(gr[0], gi[0]);
-        wave_lds_sync();
-        if (lane < W) {
-            double xr = 0.0, xi = 0.0;
-            for (int q = 0; q < G; ++q) {
-                xr += s_fold[q * W + lane].x;
-                xi += s_fold[q * W + lane].y;
-            }
-            gr[0] = xr;
-            gi[0] = xi;
-        } else {
-            gr[0] = 0.0;
-            gi[0] = 0.0;
-        }
-        wave_lds_sync();
-    }
-    __syncthreads();
-    double2* s_g = reinterpret_cast<double2*>(lds + (size_t)wpad * 16);
-    double* s_misc = reinterpret_cast<double*>(s_g + 2 * 64);   // after KW <= 2 slots of 64
-    for (int w = 0; w < nwaves; ++w) {
-        if (wave == w) {
-#pragma unroll
-            for (int s = 0; s < KW; ++s) {
-                double2 g = make_double2(gr[s], gi[s]);
-                if (w > 0) {
-                    const double2 o = s_g[s * 64 + lane];
-                    g.x += o.x;
-                    g.y += o.y;
-                }
-                s_g[s * 64 + lane] = g;
-            }
-            if (lane == 0) {
-                s_misc[0] = (w > 0 ? s_misc[0] : 0.0) + dsum;
-                s_misc[1] = (w > 0 ? s_misc[1] : 0.0) + (double)nbad;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        rec[0] = s_misc[0];
-        rec[1] = s_misc[1];
+    const double dsum = wave_allsum(st.dsum);
+    const int nbad = wave_allsum_int(st.nbad);
+    if (lane == 0) {
+        s_misc[wave][0] = dsum;
+        s_misc[wave][1] = (double)nbad;
     }
     if (GRAD) {
-        for (int a = threadIdx.x; a < W; a += blockDim.x) {
-            rec[2 + 2 * a] = s_g[a].x;
-            rec[3 + 2 * a] = s_g[a].y;
+        // lanes of the same sub-lane index hold the same waves: sum them in
+        // lane order, real parts then imaginary parts
+        double* red = s_red[wave];
+        const int n_out = WL << lq;   // padded row length
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri) {
+            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < WL; ++k) red[lane * (WL + 1) + k] = ri ? st.gi[k] : st.gr[k];
+            wave_lds_sync();
+            for (int o = lane; o < n_out; o += 64) {
+                const int s = o / WL, k = o - s * WL;
+                double x = 0.0;
+                for (int e = 0; e < (64 >> lq); ++e) x += red[((e << lq) + s) * (WL + 1) + k];
+                s_tot[wave][2 * o + ri] = x;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double d = 0.0, b = 0.0;
+        for (int w = 0; w < nwaves; ++w) {
+            d += s_misc[w][0];
+            b += s_misc[w][1];
+        }
+        rec[0] = d;
+        rec[1] = b;
+    }
+    if (GRAD) {
+        for (int o = threadIdx.x; o < 2 * W; o += blockDim.x) {
+            double x = 0.0;
+            for (int w = 0; w < nwaves; ++w) x += s_tot[w][o];
+            rec[2 + o] = x;
         }
     }
 }
 
-template <int KW, bool GRAD>
-__global__ __launch_bounds__(256) void k_amp_fused(const float4* __restrict__ amp, int64_t n_events,
-                                                   int64_t n_tiles, int W, int wpad, VParams vp,
-                                                   double* __restrict__ partials, int rec_len)
+template <int WL, bool GRAD>
+__global__ __launch_bounds__(64 * kAmpBlockWaves) void k_amp_fused(
+    const float4* __restrict__ amp, int64_t n_events, int64_t n_steps, int W, int lq, VParams vp,
+    double* __restrict__ partials, int rec_len)
 {
-    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
-    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
-    amp_block<KW, GRAD>(amp, n_events, t0, t1, W, wpad, vp.v,
+    const int64_t k0 = (int64_t)blockIdx.x * n_steps / gridDim.x;
+    const int64_t k1 = (int64_t)(blockIdx.x + 1) * n_steps / gridDim.x;
+    amp_block<WL, GRAD>(amp, n_events, k0, k1, W, lq, vp.v,
                         partials + (int64_t)blockIdx.x * rec_len);
 }
 
 // ---- many evaluations, possibly of different models, in one launch --------
-// Block u takes work unit u: tiles [t0, t1) of job units[u].job, whose V is at
+// Block u takes work unit u: steps [k0, k1) of job units[u].job, whose V is at
 // params + job.v_off; its record is record u (stride rec_stride doubles).
-template <int KW>
-__global__ __launch_bounds__(256) void k_amp_multi(const MultiJob* __restrict__ jobs,
-                                                   const MultiUnit* __restrict__ units,
-                                                   const double* __restrict__ params,
-                                                   double* __restrict__ recs, int rec_stride,
-                                                   int unit_off)
+template <int WL>
+__global__ __launch_bounds__(64 * kAmpBlockWaves) void k_amp_multi(
+    const MultiJob* __restrict__ jobs, const MultiUnit* __restrict__ units,
+    const double* __restrict__ params, double* __restrict__ recs, int rec_stride, int unit_off)
 {
     const int u_idx = unit_off + blockIdx.x;
     const MultiUnit u = units[u_idx];
     const MultiJob j = jobs[u.job];
-    amp_block<KW, true>((const float4*)j.amp, j.n_events, u.t0, u.t1, j.W, j.wpad,
+    amp_block<WL, true>((const float4*)j.amp, j.n_events, u.k0, u.k1, j.W, j.lq,
                         params + j.v_off, recs + (int64_t)u_idx * rec_stride);
 }
 
-// width classes: rows of at most 16, 32, 48, 64 and 128 waves
-int amp_multi_class(int wpad)
+int amp_multi_class(int wl) { return wl / 2 - 1; }
+
+template <int WL>
+static hipError_t launch_multi_class(const MultiLaunch& ml, const MultiClass& k, hipStream_t s)
 {
-    return wpad <= 16 ? 0 : wpad <= 32 ? 1 : wpad <= 48 ? 2 : wpad <= 64 ? 3 : 4;
+    hipLaunchKernelGGL((k_amp_multi<WL>), dim3(k.n_units), dim3(64 * kAmpBlockWaves), 0, s,
+                       ml.jobs, ml.units, ml.params, ml.recs, ml.rec_stride, k.unit_off);
+    return hipGetLastError();
 }
 
 hipError_t launch_amp_multi(const MultiLaunch& ml, hipStream_t s)
@@ -265,100 +257,99 @@ hipError_t launch_amp_multi(const MultiLaunch& ml, hipStream_t s)
     for (int c = 0; c < ml.n_classes; ++c) {
         const MultiClass& k = ml.cls[c];
         if (k.n_units == 0) continue;
-        const int waves = amp_waves_per_block(k.wpad);
-        const size_t lds = amp_lds_bytes(k.wpad, waves);
-        const dim3 grid(k.n_units), block(64 * waves);
-        if (k.wpad <= 64)
-            hipLaunchKernelGGL((k_amp_multi<1>), grid, block, lds, s, ml.jobs, ml.units, ml.params,
-                               ml.recs, ml.rec_stride, k.unit_off);
-        else
-            hipLaunchKernelGGL((k_amp_multi<2>), grid, block, lds, s, ml.jobs, ml.units, ml.params,
-                               ml.recs, ml.rec_stride, k.unit_off);
-        const hipError_t e = hipGetLastError();
+        hipError_t e = hipErrorInvalidValue;
+        switch (k.wl) {
+        case 2: e = launch_multi_class<2>(ml, k, s); break;
+        case 4: e = launch_multi_class<4>(ml, k, s); break;
+        case 6: e = launch_multi_class<6>(ml, k, s); break;
+        case 8: e = launch_multi_class<8>(ml, k, s); break;
+        case 10: e = launch_multi_class<10>(ml, k, s); break;
+        case 12: e = launch_multi_class<12>(ml, k, s); break;
+        case 14: e = launch_multi_class<14>(ml, k, s); break;
+        case 16: e = launch_multi_class<16>(ml, k, s); break;
+        default: break;
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-int amp_multi_waves(int wpad) { return amp_waves_per_block(wpad); }
-
-hipError_t amp_multi_prepare(int wpad)
+template <int WL>
+static int amp_grid_wl(const Model& m)
 {
-    const size_t lds = amp_lds_bytes(wpad, amp_waves_per_block(wpad));
-    if (lds > 65536) {
-        const void* fns[] = {(const void*)&k_amp_multi<1>, (const void*)&k_amp_multi<2>};
-        for (const void* f : fns) {
-            const hipError_t e =
-                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-        }
-    }
-    return hipSuccess;
-}
-
-template <int KW>
-static const void* amp_symbol()
-{
-    return (const void*)&k_amp_fused<KW, true>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_amp_fused<WL, true>,
+                                                     64 * kAmpBlockWaves, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int64_t n_steps = m.n_tiles << m.amp_lq;
+    int64_t g = (int64_t)m.cus * per_cu;
+    // at least 4 steps per wavefront
+    const int64_t max_blocks = (n_steps + 4 * kAmpBlockWaves - 1) / (4 * kAmpBlockWaves);
+    if (g > max_blocks) g = max_blocks;
+    return (int)(g < 1 ? 1 : g);
 }
 
 int amp_fused_grid(Model& m)
 {
-    const int nw = amp_waves_per_block(m.wpad);
-    m.amp_waves = nw;
-    const void* fn = (m.wpad <= 64) ? amp_symbol<1>() : amp_symbol<2>();
-    const size_t lds = amp_lds_bytes(m.wpad, nw);
-    if (lds > 65536) {
-        // wide rows: allow more than the default 64 KB of dynamic LDS
-        const void* fns[] = {(const void*)&k_amp_fused<1, true>, (const void*)&k_amp_fused<1, false>,
-                             (const void*)&k_amp_fused<2, true>, (const void*)&k_amp_fused<2, false>};
-        for (const void* f : fns)
-            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    m.amp_waves = kAmpBlockWaves;
+    switch (m.amp_wl) {
+    case 2: return amp_grid_wl<2>(m);
+    case 4: return amp_grid_wl<4>(m);
+    case 6: return amp_grid_wl<6>(m);
+    case 8: return amp_grid_wl<8>(m);
+    case 10: return amp_grid_wl<10>(m);
+    case 12: return amp_grid_wl<12>(m);
+    case 14: return amp_grid_wl<14>(m);
+    default: return amp_grid_wl<16>(m);
     }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * nw, lds) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    int64_t g = (int64_t)m.cus * per_cu;
-    const int64_t max_blocks = (m.n_tiles + nw - 1) / nw;
-    if (g > max_blocks) g = max_blocks;
-    return (int)(g < 1 ? 1 : g);
+}
+
+template <int WL>
+static hipError_t launch_amp_wl(const Model& m, const VParams& vp, bool grad, hipStream_t s,
+                                const LaunchEvents& ev)
+{
+    const float4* a = (const float4*)m.d_data;
+    const int64_t n_steps = m.n_tiles << m.amp_lq;
+    const dim3 grid(m.grid), block(64 * kAmpBlockWaves);
+    if (grad)
+        hipExtLaunchKernelGGL((k_amp_fused<WL, true>), grid, block, 0, s, ev.start, ev.stop, 0, a,
+                              m.n, n_steps, m.W, m.amp_lq, vp, m.d_partials, m.rec_len);
+    else
+        hipExtLaunchKernelGGL((k_amp_fused<WL, false>), grid, block, 0, s, ev.start, ev.stop, 0, a,
+                              m.n, n_steps, m.W, m.amp_lq, vp, m.d_partials, m.rec_len);
+    return hipGetLastError();
 }
 
 hipError_t launch_amp_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s,
                             const LaunchEvents& ev)
 {
-    const int nw = m.amp_waves;
-    const size_t lds = amp_lds_bytes(m.wpad, nw);
-    const float4* a = (const float4*)m.d_data;
-    const dim3 grid(m.grid), block(64 * nw);
-    const hipEvent_t t0 = ev.start, t1 = ev.stop;
-    if (m.wpad <= 64) {
-        if (grad)
-            hipExtLaunchKernelGGL((k_amp_fused<1, true>), grid, block, lds, s, t0, t1, 0, a, m.n,
-                                  m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
-        else
-            hipExtLaunchKernelGGL((k_amp_fused<1, false>), grid, block, lds, s, t0, t1, 0, a, m.n,
-                                  m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
-    } else {
-        if (grad)
-            hipExtLaunchKernelGGL((k_amp_fused<2, true>), grid, block, lds, s, t0, t1, 0, a, m.n,
-                                  m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
-        else
-            hipExtLaunchKernelGGL((k_amp_fused<2, false>), grid, block, lds, s, t0, t1, 0, a, m.n,
-                                  m.n_tiles, m.W, m.wpad, vp, m.d_partials, m.rec_len);
+    switch (m.amp_wl) {
+    case 2: return launch_amp_wl<2>(m, vp, grad, s, ev);
+    case 4: return launch_amp_wl<4>(m, vp, grad, s, ev);
+    case 6: return launch_amp_wl<6>(m, vp, grad, s, ev);
+    case 8: return launch_amp_wl<8>(m, vp, grad, s, ev);
+    case 10: return launch_amp_wl<10>(m, vp, grad, s, ev);
+    case 12: return launch_amp_wl<12>(m, vp, grad, s, ev);
+    case 14: return launch_amp_wl<14>(m, vp, grad, s, ev);
+    case 16: return launch_amp_wl<16>(m, vp, grad, s, ev);
+    default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
-// complex64 padded copy of the amplitudes (complex128 input rounded to nearest)
-__global__ void k_pack_amp(const void* __restrict__ src, bool c128, int64_t n, int W, int wpad,
-                           int64_t total, float2* __restrict__ dst)
+// Lane-split complex64 copy of the amplitudes (complex128 input rounded to
+// nearest); one thread per stored complex64, zero for padding.
+__global__ void k_pack_amp(const void* __restrict__ src, bool c128, int64_t n, int W, int lq,
+                           int wl, int64_t total, float2* __restrict__ dst)
 {
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
          g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = g / wpad;
-        const int a = (int)(g % wpad);
+        const int64_t f4 = g >> 1;                  // vector index
+        const int64_t k = f4 / (32 * wl);           // step
+        const int rem = (int)(f4 - k * (32 * wl));
+        const int j = rem >> 6, lane = rem & 63;
+        const int64_t i = (k << (6 - lq)) + (lane >> lq);
+        const int a = (lane & ((1 << lq) - 1)) * wl + 2 * j + (int)(g & 1);
         float2 x = make_float2(0.f, 0.f);
         if (i < n && a < W) {
             if (c128) {
@@ -372,14 +363,14 @@ __global__ void k_pack_amp(const void* __restrict__ src, bool c128, int64_t n, i
     }
 }
 
-hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, int wpad,
+hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, AmpShape sh,
                            int64_t n_pad, float* dst, hipStream_t s)
 {
-    const int64_t total = n_pad * wpad;
+    const int64_t total = n_pad * ((int64_t)sh.wl << sh.lq);
     int64_t g = (total + 255) / 256;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_pack_amp, dim3((int)g), dim3(256), 0, s, src, src_c128, n, W, wpad,
-                       total, (float2*)dst);
+    hipLaunchKernelGGL(k_pack_amp, dim3((int)g), dim3(256), 0, s, src, src_c128, n, W, sh.lq,
+                       sh.wl, total, (float2*)dst);
     return hipGetLastError();
 }
 
@@ -395,7 +386,8 @@ namespace pwa {
 // H = sum_i J_i J_i^T over theta = (Re V_0, Im V_0, Re V_1, ...), with
 // J_i = grad_theta ln I_i = 2 [Re z_ib, -Im z_ib]_b / I_i and z_ib = conj(S_i) A_ib
 // (the derivative of Eq. 1).  Per block, tiles of 64 events:
-//   1. the tile's amplitudes into LDS (coalesced 16-byte loads);
+//   1. the tile's amplitudes into LDS, one row per event (coalesced 16-byte
+//      loads of the lane-split layout);
 //   2. wavefront 0, lane = event: S_i and w_i = 1 / I_i in FP64;
 //   3. all threads: J_i into LDS as a 64 x PJ array (PJ = 2W rounded up to 4);
 //   4. thread t: the 4 x 4 blocks (bp, bq), bp <= bq, numbered t % npair, over
@@ -403,6 +395,15 @@ namespace pwa {
 //      than 256 pairs), 16 FP64 accumulators per block.
 // Record per block: [n_bad, then 16 doubles per block pair].
 constexpr int kHessThreads = 256;
+
+__host__ __device__ inline int amp_lds_stride_words(int wpad)
+{
+    // 16-byte aligned rows whose word stride is 4 (mod 32): eight consecutive
+    // lanes reading 16 bytes each cover all 32 banks.
+    int words = 2 * wpad;
+    int pad = ((4 - words) % 32 + 32) % 32;
+    return words + pad;
+}
 
 __host__ __device__ inline int hess_pj(int W) { return (2 * W + 3) / 4 * 4; }
 __host__ __device__ inline int hess_npair(int W)
@@ -424,8 +425,8 @@ __host__ __device__ inline size_t hess_lds_bytes(int wpad)
 
 __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __restrict__ amp,
                                                               int64_t n_events, int64_t n_tiles,
-                                                              int W, int wpad, VParams vp,
-                                                              double* __restrict__ recs)
+                                                              int W, int wpad, int lq, int wl,
+                                                              VParams vp, double* __restrict__ recs)
 {
     extern __shared__ double lds_d[];
     char* lds = reinterpret_cast<char*>(lds_d);
@@ -473,8 +474,12 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
     const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
     for (int64_t t = t0; t < t1; ++t) {
         const float4* src = amp + t * kAmpTile * h;
+        // lane-split layout -> one LDS row per event (16-byte column c)
         for (int f = tid; f < kAmpTile * h; f += blockDim.x) {
-            const int ev = f / h, c = f - ev * h;
+            const int kl = f / (32 * wl), rem = f - kl * 32 * wl;
+            const int j = rem >> 6, ln = rem & 63;
+            const int ev = (kl << (6 - lq)) + (ln >> lq);
+            const int c = (ln & ((1 << lq) - 1)) * (wl >> 1) + j;
             *reinterpret_cast<float4*>(tile + ev * stride + c * 16) = src[f];
         }
         __syncthreads();
@@ -617,7 +622,8 @@ hipError_t launch_hessian(const Model& m, const VParams& vp, double* recs, doubl
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_amp_hessian, dim3(hess_grid(m)), dim3(kHessThreads), lds, s,
-                       (const float4*)m.d_data, m.n, m.n_tiles, m.W, m.wpad, vp, recs);
+                       (const float4*)m.d_data, m.n, m.n_tiles, m.W, m.wpad, m.amp_lq, m.amp_wl,
+                       vp, recs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hess_assemble, dim3(hess_assemble_blocks(m.W)), dim3(256), 0, s, recs,

@@ -245,13 +245,16 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         m->rows = 0;
         m->rec_len = 2 + 2 * W;
     } else {   // amplitude form
-        m->wpad = W + (W & 1);
+        const pwa::AmpShape sh = pwa::amp_shape(W);
+        m->amp_lq = sh.lq;
+        m->amp_wl = sh.wl;
+        m->wpad = sh.wl << sh.lq;
         m->n_tiles = (n + pwa::kAmpTile - 1) / pwa::kAmpTile;
         const int64_t n_pad = m->n_tiles * pwa::kAmpTile;
         m->data_bytes = n_pad * m->wpad * 8;
         HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
         HIP_TRY(hipEventRecord(bt[0], s));
-        HIP_TRY(pwa::launch_pack_amp(sd.ptr, data_c128, n, W, m->wpad, n_pad, (float*)m->d_data, s));
+        HIP_TRY(pwa::launch_pack_amp(sd.ptr, data_c128, n, W, sh, n_pad, (float*)m->d_data, s));
         HIP_TRY(hipEventRecord(bt[1], s));
         m->grid = pwa::amp_fused_grid(*m);
         m->rows = m->grid;
@@ -455,8 +458,9 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
     std::vector<pwa::MultiJob> jobs;
     std::vector<pwa::MultiUnit> units;
     std::vector<pwa::AsmBlock> asmb;
-    int wmax = 1, wpad_max = 2;
-    int64_t total_tiles = 0;
+    int wmax = 1;
+    int64_t total_bytes = 0;
+    std::vector<const Model*> job_model;
     int32_t out_off = 0, done_off = 0, v_off = 1;   // the completion value comes first
     for (int mi = 0; mi < n_models; ++mi) {
         const Model* m = reinterpret_cast<const Model*>(models[mi]);
@@ -468,11 +472,14 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
             j.n_events = m->n;
             j.W = m->W;
             j.wpad = m->wpad;
+            j.lq = m->amp_lq;
+            j.wl = m->amp_wl;
             j.v_off = v_off;
             j.out_off = out_off;
             j.done_off = done_off;
             j.M = (const double2*)m->d_M;
             jobs.push_back(j);
+            job_model.push_back(m);
             p->job_w.push_back(m->W);
             p->out_off.push_back(out_off);
             p->v_off.push_back(v_off);
@@ -480,36 +487,27 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
             out_off += 2 + 2 * m->W;
             done_off += 1 + m->W;
             wmax = std::max<int>(wmax, m->W);
-            wpad_max = std::max<int>(wpad_max, m->wpad);
-            total_tiles += m->n_tiles;
+            total_bytes += m->data_bytes;
         }
     }
     p->n_jobs = (int)jobs.size();
-    const int64_t tpu = std::max<int64_t>(8, (total_tiles + 2047) / 2048);
-    // units grouped by width class: class c's units are contiguous
+    // work units of about equal bytes, about 2048 in all (at least 256 KB and
+    // 16 steps each); a unit is one block of the amplitude kernel
+    const int64_t unit_bytes = std::max<int64_t>(256 << 10, (total_bytes + 2047) / 2048);
     std::vector<std::vector<pwa::MultiUnit>> by_class(pwa::kMultiClasses);
     for (int ji = 0; ji < p->n_jobs; ++ji) {
-        const Model* m = nullptr;
-        {
-            int acc = 0;
-            for (int mi = 0; mi < n_models; ++mi) {
-                if (ji < acc + k_per_model[mi]) {
-                    m = reinterpret_cast<const Model*>(models[mi]);
-                    break;
-                }
-                acc += k_per_model[mi];
-            }
-        }
-        const int64_t nt = m->n_tiles;
-        const int64_t nu = std::max<int64_t>(1, (nt + tpu - 1) / tpu);
-        std::vector<pwa::MultiUnit>& cu = by_class[pwa::amp_multi_class(m->wpad)];
+        const Model* m = job_model[ji];
+        const int64_t ns = m->n_tiles << m->amp_lq;
+        const int64_t spu = std::max<int64_t>(16, unit_bytes / (512 * (int64_t)m->amp_wl));
+        const int64_t nu = std::max<int64_t>(1, (ns + spu - 1) / spu);
+        std::vector<pwa::MultiUnit>& cu = by_class[pwa::amp_multi_class(m->amp_wl)];
         jobs[ji].rec0 = (int32_t)cu.size();   // offset within its class for now
         jobs[ji].nrec = (int32_t)nu;
         for (int64_t u = 0; u < nu; ++u) {
             pwa::MultiUnit mu{};
             mu.job = ji;
-            mu.t0 = u * nt / nu;
-            mu.t1 = (u + 1) * nt / nu;
+            mu.k0 = u * ns / nu;
+            mu.k1 = (u + 1) * ns / nu;
             cu.push_back(mu);
         }
         for (int r = 0; r <= jobs[ji].W; ++r) asmb.push_back(pwa::AsmBlock{ji, r});
@@ -519,20 +517,11 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
     std::vector<int> class_off(pwa::kMultiClasses, 0);
     for (int c = 0; c < pwa::kMultiClasses; ++c) {
         class_off[c] = (int)units.size();
-        int wpc = 2;
-        for (const auto& mu : by_class[c]) wpc = std::max<int>(wpc, jobs[mu.job].wpad);
-        ml.cls[c] = pwa::MultiClass{(int)units.size(), (int)by_class[c].size(), wpc};
+        ml.cls[c] = pwa::MultiClass{(int)units.size(), (int)by_class[c].size(), 2 * c + 2};
         units.insert(units.end(), by_class[c].begin(), by_class[c].end());
     }
-    for (int ji = 0; ji < p->n_jobs; ++ji) {
-        int w = 0;
-        for (int mi = 0, acc = 0; mi < n_models; acc += k_per_model[mi], ++mi)
-            if (ji < acc + k_per_model[mi]) {
-                w = reinterpret_cast<const Model*>(models[mi])->wpad;
-                break;
-            }
-        jobs[ji].rec0 += class_off[pwa::amp_multi_class(w)];
-    }
+    for (int ji = 0; ji < p->n_jobs; ++ji)
+        jobs[ji].rec0 += class_off[pwa::amp_multi_class(job_model[ji]->amp_wl)];
     DeviceGuard g(p->device);
     const size_t jb = sizeof(pwa::MultiJob) * jobs.size();
     const size_t ub = sizeof(pwa::MultiUnit) * units.size();
@@ -563,8 +552,6 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
     ml.rec_stride = rec_stride;
     ml.n_units = (int)units.size();
     ml.n_asm = (int)asmb.size();
-    for (int c = 0; c < ml.n_classes; ++c)
-        if (ml.cls[c].n_units > 0) HIP_TRY(pwa::amp_multi_prepare(ml.cls[c].wpad));
     // capture [parameter copy, amplitude kernel, assembly] once
     HIP_TRY(hipStreamCreate(&p->cap));
     HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));

@@ -13,8 +13,41 @@ namespace pwa {
 
 // Events per tile of the tiled table layout (see k_table.hip).
 constexpr int kTileEvents = 16;
-// Events per tile of the amplitude kernel (one wavefront's worth).
+// Events per tile of the FP32 amplitude layout (padding unit).
 constexpr int kAmpTile = 64;
+
+// Lane-split layout of the FP32 amplitude form (k_amp.hip): an event is held
+// by q = 2^lq neighbouring lanes with wl (even) waves each, so rows are q wl
+// waves long.  Chosen per W for the fewest padded waves; among equal row
+// lengths, the largest wl up to 10 (fewer lanes repeat the per-event work,
+// while the registers per lane stay moderate), else the smallest.
+constexpr int kAmpMaxLaneWaves = 16;
+struct AmpShape {
+    int lq, wl;
+};
+__host__ __device__ inline AmpShape amp_shape(int W)
+{
+    AmpShape best{0, 0};
+    int best_len = 1 << 30;
+    for (int lq = 0; lq <= 4; ++lq) {
+        const int q = 1 << lq;
+        int wl = (W + q - 1) / q;
+        wl += wl & 1;
+        if (wl < 2) wl = 2;
+        if (wl > kAmpMaxLaneWaves) continue;
+        const int len = q * wl;
+        bool take = len < best_len;
+        if (len == best_len) {
+            const bool cur_small = best.wl <= 10, new_small = wl <= 10;
+            take = (new_small && (!cur_small || wl > best.wl)) || (!new_small && !cur_small && wl < best.wl);
+        }
+        if (take) {
+            best_len = len;
+            best = AmpShape{lq, wl};
+        }
+    }
+    return best;
+}
 
 enum Form : uint32_t {
     kTable32 = PWA_FORM_TABLE,
@@ -45,7 +78,9 @@ struct Model {
     int64_t n = 0;           // data events
     int32_t W = 0;           // waves
     int32_t P = 0;           // packed entries W(W+1)/2
-    int32_t wpad = 0;        // amplitude row length (even) for the amplitude form
+    int32_t wpad = 0;        // amplitude row length q wl (FP32 amplitude form)
+    int32_t amp_lq = 0;      // FP32 amplitude form: log2 of the lanes per event
+    int32_t amp_wl = 2;      // FP32 amplitude form: waves per lane
     int64_t n_tiles = 0;     // tiles of the main kernel's layout
     int32_t grid = 0;        // blocks of the main kernel
     int32_t cus = 0;         // compute units of the device
@@ -98,6 +133,7 @@ struct MultiJob {
     const void* amp;            // the model's padded complex64 amplitudes
     int64_t n_events;
     int32_t W, wpad;
+    int32_t lq, wl;             // lane-split shape of the amplitudes
     int32_t v_off;              // offset of V in the parameter buffer (doubles)
     int32_t rec0, nrec;         // the job's records: units rec0 .. rec0 + nrec - 1
     int32_t out_off;            // offset of [nll, n_bad, grad] in the output (doubles)
@@ -107,16 +143,15 @@ struct MultiJob {
 };
 struct MultiUnit {
     int32_t job, pad;
-    int64_t t0, t1;             // tiles of 64 events
+    int64_t k0, k1;             // steps (64 / q events each) of the job's amplitudes
 };
 struct AsmBlock {
     int32_t job, role;          // role 0: NLL; 1 + b: gradient component b
 };
-// Units are grouped by row width so that each group's launch sizes its LDS
-// (and so its occupancy) for its own rows.
-constexpr int kMultiClasses = 5;
+// Units are grouped by waves per lane (one kernel instance each).
+constexpr int kMultiClasses = kAmpMaxLaneWaves / 2;
 struct MultiClass {
-    int unit_off, n_units, wpad;
+    int unit_off, n_units, wl;
 };
 struct MultiLaunch {
     const MultiJob* jobs;
@@ -153,7 +188,7 @@ hipError_t launch_pack_tiled(const void* src, bool src_is_table, bool src_c128, 
                              int64_t n_tiles, void* dst, hipStream_t s);
 hipError_t launch_pack_soa(const void* src, bool src_is_table, bool src_c128, int64_t n, int W,
                            int P, const uint32_t* pairs, double* dst, hipStream_t s);
-hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, int wpad,
+hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, AmpShape sh,
                            int64_t n_pad, float* dst, hipStream_t s);
 hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, void* dst,
                                hipStream_t s);
@@ -185,9 +220,7 @@ size_t mfma_vm_bytes(const Model& m, int n_cb);
 hipError_t launch_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s);
 hipError_t launch_amp_multi(const MultiLaunch& ml, hipStream_t s);
 hipError_t launch_assemble_multi(const MultiLaunch& ml, hipStream_t s);
-int amp_multi_waves(int wpad);
-hipError_t amp_multi_prepare(int wpad);
-int amp_multi_class(int wpad);
+int amp_multi_class(int wl);
 hipError_t launch_hessian(const Model& m, const VParams& vp, double* recs, double* out,
                           unsigned long long* done, unsigned long long seq, hipStream_t s);
 int hess_rows(const Model& m);
