@@ -146,6 +146,42 @@ def bench_batched(args):
     return out
 
 
+def bench_amplitude(args):
+    """The FP32 amplitude form at 2M events x 32 waves, 4M accepted MC (the
+    differentiation workload's sizes; flat synthetic amplitudes drawn on the
+    device): NLL+gradient throughput in the default storage shape and in the
+    shape pwa_tune_amplitude_shape picks."""
+    import torch
+    import paper_1108_5673_amd as pwa
+    from paper_1108_5673_amd import synth
+    W, N = 32, 2_000_000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11085673 + 3)
+    ws = synth.wave_set(W)
+    d = synth._amplitudes_torch(N, ws, gen, "cuda")
+    mc = synth._amplitudes_torch(2 * N, ws, gen, "cuda")
+    m = pwa.Model(d, mc, 4 * N, form="amplitude")
+    del d, mc
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([11085673, 32, 1])))
+    pts = [synth.random_v(rng, W) for _ in range(20)]
+    out = {"workload": "amplitude form, 2M events x 32 waves (512 MB complex64), 4M accepted MC; "
+                       "flat synthetic amplitudes; 20 random V (Re, Im ~ N(0, 1))"}
+    for tag in ("default", "tuned"):
+        if tag == "tuned":
+            m.tune_amplitude_shape(5)
+        r = time_model(m, pts, args.steps, args.warmup)
+        kus = 1e3 * r["kernel_ms"]
+        out[tag] = {"shape": list(m.amplitude_shape()), "evals_per_s": r["evals_per_s"],
+                    "kernel_us": kus, "achieved_gbs": 8.0 * W * N / (kus * 1e-6) / 1e9,
+                    "frac_of_8tbs": 8.0 * W * N / (kus * 1e-6) / 8e12}
+        log("amplitude w32 n2m (%s shape %s): %.0f evals/s, kernel %.1f us (%.0f GB/s)"
+            % (tag, out[tag]["shape"], r["evals_per_s"], kus, out[tag]["achieved_gbs"]))
+    m.close()
+    return out
+
+
 def bench_multi(args):
     """64 amplitude-form models of uneven size (W uniform in 8..48, N log-uniform
     in 1e5..4e6, 2N accepted MC each), one NLL+gradient of every model per
@@ -168,6 +204,14 @@ def bench_multi(args):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     log("built 64 uneven models in %.1f s" % (time.perf_counter() - t))
+    # storage shape per model, chosen by timing (pwa_tune_amplitude_shape)
+    t = time.perf_counter()
+    shapes = {}
+    for m in models:
+        sh = "%dx%d" % m.tune_amplitude_shape(5)
+        shapes[sh] = shapes.get(sh, 0) + 1
+    tune_s = time.perf_counter() - t
+    log("tuned the storage shapes in %.1f s: %s" % (tune_s, shapes))
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([11085673, 64, 2])))
     iters = 500
     walk = []
@@ -196,6 +240,7 @@ def bench_multi(args):
            "iteration_ms": 1e3 * dt, "evals_per_s": 64 / dt,
            "events_iter_per_s": n_tot / dt, "achieved_gbs": bytes_it / dt / 1e9,
            "frac_of_8tbs": bytes_it / dt / 8e12, "separate_calls_iteration_ms": 1e3 * dt_seq,
+           "tuned_shapes": shapes, "tuning_s": tune_s,
            "speedup_vs_separate_calls": dt_seq / dt}
     if keep:
         import oracle
@@ -232,6 +277,8 @@ def main():
                     help="skip the 256-vector matrix-core measurement")
     ap.add_argument("--no-multi", action="store_true",
                     help="skip the 64-model batch measurement")
+    ap.add_argument("--no-amplitude", action="store_true",
+                    help="skip the amplitude-form measurement at 2M events x 32 waves")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -323,6 +370,9 @@ def main():
     batched = None
     if not args.no_batched:
         batched = bench_batched(args)
+    amplitude = None
+    if not args.no_amplitude:
+        amplitude = bench_amplitude(args)
     multi = None
     if not args.no_multi:
         multi = bench_multi(args)
@@ -389,6 +439,7 @@ def main():
         "latency_us": f["latency_us"],
         "prefit": prefit,
         "fit": fit_info,
+        "amplitude_w32_n2m": amplitude,
         "batched_k256": batched,
         "multi_model_64": multi,
         "roofline": roofline,

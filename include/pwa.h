@@ -196,10 +196,39 @@ typedef struct pwa_info {
 int pwa_model_info(const pwa_model* model, pwa_info* out);
 
 /* Copy the model's table back in the canonical packed N x P layout (complex64
- * for PWA_FORM_TABLE, complex128 for the FP64 forms); for the 16-bit amplitude
- * forms, the stored amplitudes widened to complex64 (N x W).  Not for
- * PWA_FORM_AMPLITUDE. */
+ * for PWA_FORM_TABLE, complex128 for the FP64 forms); for the amplitude forms,
+ * the stored amplitudes as complex64, N x W row-major (widened from the
+ * 16-bit forms). */
 int pwa_copy_table(const pwa_model* model, void* out_host, void* hip_stream);
+
+/*
+ * Storage shape of a PWA_FORM_AMPLITUDE model (Eq. 1: S_i = sum_a V_a A_ia).
+ * Each event's amplitudes are spread over lanes_per_event (1, 2, 4, 8 or 16)
+ * neighbouring lanes of a wavefront, each holding waves_per_lane (even, 2..16)
+ * of its waves; rows are padded with zero waves to lanes x waves_per_lane >= W.
+ * pwa_build_table picks the shape with the fewest padded waves, counting rows
+ * of more than 10 waves per lane 25 % longer (such lanes need more registers,
+ * which halves the wavefronts in flight); among equal costs, the largest
+ * waves_per_lane up to 10, else the smallest.
+ *
+ * pwa_set_amplitude_shape re-stores the amplitudes in another shape (device
+ * memory for one extra N x W complex64 copy is taken while it runs); it
+ * returns PWA_ERR_INVALID for a shape that does not hold W waves.  Results of
+ * every shape agree to FP64 rounding; for a given shape they repeat bit for
+ * bit.  pwa_tune_amplitude_shape times `evals` gradient evaluations of the
+ * streaming kernel in each candidate shape (per lane count, the fewest waves
+ * per lane that hold W, when the row is at most 25 % longer than the
+ * shortest), leaves the model in the fastest and returns it (either output
+ * pointer may be NULL).  Both synchronise hip_stream and must not run
+ * concurrently with evaluations of the model; a cached multi-model plan that
+ * uses the model is rebuilt at its next call.
+ */
+int pwa_get_amplitude_shape(const pwa_model* model, int32_t* lanes_per_event,
+                            int32_t* waves_per_lane);
+int pwa_set_amplitude_shape(pwa_model* model, int32_t lanes_per_event, int32_t waves_per_lane,
+                            void* hip_stream);
+int pwa_tune_amplitude_shape(pwa_model* model, int32_t evals, void* hip_stream,
+                             int32_t* lanes_per_event, int32_t* waves_per_lane);
 
 /* Copy M (W x W complex128, row-major) to host memory. */
 int pwa_copy_mc_matrix(const pwa_model* model, double* out_host, void* hip_stream);

@@ -180,9 +180,9 @@ class Model:
         return {k: getattr(inf, k) for k, _ in _native.Info._fields_}
 
     def table(self) -> np.ndarray:
-        """The stored table in canonical packed (N, P) layout; for the 16-bit
+        """The stored table in canonical packed (N, P) layout; for the
         amplitude forms the stored amplitudes as complex64 (N, W)."""
-        if self.form in ("amplitude_bf16", "amplitude_fp16"):
+        if self.form in ("amplitude", "amplitude_bf16", "amplitude_fp16"):
             out = np.zeros((self.n_data, self.n_waves), np.complex64)
         else:
             dt = np.complex64 if self.form == "table" else np.complex128
@@ -202,6 +202,25 @@ class Model:
             raise ValueError("M must be (W, W)")
         _native.check(_native.lib().pwa_set_mc_matrix(self._handle(), a.ctypes.data,
                                                       self._stream))
+
+    def amplitude_shape(self):
+        """(lanes per event, waves per lane) of a FP32 amplitude-form model."""
+        q, wl = ctypes.c_int32(0), ctypes.c_int32(0)
+        _native.check(_native.lib().pwa_get_amplitude_shape(self._handle(), ctypes.byref(q),
+                                                            ctypes.byref(wl)))
+        return q.value, wl.value
+
+    def set_amplitude_shape(self, lanes_per_event: int, waves_per_lane: int) -> None:
+        _native.check(_native.lib().pwa_set_amplitude_shape(self._handle(), int(lanes_per_event),
+                                                            int(waves_per_lane), self._stream))
+
+    def tune_amplitude_shape(self, evals: int = 5):
+        """Time the candidate storage shapes, keep the fastest; returns it."""
+        q, wl = ctypes.c_int32(0), ctypes.c_int32(0)
+        _native.check(_native.lib().pwa_tune_amplitude_shape(self._handle(), int(evals),
+                                                             self._stream, ctypes.byref(q),
+                                                             ctypes.byref(wl)))
+        return q.value, wl.value
 
     def set_timing(self, enable: bool) -> None:
         _native.check(_native.lib().pwa_set_timing(self._handle(), int(bool(enable))))

@@ -34,7 +34,8 @@ EXPORTED = (
     "pwa_last_error", "pwa_model_info", "pwa_copy_table", "pwa_copy_mc_matrix",
     "pwa_set_mc_matrix", "pwa_set_timing", "pwa_get_timing", "pwa_build_timing",
     "pwa_lbfgs_default_options", "pwa_lbfgs_minimize", "pwa_fit_lbfgs", "pwa_nll_grad_hess",
-    "pwa_newton_minimize", "pwa_fit_fumili",
+    "pwa_newton_minimize", "pwa_fit_fumili", "pwa_get_amplitude_shape",
+    "pwa_set_amplitude_shape", "pwa_tune_amplitude_shape",
 )
 
 PWA_LBFGS_CONVERGED_GRADIENT = 0
@@ -123,6 +124,10 @@ def _declare(L):
     L.pwa_copy_mc_matrix.argtypes = [p, p, p]
     L.pwa_set_mc_matrix.argtypes = [p, p, p]
     L.pwa_set_timing.argtypes = [p, ctypes.c_int]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    L.pwa_get_amplitude_shape.argtypes = [p, i32p, i32p]
+    L.pwa_set_amplitude_shape.argtypes = [p, ctypes.c_int32, ctypes.c_int32, p]
+    L.pwa_tune_amplitude_shape.argtypes = [p, ctypes.c_int32, p, i32p, i32p]
     L.pwa_get_timing.argtypes = [p, dp, ctypes.POINTER(i64)]
     L.pwa_build_timing.argtypes = [p, dp, dp]
     L.pwa_lbfgs_default_options.argtypes = [ctypes.POINTER(LbfgsOptions)]

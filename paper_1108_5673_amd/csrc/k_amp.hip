@@ -252,26 +252,21 @@ static hipError_t launch_multi_class(const MultiLaunch& ml, const MultiClass& k,
     return hipGetLastError();
 }
 
-hipError_t launch_amp_multi(const MultiLaunch& ml, hipStream_t s)
+hipError_t launch_amp_multi_class(const MultiLaunch& ml, int c, hipStream_t s)
 {
-    for (int c = 0; c < ml.n_classes; ++c) {
-        const MultiClass& k = ml.cls[c];
-        if (k.n_units == 0) continue;
-        hipError_t e = hipErrorInvalidValue;
-        switch (k.wl) {
-        case 2: e = launch_multi_class<2>(ml, k, s); break;
-        case 4: e = launch_multi_class<4>(ml, k, s); break;
-        case 6: e = launch_multi_class<6>(ml, k, s); break;
-        case 8: e = launch_multi_class<8>(ml, k, s); break;
-        case 10: e = launch_multi_class<10>(ml, k, s); break;
-        case 12: e = launch_multi_class<12>(ml, k, s); break;
-        case 14: e = launch_multi_class<14>(ml, k, s); break;
-        case 16: e = launch_multi_class<16>(ml, k, s); break;
-        default: break;
-        }
-        if (e != hipSuccess) return e;
+    const MultiClass& k = ml.cls[c];
+    if (k.n_units == 0) return hipSuccess;
+    switch (k.wl) {
+    case 2: return launch_multi_class<2>(ml, k, s);
+    case 4: return launch_multi_class<4>(ml, k, s);
+    case 6: return launch_multi_class<6>(ml, k, s);
+    case 8: return launch_multi_class<8>(ml, k, s);
+    case 10: return launch_multi_class<10>(ml, k, s);
+    case 12: return launch_multi_class<12>(ml, k, s);
+    case 14: return launch_multi_class<14>(ml, k, s);
+    case 16: return launch_multi_class<16>(ml, k, s);
+    default: return hipErrorInvalidValue;
     }
-    return hipSuccess;
 }
 
 template <int WL>
@@ -374,6 +369,34 @@ hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, Amp
     return hipGetLastError();
 }
 
+// Row-major complex64 copy (N x W) of amplitudes stored in shape (lq, wl).
+__global__ void k_unpack_amp(const float2* __restrict__ src, int64_t n, int W, int lq, int wl,
+                             float2* __restrict__ dst)
+{
+    const int64_t total = n * W;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = g / W;
+        const int a = (int)(g - i * W);
+        const int64_t k = i >> (6 - lq);                       // step
+        const int lane = ((int)(i & ((64 >> lq) - 1)) << lq) | (a / wl);
+        const int kk = a % wl;
+        dst[g] = src[((k * (wl / 2) + kk / 2) * 64 + lane) * 2 + (kk & 1)];
+    }
+}
+
+hipError_t launch_unpack_amp(const void* src, int64_t n, int W, AmpShape sh, float* dst,
+                             hipStream_t s)
+{
+    const int64_t total = n * W;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_unpack_amp, dim3((int)g), dim3(256), 0, s, (const float2*)src, n, W,
+                       sh.lq, sh.wl, (float2*)dst);
+    return hipGetLastError();
+}
+
 }  // namespace pwa
 
 namespace pwa {
@@ -393,8 +416,12 @@ namespace pwa {
 //   4. thread t: the 4 x 4 blocks (bp, bq), bp <= bq, numbered t % npair, over
 //      the events of its split t / npair (splits of the 64 events when fewer
 //      than 256 pairs), 16 FP64 accumulators per block.
-// Record per block: [n_bad, then 16 doubles per block pair].
+// Beyond 3 x 256 block pairs (W > 76) the pairs form groups along the grid's
+// second dimension, each group streaming the tiles again.  J is held for 64
+// events at a time, or 32 or 16 when the LDS cannot hold 64.
+// Record per block column: [n_bad, then 16 doubles per block pair].
 constexpr int kHessThreads = 256;
+constexpr int kMaxPairs = 3;   // block pairs per thread in one group
 
 __host__ __device__ inline int amp_lds_stride_words(int wpad)
 {
@@ -412,21 +439,30 @@ __host__ __device__ inline int hess_npair(int W)
     return nb * (nb + 1) / 2;
 }
 __host__ __device__ inline int hess_rec_len(int W) { return 1 + 16 * hess_npair(W); }
-__host__ __device__ inline size_t hess_lds_bytes(int wpad)
+// LDS of one block: the amplitude tile, J of ej events at a time, S and w.
+__host__ __device__ inline size_t hess_lds_bytes(int W, int wpad, int ej)
 {
-    const int W = wpad;   // upper bound of the wave count
     const size_t main = (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4   // amplitude tile
-                        + (size_t)kAmpTile * hess_pj(W) * 8                  // J
+                        + (size_t)ej * hess_pj(W) * 8                        // J
                         + (size_t)kAmpTile * 16 + (size_t)kAmpTile * 8       // S, w
                         + 16;                                                // n_bad
     const size_t combine = (size_t)kHessThreads * 16 * 8;   // partial blocks at the end
     return (main > combine ? main : combine) + 16;
 }
 
+// Events whose J are held at once: the whole tile when the LDS allows.
+inline int hess_ej(int W, int wpad)
+{
+    int ej = kAmpTile;
+    while (ej > 16 && hess_lds_bytes(W, wpad, ej) > 160 * 1024) ej >>= 1;
+    return ej;
+}
+
 __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __restrict__ amp,
                                                               int64_t n_events, int64_t n_tiles,
                                                               int W, int wpad, int lq, int wl,
-                                                              VParams vp, double* __restrict__ recs)
+                                                              int ej, VParams vp,
+                                                              double* __restrict__ recs)
 {
     extern __shared__ double lds_d[];
     char* lds = reinterpret_cast<char*>(lds_d);
@@ -436,26 +472,29 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
     const int npair = nb * (nb + 1) / 2;
     char* tile = lds;
     double* s_J = reinterpret_cast<double*>(tile + (size_t)kAmpTile * stride);
-    double2* s_S = reinterpret_cast<double2*>(s_J + (size_t)kAmpTile * PJ);
+    double2* s_S = reinterpret_cast<double2*>(s_J + (size_t)ej * PJ);
     double* s_w = reinterpret_cast<double*>(s_S + kAmpTile);
     // the count sits past both the tile data and the combine area
-    int* s_bad = reinterpret_cast<int*>(lds + hess_lds_bytes(wpad) - 16);
+    int* s_bad = reinterpret_cast<int*>(lds + hess_lds_bytes(W, wpad, ej) - 16);
     const int h = wpad >> 1;
     const int tid = threadIdx.x;
 
-    // this thread's block pairs and event split
-    const int splits = npair >= kHessThreads ? 1 : kHessThreads / npair;
-    const int split = tid / (npair < kHessThreads ? npair : kHessThreads);
-    const int pair0 = tid % (npair < kHessThreads ? npair : kHessThreads);
+    // this block's group of block pairs (blockIdx.y: groups of up to 3 x 256
+    // pairs), this thread's pairs in it and its event split
+    const int pg0 = blockIdx.y * kMaxPairs * kHessThreads;
+    const int npg = min(npair - pg0, kMaxPairs * kHessThreads);
+    const int splits = npg >= kHessThreads ? 1 : kHessThreads / npg;
+    const int split = tid / (npg < kHessThreads ? npg : kHessThreads);
+    const int pair0 = tid % (npg < kHessThreads ? npg : kHessThreads);
     const bool active = split < splits;
-    constexpr int kMaxPairs = 3;   // pairs per thread: npair <= 3 * 256 (W <= 64)
     double acc[kMaxPairs][16];
     int bp[kMaxPairs], bq[kMaxPairs];
 #pragma unroll
     for (int r = 0; r < kMaxPairs; ++r) {
-        const int pr = pair0 + r * kHessThreads;
+        const int pl = pair0 + r * kHessThreads;
+        const int pr = pg0 + pl;
         bp[r] = bq[r] = -1;
-        if (active && (r == 0 || npair > kHessThreads) && pr < npair) {
+        if (active && (r == 0 || npg > kHessThreads) && pl < npg) {
             // pair index -> (bp, bq), row-major upper triangle
             int rem = pr, row = 0;
             while (rem >= nb - row) {
@@ -501,62 +540,66 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
             s_w[tid] = ok ? 2.0 / I : (valid ? NAN : 0.0);
         }
         __syncthreads();
-        for (int f = tid; f < kAmpTile * PJ; f += blockDim.x) {
-            const int ev = f / PJ, p = f - ev * PJ;
-            double j = 0.0;
-            if (p < 2 * W) {
-                const int b = p >> 1;
-                const float2 x = *reinterpret_cast<const float2*>(tile + ev * stride + b * 8);
-                const double2 S = s_S[ev];
-                // z = conj(S) A_b
-                const double zr = S.x * (double)x.x + S.y * (double)x.y;
-                const double zi = S.x * (double)x.y - S.y * (double)x.x;
-                j = s_w[ev] * ((p & 1) ? -zi : zr);
+        // J of ej events at a time (all 64 when the LDS holds them)
+        for (int e0 = 0; e0 < kAmpTile; e0 += ej) {
+            for (int f = tid; f < ej * PJ; f += blockDim.x) {
+                const int ev = e0 + f / PJ, p = f - (ev - e0) * PJ;
+                double j = 0.0;
+                if (p < 2 * W) {
+                    const int b = p >> 1;
+                    const float2 x = *reinterpret_cast<const float2*>(tile + ev * stride + b * 8);
+                    const double2 S = s_S[ev];
+                    // z = conj(S) A_b
+                    const double zr = S.x * (double)x.x + S.y * (double)x.y;
+                    const double zi = S.x * (double)x.y - S.y * (double)x.x;
+                    j = s_w[ev] * ((p & 1) ? -zi : zr);
+                }
+                s_J[f] = j;
             }
-            s_J[f] = j;
-        }
-        __syncthreads();
-        if (active) {
+            __syncthreads();
+            if (active) {
 #pragma unroll
-            for (int r = 0; r < kMaxPairs; ++r) {
-                if (bp[r] < 0) continue;
-                for (int ev = split; ev < kAmpTile; ev += splits) {
-                    const double* Jr = s_J + ev * PJ;
-                    const double2 a01 = *reinterpret_cast<const double2*>(Jr + 4 * bp[r]);
-                    const double2 a23 = *reinterpret_cast<const double2*>(Jr + 4 * bp[r] + 2);
-                    const double2 b01 = *reinterpret_cast<const double2*>(Jr + 4 * bq[r]);
-                    const double2 b23 = *reinterpret_cast<const double2*>(Jr + 4 * bq[r] + 2);
-                    const double ai[4] = {a01.x, a01.y, a23.x, a23.y};
-                    const double bj[4] = {b01.x, b01.y, b23.x, b23.y};
+                for (int r = 0; r < kMaxPairs; ++r) {
+                    if (bp[r] < 0) continue;
+                    for (int ev = split; ev < ej; ev += splits) {
+                        const double* Jr = s_J + ev * PJ;
+                        const double2 a01 = *reinterpret_cast<const double2*>(Jr + 4 * bp[r]);
+                        const double2 a23 = *reinterpret_cast<const double2*>(Jr + 4 * bp[r] + 2);
+                        const double2 b01 = *reinterpret_cast<const double2*>(Jr + 4 * bq[r]);
+                        const double2 b23 = *reinterpret_cast<const double2*>(Jr + 4 * bq[r] + 2);
+                        const double ai[4] = {a01.x, a01.y, a23.x, a23.y};
+                        const double bj[4] = {b01.x, b01.y, b23.x, b23.y};
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
+                        for (int i = 0; i < 4; ++i)
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) acc[r][4 * i + j] += ai[i] * bj[j];
+                            for (int j = 0; j < 4; ++j) acc[r][4 * i + j] += ai[i] * bj[j];
+                    }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // combine the event splits of each pair in split order, write the record
     double* rec = recs + (int64_t)blockIdx.x * hess_rec_len(W);
     double* s_part = reinterpret_cast<double*>(lds);   // reuses the tile area
     for (int r = 0; r < kMaxPairs; ++r) {
-        if (r > 0 && npair <= kHessThreads) break;
+        if (r > 0 && npg <= kHessThreads) break;
         __syncthreads();
         if (active && bp[r] >= 0)
             for (int k = 0; k < 16; ++k) s_part[(size_t)tid * 16 + k] = acc[r][k];
         __syncthreads();
         const int base = r * kHessThreads;
-        const int np_here = min(npair - base, kHessThreads);
+        const int np_here = min(npg - base, kHessThreads);
+        if (np_here <= 0) break;
         for (int e = tid; e < np_here * 16; e += blockDim.x) {
             const int pr = e / 16, k = e % 16;
             double x = 0.0;
-            for (int sp = 0; sp < splits; ++sp) x += s_part[(size_t)(sp * npair + pr) * 16 + k];
-            rec[1 + (size_t)(base + pr) * 16 + k] = x;
+            for (int sp = 0; sp < splits; ++sp) x += s_part[(size_t)(sp * npg + pr) * 16 + k];
+            rec[1 + (size_t)(pg0 + base + pr) * 16 + k] = x;
         }
     }
-    if (tid == 0) rec[0] = (double)*s_bad;
+    if (tid == 0 && blockIdx.y == 0) rec[0] = (double)*s_bad;
 }
 
 // Sum of the block records in block order; one thread per entry of the
@@ -614,16 +657,18 @@ int hess_assemble_blocks(int W) { return (4 * W * W + 255) / 256; }
 hipError_t launch_hessian(const Model& m, const VParams& vp, double* recs, double* out,
                           unsigned long long* done, unsigned long long seq, hipStream_t s)
 {
-    const size_t lds = hess_lds_bytes(m.wpad);
+    const int ej = hess_ej(m.W, m.wpad);
+    const size_t lds = hess_lds_bytes(m.W, m.wpad, ej);
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute((const void*)&k_amp_hessian,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_amp_hessian, dim3(hess_grid(m)), dim3(kHessThreads), lds, s,
+    const int groups = (hess_npair(m.W) + kMaxPairs * kHessThreads - 1) / (kMaxPairs * kHessThreads);
+    hipLaunchKernelGGL(k_amp_hessian, dim3(hess_grid(m), groups), dim3(kHessThreads), lds, s,
                        (const float4*)m.d_data, m.n, m.n_tiles, m.W, m.wpad, m.amp_lq, m.amp_wl,
-                       vp, recs);
+                       ej, vp, recs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hess_assemble, dim3(hess_assemble_blocks(m.W)), dim3(256), 0, s, recs,

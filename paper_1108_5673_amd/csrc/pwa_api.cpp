@@ -409,6 +409,9 @@ struct MultiPlan {
     int n_done = 0;
     pwa::MultiLaunch ml{};
     hipStream_t cap = nullptr;
+    hipStream_t side[pwa::kMultiClasses] = {};   // branches of the graph, one per class
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[pwa::kMultiClasses] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     unsigned long long seq = 0;
@@ -424,6 +427,11 @@ void destroy_plan(MultiPlan* p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap) (void)hipStreamDestroy(p->cap);
+    for (int c = 0; c < pwa::kMultiClasses; ++c) {
+        if (p->side[c]) (void)hipStreamDestroy(p->side[c]);
+        if (p->join[c]) (void)hipEventDestroy(p->join[c]);
+    }
+    if (p->fork) (void)hipEventDestroy(p->fork);
     if (p->d_tables) (void)hipFree(p->d_tables);
     if (p->d_params) (void)hipFree(p->d_params);
     if (p->d_recs) (void)hipFree(p->d_recs);
@@ -491,12 +499,19 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
         }
     }
     p->n_jobs = (int)jobs.size();
-    // work units of about equal bytes, about 2048 in all (at least 256 KB and
-    // 16 steps each); a unit is one block of the amplitude kernel
-    const int64_t unit_bytes = std::max<int64_t>(256 << 10, (total_bytes + 2047) / 2048);
+    (void)total_bytes;
+    // work units of about equal bytes within a class (one launch per class of
+    // waves per lane), about 2048 per class and at least 256 KB and 16 steps
+    // each; a unit is one block of the amplitude kernel, and the hardware hands
+    // units to compute units as they free up
+    std::vector<int64_t> class_bytes(pwa::kMultiClasses, 0);
+    for (int ji = 0; ji < p->n_jobs; ++ji)
+        class_bytes[pwa::amp_multi_class(job_model[ji]->amp_wl)] += job_model[ji]->data_bytes;
     std::vector<std::vector<pwa::MultiUnit>> by_class(pwa::kMultiClasses);
     for (int ji = 0; ji < p->n_jobs; ++ji) {
         const Model* m = job_model[ji];
+        const int c = pwa::amp_multi_class(m->amp_wl);
+        const int64_t unit_bytes = std::max<int64_t>(256 << 10, (class_bytes[c] + 2047) / 2048);
         const int64_t ns = m->n_tiles << m->amp_lq;
         const int64_t spu = std::max<int64_t>(16, unit_bytes / (512 * (int64_t)m->amp_wl));
         const int64_t nu = std::max<int64_t>(1, (ns + spu - 1) / spu);
@@ -552,12 +567,33 @@ int build_plan(pwa_model* const* models, int n_models, const int32_t* k_per_mode
     ml.rec_stride = rec_stride;
     ml.n_units = (int)units.size();
     ml.n_asm = (int)asmb.size();
-    // capture [parameter copy, amplitude kernel, assembly] once
+    // capture [parameter copy, one amplitude launch per class, assembly] once;
+    // the class launches are independent branches of the graph
     HIP_TRY(hipStreamCreate(&p->cap));
+    HIP_TRY(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
+    int first = -1;
+    for (int c = 0; c < ml.n_classes; ++c) {
+        if (ml.cls[c].n_units == 0) continue;
+        if (first < 0) {
+            first = c;
+            continue;
+        }
+        HIP_TRY(hipStreamCreate(&p->side[c]));
+        HIP_TRY(hipEventCreateWithFlags(&p->join[c], hipEventDisableTiming));
+    }
     HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipMemcpyAsync(p->d_params, p->h_params, p->params_bytes, hipMemcpyHostToDevice,
                                   p->cap);
-    if (e == hipSuccess) e = pwa::launch_amp_multi(ml, p->cap);
+    if (e == hipSuccess) e = hipEventRecord(p->fork, p->cap);
+    for (int c = 0; c < ml.n_classes && e == hipSuccess; ++c) {
+        if (!p->side[c]) continue;
+        e = hipStreamWaitEvent(p->side[c], p->fork, 0);
+        if (e == hipSuccess) e = pwa::launch_amp_multi_class(ml, c, p->side[c]);
+        if (e == hipSuccess) e = hipEventRecord(p->join[c], p->side[c]);
+    }
+    if (e == hipSuccess && first >= 0) e = pwa::launch_amp_multi_class(ml, first, p->cap);
+    for (int c = 0; c < ml.n_classes && e == hipSuccess; ++c)
+        if (p->join[c]) e = hipStreamWaitEvent(p->cap, p->join[c], 0);
     if (e == hipSuccess) e = pwa::launch_assemble_multi(ml, p->cap);
     const hipError_t e2 = hipStreamEndCapture(p->cap, &p->graph);
     if (e != hipSuccess) return device_fail(e, "multi-evaluation capture");
@@ -765,6 +801,57 @@ int evaluate(const pwa_model* cm, const double* v, double* nll, double* grad, vo
 }
 
 }  // namespace
+
+// Re-store the FP32 amplitudes of m in shape sh (through a row-major copy).
+int reshape_amp(Model* m, pwa::AmpShape sh, hipStream_t s)
+{
+    if (sh.lq == m->amp_lq && sh.wl == m->amp_wl) return PWA_OK;
+    forget_model(m);   // a cached multi-model plan holds the old layout
+    const int64_t n_pad = m->n_tiles * pwa::kAmpTile;
+    const int64_t new_bytes = n_pad * ((int64_t)sh.wl << sh.lq) * 8;
+    void* tmp = nullptr;
+    void* nd = nullptr;
+    HIP_TRY(hipMalloc(&tmp, std::max<size_t>(8, (size_t)m->n * m->W * 8)));
+    hipError_t e = hipMalloc(&nd, new_bytes);
+    if (e == hipSuccess)
+        e = pwa::launch_unpack_amp(m->d_data, m->n, m->W, pwa::AmpShape{m->amp_lq, m->amp_wl},
+                                   (float*)tmp, s);
+    if (e == hipSuccess) e = pwa::launch_pack_amp(tmp, false, m->n, m->W, sh, n_pad, (float*)nd, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) {
+        if (nd) (void)hipFree(nd);
+        return device_fail(e, "amplitude re-store");
+    }
+    (void)hipFree(m->d_data);
+    m->d_data = nd;
+    m->data_bytes = new_bytes;
+    m->amp_lq = sh.lq;
+    m->amp_wl = sh.wl;
+    m->wpad = sh.wl << sh.lq;
+    const int old_rows = m->rows;
+    m->grid = pwa::amp_fused_grid(*m);
+    m->rows = m->grid;
+    if (m->rows > old_rows) {
+        (void)hipFree(m->d_partials);
+        m->d_partials = nullptr;
+        HIP_TRY(hipMalloc(&m->d_partials, sizeof(double) * (size_t)m->rows * m->rec_len));
+    }
+    return PWA_OK;
+}
+
+bool valid_shape(int W, int lanes, int wl)
+{
+    const bool pow2 = lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16;
+    return pow2 && wl >= 2 && wl <= pwa::kAmpMaxLaneWaves && (wl % 2) == 0 && lanes * wl >= W;
+}
+
+int log2_lanes(int lanes)
+{
+    int lq = 0;
+    while ((1 << lq) < lanes) ++lq;
+    return lq;
+}
 
 extern "C" {
 
@@ -980,9 +1067,20 @@ int pwa_copy_table(const pwa_model* model, void* out_host, void* hip_stream)
 {
     if (!model || !out_host) return fail(PWA_ERR_INVALID, "NULL model or out_host");
     const Model* m = reinterpret_cast<const Model*>(model);
-    if (m->form == pwa::kAmp32) return fail(PWA_ERR_INVALID, "amplitude-form model has no table");
     DeviceGuard g(m->device);
     hipStream_t s = (hipStream_t)hip_stream;
+    if (m->form == pwa::kAmp32) {   // the stored complex64 amplitudes, N x W
+        const size_t bytes = (size_t)m->n * m->W * 8;
+        void* tmp = nullptr;
+        HIP_TRY(hipMalloc(&tmp, std::max<size_t>(bytes, 8)));
+        hipError_t e = pwa::launch_unpack_amp(m->d_data, m->n, m->W,
+                                              pwa::AmpShape{m->amp_lq, m->amp_wl}, (float*)tmp, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(out_host, tmp, bytes, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return device_fail(e, "amplitude copy");
+        return PWA_OK;
+    }
     if (is_mfma(m)) {   // the stored 16-bit amplitudes, widened to complex64
         const size_t bytes = (size_t)m->n * m->W * 8;
         void* tmp = nullptr;
@@ -1033,6 +1131,96 @@ int pwa_set_mc_matrix(pwa_model* model, const double* m_host, void* hip_stream)
     HIP_TRY(hipMemcpyAsync(m->d_M, m_host, sizeof(double) * 2 * m->W * m->W,
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return PWA_OK;
+}
+
+int pwa_get_amplitude_shape(const pwa_model* model, int32_t* lanes_per_event,
+                            int32_t* waves_per_lane)
+{
+    if (!model || !lanes_per_event || !waves_per_lane) return fail(PWA_ERR_INVALID, "NULL argument");
+    const Model* m = reinterpret_cast<const Model*>(model);
+    if (m->form != pwa::kAmp32) return fail(PWA_ERR_INVALID, "not a PWA_FORM_AMPLITUDE model");
+    *lanes_per_event = 1 << m->amp_lq;
+    *waves_per_lane = m->amp_wl;
+    return PWA_OK;
+}
+
+int pwa_set_amplitude_shape(pwa_model* model, int32_t lanes_per_event, int32_t waves_per_lane,
+                            void* hip_stream)
+{
+    if (!model) return fail(PWA_ERR_INVALID, "NULL model");
+    Model* m = reinterpret_cast<Model*>(model);
+    if (m->form != pwa::kAmp32) return fail(PWA_ERR_INVALID, "not a PWA_FORM_AMPLITUDE model");
+    if (!valid_shape(m->W, lanes_per_event, waves_per_lane))
+        return fail(PWA_ERR_INVALID, "shape %d x %d does not hold %d waves (lanes 1..16, power of "
+                    "two; waves per lane even, 2..16)", lanes_per_event, waves_per_lane, m->W);
+    DeviceGuard g(m->device);
+    return reshape_amp(m, pwa::AmpShape{log2_lanes(lanes_per_event), waves_per_lane},
+                       (hipStream_t)hip_stream);
+}
+
+int pwa_tune_amplitude_shape(pwa_model* model, int32_t evals, void* hip_stream,
+                             int32_t* lanes_per_event, int32_t* waves_per_lane)
+{
+    if (!model) return fail(PWA_ERR_INVALID, "NULL model");
+    Model* m = reinterpret_cast<Model*>(model);
+    if (m->form != pwa::kAmp32) return fail(PWA_ERR_INVALID, "not a PWA_FORM_AMPLITUDE model");
+    if (evals < 1) return fail(PWA_ERR_INVALID, "evals must be >= 1");
+    DeviceGuard g(m->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    // candidates: per lane count, the fewest even waves per lane that hold W,
+    // if the row is at most a quarter longer than the shortest one
+    std::vector<pwa::AmpShape> cand;
+    int shortest = 1 << 30;
+    for (int lq = 0; lq <= 4; ++lq) {
+        int wl = (m->W + (1 << lq) - 1) >> lq;
+        wl = std::max(2, wl + (wl & 1));
+        if (wl <= pwa::kAmpMaxLaneWaves) shortest = std::min(shortest, wl << lq);
+    }
+    for (int lq = 0; lq <= 4; ++lq) {
+        int wl = (m->W + (1 << lq) - 1) >> lq;
+        wl = std::max(2, wl + (wl & 1));
+        if (wl <= pwa::kAmpMaxLaneWaves && 4 * (wl << lq) <= 5 * shortest)
+            cand.push_back(pwa::AmpShape{lq, wl});
+    }
+    pwa::VParams vp;
+    std::memset(&vp, 0, sizeof vp);
+    for (int a = 0; a < m->W; ++a) vp.v[2 * a] = 1.0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev_guard{e0, e1};
+    pwa::AmpShape best{m->amp_lq, m->amp_wl};
+    float best_ms = 0.f;
+    bool have = false;
+    for (const pwa::AmpShape& sh : cand) {
+        int rc = reshape_amp(m, sh, s);
+        if (rc != PWA_OK) return rc;
+        HIP_TRY(pwa::launch_amp_fused(*m, vp, true, s, pwa::LaunchEvents{}));   // warm-up
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int k = 0; k < evals; ++k)
+            HIP_TRY(pwa::launch_amp_fused(*m, vp, true, s, pwa::LaunchEvents{}));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (!have || ms < best_ms) {
+            best = sh;
+            best_ms = ms;
+            have = true;
+        }
+    }
+    const int rc = reshape_amp(m, best, s);
+    if (rc != PWA_OK) return rc;
+    if (lanes_per_event) *lanes_per_event = 1 << best.lq;
+    if (waves_per_lane) *waves_per_lane = best.wl;
     return PWA_OK;
 }
 

@@ -18,9 +18,9 @@ constexpr int kAmpTile = 64;
 
 // Lane-split layout of the FP32 amplitude form (k_amp.hip): an event is held
 // by q = 2^lq neighbouring lanes with wl (even) waves each, so rows are q wl
-// waves long.  Chosen per W for the fewest padded waves; among equal row
-// lengths, the largest wl up to 10 (fewer lanes repeat the per-event work,
-// while the registers per lane stay moderate), else the smallest.
+// waves long.  The default shape minimises the padded row length, counted 25 %
+// longer when wl > 10 (the registers of such lanes leave one wavefront per
+// SIMD); among equal costs, the largest wl up to 10, else the smallest.
 constexpr int kAmpMaxLaneWaves = 16;
 struct AmpShape {
     int lq, wl;
@@ -28,21 +28,21 @@ struct AmpShape {
 __host__ __device__ inline AmpShape amp_shape(int W)
 {
     AmpShape best{0, 0};
-    int best_len = 1 << 30;
+    int best_cost = 1 << 30;
     for (int lq = 0; lq <= 4; ++lq) {
         const int q = 1 << lq;
         int wl = (W + q - 1) / q;
         wl += wl & 1;
         if (wl < 2) wl = 2;
         if (wl > kAmpMaxLaneWaves) continue;
-        const int len = q * wl;
-        bool take = len < best_len;
-        if (len == best_len) {
+        const int cost = q * wl * (wl > 10 ? 5 : 4);
+        bool take = cost < best_cost;
+        if (cost == best_cost) {
             const bool cur_small = best.wl <= 10, new_small = wl <= 10;
             take = (new_small && (!cur_small || wl > best.wl)) || (!new_small && !cur_small && wl < best.wl);
         }
         if (take) {
-            best_len = len;
+            best_cost = cost;
             best = AmpShape{lq, wl};
         }
     }
@@ -213,12 +213,14 @@ hipError_t launch_colsum(const double* partials, int rows, int cols, int stride,
 hipError_t launch_pack_mfma(const void* src, bool c128, int64_t n, int W, bool bf,
                             const Model& m, hipStream_t s);
 hipError_t launch_unpack_mfma(const Model& m, float* dst, hipStream_t s);
+hipError_t launch_unpack_amp(const void* src, int64_t n, int W, AmpShape sh, float* dst,
+                             hipStream_t s);
 hipError_t launch_mfma_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
                              const LaunchEvents& ev);
 int mfma_chunks(const Model& m, int n_cb);
 size_t mfma_vm_bytes(const Model& m, int n_cb);
 hipError_t launch_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s);
-hipError_t launch_amp_multi(const MultiLaunch& ml, hipStream_t s);
+hipError_t launch_amp_multi_class(const MultiLaunch& ml, int c, hipStream_t s);
 hipError_t launch_assemble_multi(const MultiLaunch& ml, hipStream_t s);
 int amp_multi_class(int wl);
 hipError_t launch_hessian(const Model& m, const VParams& vp, double* recs, double* out,

@@ -22,7 +22,7 @@ def _frob(a, b):
 
 
 @pytest.mark.parametrize("w,n", [(1, 1), (2, 70), (4, 1000), (7, 4099), (20, 5000), (33, 700),
-                                 (48, 2000), (64, 300)])
+                                 (48, 2000), (64, 300), (77, 500), (100, 700), (128, 300)])
 def test_fumili_matches_oracle(w, n):
     o = oracle.get()
     s = synth.small_sample(w, n, 3 * n + 7, seed=4000 + 10 * w + n, n_points=2)
