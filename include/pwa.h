@@ -253,7 +253,9 @@ int pwa_get_timing(pwa_model* model, double* total_ms, int64_t* launches);
  * when the model was built, in milliseconds: table_ms covers the preparation
  * of the table (or the amplitude copy) from the device-resident input, mc_ms
  * the MC integral M (0 when n_mc_acc == 0).  Staging host inputs to the device
- * is not included.
+ * is not included.  For the table forms and the MC integral the interval
+ * starts when the first kernel is dispatched (a first launch's host-side set-up
+ * is not counted); for the other forms it starts with a plain event.
  */
 int pwa_build_timing(const pwa_model* model, double* table_ms, double* mc_ms);
 

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "pwa_internal.h"
 #include "tail.h"
@@ -18,86 +19,193 @@
 
 namespace pwa {
 
-constexpr int kGramChunk = 32;     // MC events staged in LDS at a time
+// ---- the MC integral: sum_j B_ja conj(B_jb) over accepted events ---------
+// A Hermitian rank-N_acc update, register-blocked: the waves form blocks of 4
+// and each thread accumulates the 4 x 4 complex products of one pair of
+// blocks (bp <= bq) in FP64 registers, over the events of its split of each
+// chunk (splits of the chunk's events when there are fewer than 256 pairs, up
+// to 3 pairs per thread beyond).  Chunks of E events are staged in LDS in the
+// input precision, the next chunk's loads in flight while the current one is
+// used.  Each block writes one record of 2P doubles in packed (a <= b) order;
+// k_colsum then sums the records in block order.
 constexpr int kGramMaxRows = 512;  // partial records of the MC matrix build
-constexpr int kGramMaxSlots = 33;  // entries per thread: P <= 256 * 33 (W <= 128)
+constexpr int kGramMaxPairs = 3;   // block pairs per thread: nb(nb+1)/2 <= 768, W <= 152
+constexpr int kGramPre = 16;       // staged elements per thread and chunk (E x 4nb <= 4096)
 
-int gram_rows(int64_t n_acc)
+// events per chunk: as many as kGramPre elements per thread stage, in steps of 16
+int gram_chunk(int W)
 {
-    int64_t chunks = (n_acc + kGramChunk - 1) / kGramChunk;
+    const int wp = 4 * ((W + 3) / 4);
+    int E = (kGramPre * 256 / wp) / 16 * 16;
+    if (E > 256) E = 256;
+    return E < 16 ? 16 : E;
+}
+
+int gram_rows(int64_t n_acc, int W)
+{
+    const int E = gram_chunk(W);
+    int64_t chunks = (n_acc + E - 1) / E;
     if (chunks > kGramMaxRows) chunks = kGramMaxRows;
     return (int)(chunks < 1 ? 1 : chunks);
 }
 
-template <bool C128>
+template <bool C128, int NP>
 __global__ __launch_bounds__(256) void k_gram(const void* __restrict__ mc, int64_t n_acc, int W,
-                                              int P, const uint32_t* __restrict__ pairs,
-                                              double* __restrict__ partials)
+                                              int E, double* __restrict__ partials)
 {
-    extern __shared__ double2 s_b[];   // kGramChunk x W
-    const int64_t nch = (n_acc + kGramChunk - 1) / kGramChunk;
-    const int64_t c0 = (int64_t)blockIdx.x * nch / gridDim.x;
-    const int64_t c1 = (int64_t)(blockIdx.x + 1) * nch / gridDim.x;
-    double ar[kGramMaxSlots], ai[kGramMaxSlots];
-    int pa[kGramMaxSlots], pb[kGramMaxSlots];
+    using In = typename std::conditional<C128, double2, float2>::type;
+    extern __shared__ double lds_g[];
+    In* s_b = reinterpret_cast<In*>(lds_g);   // E x wp
+    const In* src = reinterpret_cast<const In*>(mc);
+    const int nb = (W + 3) / 4, wp = 4 * nb;
+    const int npair = nb * (nb + 1) / 2;
+    const int P = W * (W + 1) / 2;
+    const int tid = threadIdx.x;
+    const int per = npair < 256 ? npair : 256;
+    const int splits = npair >= 256 ? 1 : 256 / npair;
+    const int split = tid / per, pair0 = tid % per;
+    const bool active = split < splits;
+    int bp[NP], bq[NP];
+    double acc[NP][32];
 #pragma unroll
-    for (int r = 0; r < kGramMaxSlots; ++r) {
-        ar[r] = 0.0;
-        ai[r] = 0.0;
-        const int e = threadIdx.x + 256 * r;
-        const uint32_t pr = (e < P) ? pairs[e] : 0u;
-        pa[r] = (int)(pr & 0xffffu);
-        pb[r] = (int)(pr >> 16);
+    for (int r = 0; r < NP; ++r) {
+        const int pl = pair0 + r * 256;
+        bp[r] = bq[r] = -1;
+        if (active && pl < npair) {
+            int rem = pl, row = 0;
+            while (rem >= nb - row) {
+                rem -= nb - row;
+                ++row;
+            }
+            bp[r] = row;
+            bq[r] = row + rem;
+        }
+#pragma unroll
+        for (int k = 0; k < 32; ++k) acc[r][k] = 0.0;
     }
 
+    const int64_t nch = (n_acc + E - 1) / E;
+    const int64_t c0 = (int64_t)blockIdx.x * nch / gridDim.x;
+    const int64_t c1 = (int64_t)(blockIdx.x + 1) * nch / gridDim.x;
+    const int n_el = E * wp;
+    In pre[kGramPre];
+    auto load_chunk = [&](int64_t c) {
+        const int64_t j0 = c * E;
+#pragma unroll
+        for (int q = 0; q < kGramPre; ++q) {
+            const int idx = tid + 256 * q;
+            const int j = idx / wp, a = idx - (idx / wp) * wp;
+            In x;
+            x.x = 0.0;
+            x.y = 0.0;
+            if (idx < n_el && a < W && j0 + j < n_acc) x = src[(j0 + j) * W + a];
+            pre[q] = x;
+        }
+    };
+    if (c0 < c1) load_chunk(c0);
     for (int64_t c = c0; c < c1; ++c) {
-        for (int idx = threadIdx.x; idx < kGramChunk * W; idx += blockDim.x) {
-            const int64_t j = c * kGramChunk + idx / W;
-            const int a = idx % W;
-            double2 x = make_double2(0.0, 0.0);
-            if (j < n_acc) {
-                if (C128) x = reinterpret_cast<const double2*>(mc)[j * W + a];
-                else {
-                    const float2 f = reinterpret_cast<const float2*>(mc)[j * W + a];
-                    x = make_double2(f.x, f.y);
-                }
-            }
-            s_b[idx] = x;
+#pragma unroll
+        for (int q = 0; q < kGramPre; ++q) {
+            const int idx = tid + 256 * q;
+            if (idx < n_el) s_b[idx] = pre[q];
         }
         __syncthreads();
-        for (int j = 0; j < kGramChunk; ++j) {
+        if (c + 1 < c1) load_chunk(c + 1);
+        const int ne = (int)((n_acc - c * E) < E ? (n_acc - c * E) : E);
+        if (active) {
 #pragma unroll
-            for (int r = 0; r < kGramMaxSlots; ++r) {
-                if (threadIdx.x + 256 * r < P) {
-                    const double2 x = s_b[j * W + pa[r]], y = s_b[j * W + pb[r]];
-                    ar[r] += x.x * y.x + x.y * y.y;    // Re x conj(y)
-                    ai[r] += x.y * y.x - x.x * y.y;    // Im x conj(y)
+            for (int r = 0; r < NP; ++r) {
+                if (bp[r] < 0) continue;
+                for (int j = split; j < ne; j += splits) {
+                    const In* row = s_b + j * wp;
+                    double xr[4], xi[4], yr[4], yi[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const In x = row[4 * bp[r] + i], y = row[4 * bq[r] + i];
+                        xr[i] = (double)x.x;
+                        xi[i] = (double)x.y;
+                        yr[i] = (double)y.x;
+                        yi[i] = (double)y.y;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            acc[r][2 * (4 * i + k)] += xr[i] * yr[k] + xi[i] * yi[k];       // Re x conj(y)
+                            acc[r][2 * (4 * i + k) + 1] += xi[i] * yr[k] - xr[i] * yi[k];   // Im x conj(y)
+                        }
                 }
             }
         }
         __syncthreads();
     }
+
+    // combine the splits of each pair in split order, half a block at a time,
+    // into the packed record
     double* rec = partials + (int64_t)blockIdx.x * 2 * P;
+    double* s_part = lds_g;   // 256 x 16 doubles
+    for (int r = 0; r < NP; ++r) {
+        const int base = r * 256;
+        const int np_here = (npair - base) < 256 ? (npair - base) : 256;
+        if (np_here <= 0) break;
+        for (int half = 0; half < 2; ++half) {
+            __syncthreads();
+            if (active && bp[r] >= 0)
 #pragma unroll
-    for (int r = 0; r < kGramMaxSlots; ++r) {
-        const int e = threadIdx.x + 256 * r;
-        if (e < P) {
-            rec[2 * e] = ar[r];
-            rec[2 * e + 1] = ai[r];
+                for (int k = 0; k < 16; ++k) s_part[tid * 16 + k] = acc[r][16 * half + k];
+            __syncthreads();
+            for (int e = tid; e < np_here * 16; e += blockDim.x) {
+                const int pl = e / 16, k = e % 16;
+                double x = 0.0;
+                for (int sp = 0; sp < splits; ++sp) x += s_part[(sp * per + pl) * 16 + k];
+                // element (i, kk) of the block pair, real or imaginary part
+                const int el = 16 * half + k;
+                const int i = (el >> 1) / 4, kk = (el >> 1) % 4, part = el & 1;
+                int rem = base + pl, row = 0;
+                while (rem >= nb - row) {
+                    rem -= nb - row;
+                    ++row;
+                }
+                const int a = 4 * row + i, b = 4 * (row + rem) + kk;
+                if (a <= b && b < W) rec[2 * packed_index(W, a, b) + part] = x;
+            }
         }
     }
 }
 
-hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, int P,
-                       const uint32_t* pairs, double* partials, int rows, hipStream_t s)
+hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, double* partials,
+                       int rows, hipStream_t s, const LaunchEvents& ev)
 {
-    const size_t lds = sizeof(double2) * kGramChunk * W;
-    if (c128)
-        hipLaunchKernelGGL(k_gram<true>, dim3(rows), dim3(256), lds, s, mc, n_acc, W, P, pairs,
-                           partials);
-    else
-        hipLaunchKernelGGL(k_gram<false>, dim3(rows), dim3(256), lds, s, mc, n_acc, W, P, pairs,
-                           partials);
+    const int E = gram_chunk(W);
+    const int nb = (W + 3) / 4;
+    const int npair = nb * (nb + 1) / 2;
+    const int np = (npair + 255) / 256;
+    const size_t stage = (size_t)E * 4 * nb * (c128 ? 16 : 8);
+    const size_t lds = stage > 256 * 16 * 8 ? stage : 256 * 16 * 8;
+    const dim3 grid(rows), block(256);
+    const void* fns[6] = {(const void*)&k_gram<false, 1>, (const void*)&k_gram<false, 2>,
+                          (const void*)&k_gram<false, 3>, (const void*)&k_gram<true, 1>,
+                          (const void*)&k_gram<true, 2>, (const void*)&k_gram<true, 3>};
+    if (np < 1 || np > kGramMaxPairs) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(fns[(c128 ? 3 : 0) + np - 1],
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+#define PWA_GRAM(C, N)                                                                        \
+    hipExtLaunchKernelGGL((k_gram<C, N>), grid, block, lds, s, ev.start, ev.stop, 0, mc, n_acc, \
+                          W, E, partials)
+    if (c128) {
+        if (np == 1) PWA_GRAM(true, 1);
+        else if (np == 2) PWA_GRAM(true, 2);
+        else PWA_GRAM(true, 3);
+    } else {
+        if (np == 1) PWA_GRAM(false, 1);
+        else if (np == 2) PWA_GRAM(false, 2);
+        else PWA_GRAM(false, 3);
+    }
+#undef PWA_GRAM
     return hipGetLastError();
 }
 

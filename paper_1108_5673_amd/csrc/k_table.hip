@@ -61,20 +61,70 @@ __device__ inline double2 source_entry(const void* src, bool src_is_table, bool 
     return herm_product(x.x, x.y, y.x, y.y);
 }
 
-__global__ void k_pack_tiled(const void* __restrict__ src, bool src_is_table, bool src_c128,
-                             int64_t n, int W, int P, const uint32_t* __restrict__ pairs,
-                             bool store_c128, int64_t total, void* __restrict__ dst)
+// One thread per stored 16-byte vector (the EV events of one entry that share
+// it), one tile per block at a time: consecutive threads write consecutive
+// vectors, so a wavefront stores 1 KB contiguous (non-temporal: the table is
+// not read back by this kernel).  From amplitudes, the tile's 16 events are
+// first staged in LDS in FP64 and the pair list is kept in LDS.
+constexpr int kPackMaxW = PWA_MAX_WAVES_TABLE;
+__global__ __launch_bounds__(256) void k_pack_tiled(const void* __restrict__ src,
+                                                    bool src_is_table, bool src_c128, int64_t n,
+                                                    int W, int P,
+                                                    const uint32_t* __restrict__ pairs,
+                                                    bool store_c128, int64_t n_tiles,
+                                                    void* __restrict__ dst)
 {
-    const int esz = store_c128 ? 16 : 8;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = g / P;
-        const int e = (int)(g % P);
-        double2 t = make_double2(0.0, 0.0);
-        if (i < n) t = source_entry(src, src_is_table, src_c128, i, e, W, P, pairs);
-        char* d = reinterpret_cast<char*>(dst) + tiled_offset(i, e, P, esz);
-        if (store_c128) *reinterpret_cast<double2*>(d) = t;
-        else *reinterpret_cast<float2*>(d) = make_float2((float)t.x, (float)t.y);
+    __shared__ double2 s_a[kTileEvents * kPackMaxW];
+    __shared__ uint32_t s_pair[kPackMaxW * (kPackMaxW + 1) / 2];
+    const int ev = store_c128 ? 1 : 2;           // events per vector
+    const int nvec = kTileEvents / ev;           // vectors per entry and tile
+    const int per_tile = P * nvec;               // vectors per tile
+    if (!src_is_table)
+        for (int e = threadIdx.x; e < P; e += blockDim.x) s_pair[e] = pairs[e];
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int64_t ibase = t * kTileEvents;
+        if (!src_is_table) {
+            __syncthreads();   // the previous tile's reads are done
+            for (int x = threadIdx.x; x < kTileEvents * W; x += blockDim.x) {
+                const int64_t i = ibase + x / W;
+                s_a[x] = i < n ? load_c(src, ibase * W + x, src_c128) : make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+        }
+        char* tb = reinterpret_cast<char*>(dst) + t * (int64_t)per_tile * 16;
+        for (int o = threadIdx.x; o < per_tile; o += blockDim.x) {
+            const int k = o / (64 * nvec);       // slot
+            const int r = o - k * 64 * nvec;
+            const int nk = (P - 64 * k) < 64 ? (P - 64 * k) : 64;
+            const int v = r / nk, lane = r - v * nk;
+            const int e = 64 * k + lane;
+            const int j0 = v * ev;               // first event of the vector in the tile
+            double2 t0, t1 = make_double2(0.0, 0.0);
+            if (src_is_table) {
+                t0 = ibase + j0 < n ? load_c(src, (ibase + j0) * P + e, src_c128)
+                                    : make_double2(0.0, 0.0);
+                if (ev == 2 && ibase + j0 + 1 < n)
+                    t1 = load_c(src, (ibase + j0 + 1) * P + e, src_c128);
+            } else {
+                const uint32_t pr = s_pair[e];
+                const int a = (int)(pr & 0xffffu), b = (int)(pr >> 16);
+                const double2 x0 = s_a[j0 * W + a], y0 = s_a[j0 * W + b];
+                t0 = herm_product(x0.x, x0.y, y0.x, y0.y);
+                if (ev == 2) {
+                    const double2 x1 = s_a[(j0 + 1) * W + a], y1 = s_a[(j0 + 1) * W + b];
+                    t1 = herm_product(x1.x, x1.y, y1.x, y1.y);
+                }
+            }
+            if (store_c128) {
+                typedef double d2v __attribute__((ext_vector_type(2)));
+                d2v q = {t0.x, t0.y};
+                __builtin_nontemporal_store(q, reinterpret_cast<d2v*>(tb + (int64_t)o * 16));
+            } else {
+                typedef float f4v __attribute__((ext_vector_type(4)));
+                f4v q = {(float)t0.x, (float)t0.y, (float)t1.x, (float)t1.y};
+                __builtin_nontemporal_store(q, reinterpret_cast<f4v*>(tb + (int64_t)o * 16));
+            }
+        }
     }
 }
 
@@ -102,11 +152,11 @@ static int grid_for(int64_t total, int block)
 
 hipError_t launch_pack_tiled(const void* src, bool src_is_table, bool src_c128, int64_t n,
                              int W, int P, const uint32_t* pairs, bool store_c128,
-                             int64_t n_tiles, void* dst, hipStream_t s)
+                             int64_t n_tiles, void* dst, hipStream_t s, const LaunchEvents& ev)
 {
-    const int64_t total = n_tiles * kTileEvents * (int64_t)P;
-    hipLaunchKernelGGL(k_pack_tiled, dim3(grid_for(total, 256)), dim3(256), 0, s, src,
-                       src_is_table, src_c128, n, W, P, pairs, store_c128, total, dst);
+    const int64_t g = n_tiles < 4096 ? (n_tiles < 1 ? 1 : n_tiles) : 4096;
+    hipExtLaunchKernelGGL(k_pack_tiled, dim3((int)g), dim3(256), 0, s, ev.start, ev.stop, 0, src,
+                          src_is_table, src_c128, n, W, P, pairs, store_c128, n_tiles, dst);
     return hipGetLastError();
 }
 

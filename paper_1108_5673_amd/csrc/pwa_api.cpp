@@ -202,10 +202,8 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         m->n_tiles = (n + pwa::kTileEvents - 1) / pwa::kTileEvents;
         m->data_bytes = m->n_tiles * pwa::kTileEvents * (int64_t)P * (c128 ? 16 : 8);
         HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
-        HIP_TRY(hipEventRecord(bt[0], s));
         HIP_TRY(pwa::launch_pack_tiled(sd.ptr, in_table, data_c128, n, W, P, m->d_pairs, c128,
-                                       m->n_tiles, m->d_data, s));
-        HIP_TRY(hipEventRecord(bt[1], s));
+                                       m->n_tiles, m->d_data, s, pwa::LaunchEvents{bt[0], bt[1]}));
         m->kslots = pwa::select_kslots(P, c128);
         if (m->kslots < 0) return fail(PWA_ERR_INVALID, "n_waves %d too large for the table form", W);
         m->subtile = pwa::default_subtile(m->kslots, c128);
@@ -268,12 +266,14 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         Staged sm;
         rc = stage(mc, (size_t)n_acc * W * (mc_c128 ? 16 : 8), s, sm);
         if (rc != PWA_OK) return rc;
-        const int grows = pwa::gram_rows(n_acc);
+        const int grows = pwa::gram_rows(n_acc, W);
         double* gpart = nullptr;
         HIP_TRY(hipMalloc(&gpart, sizeof(double) * 2 * P * (size_t)grows));
         hipError_t e = hipStreamSynchronize(s);   // the MC input staged
-        if (e == hipSuccess) e = hipEventRecord(bt[2], s);
-        if (e == hipSuccess) e = pwa::launch_gram(sm.ptr, mc_c128, n_acc, W, P, m->d_pairs, gpart, grows, s);
+        // dispatch-stamped start of the first kernel, plain event after the last
+        if (e == hipSuccess)
+            e = pwa::launch_gram(sm.ptr, mc_c128, n_acc, W, gpart, grows, s,
+                                 pwa::LaunchEvents{bt[2], nullptr});
         if (e == hipSuccess) e = pwa::launch_colsum(gpart, grows, 2 * P, 2 * P, m->d_colsum, s);
         if (e == hipSuccess) e = pwa::launch_expand_m(m->d_colsum, W, n_gen, m->d_M, s);
         if (e == hipSuccess) e = hipEventRecord(bt[3], s);

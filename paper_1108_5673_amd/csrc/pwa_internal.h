@@ -185,7 +185,7 @@ struct MfmaBatch {
 // build step
 hipError_t launch_pack_tiled(const void* src, bool src_is_table, bool src_c128, int64_t n,
                              int W, int P, const uint32_t* pairs, bool store_c128,
-                             int64_t n_tiles, void* dst, hipStream_t s);
+                             int64_t n_tiles, void* dst, hipStream_t s, const LaunchEvents& ev);
 hipError_t launch_pack_soa(const void* src, bool src_is_table, bool src_c128, int64_t n, int W,
                            int P, const uint32_t* pairs, double* dst, hipStream_t s);
 hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, AmpShape sh,
@@ -193,11 +193,11 @@ hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, Amp
 hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, void* dst,
                                hipStream_t s);
 hipError_t launch_unpack_soa(const double* src, int64_t n, int P, double* dst, hipStream_t s);
-hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, int P,
-                       const uint32_t* pairs, double* partials, int rows, hipStream_t s);
+hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, double* partials,
+                       int rows, hipStream_t s, const LaunchEvents& ev);
 hipError_t launch_expand_m(const double* packed_colsum, int W, int64_t n_gen, double* M,
                            hipStream_t s);
-int gram_rows(int64_t n_acc);
+int gram_rows(int64_t n_acc, int W);
 int plain_rows(int64_t n);
 
 // evaluation

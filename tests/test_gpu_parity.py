@@ -105,6 +105,22 @@ def test_mc_matrix(form):
     assert np.array_equal(got, got.conj().T)
 
 
+@pytest.mark.parametrize("c128", [False, True])
+@pytest.mark.parametrize("w,n_acc", [(1, 1), (5, 63), (20, 64), (20, 65), (20, 40_017),
+                                     (64, 9_999), (65, 33), (65, 5_000), (128, 2_049)])
+def test_mc_matrix_sizes(c128, w, n_acc):
+    """M over ragged chunk tails, several chunks per block, and the register
+    blocking's 1, 2 and 3 block pairs per thread (W up to 128)."""
+    s = synth.small_sample(w, 10, n_acc, seed=500 + w + n_acc)
+    m = s.mc if c128 else s.mc.astype(np.complex64)
+    model = pwa.Model(s.data.astype(np.complex64), m, 2 * n_acc + 1, form="amplitude")
+    ref = _o().mc_matrix(m.astype(np.complex128), 2 * n_acc + 1)
+    got = model.mc_matrix()
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref), (w, n_acc)
+    assert np.array_equal(got, got.conj().T)
+    model.close()
+
+
 def test_no_mc_gives_zero_matrix():
     s = synth.small_sample(3, 50, 4, seed=4)
     model = pwa.Model(s.data.astype(np.complex64), None, 1, form="table")
