@@ -237,12 +237,15 @@ int pwa_copy_mc_matrix(const pwa_model* model, double* out_host, void* hip_strea
 int pwa_set_mc_matrix(pwa_model* model, const double* m_host, void* hip_stream);
 
 /*
- * Kernel timing: while enabled, every evaluation has the runtime stamp two HIP
- * events with the begin and end of the main (event-streaming) kernel's
- * dispatch on the evaluation's stream (for PWA_PRECISION_FP64_PLAIN, the begin
- * of the first pass and the end of the second); pwa_get_timing returns the
- * accumulated device time of those kernels in milliseconds and the number of
- * launches timed, and resets both.
+ * Kernel timing: with enable = k > 0, every k-th evaluation (the first, then
+ * every k-th after it; 1 = all) has the runtime stamp two HIP events with the
+ * begin and end of the main (event-streaming) kernel's dispatch on the
+ * evaluation's stream (for PWA_PRECISION_FP64_PLAIN, the begin of the first
+ * pass and the end of the second); enable = 0 turns timing off.  A stamped
+ * launch costs the evaluation some microseconds, so sampling every k-th keeps
+ * a throughput measurement close to an untimed one.  The events are read back
+ * lazily: pwa_get_timing returns the accumulated device time of the timed
+ * kernels in milliseconds and their number, and resets both.
  */
 int pwa_set_timing(pwa_model* model, int enable);
 int pwa_get_timing(pwa_model* model, double* total_ms, int64_t* launches);

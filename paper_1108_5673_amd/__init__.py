@@ -64,6 +64,9 @@ def _buffer(x, what: str):
 
 def _v_array(v, n_waves: int) -> np.ndarray:
     """Production amplitudes as 2W doubles (re, im interleaved)."""
+    if (type(v) is np.ndarray and v.dtype == np.float64 and v.ndim == 1
+            and v.shape[0] == 2 * n_waves and v.flags.c_contiguous):
+        return v
     if _is_torch(v):
         v = v.detach().cpu().numpy()
     a = np.asarray(v)
@@ -152,7 +155,7 @@ class Model:
         """(NLL, gradient as 2W doubles [dRe V_0, dIm V_0, ...])."""
         va = _v_array(v, self.n_waves)
         out = ctypes.c_double(0.0)
-        g = np.zeros(2 * self.n_waves, np.float64)
+        g = np.empty(2 * self.n_waves, np.float64)
         st = _native.check(_native.lib().pwa_nll_grad(self._handle(), va.ctypes.data,
                                                       ctypes.byref(out), g.ctypes.data,
                                                       self._stream))
@@ -222,8 +225,10 @@ class Model:
                                                              ctypes.byref(wl)))
         return q.value, wl.value
 
-    def set_timing(self, enable: bool) -> None:
-        _native.check(_native.lib().pwa_set_timing(self._handle(), int(bool(enable))))
+    def set_timing(self, enable, every: int = 1) -> None:
+        """Time every `every`-th evaluation's main kernel (off when enable is false)."""
+        _native.check(_native.lib().pwa_set_timing(self._handle(),
+                                                   int(every) if enable else 0))
 
     def timing(self):
         """(total device milliseconds of the main kernel, launches) since the last call."""

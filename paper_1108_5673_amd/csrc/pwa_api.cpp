@@ -132,8 +132,10 @@ void release(Model* m)
 
     if (m->h_out) (void)hipHostFree(m->h_out);
     if (m->h_done) (void)hipHostFree(m->h_done);
-    if (m->ev0) (void)hipEventDestroy(m->ev0);
-    if (m->ev1) (void)hipEventDestroy(m->ev1);
+    for (int k = 0; k < Model::kTimingRing; ++k) {
+        if (m->ev_start[k]) (void)hipEventDestroy(m->ev_start[k]);
+        if (m->ev_stop[k]) (void)hipEventDestroy(m->ev_stop[k]);
+    }
     delete m;
 }
 
@@ -177,8 +179,6 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
 
     // build-step timing: events around the table preparation and the MC
     // integral kernels (the inputs are already on the device by then)
-    HIP_TRY(hipEventCreate(&m->ev0));
-    HIP_TRY(hipEventCreate(&m->ev1));
     hipEvent_t bt[4] = {nullptr, nullptr, nullptr, nullptr};
     struct EventsGuard {
         hipEvent_t* e;
@@ -304,6 +304,46 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
     return PWA_OK;
 }
 
+// Add the kernel time of the `count` oldest unread timed launches.
+int read_timing(Model* m, int count)
+{
+    const int R = Model::kTimingRing;
+    for (int k = 0; k < count; ++k) {
+        const int slot = ((m->ev_next - m->ev_pending) % R + R) % R;
+        HIP_TRY(hipEventSynchronize(m->ev_stop[slot]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, m->ev_start[slot], m->ev_stop[slot]));
+        m->timed_ms += ms;
+        m->timed_launches += 1;
+        --m->ev_pending;
+    }
+    return PWA_OK;
+}
+
+// Event pair for the next timed launch (reading back the oldest when the ring
+// is full: that launch finished long ago).
+int timing_slot(Model* m, pwa::LaunchEvents* ev)
+{
+    const int R = Model::kTimingRing;
+    if (m->ev_pending == R) {
+        const int rc = read_timing(m, 1);
+        if (rc != PWA_OK) return rc;
+    }
+    const int slot = m->ev_next;
+    ev->start = m->ev_start[slot];
+    ev->stop = m->ev_stop[slot];
+    m->ev_next = (slot + 1) % R;
+    ++m->ev_pending;
+    return PWA_OK;
+}
+
+// Whether this evaluation is one of the timed ones.
+bool take_timing(Model* m)
+{
+    if (m->timing <= 0) return false;
+    return (m->timing_count++ % m->timing) == 0;
+}
+
 int check_v(const double* v, int W)
 {
     for (int k = 0; k < 2 * W; ++k)
@@ -332,8 +372,8 @@ int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, 
     ta.amplitude = m->form == pwa::kAmp32 ? 1 : 0;
     pwa::LaunchEvents ev;
     if (timed) {
-        ev.start = m->ev0;
-        ev.stop = m->ev1;
+        const int rc = timing_slot(m, &ev);
+        if (rc != PWA_OK) return rc;
     }
     hipError_t e;
     if (m->form == pwa::kTable32 || m->form == pwa::kTable64Fused)
@@ -354,7 +394,7 @@ int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, 
 // host memory: every assembly block stores `seq` in its completion word after
 // its outputs.  The host polls the words; every few thousand polls it asks the
 // runtime whether the stream failed or finished without them.
-int wait_for(Model* m, unsigned long long seq, int nblk, hipStream_t s, bool timed)
+int wait_for(Model* m, unsigned long long seq, int nblk, hipStream_t s)
 {
     volatile unsigned long long* done = m->h_done;
     auto all_done = [&]() {
@@ -374,13 +414,6 @@ int wait_for(Model* m, unsigned long long seq, int nblk, hipStream_t s, bool tim
         }
     }
     std::atomic_thread_fence(std::memory_order_acquire);
-    if (timed) {
-        HIP_TRY(hipEventSynchronize(m->ev1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, m->ev0, m->ev1));
-        m->timed_ms += ms;
-        m->timed_launches += 1;
-    }
     return PWA_OK;
 }
 
@@ -745,12 +778,12 @@ int eval_mfma(Model* m, const double* v, int K, hipStream_t s, bool timed)
     b.chunks = chunks;
     pwa::LaunchEvents ev;
     if (timed) {
-        ev.start = m->ev0;
-        ev.stop = m->ev1;
+        rc = timing_slot(m, &ev);
+        if (rc != PWA_OK) return rc;
     }
     const hipError_t e = pwa::launch_mfma_batch(*m, b, s, ev);
     if (e != hipSuccess) return device_fail(e, "matrix-core evaluation launch");
-    return wait_for(m, b.seq, K, s, timed);
+    return wait_for(m, b.seq, K, s);
 }
 
 // Wait until all n words hold seq (see wait_for).
@@ -786,13 +819,13 @@ int evaluate(const pwa_model* cm, const double* v, double* nll, double* grad, vo
     hipStream_t s = (hipStream_t)stream;
     const bool want_grad = grad != nullptr;
     if (is_mfma(m)) {
-        rc = eval_mfma(m, v, 1, s, m->timing);
+        rc = eval_mfma(m, v, 1, s, take_timing(m));
     } else {
         unsigned long long seq = 0;
         int nblk = 0;
-        rc = enqueue_eval(m, v, want_grad, 0, s, m->timing, &seq, &nblk);
+        rc = enqueue_eval(m, v, want_grad, 0, s, take_timing(m), &seq, &nblk);
         if (rc != PWA_OK) return rc;
-        rc = wait_for(m, seq, nblk, s, m->timing);
+        rc = wait_for(m, seq, nblk, s);
     }
     if (rc != PWA_OK) return rc;
     *nll = m->h_out[0];
@@ -995,7 +1028,7 @@ int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k
         DeviceGuard g(m->device);
         if (is_mfma(m)) {
             if (K > 0) {
-                const int rc = eval_mfma(m, vp, K, s, m->timing);
+                const int rc = eval_mfma(m, vp, K, s, take_timing(m));
                 if (rc != PWA_OK) return rc;
             }
         } else {
@@ -1011,7 +1044,7 @@ int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k
                 if (rc != PWA_OK) return rc;
             }
             if (K > 0) {
-                const int rc = wait_for(m, seq, nblk, s, false);
+                const int rc = wait_for(m, seq, nblk, s);
                 if (rc != PWA_OK) return rc;
             }
         }
@@ -1228,7 +1261,16 @@ int pwa_set_timing(pwa_model* model, int enable)
 {
     if (!model) return fail(PWA_ERR_INVALID, "NULL model");
     Model* m = reinterpret_cast<Model*>(model);
-    m->timing = enable != 0;
+    if (enable && !m->ev_start[0]) {
+        DeviceGuard g(m->device);
+        for (int k = 0; k < Model::kTimingRing; ++k) {
+            HIP_TRY(hipEventCreate(&m->ev_start[k]));
+            HIP_TRY(hipEventCreate(&m->ev_stop[k]));
+        }
+    }
+    if (enable < 0) return fail(PWA_ERR_INVALID, "enable must be >= 0");
+    m->timing = enable;
+    m->timing_count = 0;
     return PWA_OK;
 }
 
@@ -1245,6 +1287,11 @@ int pwa_get_timing(pwa_model* model, double* total_ms, int64_t* launches)
 {
     if (!model || !total_ms || !launches) return fail(PWA_ERR_INVALID, "NULL argument");
     Model* m = reinterpret_cast<Model*>(model);
+    if (m->ev_pending > 0) {
+        DeviceGuard g(m->device);
+        const int rc = read_timing(m, m->ev_pending);
+        if (rc != PWA_OK) return rc;
+    }
     *total_ms = m->timed_ms;
     *launches = m->timed_launches;
     m->timed_ms = 0.0;

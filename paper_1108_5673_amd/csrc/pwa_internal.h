@@ -102,8 +102,15 @@ struct Model {
     unsigned long long seq = 0;     // last published completion value
     int32_t out_cap = 1;            // evaluations h_out can hold
 
-    bool timing = false;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int timing = 0;        // time every timing-th evaluation (0: none)
+    int64_t timing_count = 0;
+    // kernel timing: a ring of event pairs, read back only when a slot is
+    // reused or the totals are asked for (no host wait per evaluation)
+    static constexpr int kTimingRing = 64;
+    hipEvent_t ev_start[kTimingRing] = {};
+    hipEvent_t ev_stop[kTimingRing] = {};
+    int ev_next = 0;       // slot of the next timed launch
+    int ev_pending = 0;    // timed launches not read back yet (the slots before ev_next)
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
     double build_table_ms = 0.0;   // device time of the table (or amplitude) preparation

@@ -248,6 +248,19 @@ def test_timing_counters():
     model.set_timing(False)
     model.nll_grad(s.points[0])
     assert model.timing() == (0.0, 0)
+    # every 4th evaluation: the 1st, 5th, 9th of 10; more launches than the
+    # event ring holds are read back as the ring is reused
+    model.set_timing(True, every=4)
+    for k in range(10):
+        model.nll_grad(s.points[k % len(s.points)])
+    ms, n = model.timing()
+    assert n == 3 and ms > 0
+    model.set_timing(True)
+    for k in range(150):
+        model.nll_grad(s.points[k % len(s.points)])
+    ms, n = model.timing()
+    assert n == 150 and ms > 0
+    model.set_timing(False)
 
 
 def test_nonfinite_v_rejected():
