@@ -81,10 +81,14 @@ __device__ inline void amp_step(AmpRegs<WL>& r, AmpLane<WL>& st, int64_t evt, in
     for (int j = 0; j < WL / 2; ++j) {
         const float4 x = r.x[j];
         const double2 v0 = st.v[2 * j], v1 = st.v[2 * j + 1];
-        sr += v0.x * (double)x.x - v0.y * (double)x.y;
-        si += v0.x * (double)x.y + v0.y * (double)x.x;
-        sr += v1.x * (double)x.z - v1.y * (double)x.w;
-        si += v1.x * (double)x.w + v1.y * (double)x.z;
+        sr = __fma_rn(v0.x, (double)x.x, sr);
+        sr = __fma_rn(-v0.y, (double)x.y, sr);
+        si = __fma_rn(v0.x, (double)x.y, si);
+        si = __fma_rn(v0.y, (double)x.x, si);
+        sr = __fma_rn(v1.x, (double)x.z, sr);
+        sr = __fma_rn(-v1.y, (double)x.w, sr);
+        si = __fma_rn(v1.x, (double)x.w, si);
+        si = __fma_rn(v1.y, (double)x.z, si);
     }
     if (GRAD) {
         // convert again for step 3 instead of keeping FP64 copies alive
@@ -110,10 +114,14 @@ __device__ inline void amp_step(AmpRegs<WL>& r, AmpLane<WL>& st, int64_t evt, in
 #pragma unroll
         for (int j = 0; j < WL / 2; ++j) {
             const float4 x = r.x[j];
-            st.gr[2 * j] += cr * (double)x.x + ci * (double)x.y;
-            st.gi[2 * j] += ci * (double)x.x - cr * (double)x.y;
-            st.gr[2 * j + 1] += cr * (double)x.z + ci * (double)x.w;
-            st.gi[2 * j + 1] += ci * (double)x.z - cr * (double)x.w;
+            st.gr[2 * j] = __fma_rn(cr, (double)x.x, st.gr[2 * j]);
+            st.gr[2 * j] = __fma_rn(ci, (double)x.y, st.gr[2 * j]);
+            st.gi[2 * j] = __fma_rn(ci, (double)x.x, st.gi[2 * j]);
+            st.gi[2 * j] = __fma_rn(-cr, (double)x.y, st.gi[2 * j]);
+            st.gr[2 * j + 1] = __fma_rn(cr, (double)x.z, st.gr[2 * j + 1]);
+            st.gr[2 * j + 1] = __fma_rn(ci, (double)x.w, st.gr[2 * j + 1]);
+            st.gi[2 * j + 1] = __fma_rn(ci, (double)x.z, st.gi[2 * j + 1]);
+            st.gi[2 * j + 1] = __fma_rn(-cr, (double)x.w, st.gi[2 * j + 1]);
         }
     }
 }

@@ -131,8 +131,13 @@ __global__ __launch_bounds__(256) void k_gram(const void* __restrict__ mc, int64
                     for (int i = 0; i < 4; ++i)
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            acc[r][2 * (4 * i + k)] += xr[i] * yr[k] + xi[i] * yi[k];       // Re x conj(y)
-                            acc[r][2 * (4 * i + k) + 1] += xi[i] * yr[k] - xr[i] * yi[k];   // Im x conj(y)
+                            // Re and Im of x conj(y), accumulated with one FMA per product
+                            double& re = acc[r][2 * (4 * i + k)];
+                            double& im = acc[r][2 * (4 * i + k) + 1];
+                            re = __fma_rn(xr[i], yr[k], re);
+                            re = __fma_rn(xi[i], yi[k], re);
+                            im = __fma_rn(xi[i], yr[k], im);
+                            im = __fma_rn(-xr[i], yi[k], im);
                         }
                 }
             }
