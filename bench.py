@@ -117,7 +117,11 @@ def bench_batched(args):
         import oracle
         o = oracle.get()
         M64 = o.mc_matrix(s.mc, s.n_gen)
+        t = time.perf_counter()
         ref = {j: o.nll_amp(s.data, M64, s.points[j]) for j in (0, 85, 170, 255)}
+        out["oracle"] = {"evals_per_s": len(ref) / (time.perf_counter() - t),
+                         "cores": o.num_threads(),
+                         "sample": "vectors 0, 85, 170, 255 on the FP64 amplitudes"}
     for form, parts in (("amplitude_bf16", 3), ("amplitude_fp16", 2)):
         m = pwa.Model(d32, mc32, s.n_gen, form=form)
         for _ in range(2):
@@ -163,6 +167,9 @@ def bench_amplitude(args):
     d = synth._amplitudes_torch(N, ws, gen, "cuda")
     mc = synth._amplitudes_torch(2 * N, ws, gen, "cuda")
     m = pwa.Model(d, mc, 4 * N, form="amplitude")
+    d_host = mc_host = None
+    if not args.no_cpu_baseline:
+        d_host, mc_host = d.cpu().numpy(), mc.cpu().numpy()
     del d, mc
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -170,6 +177,18 @@ def bench_amplitude(args):
     pts = [synth.random_v(rng, W) for _ in range(20)]
     out = {"workload": "amplitude form, 2M events x 32 waves (512 MB complex64), 4M accepted MC; "
                        "flat synthetic amplitudes; 20 random V (Re, Im ~ N(0, 1))"}
+    ref = None
+    if not args.no_cpu_baseline:
+        # the oracle on the same complex64 amplitudes (widened), its own M
+        import oracle
+        o = oracle.get()
+        d_h = d_host.astype(np.complex128)
+        M64 = o.mc_matrix(mc_host.astype(np.complex128), 4 * N)
+        t = time.perf_counter()
+        ref = {j: o.nll_amp(d_h, M64, pts[j]) for j in (0, 1)}
+        out["oracle"] = {"evals_per_s": len(ref) / (time.perf_counter() - t),
+                         "cores": o.num_threads(), "sample": "points 0 and 1, all 2M events"}
+        del d_h
     for tag in ("default", "tuned"):
         if tag == "tuned":
             m.tune_amplitude_shape(5)
@@ -178,6 +197,11 @@ def bench_amplitude(args):
         out[tag] = {"shape": list(m.amplitude_shape()), "evals_per_s": r["evals_per_s"],
                     "kernel_us": kus, "achieved_gbs": 8.0 * W * N / (kus * 1e-6) / 1e9,
                     "frac_of_8tbs": 8.0 * W * N / (kus * 1e-6) / 8e12}
+        if ref is not None:
+            res = r["results"]
+            out[tag]["max_rel_dnll"] = max(abs(res[j][0] - ref[j][0]) / abs(ref[j][0]) for j in ref)
+            out[tag]["max_rel_grad"] = max(float(np.linalg.norm(res[j][1] - ref[j][1]) /
+                                                 np.linalg.norm(ref[j][1])) for j in ref)
         log("amplitude w32 n2m (%s shape %s): %.0f evals/s, kernel %.1f us (%.0f GB/s)"
             % (tag, out[tag]["shape"], r["evals_per_s"], kus, out[tag]["achieved_gbs"]))
     m.close()
@@ -249,9 +273,14 @@ def bench_multi(args):
         o = oracle.get()
         last = walk[iters - 1]
         worst_n, worst_g = 0.0, 0.0
+        t_or, ev_or = 0.0, 0
         for i, (d, mc, n_gen) in keep.items():
             M = o.mc_matrix(mc.astype(np.complex128), n_gen)
-            rn, rg, _ = o.nll_amp(d.astype(np.complex128), M, last[i])
+            d128 = d.astype(np.complex128)
+            t = time.perf_counter()
+            rn, rg, _ = o.nll_amp(d128, M, last[i])
+            t_or += time.perf_counter() - t
+            ev_or += d.shape[0]
             nll, g = res[i][0][0], res[i][1][0]
             dn = abs(nll - rn) / max(1.0, abs(rn))
             dg = float(np.linalg.norm(g - rg) / np.linalg.norm(rg))
@@ -259,6 +288,8 @@ def bench_multi(args):
             worst_g = max(worst_g, dg if np.isfinite(dg) else np.inf)
         out["parity"] = {"models": sorted(keep), "max_rel_dnll": worst_n, "max_rel_grad": worst_g,
                          "reference": "oracle on the same complex64 amplitudes"}
+        out["oracle"] = {"events_iter_per_s": ev_or / t_or, "cores": o.num_threads(),
+                         "sample": "one evaluation of each of the two smallest models"}
     log("multi-model: %.2f ms per iteration of 64 models (%.0f GB/s); separate calls %.2f ms"
         % (1e3 * dt, bytes_it / dt / 1e9, 1e3 * dt_seq))
     for m in models:
