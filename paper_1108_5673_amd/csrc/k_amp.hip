@@ -416,20 +416,33 @@ namespace pwa {
 // average, so the matrix is the data sum alone:
 // H = sum_i J_i J_i^T over theta = (Re V_0, Im V_0, Re V_1, ...), with
 // J_i = grad_theta ln I_i = 2 [Re z_ib, -Im z_ib]_b / I_i and z_ib = conj(S_i) A_ib
-// (the derivative of Eq. 1).  Per block, tiles of 64 events:
-//   1. the tile's amplitudes into LDS, one row per event (coalesced 16-byte
-//      loads of the lane-split layout);
-//   2. wavefront 0, lane = event: S_i and w_i = 1 / I_i in FP64;
-//   3. all threads: J_i into LDS as a 64 x PJ array (PJ = 2W rounded up to 4);
-//   4. thread t: the 4 x 4 blocks (bp, bq), bp <= bq, numbered t % npair, over
-//      the events of its split t / npair (splits of the 64 events when fewer
-//      than 256 pairs), 16 FP64 accumulators per block.
-// Beyond 3 x 256 block pairs (W > 76) the pairs form groups along the grid's
-// second dimension, each group streaming the tiles again.  J is held for 64
-// events at a time, or 32 or 16 when the LDS cannot hold 64.
-// Record per block column: [n_bad, then 16 doubles per block pair].
+// (the derivative of Eq. 1).
+//
+// H = J^T J over the events is a matrix product with the events as its inner
+// dimension: it runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64, D +=
+// A B with A 16 x 4 and B 4 x 16).  The 2W parameters are cut into NB blocks
+// of 16 (zero padded); a block pair (bp <= bq) accumulates
+// D[i][j] = sum_k J_k[16 bp + i] J_k[16 bq + j].  Lane l of a wavefront takes
+// event k = l / 16 of a step of 4 events and parameter i = l % 16 of every
+// block: that is where both operands of the instruction expect J_k[16 b + i]
+// (A[i][k] and B[k][j] sit in lane i + 16 k, D[4 r + l / 16][l % 16] in
+// register r), so the J values a lane forms feed the matrix cores directly.
+// Per block of 4 wavefronts, tiles of 64 events:
+//   1. the tile's amplitudes into LDS, one row per event (de-interleaving the
+//      lane-split layout);
+//   2. wavefront w takes events 16 w .. 16 w + 15 in 4 steps; per step the 16
+//      lanes of an event form partial S over waves i, i + 16, ..., sum them by
+//      an xor butterfly, then I, w = 2 / I and their J values in FP64;
+//   3. one MFMA per block pair (bp of the block's group of rows, bq >= bp).
+// Row groups: the block pairs of rows g R .. g R + R - 1 (R = NB up to 4 blocks,
+// 2 up to 8, else 1) are one group along the grid's second dimension, each
+// group streaming the tiles again.  The wavefronts are added in order through
+// LDS; the record of a block column is [n_bad, then 256 doubles (a 16 x 16
+// block, row-major) per block pair in packed order].  k_colsum adds the
+// records column by column in a fixed order and k_hess_expand writes the
+// matrix.  The next tile's amplitudes are loaded into registers while the
+// current one is used.
 constexpr int kHessThreads = 256;
-constexpr int kMaxPairs = 3;   // block pairs per thread in one group
 
 __host__ __device__ inline int amp_lds_stride_words(int wpad)
 {
@@ -440,216 +453,231 @@ __host__ __device__ inline int amp_lds_stride_words(int wpad)
     return words + pad;
 }
 
-__host__ __device__ inline int hess_pj(int W) { return (2 * W + 3) / 4 * 4; }
+__host__ __device__ inline int hess_nb(int W) { return (2 * W + 15) / 16; }
 __host__ __device__ inline int hess_npair(int W)
 {
-    const int nb = hess_pj(W) / 4;
+    const int nb = hess_nb(W);
     return nb * (nb + 1) / 2;
 }
-__host__ __device__ inline int hess_rec_len(int W) { return 1 + 16 * hess_npair(W); }
-// LDS of one block: the amplitude tile, J of ej events at a time, S and w.
-__host__ __device__ inline size_t hess_lds_bytes(int W, int wpad, int ej)
+__host__ __device__ inline int hess_rec_len(int W) { return 1 + 256 * hess_npair(W); }
+__host__ __device__ constexpr int hess_rows_per_group(int nb) { return nb <= 4 ? nb : (nb <= 8 ? 2 : 1); }
+inline int hess_groups(int W)
 {
-    const size_t main = (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4   // amplitude tile
-                        + (size_t)ej * hess_pj(W) * 8                        // J
-                        + (size_t)kAmpTile * 16 + (size_t)kAmpTile * 8       // S, w
-                        + 16;                                                // n_bad
-    const size_t combine = (size_t)kHessThreads * 16 * 8;   // partial blocks at the end
-    return (main > combine ? main : combine) + 16;
+    const int nb = hess_nb(W);
+    const int r = hess_rows_per_group(nb);
+    return (nb + r - 1) / r;
 }
 
-// Events whose J are held at once: the whole tile when the LDS allows.
-inline int hess_ej(int W, int wpad)
+template <int NB>
+__host__ __device__ constexpr size_t hess_lds_bytes(int wpad)
 {
-    int ej = kAmpTile;
-    while (ej > 16 && hess_lds_bytes(W, wpad, ej) > 160 * 1024) ej >>= 1;
-    return ej;
+    const size_t tile = (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4;
+    const size_t combine = (size_t)64 * hess_rows_per_group(NB) * NB * 4 * 8;
+    return (tile > combine ? tile : combine) + 16 * 128 /* V */ + 16;
 }
 
+typedef double hd4 __attribute__((ext_vector_type(4)));
+
+template <int NB>
 __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __restrict__ amp,
                                                               int64_t n_events, int64_t n_tiles,
                                                               int W, int wpad, int lq, int wl,
-                                                              int ej, VParams vp,
-                                                              double* __restrict__ recs)
+                                                              VParams vp, double* __restrict__ recs)
 {
+    constexpr int R = hess_rows_per_group(NB);
     extern __shared__ double lds_d[];
     char* lds = reinterpret_cast<char*>(lds_d);
     const int stride = amp_lds_stride_words(wpad) * 4;
-    const int PJ = hess_pj(W);
-    const int nb = PJ / 4;
-    const int npair = nb * (nb + 1) / 2;
+    const size_t main_bytes = hess_lds_bytes<NB>(wpad) - 16 * 128 - 16;
     char* tile = lds;
-    double* s_J = reinterpret_cast<double*>(tile + (size_t)kAmpTile * stride);
-    double2* s_S = reinterpret_cast<double2*>(s_J + (size_t)ej * PJ);
-    double* s_w = reinterpret_cast<double*>(s_S + kAmpTile);
-    // the count sits past both the tile data and the combine area
-    int* s_bad = reinterpret_cast<int*>(lds + hess_lds_bytes(W, wpad, ej) - 16);
+    double2* s_v = reinterpret_cast<double2*>(lds + main_bytes);
+    int* s_bad = reinterpret_cast<int*>(lds + main_bytes + 16 * 128);
     const int h = wpad >> 1;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int ki = lane >> 4;      // event of the step
+    const int pi = lane & 15;      // parameter within a block
+    // first row block of this group (known at compile time when one group
+    // holds every row, so that only the upper block pairs take registers)
+    const int g0 = R == NB ? 0 : (int)blockIdx.y * R;
 
-    // this block's group of block pairs (blockIdx.y: groups of up to 3 x 256
-    // pairs), this thread's pairs in it and its event split
-    const int pg0 = blockIdx.y * kMaxPairs * kHessThreads;
-    const int npg = min(npair - pg0, kMaxPairs * kHessThreads);
-    const int splits = npg >= kHessThreads ? 1 : kHessThreads / npg;
-    const int split = tid / (npg < kHessThreads ? npg : kHessThreads);
-    const int pair0 = tid % (npg < kHessThreads ? npg : kHessThreads);
-    const bool active = split < splits;
-    double acc[kMaxPairs][16];
-    int bp[kMaxPairs], bq[kMaxPairs];
-#pragma unroll
-    for (int r = 0; r < kMaxPairs; ++r) {
-        const int pl = pair0 + r * kHessThreads;
-        const int pr = pg0 + pl;
-        bp[r] = bq[r] = -1;
-        if (active && (r == 0 || npg > kHessThreads) && pl < npg) {
-            // pair index -> (bp, bq), row-major upper triangle
-            int rem = pr, row = 0;
-            while (rem >= nb - row) {
-                rem -= nb - row;
-                ++row;
-            }
-            bp[r] = row;
-            bq[r] = row + rem;
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) acc[r][k] = 0.0;
-    }
+    for (int a = tid; a < 128; a += blockDim.x)
+        s_v[a] = a < W ? make_double2(vp.v[2 * a], vp.v[2 * a + 1]) : make_double2(0.0, 0.0);
     if (tid == 0) *s_bad = 0;
+
+    hd4 D[R][NB];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int cq = 0; cq < NB; ++cq) D[rr][cq] = hd4{0.0, 0.0, 0.0, 0.0};
+    int nbad = 0;
 
     const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
     const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
+    // the next tile's vectors are loaded into registers while the current one
+    // is used, when a tile is at most PRE vectors per thread (rows of the
+    // default shapes); otherwise they are staged directly
+    constexpr int PRE = NB + 1;
+    const int n_f4 = kAmpTile * h;
+    const bool pre_ok = n_f4 <= PRE * kHessThreads;
+    float4 pre[PRE];
+    // lane-split layout -> one LDS row per event (16-byte column c)
+    auto stage = [tile, stride, wl, lq](int f, float4 x) {
+        const int kl = f / (32 * wl), rem = f - kl * 32 * wl;
+        const int j = rem >> 6, ln = rem & 63;
+        const int ev = (kl << (6 - lq)) + (ln >> lq);
+        const int c = (ln & ((1 << lq) - 1)) * (wl >> 1) + j;
+        *reinterpret_cast<float4*>(tile + ev * stride + c * 16) = x;
+    };
+    if (pre_ok && t0 < t1) {
+        const float4* src = amp + t0 * kAmpTile * h;
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) {
+            const int f = tid + kHessThreads * q;
+            pre[q] = f < n_f4 ? src[f] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
     for (int64_t t = t0; t < t1; ++t) {
-        const float4* src = amp + t * kAmpTile * h;
-        // lane-split layout -> one LDS row per event (16-byte column c)
-        for (int f = tid; f < kAmpTile * h; f += blockDim.x) {
-            const int kl = f / (32 * wl), rem = f - kl * 32 * wl;
-            const int j = rem >> 6, ln = rem & 63;
-            const int ev = (kl << (6 - lq)) + (ln >> lq);
-            const int c = (ln & ((1 << lq) - 1)) * (wl >> 1) + j;
-            *reinterpret_cast<float4*>(tile + ev * stride + c * 16) = src[f];
-        }
-        __syncthreads();
-        if (tid < kAmpTile) {
-            const char* row = tile + tid * stride;
-            double sr = 0.0, si = 0.0;
-            for (int a = 0; a < W; ++a) {
-                const float2 x = *reinterpret_cast<const float2*>(row + a * 8);
-                const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
-                sr += vr * (double)x.x - vi * (double)x.y;
-                si += vr * (double)x.y + vi * (double)x.x;
+        __syncthreads();   // the previous tile's rows are no longer read
+        if (pre_ok) {
+#pragma unroll
+            for (int q = 0; q < PRE; ++q) {
+                const int f = tid + kHessThreads * q;
+                if (f < n_f4) stage(f, pre[q]);
             }
-            const double I = sr * sr + si * si;
-            const bool valid = t * kAmpTile + tid < n_events;
-            const bool ok = valid && (I > 0.0) && (I < INFINITY);
-            if (valid && !ok) atomicAdd(s_bad, 1);   // LDS count, order-free
-            s_S[tid] = make_double2(sr, si);
-            // NaN for a degenerate event (its J, and so H, become NaN), 0 for padding
-            s_w[tid] = ok ? 2.0 / I : (valid ? NAN : 0.0);
+        } else {
+            const float4* src = amp + t * kAmpTile * h;
+            for (int f = tid; f < n_f4; f += blockDim.x) stage(f, src[f]);
         }
         __syncthreads();
-        // J of ej events at a time (all 64 when the LDS holds them)
-        for (int e0 = 0; e0 < kAmpTile; e0 += ej) {
-            for (int f = tid; f < ej * PJ; f += blockDim.x) {
-                const int ev = e0 + f / PJ, p = f - (ev - e0) * PJ;
+        if (pre_ok && t + 1 < t1) {
+            const float4* src = amp + (t + 1) * kAmpTile * h;
+#pragma unroll
+            for (int q = 0; q < PRE; ++q) {
+                const int f = tid + kHessThreads * q;
+                pre[q] = f < n_f4 ? src[f] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+#pragma unroll 1
+        for (int st = 0; st < 4; ++st) {
+            const int ev = 16 * wave + 4 * st + ki;
+            const char* row = tile + ev * stride;
+            // S over waves pi, pi + 16, ...; then summed over the event's 16 lanes
+            double sr = 0.0, si = 0.0;
+            for (int a = pi; a < W; a += 16) {
+                const float2 x = *reinterpret_cast<const float2*>(row + a * 8);
+                const double2 v = s_v[a];
+                sr = __fma_rn(v.x, (double)x.x, sr);
+                sr = __fma_rn(-v.y, (double)x.y, sr);
+                si = __fma_rn(v.x, (double)x.y, si);
+                si = __fma_rn(v.y, (double)x.x, si);
+            }
+            sr += xor_lane_f64<1>(sr);
+            si += xor_lane_f64<1>(si);
+            sr += xor_lane_f64<2>(sr);
+            si += xor_lane_f64<2>(si);
+            sr += xor_lane_f64<4>(sr);
+            si += xor_lane_f64<4>(si);
+            sr += xor_lane_f64<8>(sr);
+            si += xor_lane_f64<8>(si);
+            const double I = sr * sr + si * si;
+            const bool valid = t * kAmpTile + ev < n_events;
+            const bool ok = valid && (I > 0.0) && (I < INFINITY);
+            if (pi == 0 && valid && !ok) ++nbad;
+            // NaN for a degenerate event (its J, and so H, become NaN), 0 for padding
+            const double w = ok ? 2.0 * recip_f64(I) : (valid ? NAN : 0.0);
+            // J_k[p] for parameter p = 16 b + pi: w Re z (p even) or -w Im z (p odd),
+            // z = conj(S) A_{p / 2}
+            auto jval = [&](int b) {
+                const int p = 16 * b + pi;
                 double j = 0.0;
                 if (p < 2 * W) {
-                    const int b = p >> 1;
-                    const float2 x = *reinterpret_cast<const float2*>(tile + ev * stride + b * 8);
-                    const double2 S = s_S[ev];
-                    // z = conj(S) A_b
-                    const double zr = S.x * (double)x.x + S.y * (double)x.y;
-                    const double zi = S.x * (double)x.y - S.y * (double)x.x;
-                    j = s_w[ev] * ((p & 1) ? -zi : zr);
+                    const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
+                    const double zr = __fma_rn(sr, (double)x.x, si * (double)x.y);
+                    const double zi = __fma_rn(sr, (double)x.y, -si * (double)x.x);
+                    j = w * ((p & 1) ? -zi : zr);
                 }
-                s_J[f] = j;
-            }
-            __syncthreads();
-            if (active) {
+                return j;
+            };
+            double Jv[NB];
 #pragma unroll
-                for (int r = 0; r < kMaxPairs; ++r) {
-                    if (bp[r] < 0) continue;
-                    for (int ev = split; ev < ej; ev += splits) {
-                        const double* Jr = s_J + ev * PJ;
-                        const double2 a01 = *reinterpret_cast<const double2*>(Jr + 4 * bp[r]);
-                        const double2 a23 = *reinterpret_cast<const double2*>(Jr + 4 * bp[r] + 2);
-                        const double2 b01 = *reinterpret_cast<const double2*>(Jr + 4 * bq[r]);
-                        const double2 b23 = *reinterpret_cast<const double2*>(Jr + 4 * bq[r] + 2);
-                        const double ai[4] = {a01.x, a01.y, a23.x, a23.y};
-                        const double bj[4] = {b01.x, b01.y, b23.x, b23.y};
+            for (int cq = 0; cq < NB; ++cq) Jv[cq] = jval(cq);
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
+            for (int rr = 0; rr < R; ++rr) {
+                const int bp = g0 + rr;
+                if (bp < NB) {
+                    const double Jp = R == NB ? Jv[rr] : jval(bp);
 #pragma unroll
-                            for (int j = 0; j < 4; ++j) acc[r][4 * i + j] += ai[i] * bj[j];
-                    }
+                    for (int cq = 0; cq < NB; ++cq)
+                        if (cq >= bp)
+                            D[rr][cq] = __builtin_amdgcn_mfma_f64_16x16x4f64(Jp, Jv[cq], D[rr][cq],
+                                                                             0, 0, 0);
                 }
             }
-            __syncthreads();
         }
     }
 
-    // combine the event splits of each pair in split order, write the record
+    // n_bad: one lane per event counted; the block's total by LDS atomics
+    nbad = wave_allsum_int(nbad);
+    __syncthreads();
+    if (lane == 0 && nbad) atomicAdd(s_bad, nbad);   // LDS, order-free integer count
+    // the wavefronts' D added in wavefront order through LDS (the tile area)
+    double* s_d = reinterpret_cast<double*>(lds);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        __syncthreads();
+        if (wave == w) {
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                for (int cq = 0; cq < NB; ++cq)
+                    if (g0 + rr < NB && cq >= g0 + rr)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            double* slot = s_d + ((size_t)((rr * NB + cq) * 4 + r) * 64 + lane);
+                            *slot = (w == 0 ? 0.0 : *slot) + D[rr][cq][r];
+                        }
+        }
+    }
+    __syncthreads();
     double* rec = recs + (int64_t)blockIdx.x * hess_rec_len(W);
-    double* s_part = reinterpret_cast<double*>(lds);   // reuses the tile area
-    for (int r = 0; r < kMaxPairs; ++r) {
-        if (r > 0 && npg <= kHessThreads) break;
-        __syncthreads();
-        if (active && bp[r] >= 0)
-            for (int k = 0; k < 16; ++k) s_part[(size_t)tid * 16 + k] = acc[r][k];
-        __syncthreads();
-        const int base = r * kHessThreads;
-        const int np_here = min(npg - base, kHessThreads);
-        if (np_here <= 0) break;
-        for (int e = tid; e < np_here * 16; e += blockDim.x) {
-            const int pr = e / 16, k = e % 16;
-            double x = 0.0;
-            for (int sp = 0; sp < splits; ++sp) x += s_part[(size_t)(sp * npg + pr) * 16 + k];
-            rec[1 + (size_t)(pg0 + base + pr) * 16 + k] = x;
+    // record: block pair (bp, bq) at 1 + 256 * pair, element [i][j] row-major,
+    // from lane l = j + 16 (i % 4), register r = i / 4
+    for (int rr = 0; rr < R; ++rr) {
+        const int bp = g0 + rr;
+        if (bp >= NB) break;
+        for (int e = tid; e < (NB - bp) * 256; e += blockDim.x) {
+            const int cq = bp + e / 256, ij = e % 256;
+            const int i = ij >> 4, j = ij & 15;
+            const int l = j + 16 * (i & 3), r = i >> 2;
+            const int pair = bp * NB - bp * (bp - 1) / 2 + (cq - bp);
+            rec[1 + (size_t)pair * 256 + ij] = s_d[(size_t)((rr * NB + cq) * 4 + r) * 64 + l];
         }
     }
     if (tid == 0 && blockIdx.y == 0) rec[0] = (double)*s_bad;
 }
 
-// Sum of the block records in block order; one thread per entry of the
-// 2W x 2W matrix (full, row-major), written to pinned host memory.
-__global__ __launch_bounds__(256) void k_hess_assemble(const double* __restrict__ recs, int rows,
-                                                       int W, double* out,
-                                                       unsigned long long* done,
-                                                       unsigned long long seq)
+// The matrix from the column sums of the block records (k_colsum: one
+// wavefront per column, fixed order); one thread per entry of the 2W x 2W
+// matrix (full, row-major), written to pinned host memory.
+__global__ __launch_bounds__(256) void k_hess_expand(const double* __restrict__ colsum, int W,
+                                                     double* out, unsigned long long* done,
+                                                     unsigned long long seq)
 {
     const int P = 2 * W;
-    const int rl = hess_rec_len(W);
-    const int nb = hess_pj(W) / 4;
+    const int nb = hess_nb(W);
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < P * P) {
-        const int p = e / P, q = e % P;
-        int i = p / 4, j = q / 4;
-        int pp = p % 4, qq = q % 4;
-        if (i > j) {   // the lower triangle mirrors the upper
-            const int ti = i, tp = pp;
-            i = j;
-            pp = qq;
-            j = ti;
-            qq = tp;
+        int p = e / P, q = e % P;
+        if (p > q) {   // the lower triangle mirrors the upper
+            const int tp = p;
+            p = q;
+            q = tp;
         }
+        const int i = p / 16, j = q / 16;
         const int pair = i * nb - i * (i - 1) / 2 + (j - i);
-        const int col = 1 + pair * 16 + 4 * pp + qq;
-        double x = 0.0, bad = 0.0;
-        constexpr int kB = 16;
-        for (int r0 = 0; r0 < rows; r0 += kB) {
-            double v[kB], bv[kB];
-#pragma unroll
-            for (int k = 0; k < kB; ++k) {
-                v[k] = r0 + k < rows ? recs[(int64_t)(r0 + k) * rl + col] : 0.0;
-                bv[k] = r0 + k < rows ? recs[(int64_t)(r0 + k) * rl] : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < kB; ++k) {
-                x += v[k];
-                bad += bv[k];
-            }
-        }
-        store_system(out + e, bad > 0.0 ? NAN : x);
+        const double x = colsum[1 + pair * 256 + 16 * (p % 16) + (q % 16)];
+        store_system(out + e, colsum[0] > 0.0 ? NAN : x);
     }
     wait_vm_complete();
     __syncthreads();
@@ -657,30 +685,63 @@ __global__ __launch_bounds__(256) void k_hess_assemble(const double* __restrict_
         __hip_atomic_store(done + blockIdx.x, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-int hess_grid(const Model& m) { return (int)std::min<int64_t>(2 * m.cus, std::max<int64_t>(1, m.n_tiles)); }
-int hess_rows(const Model& m) { return hess_grid(m); }
+// block columns: fewer when the row groups multiply the blocks
+int hess_grid(const Model& m)
+{
+    const int64_t want = std::max<int64_t>(64, 4 * (int64_t)m.cus / hess_groups(m.W));
+    return (int)std::min<int64_t>(want, std::max<int64_t>(1, m.n_tiles));
+}
+// block records plus one row for their column sums
+int hess_rows(const Model& m) { return hess_grid(m) + 1; }
 int hess_rec_doubles(int W) { return hess_rec_len(W); }
 int hess_assemble_blocks(int W) { return (4 * W * W + 255) / 256; }
 
-hipError_t launch_hessian(const Model& m, const VParams& vp, double* recs, double* out,
-                          unsigned long long* done, unsigned long long seq, hipStream_t s)
+template <int NB>
+static hipError_t launch_hessian_nb(const Model& m, const VParams& vp, double* recs, hipStream_t s)
 {
-    const int ej = hess_ej(m.W, m.wpad);
-    const size_t lds = hess_lds_bytes(m.W, m.wpad, ej);
+    const size_t lds = hess_lds_bytes<NB>(m.wpad);
     if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute((const void*)&k_amp_hessian,
+        const hipError_t e = hipFuncSetAttribute((const void*)&k_amp_hessian<NB>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds);
         if (e != hipSuccess) return e;
     }
-    const int groups = (hess_npair(m.W) + kMaxPairs * kHessThreads - 1) / (kMaxPairs * kHessThreads);
-    hipLaunchKernelGGL(k_amp_hessian, dim3(hess_grid(m), groups), dim3(kHessThreads), lds, s,
-                       (const float4*)m.d_data, m.n, m.n_tiles, m.W, m.wpad, m.amp_lq, m.amp_wl,
-                       ej, vp, recs);
-    hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL((k_amp_hessian<NB>), dim3(hess_grid(m), hess_groups(m.W)),
+                       dim3(kHessThreads), lds, s, (const float4*)m.d_data, m.n, m.n_tiles, m.W,
+                       m.wpad, m.amp_lq, m.amp_wl, vp, recs);
+    return hipGetLastError();
+}
+
+hipError_t launch_hessian(const Model& m, const VParams& vp, double* recs, double* out,
+                          unsigned long long* done, unsigned long long seq, hipStream_t s)
+{
+    hipError_t e = hipErrorInvalidValue;
+    switch (hess_nb(m.W)) {
+    case 1: e = launch_hessian_nb<1>(m, vp, recs, s); break;
+    case 2: e = launch_hessian_nb<2>(m, vp, recs, s); break;
+    case 3: e = launch_hessian_nb<3>(m, vp, recs, s); break;
+    case 4: e = launch_hessian_nb<4>(m, vp, recs, s); break;
+    case 5: e = launch_hessian_nb<5>(m, vp, recs, s); break;
+    case 6: e = launch_hessian_nb<6>(m, vp, recs, s); break;
+    case 7: e = launch_hessian_nb<7>(m, vp, recs, s); break;
+    case 8: e = launch_hessian_nb<8>(m, vp, recs, s); break;
+    case 9: e = launch_hessian_nb<9>(m, vp, recs, s); break;
+    case 10: e = launch_hessian_nb<10>(m, vp, recs, s); break;
+    case 11: e = launch_hessian_nb<11>(m, vp, recs, s); break;
+    case 12: e = launch_hessian_nb<12>(m, vp, recs, s); break;
+    case 13: e = launch_hessian_nb<13>(m, vp, recs, s); break;
+    case 14: e = launch_hessian_nb<14>(m, vp, recs, s); break;
+    case 15: e = launch_hessian_nb<15>(m, vp, recs, s); break;
+    case 16: e = launch_hessian_nb<16>(m, vp, recs, s); break;
+    default: break;
+    }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_hess_assemble, dim3(hess_assemble_blocks(m.W)), dim3(256), 0, s, recs,
-                       hess_rows(m), m.W, out, done, seq);
+    const int rows = hess_grid(m), rl = hess_rec_len(m.W);
+    double* colsum = recs + (size_t)rows * rl;
+    e = launch_colsum(recs, rows, rl, rl, colsum, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hess_expand, dim3(hess_assemble_blocks(m.W)), dim3(256), 0, s, colsum,
+                       m.W, out, done, seq);
     return hipGetLastError();
 }
 
