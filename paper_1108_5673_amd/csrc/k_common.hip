@@ -1,13 +1,12 @@
 // k_common.hip -- the MC integral matrix and the fixed-order final reduction.
 //
 // M_aa' = (1/N_gen) sum_{j accepted} B_ja B*_ja' (Eq. 3, inner bracket) is built
-// once per model in FP64.  Each evaluation ends with two small kernels: a
-// column sum of the per-block partial records (one wavefront per column, a
-// fixed assignment of rows to lanes and a fixed butterfly, so results repeat
-// bit for bit), then the assembly of NLL = -sum ln I + mu and
-// G_b = 2 sum_a V_a (M_ab - U_ab) (table forms) or 2 sum_a V_a M_ab - 2 g_b
-// (amplitude form), with mu = sum_a sum_b V_a V*_b M_ab: the MC quadratic form
-// is evaluated here, in FP64, once per evaluation.
+// once per model in FP64.  Each evaluation ends with one small kernel that
+// sums the streaming kernel's per-block records in a fixed order and
+// assembles NLL = -sum ln I + mu and G_b = 2 sum_a V_a (M_ab - U_ab) (records
+// of packed U: the table forms) or 2 sum_a V_a M_ab - 2 g_b (records of g_b:
+// the amplitude form), with mu = sum_a sum_b V_a V*_b M_ab: the MC quadratic
+// form is evaluated here, in FP64, once per evaluation.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -345,7 +344,7 @@ __device__ void assemble_role(const double* v, const TailArgs& ta, int role,
     // the entries this gradient component needs: U_ab for all a (packed row and
     // column of b) or g_b; thread t works on entry a = t % nent over the record
     // range t / nent, and the ranges are added in order
-    const int nent = ta.amplitude ? 1 : W;
+    const int nent = ta.g_records ? 1 : W;
     const int chunks = kAssembleThreads / nent;
     const int a = threadIdx.x % nent;
     const int ch = threadIdx.x / nent;
@@ -353,7 +352,7 @@ __device__ void assemble_role(const double* v, const TailArgs& ta, int role,
     if (ch < chunks) {
         int col;
         double sgn = 1.0;
-        if (ta.amplitude) {
+        if (ta.g_records) {
             col = 2 + 2 * b;
         } else if (a <= b) {
             col = 2 + 2 * packed_index(W, a, b);
@@ -377,7 +376,7 @@ __device__ void assemble_role(const double* v, const TailArgs& ta, int role,
                 xr += s_acc[c * nent + l].x;
                 xi += s_acc[c * nent + l].y;
             }
-            if (ta.amplitude) {
+            if (ta.g_records) {
                 ur = xr;
                 ui = xi;
             } else {
@@ -431,7 +430,7 @@ __global__ __launch_bounds__(kAssembleThreads) void k_assemble_multi(
     ta.seq = *reinterpret_cast<const unsigned long long*>(params);
     ta.W = j.W;
     ta.grad = 1;
-    ta.amplitude = 1;
+    ta.g_records = 1;
     assemble_role(params + j.v_off, ta, ab.role, done + j.done_off + ab.role);
 }
 

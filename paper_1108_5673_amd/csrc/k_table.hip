@@ -357,21 +357,24 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int nwaves = blockDim.x >> 6;
 
-    // This wave's sub-tiles, in order: tiles t0 + wave, t0 + wave + nwaves, ...,
-    // each split into NSUB sub-tiles.  The next sub-tile is loaded while the
-    // current one is processed (two register buffers); the first load is
-    // issued before the coefficients are formed.
-    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
-    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
+    // This wave's sub-tiles, in order: sub-tiles s0 + wave, s0 + wave + nwaves,
+    // ... of the block's range (sub-tile s is part s % NSUB of tile s / NSUB;
+    // sub-tiles rather than tiles are dealt out, so that the wavefronts'
+    // shares differ by at most one sub-tile).  The next sub-tile is loaded
+    // while the current one is processed (two register buffers); the first
+    // load is issued before the coefficients are formed.
+    const int64_t n_sub = n_tiles * NSUB;
+    const int64_t s0 = (int64_t)blockIdx.x * n_sub / gridDim.x;
+    const int64_t s1 = (int64_t)(blockIdx.x + 1) * n_sub / gridDim.x;
     const int64_t tile_bytes = (int64_t)P * kTileEvents * esz;
-    const int64_t my_tiles = (t1 - t0 > wave) ? (t1 - t0 - wave + nwaves - 1) / nwaves : 0;
-    const int64_t U = my_tiles * NSUB;
-    auto tile_of = [&](int64_t u) { return t0 + wave + nwaves * (u / NSUB); };
-    auto base_of = [&](int64_t u) { return table + tile_of(u) * tile_bytes; };
-    auto first_of = [&](int64_t u) { return tile_of(u) * kTileEvents + (u % NSUB) * E; };
+    const int64_t U = (s1 - s0 > wave) ? (s1 - s0 - wave + nwaves - 1) / nwaves : 0;
+    auto sub_of = [&](int64_t u) { return s0 + wave + nwaves * u; };
+    auto base_of = [&](int64_t u) { return table + (sub_of(u) / NSUB) * tile_bytes; };
+    auto part_of = [&](int64_t u) { return (int)(sub_of(u) % NSUB); };
+    auto first_of = [&](int64_t u) { return sub_of(u) * E; };
 
     SubTile<S, K, E> a, b;
-    if (U > 0) a.load(base_of(0), 0, P, lane);
+    if (U > 0) a.load(base_of(0), part_of(0), P, lane);
 
     // coefficients c_e for every (slot, lane)
     for (int idx = threadIdx.x; idx < K * 64; idx += blockDim.x) {
@@ -395,10 +398,10 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
     FusedState fs{0.0, 1.0, 0};
 
     for (int64_t u = 0; u < U; u += 2) {
-        if (u + 1 < U) b.load(base_of(u + 1), (int)((u + 1) % NSUB), P, lane);
+        if (u + 1 < U) b.load(base_of(u + 1), part_of(u + 1), P, lane);
         process_subtile<S, K, E, GRAD>(a, s_c, lane, u, first_of(u), n_events, ur, ui, fs);
         if (u + 1 < U) {
-            if (u + 2 < U) a.load(base_of(u + 2), (int)((u + 2) % NSUB), P, lane);
+            if (u + 2 < U) a.load(base_of(u + 2), part_of(u + 2), P, lane);
             process_subtile<S, K, E, GRAD>(b, s_c, lane, u + 1, first_of(u + 1), n_events, ur, ui, fs);
         }
     }

@@ -369,7 +369,7 @@ int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, 
     ta.seq = ++m->seq;
     ta.W = m->W;
     ta.grad = grad ? 1 : 0;
-    ta.amplitude = m->form == pwa::kAmp32 ? 1 : 0;
+    ta.g_records = m->form == pwa::kAmp32 ? 1 : 0;
     pwa::LaunchEvents ev;
     if (timed) {
         const int rc = timing_slot(m, &ev);

@@ -3,7 +3,8 @@
 // its gradient, in one small kernel launched after the streaming kernel.
 //
 // Record layout (rec_len doubles): [sum ln I, n_bad, then 2 doubles per
-// accumulated entry: U_e (table forms, e < P) or g_b (amplitude form, b < W)].
+// accumulated entry: U_e of the packed table (table forms, e < P), or g_b =
+// sum_i S_i conj(A_ib) / I_i (amplitude form, b < W)].
 //
 // The kernel boundary makes every block's record visible with ordinary stores
 // and loads; no kernel synchronises across blocks.  (Cross-block tickets at
@@ -14,10 +15,10 @@
 // The assembly is split by output so that its blocks are independent:
 //   block 0      NLL = -sum ln I + mu,  mu = sum_b Re(conj(V_b) m_b),
 //                m_b = sum_a V_a M_ab (the MC term of Eq. 3), and n_bad;
-//   block 1 + b  G_b = 2 (m_b - u_b),  u_b = sum_a V_a U_ab  (table forms; U is
-//                Hermitian and stored packed, so block b reads only the W
-//                packed columns of its row and column), or
-//                G_b = 2 (m_b - g_b)  (amplitude form).
+//   block 1 + b  G_b = 2 (m_b - u_b),  u_b = sum_a V_a U_ab  (packed U records;
+//                U is Hermitian and stored packed, so block b reads only the
+//                W packed columns of its row and column), or
+//                G_b = 2 (m_b - g_b)  (g records).
 // A degenerate event (I <= 0 or not finite) is counted in n_bad, which makes
 // the NLL +inf, and carries a NaN weight, which makes every U_ab or g_b of its
 // block's record, and so every G_b, NaN.
@@ -44,7 +45,7 @@ struct TailArgs {
     unsigned long long seq;     // value published in the completion words
     int W;
     int grad;
-    int amplitude;
+    int g_records;           // records hold g_b (2W) rather than packed U (2P)
 };
 
 constexpr int kAssembleThreads = 256;
