@@ -137,6 +137,25 @@ int pwa_nll_grad(const pwa_model* model, const double* v, double* nll, double* g
                  void* hip_stream);
 
 /*
+ * Asynchronous twins of pwa_nll and pwa_nll_grad for stream-ordered use and
+ * HIP graph capture: V is read from device memory (v_dev, 2W doubles) when the
+ * work runs, and the results are written to device memory
+ * (out_dev = [nll, n_bad, grad 2W]; pwa_nll_async writes the first two).  The
+ * call only enqueues kernels on hip_stream and returns: it allocates nothing,
+ * records no memset or copy and touches no host memory, so it can be captured
+ * and replayed, each replay reading the V then in v_dev.  Nothing is checked
+ * on V (a non-finite V gives non-finite results).  A degenerate evaluation
+ * has n_bad > 0, nll = +INFINITY and a NaN gradient.  All forms but the
+ * 16-bit matrix forms.  Evaluations of one model share its scratch buffers:
+ * they must be ordered on one stream (or captured in one graph branch), also
+ * with respect to its synchronous calls.
+ */
+int pwa_nll_async(const pwa_model* model, const double* v_dev, double* out_dev,
+                  void* hip_stream);
+int pwa_nll_grad_async(const pwa_model* model, const double* v_dev, double* out_dev,
+                       void* hip_stream);
+
+/*
  * pwa_nll_batched -- many parameter sets, possibly on several models (fits
  * repeated from several starting points and several models tried, Sec. 2).
  *

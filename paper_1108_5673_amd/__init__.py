@@ -163,6 +163,23 @@ class Model:
             warnings.warn("degenerate event (I <= 0): NLL is +inf, gradient NaN")
         return out.value, g
 
+    def nll_grad_async(self, v_dev, out_dev, grad: bool = True, stream=None) -> None:
+        """Enqueue one evaluation: V read from the device tensor v_dev (2W
+        float64) when it runs, [nll, n_bad, grad 2W] written to out_dev (float64,
+        2 + 2W; the first two without grad).  Stream-ordered, capturable in a
+        graph; no synchronisation."""
+        import torch
+        for t, what, n in ((v_dev, "v_dev", 2 * self.n_waves),
+                           (out_dev, "out_dev", 2 + 2 * self.n_waves if grad else 2)):
+            if not (_is_torch(t) and t.is_cuda and t.dtype == torch.float64
+                    and t.is_contiguous() and t.numel() >= n):
+                raise ValueError("%s must be a contiguous CUDA float64 tensor of >= %d values"
+                                 % (what, n))
+        s = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        fn = _native.lib().pwa_nll_grad_async if grad else _native.lib().pwa_nll_async
+        _native.check(fn(self._handle(), ctypes.c_void_p(v_dev.data_ptr()),
+                         ctypes.c_void_p(out_dev.data_ptr()), ctypes.c_void_p(s)))
+
     # -- inspection ---------------------------------------------------------
     def nll_grad_hess(self, v):
         """(NLL, gradient (2W,), FUMILI matrix (2W, 2W)); amplitude form."""

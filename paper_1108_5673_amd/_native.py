@@ -35,7 +35,8 @@ EXPORTED = (
     "pwa_set_mc_matrix", "pwa_set_timing", "pwa_get_timing", "pwa_build_timing",
     "pwa_lbfgs_default_options", "pwa_lbfgs_minimize", "pwa_fit_lbfgs", "pwa_nll_grad_hess",
     "pwa_newton_minimize", "pwa_fit_fumili", "pwa_get_amplitude_shape",
-    "pwa_set_amplitude_shape", "pwa_tune_amplitude_shape",
+    "pwa_set_amplitude_shape", "pwa_tune_amplitude_shape", "pwa_nll_async",
+    "pwa_nll_grad_async",
 )
 
 PWA_LBFGS_CONVERGED_GRADIENT = 0
@@ -124,6 +125,8 @@ def _declare(L):
     L.pwa_copy_mc_matrix.argtypes = [p, p, p]
     L.pwa_set_mc_matrix.argtypes = [p, p, p]
     L.pwa_set_timing.argtypes = [p, ctypes.c_int]
+    L.pwa_nll_async.argtypes = [p, p, p, p]
+    L.pwa_nll_grad_async.argtypes = [p, p, p, p]
     i32p = ctypes.POINTER(ctypes.c_int32)
     L.pwa_get_amplitude_shape.argtypes = [p, i32p, i32p]
     L.pwa_set_amplitude_shape.argtypes = [p, ctypes.c_int32, ctypes.c_int32, p]

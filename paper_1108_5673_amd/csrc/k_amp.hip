@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64 * kAmpBlockWaves) void k_amp_fused(
 {
     const int64_t k0 = (int64_t)blockIdx.x * n_steps / gridDim.x;
     const int64_t k1 = (int64_t)(blockIdx.x + 1) * n_steps / gridDim.x;
-    amp_block<WL, GRAD>(amp, n_events, k0, k1, W, lq, vp.v,
+    amp_block<WL, GRAD>(amp, n_events, k0, k1, W, lq, vsrc(vp),
                         partials + (int64_t)blockIdx.x * rec_len);
 }
 
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
     const int g0 = R == NB ? 0 : (int)blockIdx.y * R;
 
     for (int a = tid; a < 128; a += blockDim.x)
-        s_v[a] = a < W ? make_double2(vp.v[2 * a], vp.v[2 * a + 1]) : make_double2(0.0, 0.0);
+        s_v[a] = a < W ? make_double2(vsrc(vp)[2 * a], vsrc(vp)[2 * a + 1]) : make_double2(0.0, 0.0);
     if (tid == 0) *s_bad = 0;
 
     hd4 D[R][NB];

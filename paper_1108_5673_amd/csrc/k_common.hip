@@ -295,9 +295,11 @@ __device__ inline double2 strided_record_sum(const TailArgs& ta, int col, int fi
 }
 
 // All of this block's result stores have completed: publish `seq` in its
-// completion word.
+// completion word (none for the asynchronous entry points: word is null in
+// every block).
 __device__ inline void publish(unsigned long long* word, unsigned long long seq)
 {
+    if (!word) return;
     wait_vm_complete();
     __syncthreads();
     if (threadIdx.x == 0)
@@ -406,7 +408,7 @@ __device__ void assemble_role(const double* v, const TailArgs& ta, int role,
 
 __global__ __launch_bounds__(kAssembleThreads) void k_assemble(VParams vp, TailArgs ta)
 {
-    assemble_role(vp.v, ta, blockIdx.x, ta.done + blockIdx.x);
+    assemble_role(vsrc(vp), ta, blockIdx.x, ta.done ? ta.done + blockIdx.x : nullptr);
 }
 
 // The assembly of many evaluations in one launch: block i is role

@@ -122,8 +122,9 @@ __global__ __launch_bounds__(256) void k_plain_intensity(const double2* __restri
     for (int e = threadIdx.x; e < P; e += blockDim.x) {
         const uint32_t pr = pairs[e];
         const int a = (int)(pr & 0xffffu), b = (int)(pr >> 16);
-        const double vr = vp.v[2 * a], vi = vp.v[2 * a + 1];
-        const double wr = vp.v[2 * b], wi = vp.v[2 * b + 1];
+        const double* v = vsrc(vp);
+        const double vr = v[2 * a], vi = v[2 * a + 1];
+        const double wr = v[2 * b], wi = v[2 * b + 1];
         const double f = (a == b) ? 1.0 : 2.0;
         s_c[e] = make_double2(f * (vr * wr + vi * wi), f * (vi * wr - vr * wi));
     }

@@ -382,8 +382,9 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
         if (idx < P) {
             const uint32_t pr = pairs[idx];
             const int wa = (int)(pr & 0xffffu), wb = (int)(pr >> 16);
-            const double vr = vp.v[2 * wa], vi = vp.v[2 * wa + 1];
-            const double wr = vp.v[2 * wb], wi = vp.v[2 * wb + 1];
+            const double* v = vsrc(vp);
+            const double vr = v[2 * wa], vi = v[2 * wa + 1];
+            const double wr = v[2 * wb], wi = v[2 * wb + 1];
             const double f = (wa == wb) ? 1.0 : 2.0;
             c.x = f * (vr * wr + vi * wi);   // Re V_a V*_b
             c.y = f * (vi * wr - vr * wi);   // Im V_a V*_b

@@ -352,20 +352,24 @@ int check_v(const double* v, int W)
 }
 
 // Enqueue one evaluation writing slot `slot` of h_out; returns the completion
-// value the last block will publish in h_done.
+// value the last block will publish in h_done.  With v_dev set (asynchronous
+// entry points), V is read from device memory, the results go to out_dev and
+// nothing is published.
 int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, bool timed,
-                 unsigned long long* seq_out, int* nblk_out)
+                 unsigned long long* seq_out, int* nblk_out, const double* v_dev = nullptr,
+                 double* out_dev = nullptr)
 {
     pwa::VParams vp;
     std::memset(&vp, 0, sizeof vp);
-    std::memcpy(vp.v, v, sizeof(double) * 2 * m->W);
+    if (v_dev) vp.dev = v_dev;
+    else std::memcpy(vp.v, v, sizeof(double) * 2 * m->W);
     pwa::TailArgs ta;
     ta.rec = m->d_partials;
     ta.rows = m->rows;
     ta.rec_len = m->rec_len;
     ta.M = (const double2*)m->d_M;
-    ta.out = m->h_out + (size_t)slot * (2 + 2 * m->W);
-    ta.done = m->h_done;
+    ta.out = v_dev ? out_dev : m->h_out + (size_t)slot * (2 + 2 * m->W);
+    ta.done = v_dev ? nullptr : m->h_done;
     ta.seq = ++m->seq;
     ta.W = m->W;
     ta.grad = grad ? 1 : 0;
@@ -886,6 +890,22 @@ int log2_lanes(int lanes)
     return lq;
 }
 
+// The asynchronous twins: enqueue only (kernels, nothing allocated, no host
+// memory touched), so that the work can be captured in a graph.
+int evaluate_async(const pwa_model* cm, const double* v_dev, double* out_dev, bool grad,
+                   void* stream)
+{
+    if (!cm || !v_dev || !out_dev) return fail(PWA_ERR_INVALID, "NULL model, v_dev or out_dev");
+    Model* m = reinterpret_cast<Model*>(const_cast<pwa_model*>(cm));
+    if (is_mfma(m))
+        return fail(PWA_ERR_INVALID, "the asynchronous entry points do not take the 16-bit forms");
+    DeviceGuard g(m->device);
+    unsigned long long seq = 0;
+    int nblk = 0;
+    return enqueue_eval(m, nullptr, grad, 0, (hipStream_t)stream, false, &seq, &nblk, v_dev,
+                        out_dev);
+}
+
 extern "C" {
 
 int pwa_build_table(const void* data, int64_t n_data, int32_t n_waves, const void* mc_amp,
@@ -988,6 +1008,17 @@ int pwa_nll_grad(const pwa_model* model, const double* v, double* nll, double* g
 {
     if (!grad) return fail(PWA_ERR_INVALID, "grad is NULL");
     return evaluate(model, v, nll, grad, hip_stream);
+}
+
+int pwa_nll_async(const pwa_model* model, const double* v_dev, double* out_dev, void* hip_stream)
+{
+    return evaluate_async(model, v_dev, out_dev, false, hip_stream);
+}
+
+int pwa_nll_grad_async(const pwa_model* model, const double* v_dev, double* out_dev,
+                       void* hip_stream)
+{
+    return evaluate_async(model, v_dev, out_dev, true, hip_stream);
 }
 
 int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k_per_model,

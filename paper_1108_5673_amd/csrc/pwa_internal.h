@@ -59,10 +59,16 @@ enum Form : uint32_t {
 };
 
 // Parameter vector passed by value in the kernel arguments: no host-to-device
-// copy is needed per evaluation.
+// copy is needed per evaluation.  The asynchronous entry points set `dev`
+// instead: V is then read from device memory when the kernel runs (so that a
+// captured graph picks up new values on every replay).
 struct VParams {
     double v[2 * PWA_MAX_WAVES_AMPLITUDE];
+    const double* dev = nullptr;
 };
+
+// Where a kernel reads V from.
+__device__ inline const double* vsrc(const VParams& vp) { return vp.dev ? vp.dev : vp.v; }
 
 // Optional timing of a launch: when non-null, the runtime stamps `start` and
 // `stop` with the begin and end times of the dispatch itself
