@@ -237,8 +237,9 @@ int pwa_copy_table(const pwa_model* model, void* out_host, void* hip_stream);
  * bit.  pwa_tune_amplitude_shape times `evals` gradient evaluations of the
  * streaming kernel in each candidate shape (per lane count, the fewest waves
  * per lane that hold W, when the row is at most 25 % longer than the
- * shortest), leaves the model in the fastest and returns it (either output
- * pointer may be NULL).  Both synchronise hip_stream and must not run
+ * shortest), twice over the candidates keeping each one's faster time, leaves
+ * the model in the fastest and returns it (either output pointer may be
+ * NULL).  Both synchronise hip_stream and must not run
  * concurrently with evaluations of the model; a cached multi-model plan that
  * uses the model is rebuilt at its next call.
  */

@@ -1261,26 +1261,31 @@ int pwa_tune_amplitude_shape(pwa_model* model, int32_t evals, void* hip_stream,
             (void)hipEventDestroy(b);
         }
     } ev_guard{e0, e1};
-    pwa::AmpShape best{m->amp_lq, m->amp_wl};
-    float best_ms = 0.f;
-    bool have = false;
-    for (const pwa::AmpShape& sh : cand) {
-        int rc = reshape_amp(m, sh, s);
-        if (rc != PWA_OK) return rc;
-        HIP_TRY(pwa::launch_amp_fused(*m, vp, true, s, pwa::LaunchEvents{}));   // warm-up
-        HIP_TRY(hipEventRecord(e0, s));
-        for (int k = 0; k < evals; ++k)
-            HIP_TRY(pwa::launch_amp_fused(*m, vp, true, s, pwa::LaunchEvents{}));
-        HIP_TRY(hipEventRecord(e1, s));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (!have || ms < best_ms) {
-            best = sh;
-            best_ms = ms;
-            have = true;
+    // two passes over the candidates, each keeping its faster time, so that a
+    // one-off slow measurement does not decide
+    std::vector<float> t_best(cand.size(), 0.f);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (size_t c = 0; c < cand.size(); ++c) {
+            int rc = reshape_amp(m, cand[c], s);
+            if (rc != PWA_OK) return rc;
+            HIP_TRY(pwa::launch_amp_fused(*m, vp, true, s, pwa::LaunchEvents{}));   // warm-up
+            HIP_TRY(hipEventRecord(e0, s));
+            for (int k = 0; k < evals; ++k)
+                HIP_TRY(pwa::launch_amp_fused(*m, vp, true, s, pwa::LaunchEvents{}));
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (pass == 0 || ms < t_best[c]) t_best[c] = ms;
         }
     }
+    pwa::AmpShape best = cand[0];
+    float best_ms = t_best[0];
+    for (size_t c = 1; c < cand.size(); ++c)
+        if (t_best[c] < best_ms) {
+            best = cand[c];
+            best_ms = t_best[c];
+        }
     const int rc = reshape_amp(m, best, s);
     if (rc != PWA_OK) return rc;
     if (lanes_per_event) *lanes_per_event = 1 << best.lq;
