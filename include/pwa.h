@@ -148,7 +148,9 @@ int pwa_nll_grad(const pwa_model* model, const double* v, double* nll, double* g
  * has n_bad > 0, nll = +INFINITY and a NaN gradient.  All forms but the
  * 16-bit matrix forms.  Evaluations of one model share its scratch buffers:
  * they must be ordered on one stream (or captured in one graph branch), also
- * with respect to its synchronous calls.
+ * with respect to its synchronous calls.  A captured graph holds the model's
+ * device buffers: while it may still be replayed, the model must not be freed
+ * or re-shaped (pwa_set_amplitude_shape, pwa_tune_amplitude_shape).
  */
 int pwa_nll_async(const pwa_model* model, const double* v_dev, double* out_dev,
                   void* hip_stream);
