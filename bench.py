@@ -348,6 +348,11 @@ def main():
     f = time_model(fused, pts, args.steps, args.warmup)
     log("fused: %.1f evals/s, kernel %.1f us, grid %d blocks on %d CUs"
         % (f["evals_per_s"], 1e3 * f["kernel_ms"], info["grid_blocks"], info["compute_units"]))
+    # the achievable read bandwidth on the same stored bytes: the fused
+    # kernel's loads with its arithmetic taken out
+    ceiling = fused.read_ceiling(reps=10)
+    log("the kernel's loads alone on the same %.2f GB: %.1f us, %.0f GB/s"
+        % (ceiling["bytes"] / 1e9, 1e3 * ceiling["ms"], ceiling["gbs"]))
 
     # a full fit on the same model from a random start (L-BFGS in the library,
     # one pwa_nll_grad per objective call)
@@ -415,7 +420,11 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                 "kernel": "k_table_fused (complex64 table)", "kernel_us": 1e3 * f["kernel_ms"],
-                "bytes_per_launch": info["stream_bytes"], "grid_blocks": info["grid_blocks"]}
+                "bytes_per_launch": info["stream_bytes"], "grid_blocks": info["grid_blocks"],
+                "read_ceiling_gbs": ceiling["gbs"], "frac_of_read_ceiling": achieved / ceiling["gbs"],
+                "read_ceiling": "fastest of 10 passes of the fused kernel's loads (same grid, "
+                                "shape and order) with its arithmetic taken out, on the same "
+                                "stored table (pwa_read_ceiling)"}
 
     cpu = None
     parity = None

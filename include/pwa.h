@@ -285,6 +285,22 @@ int pwa_get_timing(pwa_model* model, double* total_ms, int64_t* launches);
 int pwa_build_timing(const pwa_model* model, double* table_ms, double* mc_ms);
 
 /*
+ * Achievable read bandwidth on the model's stored data (the measurement
+ * reference for the streaming kernels' HBM roofline).  For the tiled tables
+ * (PWA_FORM_TABLE, PWA_PRECISION_FP64_FUSED) it runs the fused kernel's own
+ * loads (same grid, block shape, sub-tile order and register double
+ * buffering) with all arithmetic taken out; for the other forms a plain reader
+ * (one 1024-thread block per compute unit, 1 KB per wavefront load, two
+ * register buffers) that reads every stored byte once with the same
+ * non-temporal 16-byte loads.  One untimed pass, then reps timed ones (HIP
+ * events around the dispatch); *ms is the fastest, *bytes the bytes read per
+ * pass.  Synchronises hip_stream; allocates a small device buffer for the
+ * duration.
+ */
+int pwa_read_ceiling(const pwa_model* model, int32_t reps, void* hip_stream, double* ms,
+                     int64_t* bytes);
+
+/*
  * ---- Fit driver: limited-memory BFGS ---------------------------------------
  *
  * The fits of Sec. 2 minimise Eq. 3 with analytic derivatives, repeated from

@@ -255,6 +255,15 @@ class Model:
                                                    ctypes.byref(n)))
         return ms.value, n.value
 
+    def read_ceiling(self, reps: int = 5) -> dict:
+        """Fastest of `reps` passes of a plain non-temporal read of the stored
+        data: the achievable read bandwidth on the same bytes."""
+        ms = ctypes.c_double(0.0)
+        nb = ctypes.c_int64(0)
+        _native.check(_native.lib().pwa_read_ceiling(self._handle(), int(reps), self._stream,
+                                                     ctypes.byref(ms), ctypes.byref(nb)))
+        return {"ms": ms.value, "bytes": nb.value, "gbs": nb.value / (ms.value * 1e-3) / 1e9}
+
     def build_timing(self) -> dict:
         """Device milliseconds of the table preparation and of the MC integral."""
         t = ctypes.c_double(0.0)

@@ -160,6 +160,74 @@ hipError_t launch_pack_tiled(const void* src, bool src_is_table, bool src_c128, 
     return hipGetLastError();
 }
 
+// Reference reader: streams n_vec 16-byte vectors once with the same
+// non-temporal loads and the same shape as the fused kernel (one 1024-thread
+// block per compute unit, a contiguous range per block, 1 KB per wavefront
+// load), with up to twelve loads per lane in flight and no arithmetic on the data
+// beyond an xor that keeps the loads alive.  It measures the read bandwidth
+// the streaming kernels can reach on the same bytes.  Each block stores one
+// word, and only if its xor is the (practically impossible) value `magic`.
+constexpr int kReadUnroll = 6;
+typedef float rd4 __attribute__((ext_vector_type(4)));
+
+__device__ __attribute__((always_inline)) inline void read_round(rd4 (&r)[kReadUnroll],
+                                                                  const float4* p, int64_t v0,
+                                                                  int64_t v1, int64_t c, int nw,
+                                                                  int lane)
+{
+#pragma unroll
+    for (int u = 0; u < kReadUnroll; ++u) {
+        const int64_t idx = v0 + 64 * (c + (int64_t)u * nw) + lane;
+        r[u] = idx < v1 ? __builtin_nontemporal_load(reinterpret_cast<const rd4*>(p + idx))
+                        : rd4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
+__device__ __attribute__((always_inline)) inline uint32_t fold_round(const rd4 (&r)[kReadUnroll])
+{
+    uint32_t a = 0;
+#pragma unroll
+    for (int u = 0; u < kReadUnroll; ++u)
+        a ^= __float_as_uint(r[u].x) ^ __float_as_uint(r[u].y) ^ __float_as_uint(r[u].z) ^
+             __float_as_uint(r[u].w);
+    return a;
+}
+
+__global__ __launch_bounds__(1024) void k_stream_read(const float4* __restrict__ p, int64_t n_vec,
+                                                      uint32_t magic, uint32_t* __restrict__ sink)
+{
+    const int64_t v0 = (int64_t)blockIdx.x * n_vec / gridDim.x;
+    const int64_t v1 = (int64_t)(blockIdx.x + 1) * n_vec / gridDim.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t acc = 0;
+    // 64-vector chunks of the range: wavefront w takes chunks w, w + nw, ...,
+    // kReadUnroll of them per round; the next round's loads are issued before
+    // this round's values are used (two register buffers)
+    const int64_t step = (int64_t)nw * kReadUnroll;
+    rd4 x[kReadUnroll], y[kReadUnroll];
+    int64_t c = wave;
+    if (v0 + 64 * c < v1) read_round(x, p, v0, v1, c, nw, lane);
+    for (; v0 + 64 * c < v1; c += 2 * step) {
+        const bool more = v0 + 64 * (c + step) < v1;
+        if (more) read_round(y, p, v0, v1, c + step, nw, lane);
+        acc ^= fold_round(x);
+        if (!more) break;
+        if (v0 + 64 * (c + 2 * step) < v1) read_round(x, p, v0, v1, c + 2 * step, nw, lane);
+        acc ^= fold_round(y);
+    }
+    if (acc == magic) sink[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
+hipError_t launch_stream_read(const void* p, int64_t bytes, uint32_t* sink, int sink_len,
+                              hipStream_t s, const LaunchEvents& ev)
+{
+    const int64_t n_vec = bytes / 16;
+    hipExtLaunchKernelGGL(k_stream_read, dim3(sink_len / 1024), dim3(1024), 0, s, ev.start,
+                          ev.stop, 0, (const float4*)p, n_vec, 0x9e3779b9u, sink);
+    return hipGetLastError();
+}
+
 hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, void* dst,
                                hipStream_t s)
 {
@@ -494,6 +562,73 @@ static hipError_t run_fused(const Model& m, const VParams& vp, bool grad, hipStr
     return hipGetLastError();
 }
 
+// Reference reader of the tiled table: the fused kernel's loads (the same
+// grid, block shape, sub-tile order and two register buffers) with all of its
+// arithmetic taken out; an xor of the loaded bits keeps the loads alive, and
+// a thread stores only if its xor is the (practically impossible) `magic`.
+__device__ inline uint32_t bits_of(const float4& x)
+{
+    return __float_as_uint(x.x) ^ __float_as_uint(x.y) ^ __float_as_uint(x.z) ^
+           __float_as_uint(x.w);
+}
+__device__ inline uint32_t bits_of(const double2& x)
+{
+    return (uint32_t)(__double2loint(x.x) ^ __double2hiint(x.x) ^ __double2loint(x.y) ^
+                      __double2hiint(x.y));
+}
+
+template <typename S, int K, int E>
+__device__ inline uint32_t fold_subtile(const SubTile<S, K, E>& st)
+{
+    uint32_t a = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int v = 0; v < SubTile<S, K, E>::VS; ++v) a ^= bits_of(st.x[k][v]);
+    return a;
+}
+
+template <typename S, int K, int E>
+__global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_read(
+    const char* __restrict__ table, int64_t n_tiles, int P, uint32_t magic,
+    uint32_t* __restrict__ sink)
+{
+    constexpr int esz = 2 * sizeof(S);
+    constexpr int NSUB = kTileEvents / E;
+    const int lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwaves = blockDim.x >> 6;
+    const int64_t n_sub = n_tiles * NSUB;
+    const int64_t s0 = (int64_t)blockIdx.x * n_sub / gridDim.x;
+    const int64_t s1 = (int64_t)(blockIdx.x + 1) * n_sub / gridDim.x;
+    const int64_t tile_bytes = (int64_t)P * kTileEvents * esz;
+    const int64_t U = (s1 - s0 > wave) ? (s1 - s0 - wave + nwaves - 1) / nwaves : 0;
+    auto sub_of = [&](int64_t u) { return s0 + wave + nwaves * u; };
+    auto base_of = [&](int64_t u) { return table + (sub_of(u) / NSUB) * tile_bytes; };
+    auto part_of = [&](int64_t u) { return (int)(sub_of(u) % NSUB); };
+    SubTile<S, K, E> a, b;
+    uint32_t acc = 0;
+    if (U > 0) a.load(base_of(0), part_of(0), P, lane);
+    for (int64_t u = 0; u < U; u += 2) {
+        if (u + 1 < U) b.load(base_of(u + 1), part_of(u + 1), P, lane);
+        acc ^= fold_subtile(a);
+        if (u + 1 < U) {
+            if (u + 2 < U) a.load(base_of(u + 2), part_of(u + 2), P, lane);
+            acc ^= fold_subtile(b);
+        }
+    }
+    if (acc == magic) sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
+template <typename S, int K, int E>
+static hipError_t run_read(const Model& m, uint32_t* sink, hipStream_t s, const LaunchEvents& ev)
+{
+    constexpr int NT = fused_threads<S, K, E>();
+    hipExtLaunchKernelGGL((k_table_read<S, K, E>), dim3(m.grid), dim3(NT), 0, s, ev.start,
+                          ev.stop, 0, (const char*)m.d_data, m.n_tiles, m.P, 0x9e3779b9u, sink);
+    return hipGetLastError();
+}
+
 template <typename S, int K, int E>
 static const void* fused_fn()
 {
@@ -560,6 +695,33 @@ bool fused_shape_ok(const Model& m)
     if (m.form == kTable32) with_shape<float>(m.kslots, m.subtile, probe);
     else with_shape<double>(m.kslots, m.subtile, probe);
     return ok;
+}
+
+hipError_t launch_table_read(const Model& m, uint32_t* sink, hipStream_t s,
+                             const LaunchEvents& ev)
+{
+    hipError_t err = hipErrorInvalidValue;
+    if (m.form == kTable32) {
+        auto go = [&]<int K, int E>() { err = run_read<float, K, E>(m, sink, s, ev); };
+        with_shape<float>(m.kslots, m.subtile, go);
+    } else {
+        auto go = [&]<int K, int E>() { err = run_read<double, K, E>(m, sink, s, ev); };
+        with_shape<double>(m.kslots, m.subtile, go);
+    }
+    return err;
+}
+
+int table_read_threads(const Model& m)
+{
+    int nt = 0;
+    if (m.form == kTable32) {
+        auto go = [&]<int K, int E>() { nt = fused_threads<float, K, E>(); };
+        with_shape<float>(m.kslots, m.subtile, go);
+    } else {
+        auto go = [&]<int K, int E>() { nt = fused_threads<double, K, E>(); };
+        with_shape<double>(m.kslots, m.subtile, go);
+    }
+    return nt;
 }
 
 hipError_t launch_table_fused(const Model& m, const VParams& vp, bool grad, hipStream_t s,

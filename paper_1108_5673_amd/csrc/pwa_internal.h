@@ -203,6 +203,11 @@ hipError_t launch_pack_soa(const void* src, bool src_is_table, bool src_c128, in
                            int P, const uint32_t* pairs, double* dst, hipStream_t s);
 hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, AmpShape sh,
                            int64_t n_pad, float* dst, hipStream_t s);
+hipError_t launch_stream_read(const void* p, int64_t bytes, uint32_t* sink, int sink_len,
+                              hipStream_t s, const LaunchEvents& ev);
+hipError_t launch_table_read(const Model& m, uint32_t* sink, hipStream_t s,
+                             const LaunchEvents& ev);
+int table_read_threads(const Model& m);
 hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, void* dst,
                                hipStream_t s);
 hipError_t launch_unpack_soa(const double* src, int64_t n, int P, double* dst, hipStream_t s);

@@ -281,3 +281,14 @@ def test_build_timing():
     t = m.build_timing()
     assert t["table_ms"] > 0.0 and t["mc_ms"] == 0.0
     m.close()
+
+
+def test_read_ceiling():
+    """The reference read of the stored data reports the stored bytes and a
+    positive, physically possible bandwidth (below 8 TB/s of HBM3E plus the
+    caches' help on a small table)."""
+    s = synth.small_sample(20, 200_000, 100, seed=19)
+    model = pwa.Model(s.data.astype(np.complex64), s.mc.astype(np.complex64), 200)
+    r = model.read_ceiling(reps=3)
+    assert r["bytes"] == 200_000 * 210 * 8 and r["ms"] > 0 and 0 < r["gbs"] < 50_000
+    model.close()
