@@ -14,6 +14,17 @@ copies a buffer of known size (1 GiB) device to device.  `summarize` scales
 each counter of the streaming kernel by the ratio of the copy's known bytes
 to what the same counter read for the copy, and writes the per-launch HBM
 bytes with the hash of the kernel sources they were measured on.
+
+Matrix-core use of the batched kernel (k_amp_mfma, 256 vectors over the
+1M-event, 20-wave sample, bf16 then fp16 amplitudes), one rocprofv3 run per
+counter set:
+
+    rocprofv3 --pmc MfmaUtil VALUBusy -d <dir> -o derived --output-format csv -- \\
+        python3 -m paper_1108_5673_amd.profiling run-batched
+    rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_INSTS_MFMA \\
+        SQ_INSTS_VALU SQ_BUSY_CU_CYCLES GRBM_GUI_ACTIVE -d <dir> -o raw \\
+        --output-format csv -- python3 -m paper_1108_5673_amd.profiling run-batched
+    python3 -m paper_1108_5673_amd.profiling busy <derived csv> <raw csv> <out.json>
 """
 from __future__ import annotations
 
@@ -62,6 +73,26 @@ def run(evals: int = 5) -> None:
     m.close()
     print("profiling run done: %d evaluations, 3 copies of %d bytes" % (evals, COPY_BYTES),
           flush=True)
+
+
+def run_batched(reps: int = 4) -> None:
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    import paper_1108_5673_amd as pwa
+    from paper_1108_5673_amd import synth
+
+    torch.cuda.init()
+    s = synth.make_sample("w20_n1m_k256")
+    d32, mc32 = s.data.astype(np.complex64), s.mc.astype(np.complex64)
+    for form in ("amplitude_bf16", "amplitude_fp16"):
+        m = pwa.Model(d32, mc32, s.n_gen, form=form)
+        for _ in range(reps):
+            pwa.nll_batched([m], [s.points])
+        torch.cuda.synchronize()
+        m.close()
+    print("profiling run done: %d batched passes of 256 vectors per form" % reps, flush=True)
 
 
 def _rows(path: str):
@@ -124,9 +155,44 @@ def summarize(fetch_csv: str, write_csv: str, out_json: str) -> dict:
     return res
 
 
+def _is_bf16(name: str) -> bool:
+    """bf16 instance of a kernel template, by its demangled or mangled name
+    (the Itanium mangling of __bf16 is DF16b, of _Float16 DF16_)."""
+    return "bf16" in name or "DF16b" in name
+
+
+def busy(derived_csv: str, raw_csv: str, out_json: str) -> dict:
+    """Per-form medians over the dispatches of k_amp_mfma: the derived
+    percentages as rocprofv3 computes them and the raw counters."""
+    der, raw = _rows(derived_csv), _rows(raw_csv)
+    res = {"kernel": "k_amp_mfma",
+           "workload": "w20_n1m_k256: 1M events x 20 waves, 256 vectors per pass", "forms": {}}
+    for tag, want_bf16 in (("bf16", True), ("fp16", False)):
+        form = {}
+        for rows in (der, raw):
+            names = sorted({r["Kernel_Name"] for r in rows if "k_amp_mfma" in r["Kernel_Name"]
+                            and _is_bf16(r["Kernel_Name"]) == want_bf16})
+            for r in rows:
+                if r["Kernel_Name"] in names:
+                    form.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            if names:
+                form.setdefault("_names", names)
+        res["forms"][tag] = {k: (statistics.median(v) if k != "_names" else v)
+                             for k, v in form.items()}
+        res["forms"][tag]["dispatches"] = {k: len(v) for k, v in form.items() if k != "_names"}
+    with open(out_json, "w") as fo:
+        json.dump(res, fo, indent=1)
+        fo.write("\n")
+    return res
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "run":
         run(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
+    elif len(sys.argv) >= 2 and sys.argv[1] == "run-batched":
+        run_batched(int(sys.argv[2]) if len(sys.argv) > 2 else 4)
+    elif len(sys.argv) == 5 and sys.argv[1] == "busy":
+        print(json.dumps(busy(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
     elif len(sys.argv) == 5 and sys.argv[1] == "summarize":
         print(json.dumps(summarize(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
     else:
