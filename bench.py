@@ -91,13 +91,13 @@ def time_model(model, points, steps, warmup):
 
 def mfma_flops(n_events, n_waves, k, v_parts):
     """Matrix-core FLOPs of one batched pass as the kernel issues them: per
-    32-event tile and 16 vectors, the forward product (16-wide KD steps x V
-    parts) and the adjoint (32-row blocks x 2 event steps x 2 weight parts),
-    each a 32x32x16 MFMA of 32768 FLOP."""
+    16-event tile (32 rows) and 32 vectors, the forward product (16-wide KD
+    steps x V parts) and the adjoint (32-row blocks x 2 slot steps x 2 weight
+    parts), each a 32x32x16 MFMA of 32768 FLOP."""
     kd = (2 * n_waves + 15) // 16 * 16
     rb = (kd + 31) // 32
-    tiles = (n_events + 31) // 32
-    col_blocks = (2 * k + 31) // 32
+    tiles = (n_events + 15) // 16
+    col_blocks = (k + 31) // 32
     per = (kd // 16) * v_parts + rb * 2 * 2
     return tiles * col_blocks * per * 32768
 

@@ -3,27 +3,32 @@
 //
 // The fits of Sec. 2 are repeated from many starting points; evaluating K of
 // them together turns S_ik = sum_a A_ia V_ak into a matrix product.  In real
-// arithmetic, with event row x_i = [Re A_i0 .. Re A_i,W-1, Im A_i0 .. Im A_i,W-1]
-// (padded to KD = 16 * NS) and two columns per vector,
-//     Re S_ik = x_i . [Re V_k ; -Im V_k],   Im S_ik = x_i . [Im V_k ; Re V_k],
-// S = X B is an (events x KD) by (KD x 2K) product.  The adjoint needs
-// g_bk = sum_i c_ik conj(A_ib) with c_ik = S_ik / I_ik, another product
-// G = X^T C (KD x 2K) over events, whose four real blocks give
-//     Re g_bk = G[Re b][Re k] + G[Im b][Im k],  Im g_bk = G[Re b][Im k] - G[Im b][Re k].
+// arithmetic each event gives two rows over KD = 2W (padded to 16 NS) columns,
+//     x_i  = [Re A_i0, Im A_i0, Re A_i1, Im A_i1, ...],
+//     x'_i = [Im A_i0, -Re A_i0, Im A_i1, -Re A_i1, ...],
+// and each vector one column b_k = [Re V_0k, -Im V_0k, Re V_1k, -Im V_1k, ...]:
+//     Re S_ik = x_i . b_k,   Im S_ik = x'_i . b_k,
+// so S is a (2 events x KD) by (KD x K) product whose output holds Re S and
+// Im S of one (event, vector) pair in neighbouring rows.  The adjoint needs
+// g_bk = sum_i c_ik conj(A_ib) with c_ik = S_ik / I_ik, the product
+// G = Y C over the (event, Re/Im) rows with
+//     Re g_bk = sum_i Re c_ik Re A_ib + Im c_ik Im A_ib   (row 2b of Y: [Re A_ib | Im A_ib]),
+//     Im g_bk = sum_i Im c_ik Re A_ib - Re c_ik Im A_ib   (row 2b + 1: [-Im A_ib | Re A_ib]),
+// whose rows are the 2W real gradient components directly.
 //
-// Both products run on the 32x32x16 16-bit MFMA with FP32 accumulation:
-//   * forward: A operand = 32 events x 16 of KD (lane l: event l % 32, KD
-//     8 (l / 32) .. + 7), B operand = the vector matrix (lane l: column l % 32);
-//     the accumulator gives lane l column l % 32 and events 8 j + 4 (l / 32) + i
-//     in register 4 j + i;
-//   * epilogue in registers: the Re and Im columns of a vector sit in
-//     neighbouring lanes, exchanged with one DPP move; I = Re^2 + Im^2, ln I
-//     (each (event, vector) pair's logarithm taken by one of its two lanes),
-//     w = 1 / I and this lane's part of c = S w;
+// Both products run on the 32x32x16 16-bit MFMA with FP32 accumulation, over
+// tiles of 16 events (32 rows):
+//   * forward: A operand = the 32 rows of the tile x 16 of KD (lane l: row
+//     l % 32, KD 8 (l / 32) .. + 7), B operand = the vector matrix (lane l:
+//     vector l % 32); the accumulator gives lane l vector l % 32 and rows
+//     8 j + 4 (l / 32) + i in register 4 j + i, so registers 2 r and 2 r + 1
+//     are Re S and Im S of one event (event 4 j + 2 (l / 32) + i / 2);
+//   * epilogue in registers, one lane per (event, vector) pair: I = Re^2 + Im^2,
+//     ln I, w = 1 / I and c = S w;
 //   * adjoint: registers 8 s .. 8 s + 7 of the accumulator are exactly the B
-//     operand of an MFMA whose 16 k-slots are events {8 j + 4 h + i} with j in
-//     {2 s, 2 s + 1}; the A operand (lane l: KD row l % 32, the same 8 event
-//     slots) comes from a second copy of the tile stored in that event order.
+//     operand of an MFMA whose 16 k-slots are the rows 16 s .. 16 s + 15 of the
+//     tile; the A operand (lane l: output row l % 32, the same 8 slots) comes
+//     from a second copy of the tile stored in that slot order.
 //     So S never leaves the registers.
 // Scale: each vector enters as V_k / s_k with s_k the power of two nearest
 // ||V_k||_2, so S, I and c = S / I stay near unit magnitude whatever the size of
@@ -73,6 +78,7 @@ constexpr float kHalfNormalMin = 6.103515625e-05f;   // 2^-14
 template <typename T> struct H16;
 template <> struct H16<__bf16> {
     typedef __bf16 V8 __attribute__((ext_vector_type(8)));
+    typedef __bf16 V2 __attribute__((ext_vector_type(2)));
     __device__ static f32x16 mfma(V8 a, V8 b, f32x16 c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -80,6 +86,7 @@ template <> struct H16<__bf16> {
 };
 template <> struct H16<_Float16> {
     typedef _Float16 V8 __attribute__((ext_vector_type(8)));
+    typedef _Float16 V2 __attribute__((ext_vector_type(2)));
     __device__ static f32x16 mfma(V8 a, V8 b, f32x16 c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -99,54 +106,99 @@ template <typename T> __device__ inline T split_hi(float x)
         if (fabsf(x) < kHalfNormalMin) return round16<T>(0.f);
     return round16<T>(x);
 }
-// low part: the remainder, times 2^11 for fp16
-template <typename T> __device__ inline T split_lo(float x, T hi)
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two-part split of a pair of values, each part rounded to nearest even by one
+// paired conversion.  The high part is the rounded value (zero where fp16 would
+// be subnormal); the low part is the remainder, times 2^11 for fp16.
+template <typename T>
+__device__ inline void split_pair(float x0, float x1, typename H16<T>::V2& hi,
+                                  typename H16<T>::V2& lo)
 {
-    const float r = x - (float)hi;
-    return round16<T>(Split<T>::kScaledLow ? r * kLowScale : r);
+    using V2 = typename H16<T>::V2;
+    const f32x2 x = {x0, x1};
+    if constexpr (Split<T>::kScaledLow) {
+        const f32x2 xh = {fabsf(x0) < kHalfNormalMin ? 0.f : x0,
+                          fabsf(x1) < kHalfNormalMin ? 0.f : x1};
+        hi = __builtin_convertvector(xh, V2);
+    } else {
+        hi = __builtin_convertvector(x, V2);
+    }
+    const f32x2 back = __builtin_convertvector(hi, f32x2);
+    f32x2 r = {x[0] - back[0], x[1] - back[1]};
+    if constexpr (Split<T>::kScaledLow) r = f32x2{r[0] * kLowScale, r[1] * kLowScale};
+    lo = __builtin_convertvector(r, V2);
+}
+
+// a stored amplitude component: rounded to nearest even; fp16 storage holds
+// no subnormals, they are stored as zero (the value the matrix product is
+// certain to use)
+template <typename T> __device__ inline T store16(float x)
+{
+    T y = round16<T>(x);
+    if constexpr (Split<T>::kScaledLow)
+        if (fabsf((float)y) < kHalfNormalMin) y = round16<T>(0.f);
+    return y;
+}
+
+// Slot of (event e of a tile, part p: 0 Re, 1 Im) in the adjoint operand rows:
+// the forward accumulator holds it in register 8 s + u of the lanes with
+// l / 32 = h, which the adjoint MFMA of step s reads as k-slot 8 h + u.
+__device__ inline int mfma_slot(int e, int p)
+{
+    const int s = e >> 3, e7 = e & 7;
+    const int h = (e7 >> 1) & 1;
+    const int u = 4 * (e7 >> 2) + 2 * (e7 & 1) + p;
+    return 16 * s + 8 * h + u;
 }
 
 // ---- build: the two copies of the event tiles -------------------------------
-// af: [tile][32 events][KD]            (forward A operand)
-// at: [tile][RB * 32 rows][32 slots]   (adjoint A operand; slot 16 s + 8 h + t
-//                                       holds event 8 (2 s + t / 4) + 4 h + t % 4)
+// Tiles of 16 events; the buffers are zeroed before packing (padding events,
+// KD columns beyond 2W and adjoint rows beyond 2W stay zero).
+// af: [tile][32 rows][KD]            (forward A operand: rows 2e = x_e, 2e + 1 = x'_e)
+// at: [tile][RB * 32 rows][32 slots] (adjoint A operand: row 2b = [Re A_eb | Im A_eb],
+//                                     row 2b + 1 = [-Im A_eb | Re A_eb] at slots
+//                                     mfma_slot(e, 0 | 1))
 template <typename T>
 __global__ void k_pack_mfma(const void* __restrict__ src, bool c128, int64_t n, int W, int KD,
-                            int RB, int64_t n_tiles, T* __restrict__ af, T* __restrict__ at)
+                            int RB, T* __restrict__ af, T* __restrict__ at)
 {
-    const int64_t total = n_tiles * 32 * (int64_t)KD;
+    const int64_t total = n * (int64_t)W;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
          g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t ev = g / KD;       // global event (padded)
-        const int kd = (int)(g % KD);
-        float x = 0.f;
-        if (ev < n && kd < 2 * W) {
-            const int a = kd < W ? kd : kd - W;
-            if (c128) {
-                const double2 v = reinterpret_cast<const double2*>(src)[ev * W + a];
-                x = (float)(kd < W ? v.x : v.y);
-            } else {
-                const float2 v = reinterpret_cast<const float2*>(src)[ev * W + a];
-                x = kd < W ? v.x : v.y;
-            }
+        const int64_t ev = g / W;
+        const int a = (int)(g % W);
+        float re, im;
+        if (c128) {
+            const double2 v = reinterpret_cast<const double2*>(src)[g];
+            re = (float)v.x;
+            im = (float)v.y;
+        } else {
+            const float2 v = reinterpret_cast<const float2*>(src)[g];
+            re = v.x;
+            im = v.y;
         }
-        T y = round16<T>(x);
-        // fp16 storage holds no subnormals: they are stored as zero, the value
-        // the matrix product is certain to use
-        if constexpr (Split<T>::kScaledLow)
-            if (fabsf((float)y) < kHalfNormalMin) y = round16<T>(0.f);
-        af[g] = y;
-        const int64_t tile = ev / 32;
-        const int e = (int)(ev % 32);
-        const int j = e / 8, h = (e / 4) % 2, i = e % 4;
-        const int slot = 16 * (j / 2) + 8 * h + 4 * (j % 2) + i;
-        at[(tile * RB * 32 + kd) * 32 + slot] = y;
+        const T yr = store16<T>(re), yi = store16<T>(im);
+        const T nr = round16<T>(-(float)yr), ni = round16<T>(-(float)yi);   // exact
+        const int64_t tile = ev / kMfmaTile;
+        const int e = (int)(ev % kMfmaTile);
+        T* x = af + (tile * 32 + 2 * e) * KD + 2 * a;
+        x[0] = yr;
+        x[1] = yi;
+        x[KD] = yi;
+        x[KD + 1] = nr;
+        T* y = at + (tile * RB * 32 + 2 * a) * 32 + mfma_slot(e, 0);
+        y[0] = yr;
+        y[1] = yi;
+        y[32] = ni;
+        y[33] = yr;
     }
 }
 
 // ---- per call: the vector matrix, split into NP 16-bit parts --------------
 // part p at vm + p * part_elems, element [((cb * NS + s) * 2 + h) * 32 + c][8]:
-// column 32 cb + c, KD rows 16 s + 8 h .. + 7
+// vector 32 cb + c, KD rows 16 s + 8 h .. + 7
 // power of two nearest ||V_k||_2 (1 for V_k = 0)
 __device__ inline double vector_scale(const double* vk, int W)
 {
@@ -168,18 +220,15 @@ __global__ void k_prep_vmat16(const double* __restrict__ v, int K, int W, int NS
         const int h = (g / 256) % 2;
         const int s = (g / 512) % NS;
         const int cb = g / (512 * NS);
-        const int col = 32 * cb + c;
-        const int k = col / 2, part = col % 2;
+        const int k = 32 * cb + c;
         const int kd = 16 * s + 8 * h + t;
         double x = 0.0;
         if (k < K && kd < 2 * W) {
             const double sk = vector_scale(v + (size_t)k * 2 * W, W);
-            if (part == 0 && kd == 0) vscale[k] = sk;
-            const int a = kd < W ? kd : kd - W;
-            const double vr = v[(size_t)k * 2 * W + 2 * a] / sk;
-            const double vi = v[(size_t)k * 2 * W + 2 * a + 1] / sk;
-            if (kd < W) x = part == 0 ? vr : vi;     // multiplies Re A_a
-            else x = part == 0 ? -vi : vr;           // multiplies Im A_a
+            if (kd == 0) vscale[k] = sk;
+            const int a = kd / 2;
+            x = kd % 2 == 0 ? v[(size_t)k * 2 * W + 2 * a] / sk        // multiplies Re A_a
+                            : -v[(size_t)k * 2 * W + 2 * a + 1] / sk;  // multiplies Im A_a
         }
         if constexpr (Split<T>::kScaledLow) {
             const T hi = split_hi<T>((float)x);
@@ -196,21 +245,15 @@ __global__ void k_prep_vmat16(const double* __restrict__ v, int K, int W, int NS
     }
 }
 
-// exchange with the neighbouring lane (l ^ 1)
-__device__ inline float swap_pair(float x)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
-}
-
 // ---- the fused forward + epilogue + adjoint kernel -------------------------
 // grid (chunks, ceil(n_cb / B)), blocks of B = min(n_cb, mfma_waves) wavefronts:
-// wavefront w of a block takes column block cb = B blockIdx.y + w (16 vectors)
-// over every event tile of
-// the block's chunk, so the wavefronts of a block read the same tiles at about
-// the same time and all but the first find them in cache.  Records per
-// (chunk, cb, column): rec_d = [sum ln I, n_bad] (FP64; n_bad counts the
-// column's lane sums that met a degenerate event, so it is non-zero exactly when
-// one did) and rec_g = G[0 .. KD) of the column (the wavefront's FP32 sums).
+// wavefront w of a block takes column block cb = B blockIdx.y + w (32 vectors)
+// over every event tile of the block's chunk, so the wavefronts of a block
+// read the same tiles at about the same time and all but the first find them
+// in cache.  Records per (chunk, cb, vector): rec_d = [sum ln I, n_bad] (FP64;
+// n_bad counts the vector's lane sums that met a degenerate event, so it is
+// non-zero exactly when one did) and rec_g = G[0 .. KD) of the vector (the
+// wavefront's FP32 sums; rows 2b, 2b + 1 are Re g_b and Im g_b).
 // Up to 8 wavefronts per block (two per SIMD, 256 registers each); the wider
 // row lengths (NS > 4) need more registers and run 4 (one per SIMD).
 template <int NS> constexpr int mfma_waves() { return NS <= 4 ? 8 : 4; }
@@ -224,15 +267,14 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
     constexpr int KD = 16 * NS;
     constexpr int RB = (NS + 1) / 2;
     using V8 = typename H16<T>::V8;
+    using V2 = typename H16<T>::V2;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int h = lane >> 5, c = lane & 31;
     const int cb = (int)(blockDim.x >> 6) * blockIdx.y + wave;
     if (cb >= n_cb) return;   // no barrier follows
-    const int col = 32 * cb + c;
-    const bool col_active = col < n_cols;
-    const bool odd = (c & 1) != 0;
+    const bool col_active = 32 * cb + c < n_cols;
 
     const size_t part_elems = (size_t)n_cb * NS * 2 * 32 * 8;
     V8 vp[NP][NS];
@@ -252,25 +294,29 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
 
     const int64_t t0 = (int64_t)blockIdx.x * n_tiles / chunks;
     const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / chunks;
-    // operands of one tile: forward rows (event x KD) and adjoint rows (KD x
-    // event slots); the next tile's are loaded while this one is processed
-    struct Ops {
+    // operands of one tile: forward rows (32 rows x KD) and adjoint rows (RB x
+    // 32 rows x 32 slots)
+    struct OpsA {
         V8 a[NS];
+    };
+    struct OpsB {
         V8 b[RB][2];
     };
-    auto load = [&](Ops& o, int64_t t) {
+    auto load_a = [&](OpsA& o, int64_t t) {
         const T* ta = af + t * 32 * KD;
-        const T* tt = at + t * RB * 32 * 32;
 #pragma unroll
         for (int s = 0; s < NS; ++s) o.a[s] = *reinterpret_cast<const V8*>(ta + c * KD + 16 * s + 8 * h);
+    };
+    auto load_b = [&](OpsB& o, int64_t t) {
+        const T* tt = at + t * RB * 32 * 32;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int s2 = 0; s2 < 2; ++s2)
                 o.b[rb][s2] = *reinterpret_cast<const V8*>(tt + (rb * 32 + c) * 32 + 16 * s2 + 8 * h);
     };
-    auto process = [&](const Ops& o, int64_t t, auto fast_tag) {
-        constexpr bool fast = decltype(fast_tag)::value;
+    // S of the tile's 16 events x 32 vectors
+    auto forward = [&](const OpsA& o) {
         f32x16 acc = f32x16{};
         if constexpr (SL) {
             f32x16 acc_lo = f32x16{};
@@ -287,61 +333,51 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
 #pragma unroll
                 for (int s = 0; s < NS; ++s) acc = H16<T>::mfma(o.a[s], vp[p][s], acc);
         }
-
+        return acc;
+    };
+    auto finish = [&](const f32x16& acc, const OpsB& o, int64_t t, auto fast_tag) {
+        constexpr bool fast = decltype(fast_tag)::value;
         // Epilogue and adjoint, in two halves of 8 registers (the adjoint MFMA
-        // of half s2 takes registers 8 s2 .. 8 s2 + 7).  The two lanes of a
-        // vector (columns 2k, 2k + 1) hold the same I: of each register pair
-        // (q, q + 1) the even lane takes the logarithm of q, the odd lane that
-        // of q + 1.  A full tile whose columns all carry vectors needs no
+        // of half s2 takes registers 8 s2 .. 8 s2 + 7).  Registers (q, q + 1),
+        // q even, are Re S and Im S of event 4 (q / 4) + 2 h + (q / 2) % 2 of
+        // the tile.  A full tile whose columns all carry vectors needs no
         // validity test: a degenerate event (I not positive and finite) only
         // has to be counted (its NLL is +inf whatever the sum, and its weight
         // 0 * inf or x * NaN is NaN); the last tile and the padding columns
         // take the general path.
-        const int nvalid = (int)min<int64_t>(32, n_events - t * 32);
+        const int nvalid = (int)min<int64_t>(kMfmaTile, n_events - t * kMfmaTile);
         float lsum = 0.f;
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
-            float cp[8];
+            V8 chi, clo;
 #pragma unroll
-            for (int u = 0; u < 8; u += 2) {
-                float Ipair[2];
-                bool vp2[2];
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const int q = 8 * s2 + u + e;
-                    const float x = acc[q];
-                    const float y = swap_pair(x);
-                    const float I = x * x + y * y;
-                    const float w = __builtin_amdgcn_rcpf(I);
-                    if constexpr (fast) {
-                        cp[u + e] = x * w;
-                        vp2[e] = true;
-                    } else {
-                        const int ev = 8 * (q >> 2) + 4 * h + (q & 3);
-                        const bool valid = col_active && ev < nvalid;
-                        // positive normal or subnormal: not 0, negative, inf or NaN
-                        const bool ok = __builtin_amdgcn_classf(I, 0x180);
-                        cp[u + e] = valid ? (ok ? x * w : NAN) : 0.f;
-                        vp2[e] = valid;
-                    }
-                    Ipair[e] = I;
-                }
-                const float Iq = odd ? Ipair[1] : Ipair[0];
+            for (int r = 0; r < 4; ++r) {
+                const int q = 8 * s2 + 2 * r;
+                const float x = acc[q], y = acc[q + 1];
+                const float I = fmaf(y, y, x * x);
+                const float w = __builtin_amdgcn_rcpf(I);
+                float cr, ci;
                 // a degenerate I (0, negative, inf or NaN) makes log2 I and so
                 // this lane's sum non-finite: that is how it is detected
                 if constexpr (fast) {
-                    lsum += __builtin_amdgcn_logf(Iq);
+                    cr = x * w;
+                    ci = y * w;
+                    lsum += __builtin_amdgcn_logf(I);
                 } else {
-                    const bool vq = odd ? vp2[1] : vp2[0];
-                    lsum += vq ? __builtin_amdgcn_logf(Iq) : 0.f;
+                    const int e = 4 * (q >> 2) + 2 * h + ((q >> 1) & 1);
+                    const bool valid = col_active && e < nvalid;
+                    // positive normal or subnormal: not 0, negative, inf or NaN
+                    const bool ok = __builtin_amdgcn_classf(I, 0x180);
+                    cr = valid ? (ok ? x * w : NAN) : 0.f;
+                    ci = valid ? (ok ? y * w : NAN) : 0.f;
+                    lsum += valid ? __builtin_amdgcn_logf(I) : 0.f;
                 }
-            }
-            V8 chi, clo;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const T hi = split_hi<T>(cp[u]);
-                chi[u] = hi;
-                clo[u] = split_lo<T>(cp[u], hi);
+                V2 hi, lo;
+                split_pair<T>(cr, ci, hi, lo);
+                chi[2 * r] = hi[0];
+                chi[2 * r + 1] = hi[1];
+                clo[2 * r] = lo[0];
+                clo[2 * r + 1] = lo[1];
             }
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
@@ -353,21 +389,34 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
         dsum += (double)lsum * 0.69314718055994530942;   // log2 -> ln
     };
 
-    // the fast path: tiles below the last one, when every column carries a vector
-    const int64_t t_full = 32 * cb + 32 <= n_cols ? n_events / 32 : 0;
-    auto run = [&](const Ops& o, int64_t t) {
-        if (t < t_full) process(o, t, std::true_type{});
-        else process(o, t, std::false_type{});
+    // the fast path: tiles below the last one, when every column carries a
+    // vector.  One tile at a time, the next tile's operands loaded ahead (two
+    // wavefronts per SIMD overlap one's matrix products with the other's
+    // vector work).
+    const int64_t t_full = 32 * cb + 32 <= n_cols ? n_events / kMfmaTile : 0;
+    auto run = [&](const OpsA& oa, const OpsB& ob, int64_t t) {
+        if (t < t_full) finish(forward(oa), ob, t, std::true_type{});
+        else finish(forward(oa), ob, t, std::false_type{});
     };
-    Ops A, B;
+    OpsA a0, a1;
+    OpsB b0, b1;
     int64_t t = t0;
-    if (t < t1) load(A, t);
+    if (t < t1) {
+        load_a(a0, t);
+        load_b(b0, t);
+    }
     for (; t < t1; t += 2) {
-        if (t + 1 < t1) load(B, t + 1);
-        run(A, t);
         if (t + 1 < t1) {
-            if (t + 2 < t1) load(A, t + 2);
-            run(B, t + 1);
+            load_a(a1, t + 1);
+            load_b(b1, t + 1);
+        }
+        run(a0, b0, t);
+        if (t + 1 < t1) {
+            if (t + 2 < t1) {
+                load_a(a0, t + 2);
+                load_b(b0, t + 2);
+            }
+            run(a1, b1, t + 1);
         }
     }
 
@@ -377,8 +426,8 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
 #pragma unroll
             for (int q = 0; q < 16; ++q) g[rb][q] = fmaf(gl[rb][q], kLowUnscale, g[rb][q]);
     }
-    // records of this wavefront: G column c, rows 8 j + 4 h + i of each row
-    // block, and the column's sum ln I (lanes c and c + 32)
+    // records of this wavefront: G column c (vector 32 cb + c), rows
+    // 8 j + 4 h + i of each row block, and the vector's sum ln I (lanes c and c + 32)
     const size_t rec_idx = ((size_t)blockIdx.x * n_cb + cb) * 32 + c;
     float* gcol = rec_g + rec_idx * KD;
 #pragma unroll
@@ -422,17 +471,16 @@ __global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt
     __shared__ double s_part[kBatchAsmThreads];
     const int k = blockIdx.x;
     const int W = bt.W;
-    const int cb = (2 * k) / 32, c0 = (2 * k) % 32;
+    const int cb = k / 32, c0 = k % 32;
     const double* vk = bt.v + (size_t)k * 2 * W;
     auto ridx = [&](int ch, int cc) { return ((size_t)ch * bt.n_cb + cb) * 32 + cc; };
     for (int a = threadIdx.x; a < 2 * W; a += blockDim.x) s_v[a] = vk[a];
-    // sum ln I and n_bad over chunks (both columns of the vector)
+    // sum ln I and n_bad over chunks
     double d = 0.0, nb = 0.0;
     for (int ch = threadIdx.x; ch < bt.chunks; ch += blockDim.x) {
         const double2 p0 = *reinterpret_cast<const double2*>(bt.rec_d + 2 * ridx(ch, c0));
-        const double2 p1 = *reinterpret_cast<const double2*>(bt.rec_d + 2 * ridx(ch, c0 + 1));
-        d += p0.x + p1.x;
-        nb += p0.y + p1.y;
+        d += p0.x;
+        nb += p0.y;
     }
     __syncthreads();   // s_v
     const double sk = bt.vscale[k];
@@ -462,28 +510,24 @@ __global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt
     for (int b = threadIdx.x; b < W; b += blockDim.x)
         mu_part += s_v[2 * b] * s_m[b].x + s_v[2 * b + 1] * s_m[b].y;
     const double mu = block_sum_fixed(mu_part, s_wave);
-    // gradient: output o = 2 b + part over R chunk ranges (thread o + 2W r
-    // takes chunks r, r + R, ...); the R partial sums are added in order
-    //   part 0: G[Re b][Re c] + G[Im b][Im c],  part 1: G[Re b][Im c] - G[Im b][Re c]
+    // gradient: output o = 2 b + part (G row o: Re g_b, Im g_b) over R chunk
+    // ranges (thread o + 2W r takes chunks r, r + R, ...); the R partial sums
+    // are added in order
     const int nout = 2 * W;
     const int R = kBatchAsmThreads / nout;
     const int o = threadIdx.x % nout, r = threadIdx.x / nout;
     if (r < R) {
-        const int b = o / 2, part = o % 2;
-        const int c1 = part == 0 ? c0 : c0 + 1, c2 = part == 0 ? c0 + 1 : c0;
-        const double sg = part == 0 ? 1.0 : -1.0;
         double x = 0.0;
         constexpr int kB = 16;
         for (int ch0 = r; ch0 < bt.chunks; ch0 += kB * R) {
-            float u1[kB], u2[kB];
+            float u[kB];
 #pragma unroll
             for (int j = 0; j < kB; ++j) {
                 const int ch = ch0 + j * R;
-                u1[j] = ch < bt.chunks ? bt.rec_g[ridx(ch, c1) * bt.KD + b] : 0.f;
-                u2[j] = ch < bt.chunks ? bt.rec_g[ridx(ch, c2) * bt.KD + W + b] : 0.f;
+                u[j] = ch < bt.chunks ? bt.rec_g[ridx(ch, c0) * bt.KD + o] : 0.f;
             }
 #pragma unroll
-            for (int j = 0; j < kB; ++j) x += (double)u1[j] + sg * (double)u2[j];
+            for (int j = 0; j < kB; ++j) x += (double)u[j];
         }
         s_part[threadIdx.x] = x;
     }
@@ -517,13 +561,13 @@ static int grid_for(int64_t total, int block)
 hipError_t launch_pack_mfma(const void* src, bool c128, int64_t n, int W, bool bf,
                             const Model& m, hipStream_t s)
 {
-    const int64_t total = m.n_tiles * 32 * (int64_t)m.kd;
+    const int64_t total = n * (int64_t)W;
     if (bf)
         hipLaunchKernelGGL(k_pack_mfma<__bf16>, dim3(grid_for(total, 256)), dim3(256), 0, s, src,
-                           c128, n, W, m.kd, m.rb, m.n_tiles, (__bf16*)m.d_data, (__bf16*)m.d_at);
+                           c128, n, W, m.kd, m.rb, (__bf16*)m.d_data, (__bf16*)m.d_at);
     else
         hipLaunchKernelGGL(k_pack_mfma<_Float16>, dim3(grid_for(total, 256)), dim3(256), 0, s,
-                           src, c128, n, W, m.kd, m.rb, m.n_tiles, (_Float16*)m.d_data,
+                           src, c128, n, W, m.kd, m.rb, (_Float16*)m.d_data,
                            (_Float16*)m.d_at);
     return hipGetLastError();
 }
@@ -546,7 +590,7 @@ static void launch_main(const Model& m, const MfmaBatch& b, hipStream_t s, const
     const int gy = (b.n_cb + wpb - 1) / wpb;
     hipExtLaunchKernelGGL((k_amp_mfma<T, NS, NP>), dim3(b.chunks, gy), dim3(64 * wpb), 0,
                           s, ev.start, ev.stop, 0, (const T*)m.d_data, (const T*)m.d_at,
-                          (const T*)b.vm, m.n, m.n_tiles, 2 * b.K, b.n_cb, b.chunks, b.rec_d,
+                          (const T*)b.vm, m.n, m.n_tiles, b.K, b.n_cb, b.chunks, b.rec_d,
                           b.rec_g);
 }
 
@@ -612,7 +656,8 @@ hipError_t launch_mfma_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
     return hipGetLastError();
 }
 
-// copy of the stored 16-bit amplitudes, widened to complex64 (N x W)
+// copy of the stored 16-bit amplitudes, widened to complex64 (N x W), read
+// from the rows x_i of the forward copy
 __global__ void k_unpack_mfma(const void* __restrict__ af, bool bf, int64_t n, int W, int KD,
                               float2* __restrict__ dst)
 {
@@ -621,13 +666,14 @@ __global__ void k_unpack_mfma(const void* __restrict__ af, bool bf, int64_t n, i
          g += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = g / W;
         const int a = (int)(g % W);
+        const int64_t x = ((i / kMfmaTile) * 32 + 2 * (i % kMfmaTile)) * KD + 2 * a;
         float re, im;
         if (bf) {
-            re = (float)reinterpret_cast<const __bf16*>(af)[i * KD + a];
-            im = (float)reinterpret_cast<const __bf16*>(af)[i * KD + W + a];
+            re = (float)reinterpret_cast<const __bf16*>(af)[x];
+            im = (float)reinterpret_cast<const __bf16*>(af)[x + 1];
         } else {
-            re = (float)reinterpret_cast<const _Float16*>(af)[i * KD + a];
-            im = (float)reinterpret_cast<const _Float16*>(af)[i * KD + W + a];
+            re = (float)reinterpret_cast<const _Float16*>(af)[x];
+            im = (float)reinterpret_cast<const _Float16*>(af)[x + 1];
         }
         dst[g] = make_float2(re, im);
     }

@@ -230,12 +230,14 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
     } else if (form == PWA_FORM_AMPLITUDE_BF16 || form == PWA_FORM_AMPLITUDE_FP16) {
         m->kd = (2 * W + 15) / 16 * 16;
         m->rb = (m->kd + 31) / 32;
-        m->n_tiles = (n + 31) / 32;
-        m->data_bytes = m->n_tiles * 32 * (int64_t)m->kd * 2;
+        m->n_tiles = (n + pwa::kMfmaTile - 1) / pwa::kMfmaTile;
+        m->data_bytes = m->n_tiles * 32 * (int64_t)m->kd * 2;   // 32 rows per tile
         const size_t at_bytes = (size_t)m->n_tiles * m->rb * 32 * 32 * 2;
         HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
         HIP_TRY(hipMalloc(&m->d_at, at_bytes));
-        HIP_TRY(hipMemsetAsync(m->d_at, 0, at_bytes, s));   // rows kd .. 32 rb stay zero
+        // padding events, columns 2W .. kd and adjoint rows 2W .. 32 rb stay zero
+        HIP_TRY(hipMemsetAsync(m->d_data, 0, m->data_bytes, s));
+        HIP_TRY(hipMemsetAsync(m->d_at, 0, at_bytes, s));
         HIP_TRY(hipEventRecord(bt[0], s));
         HIP_TRY(pwa::launch_pack_mfma(sd.ptr, data_c128, n, W, form == PWA_FORM_AMPLITUDE_BF16, *m,
                                       s));
@@ -723,7 +725,7 @@ int mfma_reserve(Model* m, int K, int n_cb, int chunks)
         m->d_vm = nullptr;
         m->d_brec = nullptr;
         m->vec_cap = 0;
-        const int cb_cap = cap / 16;
+        const int cb_cap = (cap + 31) / 32;
         HIP_TRY(hipMalloc(&m->d_vb, sizeof(double) * (2 * W + 1) * (size_t)cap));
         HIP_TRY(hipHostMalloc((void**)&m->h_vstage, sizeof(double) * 2 * W * (size_t)cap,
                               hipHostMallocDefault));
@@ -761,7 +763,7 @@ int mfma_reserve(Model* m, int K, int n_cb, int chunks)
 int eval_mfma(Model* m, const double* v, int K, hipStream_t s, bool timed)
 {
     const int W = m->W;
-    const int n_cb = (2 * K + 31) / 32;
+    const int n_cb = (K + 31) / 32;
     const int chunks = pwa::mfma_chunks(*m, n_cb);
     int rc = mfma_reserve(m, K, n_cb, chunks);
     if (rc != PWA_OK) return rc;
@@ -1118,7 +1120,7 @@ int pwa_model_info(const pwa_model* model, pwa_info* out)
     case pwa::kTable64Plain: out->stream_bytes = 2 * m->n * m->P * 16; break;
     case pwa::kAmpBF16:
     case pwa::kAmpFP16:
-        out->stream_bytes = m->n_tiles * 32 * (int64_t)(m->kd + 32 * m->rb) * 2;
+        out->stream_bytes = m->n_tiles * 32 * (int64_t)(m->kd + 32 * m->rb) * 2;   // both copies
         break;
     default: out->stream_bytes = m->n * m->W * 8; break;
     }

@@ -15,6 +15,8 @@ namespace pwa {
 constexpr int kTileEvents = 16;
 // Events per tile of the FP32 amplitude layout (padding unit).
 constexpr int kAmpTile = 64;
+// Events per tile of the 16-bit matrix-core layout (two MFMA rows each).
+constexpr int kMfmaTile = 16;
 
 // Lane-split layout of the FP32 amplitude form (k_amp.hip): an event is held
 // by q = 2^lq neighbouring lanes with wl (even) waves each, so rows are q wl
@@ -185,12 +187,12 @@ struct MfmaBatch {
     double* vscale;             // K power-of-two scales of the vectors (device)
     void* vm;                   // split vector matrix (device)
     double* rec_d;              // chunks x n_cb x 32 x 2: sum ln I, n_bad (device)
-    float* rec_g;               // chunks x n_cb x 32 x kd: G columns (device)
+    float* rec_g;               // chunks x n_cb x 32 x kd: G columns, Re/Im g_b (device)
     double* out;                // K x (2 + 2W) (pinned host)
     unsigned long long* done;   // K completion words (pinned host)
     unsigned long long seq;
     int K;
-    int n_cb;                   // column blocks of 32 (16 vectors each)
+    int n_cb;                   // column blocks of 32 vectors
     int chunks;                 // event chunks
 };
 

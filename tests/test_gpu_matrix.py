@@ -91,7 +91,10 @@ def _check(form, w, n, n_mc, seed, k):
 
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("w,n,k", [(1, 1, 1), (2, 33, 3), (4, 1000, 16), (7, 4099, 17),
-                                   (20, 5000, 37), (24, 777, 64), (33, 300, 5), (64, 2000, 20)])
+                                   (20, 5000, 37), (24, 777, 64), (33, 300, 5), (64, 2000, 20),
+                                   # full 16-event tiles only; one and several full
+                                   # column blocks of 32 vectors, and one more
+                                   (20, 4096, 32), (3, 16, 33), (5, 17, 96), (16, 2048, 65)])
 def test_matrix_parity(form, w, n, k):
     _check(form, w, n, 3 * n + 11, seed=1000 * w + n + k, k=k)
 
