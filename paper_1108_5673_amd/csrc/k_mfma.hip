@@ -389,34 +389,125 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
         dsum += (double)lsum * 0.69314718055994530942;   // log2 -> ln
     };
 
-    // the fast path: tiles below the last one, when every column carries a
-    // vector.  One tile at a time, the next tile's operands loaded ahead (two
-    // wavefronts per SIMD overlap one's matrix products with the other's
-    // vector work).
-    const int64_t t_full = 32 * cb + 32 <= n_cols ? n_events / kMfmaTile : 0;
-    auto run = [&](const OpsA& oa, const OpsB& ob, int64_t t) {
-        if (t < t_full) finish(forward(oa), ob, t, std::true_type{});
-        else finish(forward(oa), ob, t, std::false_type{});
+    // ---- full tiles, software-pipelined --------------------------------------
+    // One step takes the epilogue and adjoint of tile t and the forward product
+    // of tile t + 1, in 8 pieces fenced against reordering: piece i holds the
+    // epilogue of one register pair (one (event, vector) pair of half i / 4)
+    // beside a share of the forward MFMAs, and pieces 4..7 also the adjoint
+    // MFMAs of half 0.  The wavefront issues each piece's vector instructions
+    // while its MFMAs run.
+    constexpr int kFwd = SL ? 2 * NS : NS * NP;
+    auto fwd_mfma = [&](const OpsA& an, f32x16& nx, f32x16& nxl, int m) {
+        if constexpr (SL) {
+            const int s = m >> 1;
+            if (m & 1) nxl = H16<T>::mfma(an.a[s], vp[1][s], nxl);
+            else nx = H16<T>::mfma(an.a[s], vp[0][s], nx);
+        } else {
+            const int p = NP - 1 - m / NS, s = m % NS;   // smallest parts first
+            nx = H16<T>::mfma(an.a[s], vp[p][s], nx);
+        }
     };
-    OpsA a0, a1;
-    OpsB b0, b1;
+    auto adj_mfma = [&](const OpsB& o, const V8& chi, const V8& clo, int s2, int j) {
+        const int rb = j >> 1;
+        if (j & 1) {
+            if constexpr (SL) gl[rb] = H16<T>::mfma(o.b[rb][s2], clo, gl[rb]);
+            else g[rb] = H16<T>::mfma(o.b[rb][s2], clo, g[rb]);
+        } else {
+            g[rb] = H16<T>::mfma(o.b[rb][s2], chi, g[rb]);
+        }
+    };
+    auto pair_epi = [&](const f32x16& acc, int q, float& lsum, V8& chi, V8& clo, int r) {
+        const float x = acc[q], y = acc[q + 1];
+        const float I = fmaf(y, y, x * x);
+        const float w = __builtin_amdgcn_rcpf(I);
+        lsum += __builtin_amdgcn_logf(I);
+        V2 hi, lo;
+        split_pair<T>(x * w, y * w, hi, lo);
+        chi[2 * r] = hi[0];
+        chi[2 * r + 1] = hi[1];
+        clo[2 * r] = lo[0];
+        clo[2 * r + 1] = lo[1];
+    };
+    auto step = [&](const OpsA& an, const f32x16& acc, const OpsB& o) {
+        f32x16 nx = f32x16{}, nxl = f32x16{};
+        float lsum = 0.f;
+        V8 chi0, clo0, chi1, clo1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+#pragma unroll
+            for (int m = i * kFwd / 8; m < (i + 1) * kFwd / 8; ++m) fwd_mfma(an, nx, nxl, m);
+            if (i >= 4) {
+#pragma unroll
+                for (int j = (i - 4) * 2 * RB / 4; j < (i - 3) * 2 * RB / 4; ++j)
+                    adj_mfma(o, chi0, clo0, 0, j);
+            }
+            if (i < 4) pair_epi(acc, 2 * i, lsum, chi0, clo0, i);
+            else pair_epi(acc, 8 + 2 * (i - 4), lsum, chi1, clo1, i - 4);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * RB; ++j) adj_mfma(o, chi1, clo1, 1, j);
+        dsum += (double)lsum * 0.69314718055994530942;   // log2 -> ln
+        if constexpr (SL) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) nx[q] = fmaf(nxl[q], kLowUnscale, nx[q]);
+        }
+        return nx;
+    };
+
+    // Full tiles: below the last one, when every column carries a vector (no
+    // validity tests: a degenerate event makes the lane's log sum non-finite).
+    // Operands are loaded a step ahead; loads and products past the last full
+    // tile repeat that tile and are not used.
+    const int64_t t_full = 32 * cb + 32 <= n_cols ? n_events / kMfmaTile : 0;
+    const int64_t tf = max(t0, min(t1, t_full));
     int64_t t = t0;
+    if (tf - t0 >= 2) {
+        OpsA a0, a1;
+        OpsB b0, b1;
+        load_a(a0, t0);
+        load_b(b0, t0);
+        load_a(a1, t0 + 1);
+        f32x16 s0 = forward(a0);
+        // at the top: s0 = S(t), b0 = adjoint operands of t, a1 = forward
+        // operands of t + 1 (a0 and b1 free)
+        for (; t + 2 <= tf; t += 2) {
+            load_a(a0, min(t + 2, tf - 1));
+            load_b(b1, t + 1);
+            const f32x16 s1 = step(a1, s0, b0);
+            load_a(a1, min(t + 3, tf - 1));
+            load_b(b0, min(t + 2, tf - 1));
+            s0 = step(a0, s1, b1);
+        }
+        if (t < tf) {   // an odd count: s0, b0 hold the last full tile
+            finish(s0, b0, t, std::true_type{});
+            ++t;
+        }
+    }
+    // the rest (a chunk with fewer than two full tiles, the last tile, padded
+    // columns): one tile at a time, the next tile's operands loaded ahead
+    auto run = [&](const OpsA& oa, const OpsB& ob, int64_t tt) {
+        if (tt < t_full) finish(forward(oa), ob, tt, std::true_type{});
+        else finish(forward(oa), ob, tt, std::false_type{});
+    };
     if (t < t1) {
+        OpsA a0, a1;
+        OpsB b0, b1;
         load_a(a0, t);
         load_b(b0, t);
-    }
-    for (; t < t1; t += 2) {
-        if (t + 1 < t1) {
-            load_a(a1, t + 1);
-            load_b(b1, t + 1);
-        }
-        run(a0, b0, t);
-        if (t + 1 < t1) {
-            if (t + 2 < t1) {
-                load_a(a0, t + 2);
-                load_b(b0, t + 2);
+        for (; t < t1; t += 2) {
+            if (t + 1 < t1) {
+                load_a(a1, t + 1);
+                load_b(b1, t + 1);
             }
-            run(a1, b1, t + 1);
+            run(a0, b0, t);
+            if (t + 1 < t1) {
+                if (t + 2 < t1) {
+                    load_a(a0, t + 2);
+                    load_b(b0, t + 2);
+                }
+                run(a1, b1, t + 1);
+            }
         }
     }
 
