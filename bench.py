@@ -89,6 +89,21 @@ def time_model(model, points, steps, warmup):
     }
 
 
+def host_cpu():
+    """CPU model (from /proc/cpuinfo), logical CPUs this process may use and
+    logical CPUs of the machine."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "logical_cpus": os.cpu_count()}
+
+
 def mfma_flops(n_events, n_waves, k, v_parts):
     """Matrix-core FLOPs of one batched pass as the kernel issues them: per
     16-event tile (32 rows) and 32 vectors, the forward product (16-wide KD
@@ -127,9 +142,11 @@ def bench_batched(args):
         for _ in range(2):
             pwa.nll_batched([m], [s.points])
         torch.cuda.synchronize()
-        m.set_timing(True)
+        # kernel time from event stamps on every 8th pass (a stamped launch
+        # costs about 14 us of the call)
+        m.set_timing(True, every=8)
         m.timing()
-        reps = 10
+        reps = 24
         t = time.perf_counter()
         for _ in range(reps):
             [(nll, g)] = pwa.nll_batched([m], [s.points])
@@ -204,6 +221,15 @@ def bench_amplitude(args):
                                                  np.linalg.norm(ref[j][1])) for j in ref)
         log("amplitude w32 n2m (%s shape %s): %.0f evals/s, kernel %.1f us (%.0f GB/s)"
             % (tag, out[tag]["shape"], r["evals_per_s"], kus, out[tag]["achieved_gbs"]))
+    # achievable read bandwidth on the same stored amplitudes (a plain
+    # non-temporal reader over every stored byte, pwa_read_ceiling)
+    rc = m.read_ceiling(10)
+    out["read_ceiling_gbs"] = rc["gbs"]
+    out["read_ceiling_bytes"] = rc["bytes"]
+    for tag in ("default", "tuned"):
+        out[tag]["frac_of_read_ceiling"] = out[tag]["achieved_gbs"] / rc["gbs"]
+    log("amplitude w32 n2m: plain read of the stored %.0f MB: %.1f us, %.0f GB/s"
+        % (rc["bytes"] / 1e6, 1e3 * rc["ms"], rc["gbs"]))
     m.close()
     return out
 
@@ -452,11 +478,20 @@ def main():
                "kind": "oracle",
                "sample": "first %d of the 200 walk points, all 1M events, FP64 table form "
                          "(packed complex64 table widened to complex128)" % k}
+        # the same evaluation on one host thread (first walk point), and the host
+        n_thr = o.num_threads()
+        o.set_num_threads(1)
+        t = time.perf_counter()
+        o.nll_table(T, M, pts[0])
+        cpu["one_thread"] = {"value": 1.0 / (time.perf_counter() - t), "cores": 1,
+                             "sample": "walk point 0"}
+        o.set_num_threads(n_thr)
+        cpu["host"] = host_cpu()
         parity = {"points": k, "max_abs_dnll": max(dn), "max_rel_grad_err": max(dg),
                   "reference": "oracle on the identical stored complex64 table"}
         del T
-        log("oracle: %.3f evals/s on %d threads; max |dNLL| %.2e, max grad rel %.2e"
-            % (cpu["value"], cpu["cores"], max(dn), max(dg)))
+        log("oracle: %.3f evals/s on %d threads (%.3f on one); max |dNLL| %.2e, max grad rel %.2e"
+            % (cpu["value"], cpu["cores"], cpu["one_thread"]["value"], max(dn), max(dg)))
 
     line = {
         "metric": "NLL+grad evals/s at 1M events, 20 waves: fused FP32 vs plain FP64 table",

@@ -256,8 +256,9 @@ class Model:
         return ms.value, n.value
 
     def read_ceiling(self, reps: int = 5) -> dict:
-        """Fastest of `reps` passes of a plain non-temporal read of the stored
-        data: the achievable read bandwidth on the same bytes."""
+        """Achievable read bandwidth on the stored data: the fastest of `reps`
+        passes of the fused kernel's own loads with the arithmetic taken out
+        (tiled table forms) or of a plain non-temporal reader (other forms)."""
         ms = ctypes.c_double(0.0)
         nb = ctypes.c_int64(0)
         _native.check(_native.lib().pwa_read_ceiling(self._handle(), int(reps), self._stream,
@@ -284,6 +285,20 @@ class Model:
             pass
 
 
+def _addr(a: np.ndarray) -> int:
+    return a.__array_interface__["data"][0]
+
+
+def _batch_rows(v, n_waves: int) -> np.ndarray:
+    """(K, 2W) float64 C-contiguous view or copy of K parameter vectors."""
+    a = v.detach().cpu().numpy() if _is_torch(v) else v
+    if not isinstance(a, np.ndarray) or a.dtype.kind == "c":
+        a = np.asarray(a)
+        if a.dtype.kind == "c":
+            a = np.ascontiguousarray(a, np.complex128).view(np.float64)
+    return np.ascontiguousarray(a, np.float64).reshape(-1, 2 * n_waves)
+
+
 def nll_batched(models, vs, grad: bool = True, stream=None):
     """Evaluate K_m parameter sets on each of several models.
 
@@ -292,23 +307,20 @@ def nll_batched(models, vs, grad: bool = True, stream=None):
     """
     L = _native.lib()
     n = len(models)
-    ks, flat = [], []
-    for m, v in zip(models, vs):
-        a = np.asarray(v.detach().cpu().numpy() if _is_torch(v) else v)
-        if np.iscomplexobj(a):
-            a = a.astype(np.complex128).view(np.float64)
-        a = np.ascontiguousarray(a, np.float64).reshape(-1, 2 * m.n_waves)
-        ks.append(a.shape[0])
-        flat.append(a.ravel())
-    vall = np.ascontiguousarray(np.concatenate(flat) if flat else np.zeros(0))
+    rows = [_batch_rows(v, m.n_waves) for m, v in zip(models, vs)]
+    ks = [a.shape[0] for a in rows]
+    if n == 1:
+        vall = rows[0]
+    else:
+        vall = np.concatenate([a.ravel() for a in rows]) if rows else np.zeros(0)
     total = sum(ks)
-    nll = np.zeros(total, np.float64)
-    g = np.zeros(sum(k * 2 * m.n_waves for k, m in zip(ks, models)), np.float64) if grad else None
+    nll = np.empty(total, np.float64)
+    g = np.empty(sum(k * 2 * m.n_waves for k, m in zip(ks, models)), np.float64) if grad else None
     handles = (ctypes.c_void_p * max(1, n))(*[m._handle() for m in models])
     karr = (ctypes.c_int32 * max(1, n))(*ks)
     st = stream if stream is not None else (models[0]._stream if models else None)
-    status = _native.check(L.pwa_nll_batched(handles, n, karr, vall.ctypes.data, nll.ctypes.data,
-                                             g.ctypes.data if grad else None, st))
+    status = _native.check(L.pwa_nll_batched(handles, n, karr, _addr(vall), _addr(nll),
+                                             _addr(g) if grad else None, st))
     if status == _native.PWA_WARN_DEGENERATE:
         warnings.warn("degenerate evaluation(s): NLL +inf")
     out, pos, gpos = [], 0, 0

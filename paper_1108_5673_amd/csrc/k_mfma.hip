@@ -573,6 +573,28 @@ __global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt
         d += p0.x;
         nb += p0.y;
     }
+    // gradient records: output o = 2 b + part (G row o: Re g_b, Im g_b) over R
+    // chunk ranges (thread o + 2W r takes chunks r, r + R, ... in order; the R
+    // partial sums are added in order at the end).  Issued here, in batches of
+    // 48, so that their loads overlap the reductions and M below.
+    const int nout = 2 * W;
+    const int R = kBatchAsmThreads / nout;
+    const int o = threadIdx.x % nout, r = threadIdx.x / nout;
+    if (r < R) {
+        double x = 0.0;
+        constexpr int kB = 48;
+        for (int ch0 = r; ch0 < bt.chunks; ch0 += kB * R) {
+            float u[kB];
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                const int ch = ch0 + j * R;
+                u[j] = ch < bt.chunks ? bt.rec_g[ridx(ch, c0) * bt.KD + o] : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < kB; ++j) x += (double)u[j];
+        }
+        s_part[threadIdx.x] = x;
+    }
     __syncthreads();   // s_v
     const double sk = bt.vscale[k];
     const double dsum = block_sum_fixed(d, s_wave) + 2.0 * (double)bt.n_events * log(sk);
@@ -601,28 +623,7 @@ __global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt
     for (int b = threadIdx.x; b < W; b += blockDim.x)
         mu_part += s_v[2 * b] * s_m[b].x + s_v[2 * b + 1] * s_m[b].y;
     const double mu = block_sum_fixed(mu_part, s_wave);
-    // gradient: output o = 2 b + part (G row o: Re g_b, Im g_b) over R chunk
-    // ranges (thread o + 2W r takes chunks r, r + R, ...); the R partial sums
-    // are added in order
-    const int nout = 2 * W;
-    const int R = kBatchAsmThreads / nout;
-    const int o = threadIdx.x % nout, r = threadIdx.x / nout;
-    if (r < R) {
-        double x = 0.0;
-        constexpr int kB = 16;
-        for (int ch0 = r; ch0 < bt.chunks; ch0 += kB * R) {
-            float u[kB];
-#pragma unroll
-            for (int j = 0; j < kB; ++j) {
-                const int ch = ch0 + j * R;
-                u[j] = ch < bt.chunks ? bt.rec_g[ridx(ch, c0) * bt.KD + o] : 0.f;
-            }
-#pragma unroll
-            for (int j = 0; j < kB; ++j) x += (double)u[j];
-        }
-        s_part[threadIdx.x] = x;
-    }
-    __syncthreads();
+    __syncthreads();   // s_part
     if (threadIdx.x < nout) {
         double x = 0.0;
         for (int rr = 0; rr < R; ++rr) x += s_part[rr * nout + threadIdx.x];
