@@ -237,9 +237,10 @@ def bench_amplitude(args):
 def bench_multi(args):
     """64 amplitude-form models of uneven size (W uniform in 8..48, N log-uniform
     in 1e5..4e6, 2N accepted MC each), one NLL+gradient of every model per
-    iteration through one pwa_nll_batched call (one amplitude launch and one
-    assembly, replayed from a captured graph), 500 iterations along a random
-    walk per model; and the same iterations as 64 separate calls."""
+    iteration through one pwa_nll_batched call (per class of storage shape one
+    amplitude launch, then one assembly, replayed from a captured graph), 500
+    iterations along a random walk per model, called through pwa.Batch; and
+    the same iterations through the list form and as 64 separate calls."""
     import torch
     import paper_1108_5673_amd as pwa
     from paper_1108_5673_amd import synth
@@ -272,13 +273,24 @@ def bench_multi(args):
         cur = [c + 0.01 * (rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape))
                for c in cur]
         walk.append(cur)
+    # one pwa_nll_batched call per iteration through pwa.Batch (handles, counts
+    # and output buffers set up once; one flat parameter array per iteration)
+    batch = pwa.Batch(models)
+    flat = [np.concatenate([np.ascontiguousarray(w, np.complex128).view(np.float64)
+                            for w in walk[k]]) for k in range(iters)]
     for k in range(5):
-        pwa.nll_batched(models, [w[None, :] for w in walk[k]])
+        batch(flat[k])
     torch.cuda.synchronize()
     t = time.perf_counter()
     for k in range(iters):
-        res = pwa.nll_batched(models, [w[None, :] for w in walk[k]])
+        res = batch(flat[k])
     dt = (time.perf_counter() - t) / iters
+    # the same call through the list form (nll_batched converts 64 arrays a call)
+    list_iters = 50
+    t = time.perf_counter()
+    for k in range(list_iters):
+        pwa.nll_batched(models, [w[None, :] for w in walk[k]])
+    dt_list = (time.perf_counter() - t) / list_iters
     seq_iters = 50
     t = time.perf_counter()
     for k in range(seq_iters):
@@ -292,6 +304,7 @@ def bench_multi(args):
            "iteration_ms": 1e3 * dt, "evals_per_s": 64 / dt,
            "events_iter_per_s": n_tot / dt, "achieved_gbs": bytes_it / dt / 1e9,
            "frac_of_8tbs": bytes_it / dt / 8e12, "separate_calls_iteration_ms": 1e3 * dt_seq,
+           "list_api_iteration_ms": 1e3 * dt_list,
            "tuned_shapes": shapes, "tuning_s": tune_s,
            "speedup_vs_separate_calls": dt_seq / dt}
     if keep:
@@ -316,8 +329,8 @@ def bench_multi(args):
                          "reference": "oracle on the same complex64 amplitudes"}
         out["oracle"] = {"events_iter_per_s": ev_or / t_or, "cores": o.num_threads(),
                          "sample": "one evaluation of each of the two smallest models"}
-    log("multi-model: %.2f ms per iteration of 64 models (%.0f GB/s); separate calls %.2f ms"
-        % (1e3 * dt, bytes_it / dt / 1e9, 1e3 * dt_seq))
+    log("multi-model: %.2f ms per iteration of 64 models (%.0f GB/s); list form %.2f ms; "
+        "separate calls %.2f ms" % (1e3 * dt, bytes_it / dt / 1e9, 1e3 * dt_list, 1e3 * dt_seq))
     for m in models:
         m.close()
     return out

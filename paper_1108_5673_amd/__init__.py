@@ -334,6 +334,64 @@ def nll_batched(models, vs, grad: bool = True, stream=None):
     return out
 
 
+class Batch:
+    """A fixed list of models evaluated together through one pwa_nll_batched
+    call per step, with the handle list, counts, parameter layout and output
+    buffers set up once (for callers that evaluate the same models every
+    iteration, such as a fit of many models or many starting points).
+
+    ks[m] parameter vectors of model m per call (default 1 each).  The
+    parameters of a call are one flat float64 array of `size` values: model
+    0's K_0 x 2W_0 (re, im interleaved), then model 1's, ...  `params[m]` is a
+    (K_m, 2W_m) view of an internal array of that layout, which a call uses
+    when it is given no array.  A call returns `results`: a list of
+    (nll (K_m,), grad (K_m, 2W_m) or None) views of output buffers that the
+    next call overwrites.
+    """
+
+    def __init__(self, models, ks=None, grad: bool = True, stream=None):
+        self.models = list(models)
+        n = len(self.models)
+        self.ks = [1] * n if ks is None else [int(k) for k in ks]
+        if len(self.ks) != n or any(k < 0 for k in self.ks):
+            raise ValueError("ks must hold one non-negative count per model")
+        widths = [2 * m.n_waves for m in self.models]
+        off = np.cumsum([0] + [k * w for k, w in zip(self.ks, widths)])
+        self.size = int(off[-1])
+        self._handles = (ctypes.c_void_p * max(1, n))(*[m._handle() for m in self.models])
+        self._karr = (ctypes.c_int32 * max(1, n))(*self.ks)
+        self._v = np.zeros(max(1, self.size), np.float64)
+        self._nll = np.empty(max(1, sum(self.ks)), np.float64)
+        self._g = np.empty(max(1, self.size), np.float64) if grad else None
+        self.params = [self._v[off[i]:off[i + 1]].reshape(k, w)
+                       for i, (k, w) in enumerate(zip(self.ks, widths))]
+        pos = np.cumsum([0] + self.ks)
+        self.results = [(self._nll[pos[i]:pos[i + 1]],
+                         self._g[off[i]:off[i + 1]].reshape(k, w) if grad else None)
+                        for i, (k, w) in enumerate(zip(self.ks, widths))]
+        self._stream = stream if stream is not None else (self.models[0]._stream if n else None)
+        self._nll_addr, self._g_addr = _addr(self._nll), (_addr(self._g) if grad else None)
+
+    def __call__(self, v=None):
+        if v is None:
+            a = self._v
+        else:
+            a = v.detach().cpu().numpy() if _is_torch(v) else v
+            if (not isinstance(a, np.ndarray) or a.dtype != np.float64
+                    or not a.flags.c_contiguous):
+                a = np.ascontiguousarray(a, np.float64)
+            if a.size != self.size:
+                raise ValueError("expected %d parameter values, got %d" % (self.size, a.size))
+        for m in self.models:
+            m._handle()   # raises if a model was freed
+        status = _native.check(_native.lib().pwa_nll_batched(
+            self._handles, len(self.models), self._karr, _addr(a), self._nll_addr, self._g_addr,
+            self._stream))
+        if status == _native.PWA_WARN_DEGENERATE:
+            warnings.warn("degenerate evaluation(s): NLL +inf")
+        return self.results
+
+
 def __getattr__(name):
     if name == "NLLFunction":
         from .autograd import NLLFunction

@@ -1,12 +1,13 @@
-"""Many evaluations of several FP32 amplitude models in one launch (needs an
+"""Many evaluations of several FP32 amplitude models in one call (needs an
 MI355X).
 
 pwa_nll_batched over amplitude-form models runs every (model, vector)
-evaluation as one work list: one launch of the amplitude kernel, one of the
-assembly, replayed from a graph captured once per set of models.  Checked
-against the FP64 oracle per evaluation (tolerances as for single calls: NLL
-1e-10 relative, gradient 1e-9), against single calls, across replays with other
-GPU work in between, and after a model of the cached plan is freed.
+evaluation as one work list: one launch of the amplitude kernel per class of
+storage shape and one of the assembly, replayed from a graph captured once per
+set of models.  Checked against the FP64 oracle per evaluation (tolerances as
+for single calls: NLL 1e-10 relative, gradient 1e-9), against single calls,
+across replays with other GPU work in between, after a model of the cached plan
+is freed, and through the pwa.Batch object (bitwise the same as the list form).
 """
 import numpy as np
 import pytest
@@ -94,3 +95,33 @@ def test_multi_plan_dropped_when_model_freed():
     assert np.array_equal(r1[0][0], r2[0][0]) and np.array_equal(r1[2][1], r2[1][1])
     for m in keep:
         m.close()
+
+
+def test_batch_object_matches_list_form():
+    ms = _models(SPEC[:4], seed0=90)
+    models = [m for m, *_ in ms]
+    ks = [2, 1, 3, 2]
+    vs = [s.points[:k] for (m, s, d, mc), k in zip(ms, ks)]
+    ref = pwa.nll_batched(models, vs)
+    b = pwa.Batch(models, ks)
+    flat = np.concatenate([np.ascontiguousarray(v, np.complex128).view(np.float64).ravel()
+                           for v in vs])
+    assert flat.size == b.size
+    res = b(flat)
+    for (n1, g1), (n2, g2), k, m in zip(ref, res, ks, models):
+        assert n2.shape == (k,) and g2.shape == (k, 2 * m.n_waves)
+        assert np.array_equal(n1, n2) and np.array_equal(g1, g2)
+    # the same through the parameter views, after a call with other vectors
+    b(flat[::-1].copy())
+    for p, v in zip(b.params, vs):
+        p[...] = np.ascontiguousarray(v, np.complex128).view(np.float64).reshape(p.shape)
+    res = b()
+    for (n1, g1), (n2, g2) in zip(ref, res):
+        assert np.array_equal(n1, n2) and np.array_equal(g1, g2)
+    with pytest.raises(ValueError):
+        b(flat[:-1])
+    models[2].close()
+    with pytest.raises(RuntimeError):
+        b(flat)
+    for i in (0, 1, 3):
+        models[i].close()
