@@ -112,6 +112,44 @@ def test_matrix_degenerate_event(form):
 
 
 @pytest.mark.parametrize("form", FORMS)
+def test_matrix_degenerate_event_full_blocks(form):
+    # 64 vectors (two full column blocks) over full 16-event tiles: the
+    # degenerate event lies in the tiles taken by the software pipeline
+    s = synth.small_sample(6, 4000, 5000, seed=78, n_points=64)
+    d = s.data.astype(np.complex64)
+    d[1234] = 0.0
+    model = pwa.Model(d, s.mc.astype(np.complex64), 5000, form=form)
+    with pytest.warns(UserWarning):
+        [(nll, g)] = pwa.nll_batched([model], [s.points])
+    assert np.all(np.isinf(nll)) and np.all(np.isnan(g))
+    model.close()
+
+
+def test_matrix_extreme_intensities():
+    # bf16 keeps the FP32 exponent range: events scaled by 1e-15 and 1e+15 give
+    # intensities near 1e-30 and 1e+30, whose products leave the FP32 range; the
+    # result must still match the oracle within the arithmetic bounds
+    form = "amplitude_bf16"
+    o = oracle.get()
+    s = synth.small_sample(10, 4096, 6000, seed=79, n_points=64)
+    d32 = s.data.astype(np.complex64)
+    d32[::97] *= np.float32(1e-15)
+    d32[5::89] *= np.float32(1e15)
+    mc32 = s.mc.astype(np.complex64)
+    model = pwa.Model(d32, mc32, 6000, form=form)
+    A = _round16(d32, form)
+    M = o.mc_matrix(mc32.astype(np.complex128), 6000)
+    [(nll_b, g_b)] = pwa.nll_batched([model], [s.points])
+    for j in (0, 17, 40, 63):
+        rn, rg, nbad = o.nll_amp(A, M, s.points[j])
+        assert nbad == 0
+        b_nll, b_g = _bounds(A, s.points[j], form, rn, rg)
+        assert abs(nll_b[j] - rn) <= b_nll, (j, nll_b[j], rn, b_nll)
+        assert np.linalg.norm(g_b[j] - rg) <= b_g, (j, _rel(g_b[j], rg))
+    model.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
 def test_matrix_repeatable(form):
     s = synth.small_sample(12, 3000, 4000, seed=5, n_points=40)
     model = pwa.Model(s.data.astype(np.complex64), s.mc.astype(np.complex64), 4000, form=form)
