@@ -33,9 +33,16 @@ FLAGS = [
 ]
 
 
+# Per-source additions.  k_common.hip: the FP64 matrix-core MC integral keeps
+# its loop-carried accumulators in VGPRs (with AGPR-form MFMAs the compiler
+# copies all of them out and back on every trip of the event loop).
+EXTRA_FLAGS = {"k_common.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA_FLAGS.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src),
+           "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), res.stderr))

@@ -30,6 +30,8 @@ namespace pwa {
 constexpr int kGramMaxRows = 512;  // partial records of the MC matrix build
 constexpr int kGramMaxPairs = 3;   // block pairs per thread: nb(nb+1)/2 <= 768, W <= 152
 constexpr int kGramPre = 16;       // staged elements per thread and chunk (E x 4nb <= 4096)
+constexpr int kGramMfmaMaxTiles = 4;   // matrix-core build for 2W <= 64
+constexpr int kGramDepth = 8;          // steps of loads in flight per wavefront
 
 // events per chunk: as many as kGramPre elements per thread stage, in steps of 16
 int gram_chunk(int W)
@@ -210,6 +212,175 @@ hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, double* 
         else PWA_GRAM(false, 3);
     }
 #undef PWA_GRAM
+    return hipGetLastError();
+}
+
+// ---- the MC integral on the FP64 matrix cores (2W <= 64) ------------------
+// The real Gram matrix G = sum_j x_j x_j^T of x_j = [Re B_j0 .. Re B_j,W-1,
+// Im B_j0 .. Im B_j,W-1] (zero padded to 16 T) holds the Hermitian sum:
+//   sum_j B_ja conj(B_jb) = G[a][b] + G[W+a][W+b] + i (G[W+a][b] - G[a][W+b]).
+// G is a product with the events as its inner dimension, on
+// v_mfma_f64_16x16x4f64 (D += A B with A 16 x 4, B 4 x 16): tile pair
+// (t <= u) accumulates D[i][j] = sum_k x_k[16 t + i] x_k[16 u + j] over steps
+// of 4 events.  Lane l takes event k = l / 16 of the step and component
+// i = l % 16 of every tile, which is where both operands expect x_k[16 t + i]
+// (A[i][k] and B[k][j] in lane i + 16 k; D[4 r + l / 16][l % 16] in register
+// r).  The four wavefronts of a block take every fourth step of the block's
+// range, with the values of the next kGramDepth steps in flight (the memory
+// latency is several steps of matrix work), and are added in wavefront order
+// through LDS into one record of T (T + 1) / 2 tiles of 256 doubles, in
+// register-major order [tile][r][lane].
+typedef double gd4 __attribute__((ext_vector_type(4)));
+
+template <bool C128, int T>
+__global__ __launch_bounds__(256) void k_gram_mfma(const void* __restrict__ mc, int64_t n_acc,
+                                                   int W, double* __restrict__ records)
+{
+    constexpr int NPAIR = T * (T + 1) / 2;
+    using In = typename std::conditional<C128, double2, float2>::type;
+    const In* src = reinterpret_cast<const In*>(mc);
+    __shared__ double s_acc[NPAIR * 4 * 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i = lane & 15, k = lane >> 4;
+    gd4 d[NPAIR];
+#pragma unroll
+    for (int p = 0; p < NPAIR; ++p) d[p] = gd4{0.0, 0.0, 0.0, 0.0};
+
+    const int64_t n_steps = (n_acc + 3) / 4;
+    const int64_t s0 = (int64_t)blockIdx.x * n_steps / gridDim.x;
+    const int64_t s1 = (int64_t)(blockIdx.x + 1) * n_steps / gridDim.x;
+    // component 16 t + i of this lane's event of step st, 0 beyond the data:
+    // the address is clamped into the input (n_acc >= 1) and the value
+    // multiplied by 0 or 1, so that every load is used and none is put behind
+    // a branch
+    auto load = [&](double (&x)[T], int64_t st) {
+        const int64_t j = 4 * st + k;
+        const bool ev_ok = st < s1 && j < n_acc;
+        const int64_t jj = ev_ok ? j : 0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int c = 16 * t + i;
+            const int cc = c < 2 * W ? c : 0;
+            const In b = src[jj * W + (cc < W ? cc : cc - W)];
+            const double keep = ev_ok && c < 2 * W ? 1.0 : 0.0;
+            x[t] = (double)(cc < W ? b.x : b.y) * keep;
+        }
+    };
+    auto accumulate = [&](const double (&x)[T]) {
+        int p = 0;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int u = t; u < T; ++u, ++p)
+                d[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t], x[u], d[p], 0, 0, 0);
+    };
+    // this wavefront's steps: first, first + 4, ... below s1, kGramDepth per
+    // trip, each slot of the register ring refilled kGramDepth steps ahead as
+    // soon as it is used (a step past s1 loads zeros)
+    const int64_t first = s0 + wave;
+    const int64_t n_my = first < s1 ? (s1 - first + 3) / 4 : 0;
+    double xs[kGramDepth][T];
+#pragma unroll
+    for (int q = 0; q < kGramDepth; ++q) load(xs[q], first + 4 * q);
+    for (int64_t q0 = 0; q0 < n_my; q0 += kGramDepth) {
+#pragma unroll
+        for (int q = 0; q < kGramDepth; ++q) {
+            accumulate(xs[q]);
+            load(xs[q], first + 4 * (q0 + q + kGramDepth));
+        }
+    }
+
+    // the four wavefronts in order, then the block's record
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int p = 0; p < NPAIR; ++p)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = (p * 4 + r) * 64 + lane;
+                    s_acc[e] = w == 0 ? d[p][r] : s_acc[e] + d[p][r];
+                }
+        }
+        __syncthreads();
+    }
+    double* rec = records + (int64_t)blockIdx.x * NPAIR * 256;
+    for (int e = threadIdx.x; e < NPAIR * 256; e += blockDim.x) rec[e] = s_acc[e];
+}
+
+// tiles of 16 components of the MFMA build (0: W too large, use k_gram)
+int gram_mfma_tiles(int W)
+{
+    const int T = (2 * W + 15) / 16;
+    return T <= kGramMfmaMaxTiles ? T : 0;
+}
+
+// blocks of the matrix-core build: at least 64 steps of 4 events each, up to
+// 512 (two wavefronts per SIMD)
+int gram_mfma_rows(int64_t n_acc)
+{
+    int64_t r = ((n_acc + 3) / 4 + 63) / 64;
+    if (r > kGramMaxRows) r = kGramMaxRows;
+    return (int)(r < 1 ? 1 : r);
+}
+
+int gram_mfma_record(int W)
+{
+    const int T = gram_mfma_tiles(W);
+    return T * (T + 1) / 2 * 256;
+}
+
+hipError_t launch_gram_mfma(const void* mc, bool c128, int64_t n_acc, int W, double* records,
+                            int rows, hipStream_t s, const LaunchEvents& ev)
+{
+    const int T = gram_mfma_tiles(W);
+    const dim3 grid(rows), block(256);
+#define PWA_GRAM_MFMA(C, TT)                                                                     \
+    hipExtLaunchKernelGGL((k_gram_mfma<C, TT>), grid, block, 0, s, ev.start, ev.stop, 0, mc,  \
+                          n_acc, W, records)
+    switch (T) {
+    case 1: if (c128) PWA_GRAM_MFMA(true, 1); else PWA_GRAM_MFMA(false, 1); break;
+    case 2: if (c128) PWA_GRAM_MFMA(true, 2); else PWA_GRAM_MFMA(false, 2); break;
+    case 3: if (c128) PWA_GRAM_MFMA(true, 3); else PWA_GRAM_MFMA(false, 3); break;
+    case 4: if (c128) PWA_GRAM_MFMA(true, 4); else PWA_GRAM_MFMA(false, 4); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef PWA_GRAM_MFMA
+    return hipGetLastError();
+}
+
+// summed Gram tiles -> full Hermitian W x W matrix scaled by 1/N_gen; each
+// element of G is read from its upper-triangle copy, so M is Hermitian and its
+// diagonal real exactly
+__global__ void k_expand_gram(const double* __restrict__ g, int W, int T, double inv_gen,
+                              double2* __restrict__ M)
+{
+    auto G = [&](int r, int c) {
+        if (r > c) {
+            const int x = r;
+            r = c;
+            c = x;
+        }
+        const int t = r >> 4, u = c >> 4;
+        const int p = t * T - t * (t - 1) / 2 + (u - t);
+        const int row = r & 15, col = c & 15;
+        return g[(p * 4 + (row >> 2)) * 64 + (row & 3) * 16 + col];
+    };
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < W * W;
+         idx += gridDim.x * blockDim.x) {
+        const int a = idx / W, b = idx % W;
+        const double re = G(a, b) + G(W + a, W + b);
+        const double im = G(W + a, b) - G(a, W + b);
+        M[idx] = make_double2(re * inv_gen, im * inv_gen);
+    }
+}
+
+hipError_t launch_expand_gram(const double* colsum, int W, int64_t n_gen, double* M,
+                              hipStream_t s)
+{
+    const int total = W * W;
+    hipLaunchKernelGGL(k_expand_gram, dim3((total + 255) / 256), dim3(256), 0, s, colsum, W,
+                       gram_mfma_tiles(W), 1.0 / (double)n_gen, (double2*)M);
     return hipGetLastError();
 }
 

@@ -106,11 +106,14 @@ def test_mc_matrix(form):
 
 
 @pytest.mark.parametrize("c128", [False, True])
-@pytest.mark.parametrize("w,n_acc", [(1, 1), (5, 63), (20, 64), (20, 65), (20, 40_017),
+@pytest.mark.parametrize("w,n_acc", [(1, 1), (5, 63), (8, 1_001), (16, 4_097), (20, 64),
+                                     (20, 65), (20, 40_017), (32, 20_011), (33, 777),
                                      (64, 9_999), (65, 33), (65, 5_000), (128, 2_049)])
 def test_mc_matrix_sizes(c128, w, n_acc):
-    """M over ragged chunk tails, several chunks per block, and the register
-    blocking's 1, 2 and 3 block pairs per thread (W up to 128)."""
+    """M over ragged tails.  W <= 32 runs on the FP64 matrix cores (1 to 4 tiles
+    of 16 components, several blocks and steps per wavefront); wider W on the
+    vector units (several chunks per block, the register blocking's 1, 2 and 3
+    block pairs per thread, W up to 128)."""
     s = synth.small_sample(w, 10, n_acc, seed=500 + w + n_acc)
     m = s.mc if c128 else s.mc.astype(np.complex64)
     model = pwa.Model(s.data.astype(np.complex64), m, 2 * n_acc + 1, form="amplitude")
