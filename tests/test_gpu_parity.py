@@ -108,7 +108,8 @@ def test_mc_matrix(form):
 @pytest.mark.parametrize("c128", [False, True])
 @pytest.mark.parametrize("w,n_acc", [(1, 1), (5, 63), (8, 1_001), (16, 4_097), (20, 64),
                                      (20, 65), (20, 40_017), (32, 20_011), (33, 777),
-                                     (64, 9_999), (65, 33), (65, 5_000), (128, 2_049)])
+                                     (40, 3_001), (48, 10_007), (56, 999), (64, 9_999),
+                                     (65, 33), (65, 5_000), (128, 2_049)])
 def test_mc_matrix_sizes(c128, w, n_acc):
     """M over ragged tails.  W <= 32 runs on the FP64 matrix cores (1 to 4 tiles
     of 16 components, several blocks and steps per wavefront); wider W on the
