@@ -30,7 +30,7 @@ namespace pwa {
 constexpr int kGramMaxRows = 512;  // partial records of the MC matrix build
 constexpr int kGramMaxPairs = 3;   // block pairs per thread: nb(nb+1)/2 <= 768, W <= 152
 constexpr int kGramPre = 16;       // staged elements per thread and chunk (E x 4nb <= 4096)
-constexpr int kGramMfmaMaxTiles = 4;   // matrix-core build for 2W <= 64
+constexpr int kGramMfmaMaxTiles = 8;   // matrix-core build for 2W <= 128
 constexpr int kGramDepth = 8;          // steps of loads in flight per wavefront
 
 // events per chunk: as many as kGramPre elements per thread stage, in steps of 16
@@ -215,7 +215,7 @@ hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, double* 
     return hipGetLastError();
 }
 
-// ---- the MC integral on the FP64 matrix cores (2W <= 64) ------------------
+// ---- the MC integral on the FP64 matrix cores (2W <= 128) -----------------
 // The real Gram matrix G = sum_j x_j x_j^T of x_j = [Re B_j0 .. Re B_j,W-1,
 // Im B_j0 .. Im B_j,W-1] (zero padded to 16 T) holds the Hermitian sum:
 //   sum_j B_ja conj(B_jb) = G[a][b] + G[W+a][W+b] + i (G[W+a][b] - G[a][W+b]).
@@ -308,7 +308,121 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const void* __restrict__ mc, 
     for (int e = threadIdx.x; e < NPAIR * 256; e += blockDim.x) rec[e] = s_acc[e];
 }
 
-// tiles of 16 components of the MFMA build (0: W too large, use k_gram)
+// Wider rows (5 to 8 tiles, 2W <= 128): the tile pairs no longer fit one
+// wavefront's registers, so each of the block's four wavefronts owns a fixed
+// range of pairs (at most 9) and runs over every step of the block's range.
+// The events are staged through LDS in chunks of kGramLdsEvents (one row of
+// 16 T doubles per event, [Re B | Im B | 0]), loaded once per block with
+// contiguous loads, the next chunk's in flight while one is used; each
+// wavefront reads its tiles' values from LDS.  Every pair has one owner,
+// which writes its tiles straight into the block's record.
+constexpr int kGramLdsEvents = 32;
+
+template <bool C128, int T>
+__global__ __launch_bounds__(256, 2) void k_gram_mfma_lds(const void* __restrict__ mc,
+                                                       int64_t n_acc, int W,
+                                                       double* __restrict__ records)
+{
+    constexpr int NPAIR = T * (T + 1) / 2;
+    constexpr int PPW = (NPAIR + 3) / 4;               // pairs per wavefront
+    constexpr int XW = 16 * T;                         // LDS row (doubles)
+    constexpr int E = kGramLdsEvents;
+    constexpr int PRE = E * 64 / 256;                  // staged elements per thread (W <= 64)
+    using In = typename std::conditional<C128, double2, float2>::type;
+    const In* src = reinterpret_cast<const In*>(mc);
+    __shared__ double s_x[E * XW];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int i = lane & 15, k = lane >> 4;
+    const int64_t n_ch = (n_acc + E - 1) / E;
+    const int64_t c0 = (int64_t)blockIdx.x * n_ch / gridDim.x;
+    const int64_t c1 = (int64_t)(blockIdx.x + 1) * n_ch / gridDim.x;
+    const int n_el = E * W;
+
+    // the padding columns 2W .. 16 T stay zero
+    for (int e = tid; e < E * XW; e += 256) s_x[e] = 0.0;
+    In pre[PRE];
+    // element tid + 256 q of the chunk (event idx / W, wave idx % W); the
+    // address is clamped into the input (n_acc >= 1) and the value
+    // multiplied by 0 or 1, so that no load is put behind a branch
+    auto load_chunk = [&](int64_t c) {
+        const int64_t j0 = c * E;
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) {
+            const int idx = tid + 256 * q;
+            const int j = idx / W, a = idx - j * W;
+            const bool ok = idx < n_el && j0 + j < n_acc;
+            const In b = src[ok ? (j0 + j) * W + a : 0];
+            const auto keep = ok ? 1.0f : 0.0f;
+            pre[q].x = b.x * keep;
+            pre[q].y = b.y * keep;
+        }
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) {
+            const int idx = tid + 256 * q;
+            if (idx < n_el) {
+                const int j = idx / W, a = idx - j * W;
+                s_x[j * XW + a] = (double)pre[q].x;
+                s_x[j * XW + W + a] = (double)pre[q].y;
+            }
+        }
+    };
+    gd4 d[PPW];
+#pragma unroll
+    for (int q = 0; q < PPW; ++q) d[q] = gd4{0.0, 0.0, 0.0, 0.0};
+    // this wavefront's pairs P0 .. P0 + NP - 1 (pairs t <= u in row-major
+    // order) over the staged chunk; every index a constant once unrolled
+    auto compute = [&](auto wv) {
+        constexpr int P0 = decltype(wv)::value * PPW;
+        constexpr int NP = (NPAIR - P0) < PPW ? (NPAIR - P0) : PPW;
+        for (int st = 0; st < E / 4; ++st) {
+            double x[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) x[t] = s_x[(4 * st + k) * XW + 16 * t + i];
+            int p = 0;
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int u = t; u < T; ++u, ++p)
+                    if (p >= P0 && p < P0 + NP)
+                        d[p - P0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t], x[u], d[p - P0],
+                                                                         0, 0, 0);
+        }
+    };
+    auto write = [&](auto wv) {
+        constexpr int P0 = decltype(wv)::value * PPW;
+        constexpr int NP = (NPAIR - P0) < PPW ? (NPAIR - P0) : PPW;
+        double* rec = records + (int64_t)blockIdx.x * NPAIR * 256;
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) rec[((P0 + pp) * 4 + r) * 64 + lane] = d[pp][r];
+    };
+    if (c0 < c1) load_chunk(c0);
+    for (int64_t c = c0; c < c1; ++c) {
+        __syncthreads();   // the previous chunk's reads (and the zeroing) done
+        store_chunk();
+        __syncthreads();
+        if (c + 1 < c1) load_chunk(c + 1);
+        switch (wave) {
+        case 0: compute(std::integral_constant<int, 0>{}); break;
+        case 1: compute(std::integral_constant<int, 1>{}); break;
+        case 2: compute(std::integral_constant<int, 2>{}); break;
+        default: compute(std::integral_constant<int, 3>{}); break;
+        }
+    }
+    switch (wave) {
+    case 0: write(std::integral_constant<int, 0>{}); break;
+    case 1: write(std::integral_constant<int, 1>{}); break;
+    case 2: write(std::integral_constant<int, 2>{}); break;
+    default: write(std::integral_constant<int, 3>{}); break;
+    }
+}
+
+// tiles of 16 components of the MFMA build (0: W too large, use k_gram);
+// up to 4 tiles k_gram_mfma, 5 to 8 k_gram_mfma_lds
 int gram_mfma_tiles(int W)
 {
     const int T = (2 * W + 15) / 16;
@@ -338,14 +452,22 @@ hipError_t launch_gram_mfma(const void* mc, bool c128, int64_t n_acc, int W, dou
 #define PWA_GRAM_MFMA(C, TT)                                                                     \
     hipExtLaunchKernelGGL((k_gram_mfma<C, TT>), grid, block, 0, s, ev.start, ev.stop, 0, mc,  \
                           n_acc, W, records)
+#define PWA_GRAM_LDS(C, TT)                                                                      \
+    hipExtLaunchKernelGGL((k_gram_mfma_lds<C, TT>), grid, block, 0, s, ev.start, ev.stop, 0,  \
+                          mc, n_acc, W, records)
     switch (T) {
     case 1: if (c128) PWA_GRAM_MFMA(true, 1); else PWA_GRAM_MFMA(false, 1); break;
     case 2: if (c128) PWA_GRAM_MFMA(true, 2); else PWA_GRAM_MFMA(false, 2); break;
     case 3: if (c128) PWA_GRAM_MFMA(true, 3); else PWA_GRAM_MFMA(false, 3); break;
     case 4: if (c128) PWA_GRAM_MFMA(true, 4); else PWA_GRAM_MFMA(false, 4); break;
+    case 5: if (c128) PWA_GRAM_LDS(true, 5); else PWA_GRAM_LDS(false, 5); break;
+    case 6: if (c128) PWA_GRAM_LDS(true, 6); else PWA_GRAM_LDS(false, 6); break;
+    case 7: if (c128) PWA_GRAM_LDS(true, 7); else PWA_GRAM_LDS(false, 7); break;
+    case 8: if (c128) PWA_GRAM_LDS(true, 8); else PWA_GRAM_LDS(false, 8); break;
     default: return hipErrorInvalidValue;
     }
 #undef PWA_GRAM_MFMA
+#undef PWA_GRAM_LDS
     return hipGetLastError();
 }
 

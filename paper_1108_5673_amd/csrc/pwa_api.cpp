@@ -263,7 +263,7 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
 
     // ---- MC matrix ----
     HIP_TRY(hipMalloc(&m->d_M, sizeof(double) * 2 * W * W));
-    // the MC integral: on the FP64 matrix cores (real Gram tiles) for 2W <= 64,
+    // the MC integral: on the FP64 matrix cores (real Gram tiles) for 2W <= 128,
     // else register-blocked on the vector units (packed Hermitian records)
     const bool gram_mc = pwa::gram_mfma_tiles(W) > 0;
     const int grec = gram_mc ? pwa::gram_mfma_record(W) : 2 * P;

@@ -218,7 +218,7 @@ hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, double* 
 hipError_t launch_expand_m(const double* packed_colsum, int W, int64_t n_gen, double* M,
                            hipStream_t s);
 int gram_rows(int64_t n_acc, int W);
-// the MC integral on the FP64 matrix cores, for 2W <= 64: records of
+// the MC integral on the FP64 matrix cores, for 2W <= 128: records of
 // gram_mfma_record(W) doubles per block, summed by k_colsum, then expanded
 int gram_mfma_tiles(int W);   // 0 when W is too large
 int gram_mfma_record(int W);

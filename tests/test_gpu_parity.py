@@ -111,10 +111,12 @@ def test_mc_matrix(form):
                                      (40, 3_001), (48, 10_007), (56, 999), (64, 9_999),
                                      (65, 33), (65, 5_000), (128, 2_049)])
 def test_mc_matrix_sizes(c128, w, n_acc):
-    """M over ragged tails.  W <= 32 runs on the FP64 matrix cores (1 to 4 tiles
-    of 16 components, several blocks and steps per wavefront); wider W on the
-    vector units (several chunks per block, the register blocking's 1, 2 and 3
-    block pairs per thread, W up to 128)."""
+    """M over ragged tails.  W <= 64 runs on the FP64 matrix cores: 1 to 4 tiles
+    of 16 components with every tile pair in one wavefront (several blocks and
+    steps per wavefront), 5 to 8 with the pairs split over the block's
+    wavefronts and the events staged through LDS (ragged chunks); wider W on
+    the vector units (several chunks per block, the register blocking's 1, 2
+    and 3 block pairs per thread, W up to 128)."""
     s = synth.small_sample(w, 10, n_acc, seed=500 + w + n_acc)
     m = s.mc if c128 else s.mc.astype(np.complex64)
     model = pwa.Model(s.data.astype(np.complex64), m, 2 * n_acc + 1, form="amplitude")
