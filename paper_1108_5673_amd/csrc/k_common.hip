@@ -225,11 +225,12 @@ hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, double* 
 // of 4 events.  Lane l takes event k = l / 16 of the step and component
 // i = l % 16 of every tile, which is where both operands expect x_k[16 t + i]
 // (A[i][k] and B[k][j] in lane i + 16 k; D[4 r + l / 16][l % 16] in register
-// r).  The four wavefronts of a block take every fourth step of the block's
-// range, with the values of the next kGramDepth steps in flight (the memory
-// latency is several steps of matrix work), and are added in wavefront order
-// through LDS into one record of T (T + 1) / 2 tiles of 256 doubles, in
-// register-major order [tile][r][lane].
+// r).  Up to 4 tiles (k_gram_mfma), every tile pair fits one wavefront: the
+// four wavefronts of a block take every fourth step of the block's range,
+// with the values of the next kGramDepth steps in flight (the memory latency
+// is several steps of matrix work), and are added in wavefront order through
+// LDS into one record of T (T + 1) / 2 tiles of 256 doubles, in
+// register-major order [tile][r][lane].  Wider rows: k_gram_mfma_lds below.
 typedef double gd4 __attribute__((ext_vector_type(4)));
 
 template <bool C128, int T>
