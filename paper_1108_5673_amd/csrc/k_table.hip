@@ -62,9 +62,9 @@ __device__ inline double2 source_entry(const void* src, bool src_is_table, bool 
 }
 
 // One thread per stored 16-byte vector (the EV events of one entry that share
-// it), one tile per block at a time: consecutive threads write consecutive
-// vectors, so a wavefront stores 1 KB contiguous (non-temporal: the table is
-// not read back by this kernel).  From amplitudes, the tile's 16 events are
+// it), one tile per block at a time: the lanes of a wavefront write the
+// consecutive vectors of one (slot, vector) pair, so a wavefront stores up to
+// 1 KB contiguous (non-temporal: the table is not read back by this kernel).  From amplitudes, the tile's 16 events are
 // first staged in LDS in FP64 and the pair list is kept in LDS.
 constexpr int kPackMaxW = PWA_MAX_WAVES_TABLE;
 __global__ __launch_bounds__(256) void k_pack_tiled(const void* __restrict__ src,
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(256) void k_pack_tiled(const void* __restrict__ src
     const int ev = store_c128 ? 1 : 2;           // events per vector
     const int nvec = kTileEvents / ev;           // vectors per entry and tile
     const int per_tile = P * nvec;               // vectors per tile
+    const int nslot = (P + 63) / 64;             // slots of 64 entries
     if (!src_is_table)
         for (int e = threadIdx.x; e < P; e += blockDim.x) s_pair[e] = pairs[e];
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
@@ -92,11 +93,17 @@ __global__ __launch_bounds__(256) void k_pack_tiled(const void* __restrict__ src
             __syncthreads();
         }
         char* tb = reinterpret_cast<char*>(dst) + t * (int64_t)per_tile * 16;
-        for (int o = threadIdx.x; o < per_tile; o += blockDim.x) {
-            const int k = o / (64 * nvec);       // slot
-            const int r = o - k * 64 * nvec;
+        // wavefront w takes the (slot, vector) pairs w, w + 4, ... of the tile,
+        // lane l entry 64 slot + l of it (the slot's nk entries are nk
+        // consecutive vectors): the index arithmetic is per wavefront
+        const int lane = threadIdx.x & 63;
+        const int nwave = blockDim.x >> 6;
+        for (int kv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); kv < nslot * nvec;
+             kv += nwave) {
+            const int k = kv / nvec, v = kv - k * nvec;   // slot, vector
             const int nk = (P - 64 * k) < 64 ? (P - 64 * k) : 64;
-            const int v = r / nk, lane = r - v * nk;
+            if (lane >= nk) continue;
+            const int o = k * 64 * nvec + v * nk + lane;
             const int e = 64 * k + lane;
             const int j0 = v * ev;               // first event of the vector in the tile
             double2 t0, t1 = make_double2(0.0, 0.0);
