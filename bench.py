@@ -413,12 +413,35 @@ def main():
     t = time.perf_counter()
     v_fu, fu = pwa_fit.fit_fumili(amp, v0)
     fu_s = time.perf_counter() - t
-    amp.close()
     fit_info["fumili"] = {"status": fu["message"], "iterations": fu["iterations"],
                           "evaluations": fu["evaluations"], "seconds": fu_s, "nll": fu["f"],
                           "grad_norm": fu["grad_norm"], "form": "amplitude (complex64)"}
     log("FUMILI fit from the same start: %s after %d iterations, %.3f s"
         % (fu["message"], fu["iterations"], fu_s))
+    # one NLL + gradient + FUMILI matrix call at the start point, and the
+    # oracle's matrix on the same stored amplitudes beside it
+    for _ in range(3):
+        amp.nll_grad_hess(v0)
+    reps = 20
+    t = time.perf_counter()
+    for _ in range(reps):
+        _, _, h_gpu = amp.nll_grad_hess(v0)
+    call_s = (time.perf_counter() - t) / reps
+    fm = {"call_us": 1e6 * call_s, "sample": "V = the fit's start, all 1M events, W = 20"}
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.get()
+        t = time.perf_counter()
+        h_or, _ = o.fumili_amp(d32.astype(np.complex128), v0)
+        fm["oracle_s"] = time.perf_counter() - t
+        fm["oracle_cores"] = o.num_threads()
+        fm["rel_frobenius_vs_oracle"] = float(np.linalg.norm(h_gpu - h_or) / np.linalg.norm(h_or))
+    fit_info["fumili_matrix"] = fm
+    log("NLL + gradient + FUMILI matrix: %.1f us per call%s"
+        % (fm["call_us"], "" if "oracle_s" not in fm else
+           "; oracle matrix %.2f s on %d threads, rel. difference %.1e"
+           % (fm["oracle_s"], fm["oracle_cores"], fm["rel_frobenius_vs_oracle"])))
+    amp.close()
 
     out = {}
     if not args.no_baselines:
