@@ -608,11 +608,114 @@ __device__ inline double2 v_times_m(const double* v, const double2* M, int W, in
     return make_double2(vr * x.x - vi * x.y, vr * x.y + vi * x.x);
 }
 
-// One assembly block: role 0 forms the NLL, role 1 + b the gradient component
-// b; V (2W doubles) at v; ends by publishing in `word`.
+// Block sums of four values in a fixed order (butterflies in each wavefront,
+// then the wavefront sums in wave order), with one LDS round.
+__device__ inline double4 block_sum4(double4 x)
+{
+    __shared__ double4 s_w[kAssembleThreads / 64];
+    x.x = wave_allsum(x.x);
+    x.y = wave_allsum(x.y);
+    x.z = wave_allsum(x.z);
+    x.w = wave_allsum(x.w);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        r.x += s_w[w].x;
+        r.y += s_w[w].y;
+        r.z += s_w[w].z;
+        r.w += s_w[w].w;
+    }
+    return r;
+}
+
+// One assembly block over records [sum ln I, n_bad, x_0, ..., x_{W-1}] (x_b
+// complex: u_b = sum_a V_a U_ab of the table forms, or g_b of the amplitude
+// form; both enter as G_b = 2 (m_b - x_b)).  Role 0 forms the NLL and n_bad,
+// role 1 + b the gradient component b.  Every thread issues all of its loads
+// (its records in batches of kBatch, its share of M) before adding any, so
+// that the whole block waits about one memory round trip.
+__device__ void assemble_role_g(const double* v, const TailArgs& ta, int role,
+                                unsigned long long* word)
+{
+    const int W = ta.W;
+    const int NT = blockDim.x;
+    const int col = role == 0 ? 0 : 2 * role;   // record column of this role
+    const int b = role - 1;
+    // M entries of this thread: role 0 all of M (pairs k = a W + b'), role
+    // 1 + b column b (k = a); loaded with the first batch of records
+    const int n_m = role == 0 ? W * W : W;
+    constexpr int kMaxM = 4;
+    double2 mv[kMaxM];
+#pragma unroll
+    for (int q = 0; q < kMaxM; ++q) {
+        const int k = threadIdx.x + q * NT;
+        mv[q] = k < n_m ? ta.M[role == 0 ? k : k * W + b] : make_double2(0.0, 0.0);
+    }
+    double2 acc = make_double2(0.0, 0.0);
+    const double* base = ta.rec + col;
+    for (int r0 = threadIdx.x; r0 < ta.rows; r0 += kBatch * NT) {
+        double2 x[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int row = r0 + k * NT;
+            x[k] = row < ta.rows
+                       ? *reinterpret_cast<const double2*>(base + (int64_t)row * ta.rec_len)
+                       : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            acc.x += x[k].x;
+            acc.y += x[k].y;
+        }
+    }
+    // the MC term of this thread: role 0 its part of mu = sum Re(conj(V_b') V_a
+    // M_ab'); role 1 + b its part of m_b = sum_a V_a M_ab (the rest of M, for
+    // W^2 > kMaxM NT, loaded here)
+    double2 mt = make_double2(0.0, 0.0);
+    auto add_m = [&](int k, double2 x) {
+        const int a = role == 0 ? k / W : k;
+        const double vr = v[2 * a], vi = v[2 * a + 1];
+        const double tr = vr * x.x - vi * x.y, ti = vr * x.y + vi * x.x;   // V_a M_ab'
+        if (role == 0) {
+            const int bb = k % W;
+            mt.x += v[2 * bb] * tr + v[2 * bb + 1] * ti;
+        } else {
+            mt.x += tr;
+            mt.y += ti;
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < kMaxM; ++q)
+        if (threadIdx.x + q * NT < n_m) add_m(threadIdx.x + q * NT, mv[q]);
+    for (int k = threadIdx.x + kMaxM * NT; k < n_m; k += NT)
+        add_m(k, ta.M[role == 0 ? k : k * W + b]);
+    const double4 tot = block_sum4(make_double4(acc.x, acc.y, mt.x, mt.y));
+    if (threadIdx.x == 0) {
+        if (role == 0) {
+            // tot.x = sum ln I, tot.y = n_bad, tot.z = mu
+            store_system(ta.out, tot.y > 0.0 ? INFINITY : (-tot.x + tot.z));
+            store_system(ta.out + 1, tot.y);
+        } else {
+            // a degenerate event made its records' entries NaN, and so G_b
+            store_system(ta.out + 2 + 2 * b, 2.0 * (tot.z - tot.x));
+            store_system(ta.out + 3 + 2 * b, 2.0 * (tot.w - tot.y));
+        }
+    }
+    publish(word, ta.seq);
+}
+
+// One assembly block over packed-U records [sum ln I, n_bad, U_e (2P)] (the
+// plain FP64 form): role 0 forms the NLL, role 1 + b the gradient component b
+// from the W packed entries of its row and column; V (2W doubles) at v; ends
+// by publishing in `word`.
 __device__ void assemble_role(const double* v, const TailArgs& ta, int role,
                               unsigned long long* word)
 {
+    if (ta.g_records) {
+        assemble_role_g(v, ta, role, word);
+        return;
+    }
     __shared__ double s_wave[kAssembleThreads / 64];
     __shared__ double2 s_acc[kAssembleThreads];
     const int W = ta.W;
@@ -638,9 +741,9 @@ __device__ void assemble_role(const double* v, const TailArgs& ta, int role,
     }
     const int b = role - 1;
     // the entries this gradient component needs: U_ab for all a (packed row and
-    // column of b) or g_b; thread t works on entry a = t % nent over the record
-    // range t / nent, and the ranges are added in order
-    const int nent = ta.g_records ? 1 : W;
+    // column of b); thread t works on entry a = t % W over the record range
+    // t / W, and the ranges are added in order
+    const int nent = W;
     const int chunks = kAssembleThreads / nent;
     const int a = threadIdx.x % nent;
     const int ch = threadIdx.x / nent;
@@ -648,9 +751,7 @@ __device__ void assemble_role(const double* v, const TailArgs& ta, int role,
     if (ch < chunks) {
         int col;
         double sgn = 1.0;
-        if (ta.g_records) {
-            col = 2 + 2 * b;
-        } else if (a <= b) {
+        if (a <= b) {
             col = 2 + 2 * packed_index(W, a, b);
         } else {
             col = 2 + 2 * packed_index(W, b, a);   // U_ab = conj(U_ba)
@@ -672,14 +773,9 @@ __device__ void assemble_role(const double* v, const TailArgs& ta, int role,
                 xr += s_acc[c * nent + l].x;
                 xi += s_acc[c * nent + l].y;
             }
-            if (ta.g_records) {
-                ur = xr;
-                ui = xi;
-            } else {
-                const double vr = v[2 * l], vi = v[2 * l + 1];
-                ur = vr * xr - vi * xi;
-                ui = vr * xi + vi * xr;
-            }
+            const double vr = v[2 * l], vi = v[2 * l + 1];
+            ur = vr * xr - vi * xi;
+            ui = vr * xi + vi * xr;
         }
         for (int aa = l; aa < W; aa += 64) {
             const double2 t = v_times_m(v, ta.M, W, aa, b);

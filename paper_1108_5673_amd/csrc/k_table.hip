@@ -2,16 +2,21 @@
 // precomputed because masses and widths are fixed) and the fused one-pass
 // NLL + gradient kernel that streams it on every fit iteration (Eq. 3).
 //
+// Stored entries.  T_i is Hermitian, so only the upper triangle is kept and
+// its real diagonal is stored in pairs of real values (see kDiagPair in
+// pwa_internal.h): ps = ceil(W/2) + W(W-1)/2 complex entries per event (200
+// at W = 20, 1600 bytes per event in complex64).
+//
 // Tiled layout (chosen for the streaming kernel).  A tile holds kTileEvents
-// consecutive events.  Its P packed entries are cut into slots of 64 entries:
-// slot k holds entries 64k .. 64k + n_k - 1, n_k = min(64, P - 64k).  Inside a
-// slot the 16-byte vectors are ordered [vector v][lane], lane = e mod 64, and
-// one vector holds EV = 16 / esz consecutive events of one entry (EV = 2 for
-// complex64, 1 for complex128).  One wavefront load instruction therefore
-// reads 64 x 16 = 1024 contiguous bytes (n_k x 16 in the last slot), lane l
-// always receives entry 64k + l, and a wave's tile is one contiguous block of
-// P * kTileEvents * esz bytes.  The table is not padded in the entry
-// direction; only the last tile is padded with zero events.
+// consecutive events.  Its ps stored entries are cut into slots of 64
+// entries: slot k holds entries 64k .. 64k + n_k - 1, n_k = min(64, ps - 64k).
+// Inside a slot the 16-byte vectors are ordered [vector v][lane], lane = e mod
+// 64, and one vector holds EV = 16 / esz consecutive events of one entry (EV =
+// 2 for complex64, 1 for complex128).  One wavefront load instruction
+// therefore reads 64 x 16 = 1024 contiguous bytes (n_k x 16 in the last
+// slot), lane l always receives entry 64k + l, and a wave's tile is one
+// contiguous block of ps * kTileEvents * esz bytes.  The table is not padded
+// in the entry direction; only the last tile is padded with zero events.
 #include <hip/hip_runtime.h>
 
 #include "pwa_internal.h"
@@ -48,40 +53,58 @@ __device__ inline double2 load_c(const void* p, int64_t idx, bool c128)
     return make_double2((double)f.x, (double)f.y);
 }
 
-// Entry (i, e) of the table built from amplitudes, or copied from a canonical
-// packed source table.
-__device__ inline double2 source_entry(const void* src, bool src_is_table, bool c128, int64_t i,
-                                       int e, int W, int P, const uint32_t* pairs)
-{
-    if (src_is_table) return load_c(src, i * P + e, c128);
-    const uint32_t pr = pairs[e];
-    const int a = (int)(pr & 0xffffu), b = (int)(pr >> 16);
-    const double2 x = load_c(src, i * W + a, c128);
-    const double2 y = load_c(src, i * W + b, c128);
-    return herm_product(x.x, x.y, y.x, y.y);
-}
-
 // One thread per stored 16-byte vector (the EV events of one entry that share
 // it), one tile per block at a time: the lanes of a wavefront write the
 // consecutive vectors of one (slot, vector) pair, so a wavefront stores up to
-// 1 KB contiguous (non-temporal: the table is not read back by this kernel).  From amplitudes, the tile's 16 events are
-// first staged in LDS in FP64 and the pair list is kept in LDS.
+// 1 KB contiguous (non-temporal: the table is not read back by this kernel).
+// From amplitudes, the tile's 16 events are first staged in LDS in FP64; the
+// entry descriptors are kept in LDS.  Off the diagonal an entry is
+// T_ab = A_a conj(A_b); a diagonal pair holds (|A_a|^2, |A_a2|^2), each formed
+// exactly as the real part of the same product.  From a canonical packed
+// table, the entries are copied (a diagonal pair takes the real parts of
+// T_aa and T_a2a2).
 constexpr int kPackMaxW = PWA_MAX_WAVES_TABLE;
 __global__ __launch_bounds__(256) void k_pack_tiled(const void* __restrict__ src,
                                                     bool src_is_table, bool src_c128, int64_t n,
-                                                    int W, int P,
-                                                    const uint32_t* __restrict__ pairs,
+                                                    int W, int ps,
+                                                    const uint32_t* __restrict__ slots,
                                                     bool store_c128, int64_t n_tiles,
                                                     void* __restrict__ dst)
 {
     __shared__ double2 s_a[kTileEvents * kPackMaxW];
-    __shared__ uint32_t s_pair[kPackMaxW * (kPackMaxW + 1) / 2];
+    __shared__ uint32_t s_desc[kPackMaxW / 2 + kPackMaxW * (kPackMaxW - 1) / 2];
     const int ev = store_c128 ? 1 : 2;           // events per vector
     const int nvec = kTileEvents / ev;           // vectors per entry and tile
-    const int per_tile = P * nvec;               // vectors per tile
-    const int nslot = (P + 63) / 64;             // slots of 64 entries
-    if (!src_is_table)
-        for (int e = threadIdx.x; e < P; e += blockDim.x) s_pair[e] = pairs[e];
+    const int per_tile = ps * nvec;              // vectors per tile
+    const int nslot = (ps + 63) / 64;            // slots of 64 entries
+    const int P = W * (W + 1) / 2;               // canonical entries of a source table
+    for (int e = threadIdx.x; e < ps; e += blockDim.x) s_desc[e] = slots[e];
+    __syncthreads();
+    // entry e of event j of the tile (zero for padding events)
+    auto entry = [&](int64_t ibase, int j, int e) -> double2 {
+        const uint32_t d = s_desc[e];
+        const int a = (int)(d & 0xffffu), b = (int)((d >> 16) & kNoWave);
+        if (src_is_table) {
+            const int64_t i = ibase + j;
+            if (i >= n) return make_double2(0.0, 0.0);
+            if (d & kDiagPair)
+                return make_double2(load_c(src, i * P + packed_index(W, a, a), src_c128).x,
+                                    b < W ? load_c(src, i * P + packed_index(W, b, b), src_c128).x
+                                          : 0.0);
+            return load_c(src, i * P + packed_index(W, a, b), src_c128);
+        }
+        const double2 x = s_a[j * W + a];
+        if (d & kDiagPair) {
+            double im = 0.0;
+            if (b < W) {
+                const double2 y = s_a[j * W + b];
+                im = herm_product(y.x, y.y, y.x, y.y).x;
+            }
+            return make_double2(herm_product(x.x, x.y, x.x, x.y).x, im);
+        }
+        const double2 y = s_a[j * W + b];
+        return herm_product(x.x, x.y, y.x, y.y);
+    };
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const int64_t ibase = t * kTileEvents;
         if (!src_is_table) {
@@ -101,27 +124,13 @@ __global__ __launch_bounds__(256) void k_pack_tiled(const void* __restrict__ src
         for (int kv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); kv < nslot * nvec;
              kv += nwave) {
             const int k = kv / nvec, v = kv - k * nvec;   // slot, vector
-            const int nk = (P - 64 * k) < 64 ? (P - 64 * k) : 64;
+            const int nk = (ps - 64 * k) < 64 ? (ps - 64 * k) : 64;
             if (lane >= nk) continue;
             const int o = k * 64 * nvec + v * nk + lane;
             const int e = 64 * k + lane;
             const int j0 = v * ev;               // first event of the vector in the tile
-            double2 t0, t1 = make_double2(0.0, 0.0);
-            if (src_is_table) {
-                t0 = ibase + j0 < n ? load_c(src, (ibase + j0) * P + e, src_c128)
-                                    : make_double2(0.0, 0.0);
-                if (ev == 2 && ibase + j0 + 1 < n)
-                    t1 = load_c(src, (ibase + j0 + 1) * P + e, src_c128);
-            } else {
-                const uint32_t pr = s_pair[e];
-                const int a = (int)(pr & 0xffffu), b = (int)(pr >> 16);
-                const double2 x0 = s_a[j0 * W + a], y0 = s_a[j0 * W + b];
-                t0 = herm_product(x0.x, x0.y, y0.x, y0.y);
-                if (ev == 2) {
-                    const double2 x1 = s_a[(j0 + 1) * W + a], y1 = s_a[(j0 + 1) * W + b];
-                    t1 = herm_product(x1.x, x1.y, y1.x, y1.y);
-                }
-            }
+            const double2 t0 = entry(ibase, j0, e);
+            const double2 t1 = ev == 2 ? entry(ibase, j0 + 1, e) : make_double2(0.0, 0.0);
             if (store_c128) {
                 typedef double d2v __attribute__((ext_vector_type(2)));
                 d2v q = {t0.x, t0.y};
@@ -135,18 +144,46 @@ __global__ __launch_bounds__(256) void k_pack_tiled(const void* __restrict__ src
     }
 }
 
-__global__ void k_unpack_tiled(const void* __restrict__ src, bool c128, int64_t n, int P,
-                               void* __restrict__ dst)
+// Diagonal entries of a canonical packed source table whose imaginary part is
+// not zero (or not a number): a Hermitian table has none.
+__global__ void k_check_table_diag(const void* __restrict__ src, bool c128, int64_t n, int W,
+                                   unsigned long long* __restrict__ count)
+{
+    const int P = W * (W + 1) / 2;
+    const int64_t total = n * W;
+    unsigned long long bad = 0;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = g / W;
+        const int a = (int)(g % W);
+        const double im = load_c(src, i * P + packed_index(W, a, a), c128).y;
+        if (!(im == 0.0)) ++bad;
+    }
+    bad = (unsigned long long)wave_allsum_int((int)bad);
+    if ((threadIdx.x & 63) == 0 && bad) atomicAdd(count, bad);
+}
+
+// The canonical packed table (N x P, complex, entries a <= b in row-major
+// order) from the tiled store; a diagonal entry comes back with a zero
+// imaginary part.
+__global__ void k_unpack_tiled(const void* __restrict__ src, bool c128, int64_t n, int W,
+                               const uint32_t* __restrict__ pairs, void* __restrict__ dst)
 {
     const int esz = c128 ? 16 : 8;
+    const int P = W * (W + 1) / 2;
+    const int ps = tiled_entries(W);
     const int64_t total = n * P;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
          g += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = g / P;
-        const int e = (int)(g % P);
-        const char* s = reinterpret_cast<const char*>(src) + tiled_offset(i, e, P, esz);
-        if (c128) reinterpret_cast<double2*>(dst)[g] = *reinterpret_cast<const double2*>(s);
-        else reinterpret_cast<float2*>(dst)[g] = *reinterpret_cast<const float2*>(s);
+        const uint32_t pr = pairs[g % P];
+        const int a = (int)(pr & 0xffffu), b = (int)(pr >> 16);
+        const int se = a == b ? a / 2 : tiled_offdiag_index(W, a, b);
+        const char* s = reinterpret_cast<const char*>(src) + tiled_offset(i, se, ps, esz);
+        double2 x = load_c(s, 0, c128);
+        if (a == b) x = make_double2((a & 1) ? x.y : x.x, 0.0);
+        if (c128) reinterpret_cast<double2*>(dst)[g] = x;
+        else reinterpret_cast<float2*>(dst)[g] = make_float2((float)x.x, (float)x.y);
     }
 }
 
@@ -158,12 +195,20 @@ static int grid_for(int64_t total, int block)
 }
 
 hipError_t launch_pack_tiled(const void* src, bool src_is_table, bool src_c128, int64_t n,
-                             int W, int P, const uint32_t* pairs, bool store_c128,
+                             int W, int ps, const uint32_t* slots, bool store_c128,
                              int64_t n_tiles, void* dst, hipStream_t s, const LaunchEvents& ev)
 {
     const int64_t g = n_tiles < 4096 ? (n_tiles < 1 ? 1 : n_tiles) : 4096;
     hipExtLaunchKernelGGL(k_pack_tiled, dim3((int)g), dim3(256), 0, s, ev.start, ev.stop, 0, src,
-                          src_is_table, src_c128, n, W, P, pairs, store_c128, n_tiles, dst);
+                          src_is_table, src_c128, n, W, ps, slots, store_c128, n_tiles, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_table_diag(const void* src, bool c128, int64_t n, int W,
+                                   unsigned long long* count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_table_diag, dim3(grid_for(n * W, 256)), dim3(256), 0, s, src, c128,
+                       n, W, count);
     return hipGetLastError();
 }
 
@@ -235,11 +280,11 @@ hipError_t launch_stream_read(const void* p, int64_t bytes, uint32_t* sink, int 
     return hipGetLastError();
 }
 
-hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, void* dst,
-                               hipStream_t s)
+hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int W,
+                               const uint32_t* pairs, void* dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_unpack_tiled, dim3(grid_for(n * P, 256)), dim3(256), 0, s, src, c128,
-                       n, P, dst);
+    hipLaunchKernelGGL(k_unpack_tiled, dim3(grid_for(n * (W * (W + 1) / 2), 256)), dim3(256), 0,
+                       s, src, c128, n, W, pairs, dst);
     return hipGetLastError();
 }
 
@@ -260,8 +305,10 @@ hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, voi
 //   5. broadcasts w_i through scalar registers and accumulates, from the
 //      registers loaded in step 1, U_e += w_i T_ie (FP64), the data part of
 //      the gradient; the table is read from memory exactly once.
-// At the end the wavefronts of a block are combined in LDS in a fixed order
-// and the block writes one partial record [sum ln I, n_bad, U_e...].
+// At the end the wavefronts of a block are combined in LDS in a fixed order,
+// the block contracts its U with V, u_b = sum_a V_a U_ab (U_ab = conj(U_ba),
+// the diagonal from the stored pairs), and writes one partial record
+// [sum ln I, n_bad, u_0, ..., u_{W-1}] (2 + 2W doubles).
 // ---------------------------------------------------------------------------
 template <typename S> struct Vec16;
 template <> struct Vec16<float> {
@@ -412,10 +459,50 @@ constexpr int fused_threads()
     else return (K == 2 && E == 4) ? 1024 : 256;
 }
 
+// U_ab of the block's U (stored entries in LDS): off the diagonal the stored
+// entry or its conjugate, on it one part of a stored pair.
+__device__ inline double2 u_entry(const double2* s_ue, int W, int a, int b)
+{
+    if (a == b) {
+        const double2 x = s_ue[a >> 1];
+        return make_double2((a & 1) ? x.y : x.x, 0.0);
+    }
+    if (a < b) return s_ue[tiled_offdiag_index(W, a, b)];
+    const double2 x = s_ue[tiled_offdiag_index(W, b, a)];
+    return make_double2(x.x, -x.y);
+}
+
+// u_b = sum_a V_a U_ab for b < W from U in LDS, written to rec[2 + 2b]:
+// thread t takes b = t / 32 (and b + blockDim / 32, ...) and the waves
+// a = t % 32 + 32 m; the 32 partial sums of b are added by a fixed butterfly.
+__device__ inline void contract_u(const double2* s_ue, const double* s_v, int W,
+                                  double* __restrict__ rec)
+{
+    const int j = threadIdx.x & 31;
+    for (int b0 = 0; b0 < W; b0 += blockDim.x >> 5) {
+        const int b = b0 + (threadIdx.x >> 5);   // uniform over each half wavefront
+        double xr = 0.0, xi = 0.0;
+        if (b < W) {
+            for (int a = j; a < W; a += 32) {
+                const double2 u = u_entry(s_ue, W, a, b);
+                const double vr = s_v[2 * a], vi = s_v[2 * a + 1];
+                xr = __fma_rn(vr, u.x, __fma_rn(-vi, u.y, xr));
+                xi = __fma_rn(vr, u.y, __fma_rn(vi, u.x, xi));
+            }
+        }
+#pragma unroll
+        for (int m = 16; m >= 1; m >>= 1) {
+            xr += __shfl_xor(xr, m);
+            xi += __shfl_xor(xi, m);
+        }
+        if (b < W && j == 0) *reinterpret_cast<double2*>(rec + 2 + 2 * b) = make_double2(xr, xi);
+    }
+}
+
 template <typename S, int K, int E, bool GRAD>
 __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
-    const char* __restrict__ table, int64_t n_events, int64_t n_tiles, int P,
-    const uint32_t* __restrict__ pairs, VParams vp, double* __restrict__ partials, int rec_len)
+    const char* __restrict__ table, int64_t n_events, int64_t n_tiles, int P, int W,
+    const uint32_t* __restrict__ slots, VParams vp, double* __restrict__ partials, int rec_len)
 {
     using VT = Vec16<S>;
     constexpr int esz = 2 * sizeof(S);
@@ -427,6 +514,7 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
     __shared__ double2 s_c[K * 64];
     __shared__ double2 s_u[GRAD ? (kTree ? NW / 2 : 1) * K * 64 : 1];
     __shared__ double s_misc[2 * NW];
+    __shared__ double s_v[GRAD ? 2 * PWA_MAX_WAVES_TABLE : 1];
 
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -451,21 +539,29 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
     SubTile<S, K, E> a, b;
     if (U > 0) a.load(base_of(0), part_of(0), P, lane);
 
-    // coefficients c_e for every (slot, lane)
+    // coefficients c_e for every (slot, lane): 2 V_a V*_b off the diagonal,
+    // |V_a|^2 - i |V_a2|^2 for a diagonal pair (so that Re(c_e T_ie) is the
+    // entry's share of I_i in both cases)
+    const double* v = vsrc(vp);
     for (int idx = threadIdx.x; idx < K * 64; idx += blockDim.x) {
         double2 c = make_double2(0.0, 0.0);
         if (idx < P) {
-            const uint32_t pr = pairs[idx];
-            const int wa = (int)(pr & 0xffffu), wb = (int)(pr >> 16);
-            const double* v = vsrc(vp);
+            const uint32_t d = slots[idx];
+            const int wa = (int)(d & 0xffffu), wb = (int)((d >> 16) & kNoWave);
             const double vr = v[2 * wa], vi = v[2 * wa + 1];
-            const double wr = v[2 * wb], wi = v[2 * wb + 1];
-            const double f = (wa == wb) ? 1.0 : 2.0;
-            c.x = f * (vr * wr + vi * wi);   // Re V_a V*_b
-            c.y = f * (vi * wr - vr * wi);   // Im V_a V*_b
+            if (d & kDiagPair) {
+                c.x = vr * vr + vi * vi;
+                if (wb < W) c.y = -(v[2 * wb] * v[2 * wb] + v[2 * wb + 1] * v[2 * wb + 1]);
+            } else {
+                const double wr = v[2 * wb], wi = v[2 * wb + 1];
+                c.x = 2.0 * (vr * wr + vi * wi);   // Re V_a V*_b
+                c.y = 2.0 * (vi * wr - vr * wi);   // Im V_a V*_b
+            }
         }
         s_c[idx] = c;
     }
+    if (GRAD)
+        for (int a = threadIdx.x; a < 2 * W; a += blockDim.x) s_v[a] = v[a];
     __syncthreads();
 
     double ur[K], ui[K];
@@ -514,12 +610,9 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
             }
             if (wave == 0) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int e = k * 64 + lane;
-                    if (e < P)
-                        *reinterpret_cast<double2*>(rec + 2 + 2 * e) = make_double2(ur[k], ui[k]);
-                }
+                for (int k = 0; k < K; ++k) s_u[k * 64 + lane] = make_double2(ur[k], ui[k]);
             }
+            __syncthreads();
         } else {
             // one accumulator in LDS, the wavefronts adding in turn
             for (int w = 0; w < NW; ++w) {
@@ -537,9 +630,9 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
                 }
                 __syncthreads();
             }
-            for (int e = threadIdx.x; e < P; e += blockDim.x)
-                *reinterpret_cast<double2*>(rec + 2 + 2 * e) = s_u[e];
         }
+        // s_u now holds the block's U over the stored entries
+        contract_u(s_u, s_v, W, rec);
     } else {
         __syncthreads();
     }
@@ -560,12 +653,12 @@ static hipError_t run_fused(const Model& m, const VParams& vp, bool grad, hipStr
     constexpr int NT = fused_threads<S, K, E>();
     if (grad)
         hipExtLaunchKernelGGL((k_table_fused<S, K, E, true>), dim3(m.grid), dim3(NT), 0, s,
-                              ev.start, ev.stop, 0, (const char*)m.d_data, m.n, m.n_tiles, m.P, m.d_pairs, vp,
-                           m.d_partials, m.rec_len);
+                              ev.start, ev.stop, 0, (const char*)m.d_data, m.n, m.n_tiles, m.ps,
+                              m.W, m.d_slots, vp, m.d_partials, m.rec_len);
     else
         hipExtLaunchKernelGGL((k_table_fused<S, K, E, false>), dim3(m.grid), dim3(NT), 0, s,
-                              ev.start, ev.stop, 0, (const char*)m.d_data, m.n, m.n_tiles, m.P, m.d_pairs, vp,
-                           m.d_partials, m.rec_len);
+                              ev.start, ev.stop, 0, (const char*)m.d_data, m.n, m.n_tiles, m.ps,
+                              m.W, m.d_slots, vp, m.d_partials, m.rec_len);
     return hipGetLastError();
 }
 
@@ -632,7 +725,7 @@ static hipError_t run_read(const Model& m, uint32_t* sink, hipStream_t s, const 
 {
     constexpr int NT = fused_threads<S, K, E>();
     hipExtLaunchKernelGGL((k_table_read<S, K, E>), dim3(m.grid), dim3(NT), 0, s, ev.start,
-                          ev.stop, 0, (const char*)m.d_data, m.n_tiles, m.P, 0x9e3779b9u, sink);
+                          ev.stop, 0, (const char*)m.d_data, m.n_tiles, m.ps, 0x9e3779b9u, sink);
     return hipGetLastError();
 }
 

@@ -117,6 +117,7 @@ void release(Model* m)
     DeviceGuard g(m->device);
     if (m->d_data) (void)hipFree(m->d_data);
     if (m->d_pairs) (void)hipFree(m->d_pairs);
+    if (m->d_slots) (void)hipFree(m->d_slots);
     if (m->d_M) (void)hipFree(m->d_M);
     if (m->d_partials) (void)hipFree(m->d_partials);
     if (m->d_colsum) (void)hipFree(m->d_colsum);
@@ -196,15 +197,45 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
     Staged sd;
     int rc = stage(data, in_bytes, s, sd);
     if (rc != PWA_OK) return rc;
+    m->ps = P;
+    if (in_table) {
+        // a Hermitian table has a real diagonal
+        unsigned long long* d_count = nullptr;
+        HIP_TRY(hipMalloc(&d_count, sizeof(unsigned long long)));
+        unsigned long long bad = 0;
+        hipError_t e = hipMemsetAsync(d_count, 0, sizeof bad, s);
+        if (e == hipSuccess) e = pwa::launch_check_table_diag(sd.ptr, data_c128, n, W, d_count, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&bad, d_count, sizeof bad, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(d_count);
+        if (e != hipSuccess) return device_fail(e, "table diagonal check");
+        if (bad)
+            return fail(PWA_ERR_INVALID,
+                        "the input table is not Hermitian: %llu diagonal entries have a non-zero "
+                        "imaginary part", bad);
+    }
 
     if (form == PWA_FORM_TABLE || form == PWA_PRECISION_FP64_FUSED) {
         const bool c128 = form == PWA_PRECISION_FP64_FUSED;
+        // stored entries: diagonal pairs, then the off-diagonal upper triangle
+        m->ps = pwa::tiled_entries(W);
+        std::vector<uint32_t> desc;
+        desc.reserve(m->ps);
+        for (int a = 0; a < W; a += 2)
+            desc.push_back(pwa::kDiagPair | (uint32_t)a |
+                           ((uint32_t)(a + 1 < W ? a + 1 : (int)pwa::kNoWave) << 16));
+        for (int a = 0; a < W; ++a)
+            for (int b = a + 1; b < W; ++b) desc.push_back((uint32_t)a | ((uint32_t)b << 16));
+        HIP_TRY(hipMalloc(&m->d_slots, sizeof(uint32_t) * m->ps));
+        HIP_TRY(hipMemcpyAsync(m->d_slots, desc.data(), sizeof(uint32_t) * m->ps,
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));   // desc leaves scope
         m->n_tiles = (n + pwa::kTileEvents - 1) / pwa::kTileEvents;
-        m->data_bytes = m->n_tiles * pwa::kTileEvents * (int64_t)P * (c128 ? 16 : 8);
+        m->data_bytes = m->n_tiles * pwa::kTileEvents * (int64_t)m->ps * (c128 ? 16 : 8);
         HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
-        HIP_TRY(pwa::launch_pack_tiled(sd.ptr, in_table, data_c128, n, W, P, m->d_pairs, c128,
+        HIP_TRY(pwa::launch_pack_tiled(sd.ptr, in_table, data_c128, n, W, m->ps, m->d_slots, c128,
                                        m->n_tiles, m->d_data, s, pwa::LaunchEvents{bt[0], bt[1]}));
-        m->kslots = pwa::select_kslots(P, c128);
+        m->kslots = pwa::select_kslots(m->ps, c128);
         if (m->kslots < 0) return fail(PWA_ERR_INVALID, "n_waves %d too large for the table form", W);
         m->subtile = pwa::default_subtile(m->kslots, c128);
         if (const char* env = std::getenv("PWA_TABLE_SUBTILE")) {
@@ -215,7 +246,7 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         }
         m->grid = pwa::table_fused_grid(*m);
         m->rows = m->grid;
-        m->rec_len = 2 + 2 * P;
+        m->rec_len = 2 + 2 * W;   // [sum ln I, n_bad, u_b = sum_a V_a U_ab]
     } else if (form == PWA_PRECISION_FP64_PLAIN) {
         m->data_bytes = (int64_t)n * P * 16;
         HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
@@ -383,7 +414,7 @@ int enqueue_eval(Model* m, const double* v, bool grad, int slot, hipStream_t s, 
     ta.seq = ++m->seq;
     ta.W = m->W;
     ta.grad = grad ? 1 : 0;
-    ta.g_records = m->form == pwa::kAmp32 ? 1 : 0;
+    ta.g_records = m->form == pwa::kTable64Plain ? 0 : 1;
     pwa::LaunchEvents ev;
     if (timed) {
         const int rc = timing_slot(m, &ev);
@@ -1123,8 +1154,8 @@ int pwa_model_info(const pwa_model* model, pwa_info* out)
     out->n_packed = m->P;
     out->form = (uint32_t)m->form;
     switch (m->form) {
-    case pwa::kTable32: out->stream_bytes = m->n * m->P * 8; break;
-    case pwa::kTable64Fused: out->stream_bytes = m->n * m->P * 16; break;
+    case pwa::kTable32: out->stream_bytes = m->n * m->ps * 8; break;
+    case pwa::kTable64Fused: out->stream_bytes = m->n * m->ps * 16; break;
     case pwa::kTable64Plain: out->stream_bytes = 2 * m->n * m->P * 16; break;
     case pwa::kAmpBF16:
     case pwa::kAmpFP16:
@@ -1174,7 +1205,7 @@ int pwa_copy_table(const pwa_model* model, void* out_host, void* hip_stream)
     if (m->form == pwa::kTable64Plain)
         e = pwa::launch_unpack_soa((const double*)m->d_data, m->n, m->P, (double*)tmp, s);
     else
-        e = pwa::launch_unpack_tiled(m->d_data, c128, m->n, m->P, tmp, s);
+        e = pwa::launch_unpack_tiled(m->d_data, c128, m->n, m->W, m->d_pairs, tmp, s);
     if (e == hipSuccess) e = hipMemcpyAsync(out_host, tmp, bytes, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(tmp);

@@ -13,6 +13,26 @@ namespace pwa {
 
 // Events per tile of the tiled table layout (see k_table.hip).
 constexpr int kTileEvents = 16;
+
+// Stored entries of the tiled tables.  T_i is Hermitian, so its diagonal is
+// real: the W diagonal entries are stored in pairs, (T_2d,2d, T_2d+1,2d+1) as
+// the real and imaginary part of one complex entry d < D = ceil(W / 2) (the
+// imaginary part is zero for the last entry of an odd W), followed by the
+// W(W - 1)/2 entries a < b in row-major order.  A descriptor per stored entry
+// says which: kDiagPair | a | a2 << 16 for a diagonal pair (a2 = kNoWave when
+// there is none), a | b << 16 for an off-diagonal entry.  With this layout an
+// entry's contribution to I_i is Re(c_e T_ie) for both kinds: c_e = 2 V_a V*_b
+// off the diagonal and c_e = |V_a|^2 - i |V_a2|^2 for a diagonal pair.
+constexpr uint32_t kDiagPair = 1u << 31;
+constexpr uint32_t kNoWave = 0x7fffu;
+__host__ __device__ inline int tiled_diag_entries(int W) { return (W + 1) / 2; }
+__host__ __device__ inline int tiled_entries(int W) { return (W + 1) / 2 + W * (W - 1) / 2; }
+// stored index of the off-diagonal entry (a, b), a < b
+__host__ __device__ inline int tiled_offdiag_index(int W, int a, int b)
+{
+    return (W + 1) / 2 + a * (W - 1) - a * (a - 1) / 2 + (b - a - 1);
+}
+
 // Events per tile of the FP32 amplitude layout (padding unit).
 constexpr int kAmpTile = 64;
 // Events per tile of the 16-bit matrix-core layout (two MFMA rows each).
@@ -85,7 +105,8 @@ struct Model {
     Form form = kTable32;
     int64_t n = 0;           // data events
     int32_t W = 0;           // waves
-    int32_t P = 0;           // packed entries W(W+1)/2
+    int32_t P = 0;           // packed entries W(W+1)/2 (the canonical table)
+    int32_t ps = 0;          // stored entries per event of the main kernel's table layout
     int32_t wpad = 0;        // amplitude row length q wl (FP32 amplitude form)
     int32_t amp_lq = 0;      // FP32 amplitude form: log2 of the lanes per event
     int32_t amp_wl = 2;      // FP32 amplitude form: waves per lane
@@ -101,6 +122,7 @@ struct Model {
     void* d_data = nullptr;         // table (tiled or SoA) or padded amplitudes
     int64_t data_bytes = 0;
     uint32_t* d_pairs = nullptr;    // (a | a' << 16) per packed entry
+    uint32_t* d_slots = nullptr;    // tiled tables: descriptor per stored entry
     double* d_M = nullptr;          // W x W complex128
     double* d_partials = nullptr;   // rows x rec_len
     double* d_colsum = nullptr;     // rec_len (x K for batched)
@@ -199,8 +221,12 @@ struct MfmaBatch {
 // ---- launchers (each returns the hipError_t of its launch) ----------------
 // build step
 hipError_t launch_pack_tiled(const void* src, bool src_is_table, bool src_c128, int64_t n,
-                             int W, int P, const uint32_t* pairs, bool store_c128,
+                             int W, int ps, const uint32_t* slots, bool store_c128,
                              int64_t n_tiles, void* dst, hipStream_t s, const LaunchEvents& ev);
+// counts the diagonal entries of a canonical packed source table whose
+// imaginary part is not zero (a Hermitian table has none) into *count
+hipError_t launch_check_table_diag(const void* src, bool c128, int64_t n, int W,
+                                   unsigned long long* count, hipStream_t s);
 hipError_t launch_pack_soa(const void* src, bool src_is_table, bool src_c128, int64_t n, int W,
                            int P, const uint32_t* pairs, double* dst, hipStream_t s);
 hipError_t launch_pack_amp(const void* src, bool src_c128, int64_t n, int W, AmpShape sh,
@@ -210,8 +236,8 @@ hipError_t launch_stream_read(const void* p, int64_t bytes, uint32_t* sink, int 
 hipError_t launch_table_read(const Model& m, uint32_t* sink, hipStream_t s,
                              const LaunchEvents& ev);
 int table_read_threads(const Model& m);
-hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int P, void* dst,
-                               hipStream_t s);
+hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int W,
+                               const uint32_t* pairs, void* dst, hipStream_t s);
 hipError_t launch_unpack_soa(const double* src, int64_t n, int P, double* dst, hipStream_t s);
 hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, double* partials,
                        int rows, hipStream_t s, const LaunchEvents& ev);

@@ -93,6 +93,36 @@ def test_table_bit_exact(form, w, n):
     assert got.dtype == ref.dtype and np.array_equal(got.view(np.uint8), ref.view(np.uint8))
 
 
+@pytest.mark.parametrize("form", ["table", "table_fp64_plain", "table_fp64"])
+@pytest.mark.parametrize("w,n", [(1, 3), (2, 17), (5, 40), (20, 33)])
+def test_table_input_round_trip(form, w, n):
+    """A canonical packed table given as input (PWA_INPUT_IS_TABLE) comes back
+    bit for bit: the tiled forms keep its diagonal as real pairs (odd and even
+    W), the plain form as it is."""
+    o = _o()
+    parts = [synth.small_sample(w, n, 4, seed=40 + k).data for k in (1, 2)]
+    T = o.table(parts[0]) + o.table(parts[1])
+    stored = T.astype(np.complex64) if form == "table" else T
+    model = pwa.Model(stored, None, 1, form=form, input_is_table=True)
+    got = model.table()
+    assert got.dtype == stored.dtype
+    assert np.array_equal(got.view(np.uint8), stored.view(np.uint8))
+    model.close()
+
+
+@pytest.mark.parametrize("form", ["table", "table_fp64_plain", "table_fp64"])
+def test_non_hermitian_table_rejected(form):
+    """A table whose diagonal has a non-zero imaginary part is not Hermitian
+    and is refused (PWA_ERR_INVALID) before anything is stored."""
+    o = _o()
+    T = o.table(synth.small_sample(4, 50, 4, seed=44).data)
+    T[17, 4] += 1e-3j                    # entry (1, 1): packed index 4 at W = 4
+    stored = T.astype(np.complex64) if form == "table" else T
+    with pytest.raises(pwa.PWAError) as e:
+        pwa.Model(stored, None, 1, form=form, input_is_table=True)
+    assert e.value.status == -1 and "Hermitian" in str(e.value)
+
+
 @pytest.mark.parametrize("form", FORMS)
 def test_mc_matrix(form):
     s = synth.small_sample(9, 10, 20_000, seed=3)
@@ -296,5 +326,6 @@ def test_read_ceiling():
     s = synth.small_sample(20, 200_000, 100, seed=19)
     model = pwa.Model(s.data.astype(np.complex64), s.mc.astype(np.complex64), 200)
     r = model.read_ceiling(reps=3)
-    assert r["bytes"] == 200_000 * 210 * 8 and r["ms"] > 0 and 0 < r["gbs"] < 50_000
+    # 200 stored entries per event at W = 20: 10 diagonal pairs + 190 off-diagonal
+    assert r["bytes"] == 200_000 * 200 * 8 and r["ms"] > 0 and 0 < r["gbs"] < 50_000
     model.close()

@@ -76,7 +76,8 @@ def test_w20_n1m_table_complex64(o, w20):
     model = pwa.Model(d32, mc32, s.n_gen, form="table")
     info = model.info()
     assert info["n_data"] == 1_000_000 and info["n_waves"] == 20 and info["n_packed"] == 210
-    assert info["stream_bytes"] == 1_000_000 * 210 * 8
+    # 200 stored entries: 10 pairs of the real diagonal + 190 off-diagonal
+    assert info["stream_bytes"] == 1_000_000 * 200 * 8
     got = {k: model.nll_grad(s.points[k]) for k in WALK_SAMPLE}
     model.close()
     # (a) the identical stored table
