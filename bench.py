@@ -14,8 +14,9 @@ reported value), the plain two-pass FP64 table kernels (the baseline), and the
 fused kernel over a complex128 table (ablation).  The main kernel's device time
 is taken inside the timed region with two HIP events per launch, on the stream
 the kernel runs on, which the runtime stamps with the dispatch's own begin and
-end; it is turned into achieved bandwidth from the algorithmic bytes (1680 B per
-event).  Per-call latency percentiles are host wall-clock times of the
+end; it is turned into achieved bandwidth from the algorithmic bytes (1600 B per
+event: the 190 off-diagonal complex64 entries of the Hermitian table and its 20
+real diagonal entries).  Per-call latency percentiles are host wall-clock times of the
 synchronous call.  The CPU
 oracle is timed on a bounded sample of the same walk on the host cores.
 
@@ -63,9 +64,10 @@ def time_model(model, points, steps, warmup):
     for k in range(warmup):
         model.nll_grad(points[k % len(points)])
     torch.cuda.synchronize()
-    # kernel time from HIP events on every 8th evaluation of the timed region
-    # (a stamped launch costs the call some microseconds)
-    model.set_timing(True, every=8)
+    # kernel time from HIP events on every 32nd evaluation of the timed region
+    # (a stamped launch costs its call about 18 us; one in 32 adds less than
+    # 1 us to the average step)
+    model.set_timing(True, every=32)
     model.timing()
     results, lat = [], []
     torch.cuda.synchronize()
@@ -544,7 +546,8 @@ def main():
         "storage": "complex64 packed table (FP64 arithmetic and accumulation)",
         "data": "synthetic",
         "config": {"workload": "w20_n1m: 1M events x 20 waves, packed complex64 table "
-                               "(210 entries, 1680 B per event), MC 2M accepted of 4M "
+                               "(190 complex off-diagonal + 20 real diagonal entries, 1600 B per event), "
+                               "MC 2M accepted of 4M "
                                "generated, 200-point random walk from the generating point",
                    "n_events": sample.data.shape[0], "n_waves": 20, "n_mc_acc": sample.mc.shape[0],
                    "n_mc_gen": sample.n_gen, "points": len(pts)},

@@ -135,6 +135,18 @@ class Model:
         del mkeep
         self.n_data, self.n_waves, self.form = n, w, form
         self.n_packed = w * (w + 1) // 2
+        self._setup_call_buffers(L)
+
+    def _setup_call_buffers(self, L):
+        # V in and the gradient out go through buffers owned by the model, so a
+        # call passes cached addresses (taking an array's address costs more
+        # than copying 2W doubles)
+        self._vbuf = np.empty(2 * self.n_waves, np.float64)
+        self._gbuf = np.empty(2 * self.n_waves, np.float64)
+        self._vaddr, self._gaddr = self._vbuf.ctypes.data, self._gbuf.ctypes.data
+        self._nllv = ctypes.c_double(0.0)
+        self._nllp = ctypes.byref(self._nllv)
+        self._fn_nll, self._fn_grad = L.pwa_nll, L.pwa_nll_grad
 
     # -- evaluation ---------------------------------------------------------
     def _handle(self):
@@ -143,25 +155,21 @@ class Model:
         return self._h
 
     def nll(self, v) -> float:
-        va = _v_array(v, self.n_waves)
-        out = ctypes.c_double(0.0)
-        st = _native.check(_native.lib().pwa_nll(self._handle(), va.ctypes.data, ctypes.byref(out),
-                                                 self._stream))
-        if st == _native.PWA_WARN_DEGENERATE:
-            warnings.warn("degenerate event (I <= 0): NLL is +inf")
-        return out.value
+        np.copyto(self._vbuf, _v_array(v, self.n_waves))
+        st = self._fn_nll(self._handle(), self._vaddr, self._nllp, self._stream)
+        if st:
+            if _native.check(st) == _native.PWA_WARN_DEGENERATE:
+                warnings.warn("degenerate event (I <= 0): NLL is +inf")
+        return self._nllv.value
 
     def nll_grad(self, v):
         """(NLL, gradient as 2W doubles [dRe V_0, dIm V_0, ...])."""
-        va = _v_array(v, self.n_waves)
-        out = ctypes.c_double(0.0)
-        g = np.empty(2 * self.n_waves, np.float64)
-        st = _native.check(_native.lib().pwa_nll_grad(self._handle(), va.ctypes.data,
-                                                      ctypes.byref(out), g.ctypes.data,
-                                                      self._stream))
-        if st == _native.PWA_WARN_DEGENERATE:
-            warnings.warn("degenerate event (I <= 0): NLL is +inf, gradient NaN")
-        return out.value, g
+        np.copyto(self._vbuf, _v_array(v, self.n_waves))
+        st = self._fn_grad(self._handle(), self._vaddr, self._nllp, self._gaddr, self._stream)
+        if st:
+            if _native.check(st) == _native.PWA_WARN_DEGENERATE:
+                warnings.warn("degenerate event (I <= 0): NLL is +inf, gradient NaN")
+        return self._nllv.value, self._gbuf.copy()
 
     def nll_grad_async(self, v_dev, out_dev, grad: bool = True, stream=None) -> None:
         """Enqueue one evaluation: V read from the device tensor v_dev (2W
