@@ -175,6 +175,34 @@ int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k
                     const double* v, double* nll, double* grad, void* hip_stream);
 
 /*
+ * pwa_nll_batched_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the K-vector evaluation of pwa_nll_batched on one model of a
+ * 16-bit amplitude form (PWA_FORM_AMPLITUDE_BF16 / _FP16), with every buffer
+ * of its kernels in a static device array of 16 MiB that the library holds on
+ * each device it runs on until the process ends.  It allocates nothing and
+ * only enqueues kernels on hip_stream (no memset, no copy, no host memory
+ * touched, no wait), so it can be captured and replayed.
+ *
+ *   k        1 <= k <= 1024 parameter vectors.
+ *   v_dev    k x 2W doubles in device memory, read when the work runs.
+ *   out_dev  k x (2 + 2W) doubles in device memory: per vector
+ *            [nll, n_bad, grad 2W]; a degenerate evaluation has n_bad > 0,
+ *            nll = +INFINITY and a NaN gradient.
+ * Returns PWA_ERR_INVALID for another form, for k out of range, or when the k
+ * vectors' buffers at this W exceed the static array (the split vector matrix
+ * and the records of at least one event chunk must fit); nothing is enqueued
+ * then.  When the records of the event chunks pwa_nll_batched would use fit,
+ * the results equal pwa_nll_batched's bit for bit; otherwise the events are cut
+ * into fewer chunks and the results agree within the FP32 accumulation error
+ * of the longer chunks.  Every call on one device shares that device's array:
+ * calls that overlap on one GPU (concurrent streams, or host threads without
+ * stream order between them) race and give wrong results.
+ */
+int pwa_nll_batched_noalloc(const pwa_model* model, int32_t k, const double* v_dev,
+                            double* out_dev, void* hip_stream);
+
+/*
  * pwa_nll_grad_hess -- NLL, gradient and the FUMILI second-derivative matrix
  * in one call (the paper's fits use FUMILI with analytic derivatives and ship
  * likelihood, gradient and this matrix per iteration, Sec. 5).  Amplitude form

@@ -36,7 +36,7 @@ EXPORTED = (
     "pwa_lbfgs_default_options", "pwa_lbfgs_minimize", "pwa_fit_lbfgs", "pwa_nll_grad_hess",
     "pwa_newton_minimize", "pwa_fit_fumili", "pwa_get_amplitude_shape",
     "pwa_set_amplitude_shape", "pwa_tune_amplitude_shape", "pwa_nll_async",
-    "pwa_nll_grad_async", "pwa_read_ceiling",
+    "pwa_nll_grad_async", "pwa_read_ceiling", "pwa_nll_batched_noalloc",
 )
 
 PWA_LBFGS_CONVERGED_GRADIENT = 0
@@ -129,6 +129,7 @@ def _declare(L):
     L.pwa_read_ceiling.argtypes = [p, ctypes.c_int32, p, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64)]
     L.pwa_nll_grad_async.argtypes = [p, p, p, p]
+    L.pwa_nll_batched_noalloc.argtypes = [p, i32, p, p, p]
     i32p = ctypes.POINTER(ctypes.c_int32)
     L.pwa_get_amplitude_shape.argtypes = [p, i32p, i32p]
     L.pwa_set_amplitude_shape.argtypes = [p, ctypes.c_int32, ctypes.c_int32, p]

@@ -43,6 +43,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <mutex>
 #include <type_traits>
 #include <hip/hip_fp16.h>
 
@@ -544,8 +545,8 @@ struct BatchTail {
     const double* v;       // K x 2W (device)
     const double* vscale;  // K scales s_k (device)
     const double2* M;      // W x W
-    double* out;           // K x (2 + 2W) (pinned host memory)
-    unsigned long long* done;   // K completion words (pinned host memory)
+    double* out;           // K x (2 + 2W) (pinned host memory, or device memory)
+    unsigned long long* done;   // K completion words (pinned host memory), or null
     unsigned long long seq;
 };
 
@@ -636,6 +637,7 @@ __global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt
         store_system(bt.out + (size_t)k * (2 + 2 * W), nbad > 0.0 ? INFINITY : (-dsum + mu));
         store_system(bt.out + (size_t)k * (2 + 2 * W) + 1, nbad);
     }
+    if (!bt.done) return;   // results in device memory, stream-ordered: nothing to publish
     wait_vm_complete();
     __syncthreads();
     if (threadIdx.x == 0)
@@ -746,6 +748,55 @@ hipError_t launch_mfma_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
     bt.seq = b.seq;
     hipLaunchKernelGGL(k_assemble_mfma, dim3(b.K), dim3(kBatchAsmThreads), 0, s, bt);
     return hipGetLastError();
+}
+
+// ---- the allocation-free variant: scratch in a static device array --------
+// pwa_nll_batched_noalloc keeps the split vector matrix, the vector scales and
+// the per-(chunk, column) records in `scratch`, one copy per device, held until
+// the process ends.  Host code never passes the array's name to a kernel (on
+// the host it names a stand-in, not device memory): the address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(int device, void** out)
+{
+    static std::mutex mu;
+    static void* addr[kNoAllocMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
+// Layout of one call's buffers in `scratch` (256-byte aligned pieces): the K
+// vector scales, the split vector matrix, then the records of `chunks` event
+// chunks; chunks as for pwa_nll_batched when that fits, else fewer.  Returns
+// false when not even one chunk fits.
+bool noalloc_layout(const Model& m, int K, NoAllocLayout* L)
+{
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const int n_cb = (K + 31) / 32;
+    const size_t head = up(sizeof(double) * (size_t)K) + up(mfma_vm_bytes(m, n_cb));
+    const size_t per_chunk = (size_t)n_cb * 32 * (2 * sizeof(double) + sizeof(float) * m.kd);
+    if (head + per_chunk > kNoAllocScratchBytes) return false;
+    int chunks = mfma_chunks(m, n_cb);
+    const size_t fit = (kNoAllocScratchBytes - head) / per_chunk;
+    if ((size_t)chunks > fit) chunks = (int)fit;
+    L->n_cb = n_cb;
+    L->chunks = chunks;
+    L->vscale_off = 0;
+    L->vm_off = up(sizeof(double) * (size_t)K);
+    L->rec_d_off = head;
+    L->rec_g_off = head + up((size_t)chunks * n_cb * 32 * 2 * sizeof(double));
+    return L->rec_g_off + (size_t)chunks * n_cb * 32 * sizeof(float) * m.kd <=
+           kNoAllocScratchBytes;
 }
 
 // copy of the stored 16-bit amplitudes, widened to complex64 (N x W), read

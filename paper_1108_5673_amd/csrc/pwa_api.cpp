@@ -1062,6 +1062,42 @@ int pwa_nll_grad_async(const pwa_model* model, const double* v_dev, double* out_
     return evaluate_async(model, v_dev, out_dev, true, hip_stream);
 }
 
+int pwa_nll_batched_noalloc(const pwa_model* model, int32_t k, const double* v_dev,
+                            double* out_dev, void* hip_stream)
+{
+    if (!model || !v_dev || !out_dev) return fail(PWA_ERR_INVALID, "NULL model, v_dev or out_dev");
+    const Model* m = reinterpret_cast<const Model*>(model);
+    if (!is_mfma(m))
+        return fail(PWA_ERR_INVALID,
+                    "pwa_nll_batched_noalloc takes the 16-bit amplitude forms only");
+    if (k < 1 || k > pwa::kNoAllocMaxVectors)
+        return fail(PWA_ERR_INVALID, "k must be in [1, %d] (got %d)", pwa::kNoAllocMaxVectors, k);
+    pwa::NoAllocLayout L;
+    if (!pwa::noalloc_layout(*m, k, &L))
+        return fail(PWA_ERR_INVALID,
+                    "%d vectors at W = %d need more than the %zu bytes of the static scratch", k,
+                    m->W, pwa::kNoAllocScratchBytes);
+    DeviceGuard g(m->device);
+    void* base = nullptr;
+    HIP_TRY(pwa::noalloc_scratch(m->device, &base));
+    char* b8 = static_cast<char*>(base);
+    pwa::MfmaBatch b;
+    b.v = v_dev;
+    b.vscale = reinterpret_cast<double*>(b8 + L.vscale_off);
+    b.vm = b8 + L.vm_off;
+    b.rec_d = reinterpret_cast<double*>(b8 + L.rec_d_off);
+    b.rec_g = reinterpret_cast<float*>(b8 + L.rec_g_off);
+    b.out = out_dev;
+    b.done = nullptr;
+    b.seq = 0;
+    b.K = k;
+    b.n_cb = L.n_cb;
+    b.chunks = L.chunks;
+    const hipError_t e = pwa::launch_mfma_batch(*m, b, (hipStream_t)hip_stream, pwa::LaunchEvents{});
+    if (e != hipSuccess) return device_fail(e, "matrix-core evaluation launch");
+    return PWA_OK;
+}
+
 int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k_per_model,
                     const double* v, double* nll, double* grad, void* hip_stream)
 {

@@ -274,6 +274,17 @@ hipError_t launch_mfma_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
                              const LaunchEvents& ev);
 int mfma_chunks(const Model& m, int n_cb);
 size_t mfma_vm_bytes(const Model& m, int n_cb);
+// allocation-free matrix-core evaluation (pwa_nll_batched_noalloc): a static
+// device array of kNoAllocScratchBytes per device and the layout of one call in it
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+constexpr int kNoAllocMaxVectors = 1024;
+struct NoAllocLayout {
+    int n_cb, chunks;
+    size_t vscale_off, vm_off, rec_d_off, rec_g_off;   // byte offsets in the scratch array
+};
+hipError_t noalloc_scratch(int device, void** out);
+bool noalloc_layout(const Model& m, int K, NoAllocLayout* L);
 hipError_t launch_assemble(const VParams& vp, const TailArgs& ta, hipStream_t s);
 hipError_t launch_amp_multi_class(const MultiLaunch& ml, int c, hipStream_t s);
 hipError_t launch_assemble_multi(const MultiLaunch& ml, hipStream_t s);
