@@ -119,6 +119,13 @@ def mfma_flops(n_events, n_waves, k, v_parts):
     return tiles * col_blocks * per * 32768
 
 
+def mfma_algorithmic_flops(n_events, n_waves, k, v_parts):
+    """The products the batched pass must form, without padding: the forward
+    S = A V as a real product of 2N rows x 2W x 2K per V part (8 N W K FLOP
+    each) and the adjoint over two weight parts (8 N W K each)."""
+    return 8 * n_events * n_waves * k * (v_parts + 2)
+
+
 def bench_batched(args):
     """The 256 random starting points of w20_n1m_k256 in one pass of the
     matrix-core amplitude forms (bf16 and fp16 amplitudes)."""
@@ -145,7 +152,7 @@ def bench_batched(args):
             pwa.nll_batched([m], [s.points])
         torch.cuda.synchronize()
         # kernel time from event stamps on every 8th pass (a stamped launch
-        # costs about 14 us of the call)
+        # costs about 18 us of the call)
         m.set_timing(True, every=8)
         m.timing()
         reps = 24
@@ -156,17 +163,34 @@ def bench_batched(args):
         ms, n = m.timing()
         kus = 1e3 * ms / max(1, n)
         fl = mfma_flops(s.data.shape[0], 20, 256, parts)
+        fa = mfma_algorithmic_flops(s.data.shape[0], 20, 256, parts)
         r = {"evals_per_s": 256 / dt, "batch_us": 1e6 * dt, "kernel_us": kus,
-             "mfma_tflops": fl / (kus * 1e-6) / 1e12, "mfma_peak_tflops": 2500.0,
-             "mfma_frac": fl / (kus * 1e-6) / 2.5e15,
+             "mfma_tflops": fa / (kus * 1e-6) / 1e12, "mfma_peak_tflops": 2500.0,
+             "mfma_frac": fa / (kus * 1e-6) / 2.5e15,
+             "mfma_flops_algorithmic": fa, "mfma_flops_issued": fl,
+             "mfma_issued_tflops": fl / (kus * 1e-6) / 1e12,
+             "mfma_issued_frac": fl / (kus * 1e-6) / 2.5e15,
              "events_iter_per_s": 256 / dt * s.data.shape[0]}
         if ref is not None:
             r["max_abs_dnll_vs_fp64_amplitudes"] = max(abs(nll[j] - ref[j][0]) for j in ref)
             r["max_rel_grad_vs_fp64_amplitudes"] = max(
                 float(np.linalg.norm(g[j] - ref[j][1]) / np.linalg.norm(ref[j][1])) for j in ref)
+            # the kernel's own error: the oracle on the identical stored 16-bit
+            # amplitudes (the model's copy, widened exactly)
+            a16 = m.table().astype(np.complex128)
+            M32 = o.mc_matrix(mc32.astype(np.complex128), s.n_gen)
+            same = {j: o.nll_amp(a16, M32, s.points[j]) for j in ref}
+            del a16
+            r["max_abs_dnll_vs_identical_inputs"] = max(abs(nll[j] - same[j][0]) for j in same)
+            r["max_rel_dnll_vs_identical_inputs"] = max(
+                abs(nll[j] - same[j][0]) / abs(same[j][0]) for j in same)
+            r["max_rel_grad_vs_identical_inputs"] = max(
+                float(np.linalg.norm(g[j] - same[j][1]) / np.linalg.norm(same[j][1]))
+                for j in same)
         out[form] = r
-        log("batched %s: %.0f evals/s, kernel %.1f us (%.0f TFLOP/s on the matrix cores)"
-            % (form, r["evals_per_s"], kus, r["mfma_tflops"]))
+        log("batched %s: %.0f evals/s, kernel %.1f us (%.0f TFLOP/s algorithmic, %.0f issued on "
+            "the matrix cores)" % (form, r["evals_per_s"], kus, r["mfma_tflops"],
+                                   r["mfma_issued_tflops"]))
         m.close()
     return out
 

@@ -38,8 +38,12 @@
 // form).  V is split into 16-bit parts (three for bf16, two for fp16: about
 // 24 and 22 significant bits) whose products are accumulated, so that the
 // parameters, which every event shares, add no coherent 16-bit rounding; the
-// weights c are split into two parts (see Split below).  ln I is summed in FP64 per lane, and all
-// cross-block sums are FP64.
+// weights c are split into two parts (see Split below).  Per lane, log2 I of
+// the step's eight (event, vector) pairs is taken in FP32 (hardware v_log_f32)
+// and summed in FP32, then added to an FP64 lane sum.  The adjoint's FP32
+// accumulators add at most kFoldTiles tiles: they are then added into FP64
+// sums in LDS (one slot per lane and accumulator register) and restart from
+// zero.  All cross-block sums are FP64.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
@@ -113,9 +117,29 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 // Two-part split of a pair of values, each part rounded to nearest even by one
 // paired conversion.  The high part is the rounded value (zero where fp16 would
 // be subnormal); the low part is the remainder, times 2^11 for fp16.
+// The remainders x_j - hi_j are exact in FP32 (hi_j is x_j rounded to 8 or 11
+// significant bits); each comes from one dot-product instruction of the packed
+// high parts with m0 = (-1, 0) or m1 = (0, -1) added to x_j, whose bf16 x bf16
+// and f16 x f16 products are exact.  The multipliers must be held in registers
+// (make_split_multipliers): written as vector constants, the compiler encodes
+// (-1, 0) as the FP32 inline constant -1.0, whose 16-bit halves the
+// instruction reads as (0, -1), so the wrong part would be subtracted.
+template <typename T> struct SplitMul {
+    typename H16<T>::V2 m0, m1;
+};
+template <typename T> __device__ inline SplitMul<T> make_split_multipliers()
+{
+    using V2 = typename H16<T>::V2;
+    // -1 in the low or the high 16 bits: 0xBF80 (bf16) or 0xBC00 (fp16)
+    unsigned lo = Split<T>::kScaledLow ? 0x0000BC00u : 0x0000BF80u;
+    unsigned hi = lo << 16;
+    asm volatile("" : "+v"(lo), "+v"(hi));   // registers, never inline constants
+    return SplitMul<T>{__builtin_bit_cast(V2, lo), __builtin_bit_cast(V2, hi)};
+}
+
 template <typename T>
-__device__ inline void split_pair(float x0, float x1, typename H16<T>::V2& hi,
-                                  typename H16<T>::V2& lo)
+__device__ inline void split_pair(float x0, float x1, const SplitMul<T>& sm,
+                                  typename H16<T>::V2& hi, typename H16<T>::V2& lo)
 {
     using V2 = typename H16<T>::V2;
     const f32x2 x = {x0, x1};
@@ -126,9 +150,14 @@ __device__ inline void split_pair(float x0, float x1, typename H16<T>::V2& hi,
     } else {
         hi = __builtin_convertvector(x, V2);
     }
-    const f32x2 back = __builtin_convertvector(hi, f32x2);
-    f32x2 r = {x[0] - back[0], x[1] - back[1]};
-    if constexpr (Split<T>::kScaledLow) r = f32x2{r[0] * kLowScale, r[1] * kLowScale};
+    f32x2 r;
+    if constexpr (Split<T>::kScaledLow) {
+        r[0] = __builtin_amdgcn_fdot2(hi, sm.m0, x0, false) * kLowScale;
+        r[1] = __builtin_amdgcn_fdot2(hi, sm.m1, x1, false) * kLowScale;
+    } else {
+        r[0] = __builtin_amdgcn_fdot2_f32_bf16(hi, sm.m0, x0, false);
+        r[1] = __builtin_amdgcn_fdot2_f32_bf16(hi, sm.m1, x1, false);
+    }
     lo = __builtin_convertvector(r, V2);
 }
 
@@ -254,10 +283,13 @@ __global__ void k_prep_vmat16(const double* __restrict__ v, int K, int W, int NS
 // in cache.  Records per (chunk, cb, vector): rec_d = [sum ln I, n_bad] (FP64;
 // n_bad counts the vector's lane sums that met a degenerate event, so it is
 // non-zero exactly when one did) and rec_g = G[0 .. KD) of the vector (the
-// wavefront's FP32 sums; rows 2b, 2b + 1 are Re g_b and Im g_b).
+// wavefront's FP64 sums rounded to FP32; rows 2b, 2b + 1 are Re g_b and Im g_b).
 // Up to 8 wavefronts per block (two per SIMD, 256 registers each); the wider
 // row lengths (NS > 4) need more registers and run 4 (one per SIMD).
 template <int NS> constexpr int mfma_waves() { return NS <= 4 ? 8 : 4; }
+// An FP32 adjoint accumulator is folded into FP64 once it has added at least
+// kFoldTiles tiles (so never more than kFoldTiles + 1).
+constexpr int kFoldTiles = 32;
 
 template <typename T, int NS, int NP>
 __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
@@ -286,12 +318,37 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
             vp[p][s] = *reinterpret_cast<const V8*>(
                 vm + p * part_elems + ((size_t)((cb * NS + s) * 2 + h) * 32 + c) * 8);
     constexpr bool SL = Split<T>::kScaledLow;
+    const SplitMul<T> smul = make_split_multipliers<T>();
     f32x16 g[RB], gl[SL ? RB : 1];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) g[rb] = f32x16{};
 #pragma unroll
     for (int rb = 0; rb < (SL ? RB : 1); ++rb) gl[rb] = f32x16{};
     double dsum = 0.0;
+    // FP64 sums of the adjoint accumulators: slot [wave][rb][q][lane], each
+    // owned by one lane (no synchronisation needed)
+    __shared__ double s_gacc[mfma_waves<NS>() * RB * 16 * 64];
+    double* gacc = s_gacc + (size_t)wave * RB * 16 * 64 + lane;
+#pragma unroll
+    for (int j = 0; j < RB * 16; ++j) gacc[64 * j] = 0.0;
+    int since_fold = 0;   // tiles added to g, gl since they were last folded
+    auto fold = [&]() {
+        since_fold = 0;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                float x = g[rb][q];
+                if constexpr (SL) x = fmaf(gl[rb][q], kLowUnscale, x);
+                // LDS add without a return (the slot is this lane's own)
+                __hip_atomic_fetch_add(gacc + 64 * (16 * rb + q), (double)x, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) g[rb] = f32x16{};
+#pragma unroll
+        for (int rb = 0; rb < (SL ? RB : 1); ++rb) gl[rb] = f32x16{};
+    };
 
     const int64_t t0 = (int64_t)blockIdx.x * n_tiles / chunks;
     const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / chunks;
@@ -374,7 +431,7 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
                     lsum += valid ? __builtin_amdgcn_logf(I) : 0.f;
                 }
                 V2 hi, lo;
-                split_pair<T>(cr, ci, hi, lo);
+                split_pair<T>(cr, ci, smul, hi, lo);
                 chi[2 * r] = hi[0];
                 chi[2 * r + 1] = hi[1];
                 clo[2 * r] = lo[0];
@@ -417,21 +474,30 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
             g[rb] = H16<T>::mfma(o.b[rb][s2], chi, g[rb]);
         }
     };
-    auto pair_epi = [&](const f32x16& acc, int q, float& lsum, V8& chi, V8& clo, int r) {
+    // One (event, vector) pair of the step's epilogue: I, the weights split
+    // into 16-bit parts; returns I.  The logarithms are taken per product of
+    // four intensities (see step).
+    auto pair_epi = [&](const f32x16& acc, int q, V8& chi, V8& clo, int r) {
         const float x = acc[q], y = acc[q + 1];
         const float I = fmaf(y, y, x * x);
         const float w = __builtin_amdgcn_rcpf(I);
-        lsum += __builtin_amdgcn_logf(I);
         V2 hi, lo;
-        split_pair<T>(x * w, y * w, hi, lo);
+        split_pair<T>(x * w, y * w, smul, hi, lo);
         chi[2 * r] = hi[0];
         chi[2 * r + 1] = hi[1];
         clo[2 * r] = lo[0];
         clo[2 * r + 1] = lo[1];
+        return I;
     };
+    // sum_i log2 I_i of a step: log2 of the products of pairs 0-3 and 4-7, each
+    // one FP32 logarithm.  When a product is not a positive normal number (an
+    // intensity far from 1 under- or overflowed it, or an event is degenerate)
+    // in some lane, the wavefront takes the eight logarithms instead; a
+    // degenerate I then makes the sum non-finite, which is how it is counted.
     auto step = [&](const OpsA& an, const f32x16& acc, const OpsB& o) {
         f32x16 nx = f32x16{}, nxl = f32x16{};
-        float lsum = 0.f;
+        float I[8];
+        float p0 = 1.f, p1 = 1.f, l0 = 0.f, l1 = 0.f;
         V8 chi0, clo0, chi1, clo1;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -442,12 +508,32 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
                 for (int j = (i - 4) * 2 * RB / 4; j < (i - 3) * 2 * RB / 4; ++j)
                     adj_mfma(o, chi0, clo0, 0, j);
             }
-            if (i < 4) pair_epi(acc, 2 * i, lsum, chi0, clo0, i);
-            else pair_epi(acc, 8 + 2 * (i - 4), lsum, chi1, clo1, i - 4);
+            if (i < 4) {
+                I[i] = pair_epi(acc, 2 * i, chi0, clo0, i);
+                p0 *= I[i];
+            } else {
+                I[i] = pair_epi(acc, 8 + 2 * (i - 4), chi1, clo1, i - 4);
+                p1 *= I[i];
+            }
+            if (i == 3) {
+                l0 = __builtin_amdgcn_logf(p0);
+                asm volatile("" : "+v"(l0));   // keep the logarithm in this piece
+            }
+            if (i == 7) {
+                l1 = __builtin_amdgcn_logf(p1);
+                asm volatile("" : "+v"(l1));
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int j = 0; j < 2 * RB; ++j) adj_mfma(o, chi1, clo1, 1, j);
+        float lsum = l0 + l1;
+        // positive normal: class bit 8
+        if (!(__builtin_amdgcn_classf(p0, 0x100) && __builtin_amdgcn_classf(p1, 0x100))) {
+            lsum = 0.f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) lsum += __builtin_amdgcn_logf(I[i]);
+        }
         dsum += (double)lsum * 0.69314718055994530942;   // log2 -> ln
         if constexpr (SL) {
 #pragma unroll
@@ -479,10 +565,13 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
             load_a(a1, min(t + 3, tf - 1));
             load_b(b0, min(t + 2, tf - 1));
             s0 = step(a0, s1, b1);
+            since_fold += 2;
+            if (since_fold >= kFoldTiles) fold();
         }
         if (t < tf) {   // an odd count: s0, b0 hold the last full tile
             finish(s0, b0, t, std::true_type{});
             ++t;
+            ++since_fold;
         }
     }
     // the rest (a chunk with fewer than two full tiles, the last tile, padded
@@ -509,15 +598,11 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
                 }
                 run(a1, b1, t + 1);
             }
+            since_fold += t + 1 < t1 ? 2 : 1;
+            if (since_fold >= kFoldTiles) fold();
         }
     }
-
-    if constexpr (SL) {
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) g[rb][q] = fmaf(gl[rb][q], kLowUnscale, g[rb][q]);
-    }
+    fold();   // the FP64 sums now hold everything; g, gl are zero
     // records of this wavefront: G column c (vector 32 cb + c), rows
     // 8 j + 4 h + i of each row block, and the vector's sum ln I (lanes c and c + 32)
     const size_t rec_idx = ((size_t)blockIdx.x * n_cb + cb) * 32 + c;
@@ -527,7 +612,7 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int r = rb * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
-            if (r < KD) gcol[r] = g[rb][q];
+            if (r < KD) gcol[r] = (float)gacc[64 * (16 * rb + q)];
         }
     const double other = __shfl_xor(dsum, 32);
     if (h == 0) {

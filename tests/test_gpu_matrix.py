@@ -6,17 +6,28 @@ float16 results below the smallest normal stored as zero), which the library
 must store bit for bit; the oracle then evaluates Eq. 3 in
 FP64 on those rounded amplitudes.
 
-Tolerances, from the arithmetic of the kernel.  S_i = sum_a A_ia V_a is
-accumulated in FP32 over n_t = 2W x (parts of V) exact 16-bit products, so
-|dS_i| <= e_i = n_t 2^-24 sum_a |A_ia||V_a| (V itself carried to 22-24 bits);
-an event whose S_i nearly cancels has a large relative error, which enters
-ln I_i as 2 e_i / |S_i| and the adjoint weight c_i = 1 / conj(S_i) as
-e_i / |S_i|^2.  Per point:
-  |dNLL|   <= 4 sum_i 2 e_i / |S_i|  + 1e-6 N + 1e-9 |NLL|
-              (the second term: FP32 logarithms and the scale of the sums),
-  ||dG||_2 <= 4 * 2 sqrt(2) || sum_i |A_i| e_i / |S_i|^2 ||_2 + r ||G||_2,
-with r the weight split's relative precision (1e-5 for bfloat16, whose two
-parts carry 16 bits, 1e-6 for float16 with 22 bits).
+Tolerances, from the arithmetic of the kernel (u = 2^-24, the FP32 unit
+roundoff).  S_i = sum_a A_ia V_a is accumulated in FP32 over n_t = 2W x (parts
+of V) exact 16-bit products, so |dS_i| <= e_i = n_t u sum_a |A_ia||V_a| (V
+itself carried to 22-24 bits); an event whose S_i nearly cancels has a large
+relative error, which enters ln I_i as 2 e_i / |S_i| and the adjoint weight
+c_i = 1 / conj(S_i) as e_i / |S_i|^2.  The kernel works on V / s (s the power
+of two nearest ||V||), takes log2 of products of four I' = I / s^2 (three FP32
+roundings, at most 3 u / ln 2 in log2 per product) with the FP32 hardware
+logarithm (error below 2^-21 absolute plus 2 u |log2|, and |log2 of a
+product| <= the sum of the four |log2 I'|), or of each I' where a product
+leaves the normal range, and adds a lane's eight in FP32 before an FP64 lane
+sum (8 u |log2 I'| more); per event at most 2^-21 + 10 u |log2 I'|.  The weights c are
+split into two 16-bit parts (relative error 2^-16 for bfloat16, 2^-22 for
+float16), and an FP32 adjoint accumulator adds at most kFoldTiles + 1 = 33
+tiles (four MFMA steps of 16 products each per tile) before it is folded
+into FP64, plus one rounding each for the fold and the FP32 record:
+gamma = (4 x 33 + 6) u per accumulated term.  Per point, with
+a_b = sum_i |A_ib| / |S_i| (the sum of |terms| of g_b):
+  |dNLL|   <= 4 sum_i 2 e_i / |S_i| + ln 2 sum_i (2^-21 + 10 u |log2 I'_i|)
+              + 1e-9 |NLL|,
+  ||dG||_2 <= 8 sqrt(2) || sum_i |A_i| e_i / |S_i|^2 ||_2
+              + 4 (gamma + split) ||a||_2 + 1e-12 ||G||_2.
 """
 import numpy as np
 import pytest
@@ -28,8 +39,10 @@ from paper_1108_5673_amd import synth
 pytestmark = pytest.mark.gpu
 
 FORMS = ["amplitude_bf16", "amplitude_fp16"]
-G_REL = {"amplitude_bf16": 1e-5, "amplitude_fp16": 1e-6}
 V_PARTS = {"amplitude_bf16": 3, "amplitude_fp16": 2}
+U32 = 2.0 ** -24
+SPLIT = {"amplitude_bf16": 2.0 ** -16, "amplitude_fp16": 2.0 ** -22}
+FOLD_TILES = 32
 
 
 def _round16(a: np.ndarray, form: str) -> np.ndarray:
@@ -52,14 +65,26 @@ def _rel(g, ref):
     return float(np.linalg.norm(np.asarray(g) - ref) / np.linalg.norm(ref))
 
 
+def _scale(V):
+    """The power of two nearest ||V||_2 that the kernel divides V by."""
+    nn = float(np.sum(np.abs(V) ** 2))
+    return 1.0 if not nn > 0 else 2.0 ** np.rint(0.5 * np.log2(nn))
+
+
 def _bounds(A, V, form, nll_ref, g_ref):
     """(|dNLL| bound, ||dG|| bound) of the derivation above."""
     n, w = A.shape
     S = A @ V
-    e = 2 * w * V_PARTS[form] * 2.0 ** -24 * (np.abs(A) @ np.abs(V))
-    b_nll = 4 * np.sum(2 * e / np.abs(S)) + 1e-6 * n + 1e-9 * abs(nll_ref)
-    du = np.abs(A).T @ (e / np.abs(S) ** 2)
-    b_g = 4 * 2 * np.sqrt(2) * np.linalg.norm(du) + G_REL[form] * np.linalg.norm(g_ref)
+    aS = np.abs(S)
+    e = 2 * w * V_PARTS[form] * U32 * (np.abs(A) @ np.abs(V))
+    log2i = np.log2(aS ** 2 / _scale(V) ** 2)
+    b_nll = (4 * np.sum(2 * e / aS) + np.log(2) * np.sum(2.0 ** -21 + 10 * U32 * np.abs(log2i))
+             + 1e-9 * abs(nll_ref))
+    du = np.abs(A).T @ (e / aS ** 2)
+    a = np.abs(A).T @ (1.0 / aS)
+    gamma = (4 * (FOLD_TILES + 1) + 6) * U32
+    b_g = (8 * np.sqrt(2) * np.linalg.norm(du) + 4 * (gamma + SPLIT[form]) * np.linalg.norm(a)
+           + 1e-12 * np.linalg.norm(g_ref))
     return b_nll, b_g
 
 
@@ -97,6 +122,28 @@ def _check(form, w, n, n_mc, seed, k):
                                    (20, 4096, 32), (3, 16, 33), (5, 17, 96), (16, 2048, 65)])
 def test_matrix_parity(form, w, n, k):
     _check(form, w, n, 3 * n + 11, seed=1000 * w + n + k, k=k)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_matrix_long_chunks(form):
+    """1024 vectors over 10^5 events at 20 waves: 32 column blocks leave 64
+    event chunks of about 98 tiles each, so the adjoint accumulators are folded
+    into FP64 several times per chunk (every 32 tiles) before a record is
+    written; three vectors against the oracle within the derived bounds."""
+    o = oracle.get()
+    s = synth.small_sample(20, 100_000, 4_000, seed=1024, n_points=1024)
+    d32, mc32 = s.data.astype(np.complex64), s.mc.astype(np.complex64)
+    model = pwa.Model(d32, mc32, 9_000, form=form)
+    A = _round16(d32, form)
+    M = o.mc_matrix(mc32.astype(np.complex128), 9_000)
+    [(nll_b, g_b)] = pwa.nll_batched([model], [s.points])
+    for j in (0, 511, 1023):
+        rn, rg, nbad = o.nll_amp(A, M, s.points[j])
+        assert nbad == 0
+        b_nll, b_g = _bounds(A, s.points[j], form, rn, rg)
+        assert abs(nll_b[j] - rn) <= b_nll, (form, j, nll_b[j], rn, b_nll)
+        assert np.linalg.norm(g_b[j] - rg) <= b_g, (form, j, _rel(g_b[j], rg))
+    model.close()
 
 
 @pytest.mark.parametrize("form", FORMS)

@@ -115,7 +115,10 @@ def test_w20_n1m_table_complex128(o, w20, form):
         assert _rel(g, rg) <= 1e-10, (form, k, _rel(g, rg))
 
 
-def test_w20_n1m_k256_batched(o):
+def test_w20_n1m_256_points_table_batched_call(o):
+    """The 256 starting points of w20_n1m_k256 on the complex64 table through
+    one pwa_nll_batched call (one table pass per point): equal to single calls
+    bit for bit, and a sample against the oracle on the identical table."""
     k = synth.make_sample("w20_n1m_k256")
     assert k.points.shape == (256, 20) and k.data.shape == (1_000_000, 20)
     d, mc = k.data.astype(np.complex64), k.mc.astype(np.complex64)
@@ -135,6 +138,29 @@ def test_w20_n1m_k256_batched(o):
             continue
         assert abs(nll_b[j] - rn) <= 1e-12 * max(abs(rn), 1e6), (j, nll_b[j], rn)
         assert _rel(g_b[j], rg) <= 1e-10, (j, _rel(g_b[j], rg))
+
+
+@pytest.mark.parametrize("form", ["amplitude_bf16", "amplitude_fp16"])
+def test_w20_n1m_k256_matrix_cores(o, form):
+    """The batched-starting-points workload at full size on the matrix cores:
+    1M events, 20 waves, 256 vectors in one pass (8 column blocks, 256 event
+    chunks of about 245 tiles each), vectors 0, 85, 170 and 255 against the
+    oracle on the identical 16-bit amplitudes within the derived bounds of
+    tests/test_gpu_matrix.py."""
+    from test_gpu_matrix import _bounds, _round16
+    k = synth.make_sample("w20_n1m_k256")
+    d, mc = k.data.astype(np.complex64), k.mc.astype(np.complex64)
+    model = pwa.Model(d, mc, k.n_gen, form=form)
+    [(nll_b, g_b)] = pwa.nll_batched([model], [k.points])
+    model.close()
+    A = _round16(d, form)
+    M = o.mc_matrix(mc.astype(np.complex128), k.n_gen)
+    for j in (0, 85, 170, 255):
+        rn, rg, nbad = o.nll_amp(A, M, k.points[j])
+        assert nbad == 0
+        b_nll, b_g = _bounds(A, k.points[j], form, rn, rg)
+        assert abs(nll_b[j] - rn) <= b_nll, (form, j, nll_b[j], rn, b_nll)
+        assert np.linalg.norm(g_b[j] - rg) <= b_g, (form, j, _rel(g_b[j], rg))
 
 
 @pytest.fixture(scope="module")
