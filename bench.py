@@ -427,14 +427,17 @@ def main():
     t = time.perf_counter()
     v_fit, fres = pwa_fit.fit_lbfgs(fused, v0)
     fit_s = time.perf_counter() - t
-    fit_info = {"start": "Re, Im V ~ N(0, 1)", "status": fres["message"],
+    fit_info = {"start": "Re, Im V ~ N(0, 1) (the FUMILI driver scales it to mu = N)",
+                "status": fres["message"],
                 "iterations": fres["iterations"], "evaluations": fres["evaluations"],
                 "seconds": fit_s, "evals_per_s": fres["evaluations"] / fit_s,
                 "nll": fres["f"], "grad_norm": fres["grad_norm"]}
     log("fit from a random start: %s after %d iterations, %d evaluations, %.3f s"
         % (fres["message"], fres["iterations"], fres["evaluations"], fit_s))
-    # the same start with FUMILI steps (NLL, gradient and FUMILI matrix per
-    # iteration) on the amplitude form of the same sample
+    # the same start with FUMILI steps (NLL and gradient at trial points, the
+    # FUMILI matrix at the points taken) on the amplitude form of the same
+    # sample; then both drivers from a start near the generating point (5 %
+    # complex noise per wave), the regime of fits repeated around a solution
     amp = pwa.Model(d32, mc32, sample.n_gen, form="amplitude")
     t = time.perf_counter()
     v_fu, fu = pwa_fit.fit_fumili(amp, v0)
@@ -444,6 +447,17 @@ def main():
                           "grad_norm": fu["grad_norm"], "form": "amplitude (complex64)"}
     log("FUMILI fit from the same start: %s after %d iterations, %.3f s"
         % (fu["message"], fu["iterations"], fu_s))
+    v_near = sample.v_true * (1 + 0.05 * (rng.standard_normal(20) + 1j * rng.standard_normal(20)))
+    near = {"start": "V_true (1 + 0.05 (xi + i eta)), xi, eta ~ N(0, 1) per wave"}
+    for tag, fn, mdl in (("fumili", pwa_fit.fit_fumili, amp), ("lbfgs", pwa_fit.fit_lbfgs, fused)):
+        t = time.perf_counter()
+        _, r = fn(mdl, v_near)
+        near[tag] = {"status": r["message"], "iterations": r["iterations"],
+                     "evaluations": r["evaluations"], "seconds": time.perf_counter() - t,
+                     "nll": r["f"]}
+    fit_info["near_generating_point"] = near
+    log("from a start near the generating point: FUMILI %d iterations, L-BFGS %d"
+        % (near["fumili"]["iterations"], near["lbfgs"]["iterations"]))
     # one NLL + gradient + FUMILI matrix call at the start point, and the
     # oracle's matrix on the same stored amplitudes beside it
     for _ in range(3):

@@ -169,7 +169,12 @@ int pwa_nll_grad_async(const pwa_model* model, const double* v_dev, double* out_
  *
  * Returns PWA_WARN_DEGENERATE if any evaluation is degenerate (those entries
  * are +INFINITY / NaN); other entries are valid.  The K_m evaluations of a
- * model are queued back to back and waited for once.
+ * model are queued back to back and waited for once.  When every model is of
+ * PWA_FORM_AMPLITUDE (and there are at least two evaluations), the call runs
+ * as one work list replayed from a captured HIP graph: the plans (work list,
+ * buffers, graph) of the 8 most recent distinct (model, K) lists are kept, so
+ * that alternating model sets replay without a new capture; freeing or
+ * re-shaping a model drops the plans that use it.
  */
 int pwa_nll_batched(pwa_model* const* models, int32_t n_models, const int32_t* k_per_model,
                     const double* v, double* nll, double* grad, void* hip_stream);
@@ -267,11 +272,13 @@ int pwa_copy_table(const pwa_model* model, void* out_host, void* hip_stream);
  * bit.  pwa_tune_amplitude_shape times `evals` gradient evaluations of the
  * streaming kernel in each candidate shape (per lane count, the fewest waves
  * per lane that hold W, when the row is at most 25 % longer than the
- * shortest), twice over the candidates keeping each one's faster time, leaves
- * the model in the fastest and returns it (either output pointer may be
- * NULL).  Both synchronise hip_stream and must not run
- * concurrently with evaluations of the model; a cached multi-model plan that
- * uses the model is rebuilt at its next call.
+ * shortest), three times over the candidates keeping each one's fastest and
+ * slowest time; it leaves the default shape unless a candidate's fastest time
+ * beats the default's by more than the spread (slowest minus fastest) of
+ * either, leaves the model in the shape chosen and returns it (either output
+ * pointer may be NULL).  Both synchronise hip_stream and must not run
+ * concurrently with evaluations of the model; cached multi-model plans that
+ * use the model are rebuilt at their next call.
  */
 int pwa_get_amplitude_shape(const pwa_model* model, int32_t* lanes_per_event,
                             int32_t* waves_per_lane);
@@ -383,8 +390,8 @@ int pwa_lbfgs_minimize(int32_t n, double* x, pwa_objective fn, void* ctx,
  * Fit V on a model: minimise NLL(V) from v (2W doubles, host, overwritten with
  * the fitted V).  The NLL is invariant under a global phase of V, so the start
  * is first rotated to make V_0 real and non-negative and Im V_0 is then held
- * at zero (options->fixed_index is ignored); Re V_0 may change sign.  Each objective call is one
- * pwa_nll_grad on hip_stream.
+ * at zero (options->fixed_index is ignored); Re V_0 may change sign.  Each
+ * objective call is one pwa_nll_grad on hip_stream.
  */
 int pwa_fit_lbfgs(const pwa_model* model, double* v, const pwa_lbfgs_options* options,
                   pwa_lbfgs_result* res, void* hip_stream);
@@ -392,14 +399,22 @@ int pwa_fit_lbfgs(const pwa_model* model, double* v, const pwa_lbfgs_options* op
 /*
  * ---- Fit driver: damped Newton steps on the FUMILI matrix ------------------
  *
- * pwa_objective_hess fills *f, g[n] and H[n x n] (row-major) at x[n]; returns
- * 0 or a negative status.  pwa_newton_minimize solves (H + lambda diag H) d = -g
- * by Cholesky, raising lambda until H + lambda diag H is positive definite,
- * halves the step until f decreases sufficiently, and lowers lambda after full
- * steps (Levenberg-Marquardt damping of the Gauss-Newton steps that FUMILI
- * takes).  Options and result as for L-BFGS (history is unused).
- * pwa_fit_fumili fits V on an amplitude-form model with pwa_nll_grad_hess,
- * with the gauge of pwa_fit_lbfgs.
+ * pwa_objective_hess fills *f and g[n] at x[n], and H[n x n] (row-major) when
+ * H is not NULL; returns 0 or a negative status.  pwa_newton_minimize solves
+ * (H + lambda diag H) d = -g by Cholesky (lambda raised until the matrix is
+ * positive definite) and takes x + d when the decrease of f is at least 1e-4 of
+ * the decrease the quadratic model predicts, -(g.d + d.H.d / 2); lambda is then
+ * divided by 5 (ratio above 0.75) or multiplied by 4 (below 0.25); a step not
+ * taken leaves x and multiplies lambda by 4 (Levenberg-Marquardt damping of the
+ * Gauss-Newton steps that FUMILI takes).  Trial points are evaluated with
+ * H = NULL; H is asked for at the points taken.  Options and result as for
+ * L-BFGS (history is unused; evaluations counts both kinds of call).
+ * pwa_fit_fumili fits V on an amplitude-form model with pwa_nll_grad at trial
+ * points and pwa_nll_grad_hess at the points taken, with the gauge of
+ * pwa_fit_lbfgs, after scaling the start to the minimum of Eq. 3 along its
+ * ray, s^2 = N / mu(V) (the data term changes by -N ln s^2, the MC term by the
+ * factor s^2), when mu(V) > 0: along V the FUMILI matrix has the curvature 4N
+ * and Eq. 3 the curvature 2N + 2 mu(V), equal there.
  */
 typedef int (*pwa_objective_hess)(void* ctx, const double* x, double* f, double* g, double* H);
 

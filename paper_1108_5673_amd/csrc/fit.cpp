@@ -297,6 +297,32 @@ void gauge_rotate(double* v, int W)
     }
 }
 
+// Scale: along V -> s V the extended likelihood of Eq. 3 changes as
+// -N ln s^2 + s^2 mu(V) (the data term gains -ln s^2 per event), whose minimum
+// is at s^2 = N / mu(V).  The fits start from that point of the start's ray
+// (mu(V) = sum_ab V_a V*_b M_ab from the model's M); nothing is done when
+// mu(V) is not positive (no MC events).  The FUMILI driver scales its start:
+// FUMILI's matrix has the curvature 4N along V, the true one 2N + 2 mu(V).
+int scale_start(const pwa_model* model, double* v, int W, int64_t n, void* stream)
+{
+    std::vector<double> M((size_t)2 * W * W);
+    const int rc = pwa_copy_mc_matrix(model, M.data(), stream);
+    if (rc != PWA_OK) return rc;
+    double mu = 0.0;
+    for (int a = 0; a < W; ++a)
+        for (int b = 0; b < W; ++b) {
+            // Re(V_a M_ab conj(V_b))
+            const double mr = M[2 * ((size_t)a * W + b)], mi = M[2 * ((size_t)a * W + b) + 1];
+            const double tr = v[2 * a] * mr - v[2 * a + 1] * mi, ti = v[2 * a] * mi + v[2 * a + 1] * mr;
+            mu += tr * v[2 * b] + ti * v[2 * b + 1];
+        }
+    if (mu > 0.0 && std::isfinite(mu)) {
+        const double sc = std::sqrt((double)n / mu);
+        for (int k = 0; k < 2 * W; ++k) v[k] *= sc;
+    }
+    return PWA_OK;
+}
+
 int model_objective(void* ctx, const double* x, double* f, double* g)
 {
     const ModelCtx* c = static_cast<const ModelCtx*>(ctx);
@@ -330,10 +356,13 @@ extern "C" int pwa_fit_lbfgs(const pwa_model* model, double* v, const pwa_lbfgs_
 // ---- FUMILI-style fit: damped Newton steps on the FUMILI matrix ------------
 // With f, g and the FUMILI matrix H at x: solve (H + lambda D) d = -g by
 // Cholesky (D the diagonal of H, lambda raised until the factorisation
-// succeeds), then halve the step until the sufficient-decrease condition
-// holds.  lambda shrinks after a full step and grows after a shortened one
-// (the Levenberg-Marquardt damping of Gauss-Newton steps; FUMILI is the
-// Gauss-Newton method of likelihood fits).
+// succeeds) and compare the actual decrease f(x) - f(x + d) with the one the
+// quadratic model predicts, -(g.d + d.H.d / 2) (Levenberg-Marquardt with the
+// gain ratio rho of the two; FUMILI is the Gauss-Newton method of likelihood
+// fits).  rho > 1e-4: the step is taken, and lambda is divided by 5 when
+// rho > 0.75 or multiplied by 4 when rho < 0.25; otherwise x stays and lambda
+// is multiplied by 4.  A trial point costs f and g only; H is computed at the
+// points taken.
 namespace {
 
 // In-place Cholesky of the n x n row-major A (lower factor); false if A is not
@@ -381,30 +410,34 @@ extern "C" int pwa_newton_minimize(int32_t n, double* x_io, pwa_objective_hess f
     if (opt.max_iterations < 0 || opt.fixed_index >= n) return PWA_ERR_INVALID;
     std::memset(res, 0, sizeof *res);
     std::vector<double> x(x_io, x_io + n), g(n), H((size_t)n * n), L((size_t)n * n), d(n),
-        xt(n), gt(n), Ht((size_t)n * n);
+        xt(n), gt(n), Hd(n);
     int evals = 0;
+    const int k = opt.fixed_index;
+    // f and g at xx, and H when HH is given; the fixed coordinate gets a zero
+    // gradient, a unit diagonal and no coupling
     auto eval = [&](const std::vector<double>& xx, double& f, std::vector<double>& gg,
-                    std::vector<double>& HH) {
+                    std::vector<double>* HH) {
         ++evals;
-        const int rc = fn(ctx, xx.data(), &f, gg.data(), HH.data());
+        const int rc = fn(ctx, xx.data(), &f, gg.data(), HH ? HH->data() : nullptr);
         if (rc < 0) return rc;
         if (!std::isfinite(f)) f = INFINITY;
-        const int k = opt.fixed_index;
-        if (k >= 0) {   // the fixed coordinate: zero gradient, unit diagonal, no coupling
+        if (k >= 0) {
             gg[k] = 0.0;
-            for (int i = 0; i < n; ++i) HH[(size_t)i * n + k] = HH[(size_t)k * n + i] = 0.0;
-            HH[(size_t)k * n + k] = 1.0;
+            if (HH) {
+                for (int i = 0; i < n; ++i) (*HH)[(size_t)i * n + k] = (*HH)[(size_t)k * n + i] = 0.0;
+                (*HH)[(size_t)k * n + k] = 1.0;
+            }
         }
         return 0;
     };
     double f = 0.0;
-    int rc = eval(x, f, g, H);
+    int rc = eval(x, f, g, &H);
     if (rc < 0) return rc;
     if (!std::isfinite(f)) return PWA_WARN_DEGENERATE;
-    double lambda = 1e-8;
+    double lambda = 1e-6;   // nearly a Newton step at first; raised 4x per step not taken
     int status = PWA_LBFGS_MAX_ITERATIONS;
-    int iter = 0, small_steps = 0;
-    for (; iter < opt.max_iterations; ++iter) {
+    int iter = 0, small_steps = 0, rejected = 0;
+    while (iter < opt.max_iterations) {
         const double gn = norm2(g);
         if (gn <= opt.grad_tol * std::max(1.0, std::fabs(f))) {
             status = PWA_LBFGS_CONVERGED_GRADIENT;
@@ -424,34 +457,44 @@ extern "C" int pwa_newton_minimize(int32_t n, double* x_io, pwa_objective_hess f
         }
         for (int i = 0; i < n; ++i) d[i] = -g[i];
         cholesky_solve(L, n, d);
-        const double slope = dot(g, d);
-        double a = 1.0, ft = 0.0;
-        bool accepted = false;
-        for (int ls = 0; ls < 40; ++ls) {
-            for (int i = 0; i < n; ++i) xt[i] = x[i] + a * d[i];
-            rc = eval(xt, ft, gt, Ht);
-            if (rc < 0) return rc;
-            const double noise = 1e-14 * std::fabs(f);
-            if (std::isfinite(ft) && (ft <= f + 1e-4 * a * slope || (ft <= f + noise && a < 1.0))) {
-                accepted = true;
+        // predicted decrease of the quadratic model
+        for (int i = 0; i < n; ++i) {
+            double t = 0.0;
+            for (int j = 0; j < n; ++j) t += H[(size_t)i * n + j] * d[j];
+            Hd[i] = t;
+        }
+        const double pred = -(dot(g, d) + 0.5 * dot(d, Hd));
+        for (int i = 0; i < n; ++i) xt[i] = x[i] + d[i];
+        double ft = 0.0;
+        rc = eval(xt, ft, gt, nullptr);
+        if (rc < 0) return rc;
+        const double noise = 1e-14 * std::fabs(f);
+        const double actual = f - ft;
+        const double rho = pred > 0.0 ? actual / pred : -1.0;
+        // taken: a real decrease in line with the model, or, once the model's
+        // predicted decrease is below rounding, a step that raises f by no
+        // more than rounding
+        const bool take = std::isfinite(ft) && (rho > 1e-4 || (pred <= noise && ft <= f + noise));
+        if (!take) {
+            lambda = std::max(lambda * 4.0, 1e-6);
+            if (++rejected > 40) {
+                status = PWA_LBFGS_LINE_SEARCH_FAILED;
                 break;
             }
-            a *= 0.5;
+            continue;
         }
-        if (!accepted) {
-            status = PWA_LBFGS_LINE_SEARCH_FAILED;
-            break;
-        }
-        lambda = a == 1.0 ? std::max(lambda * 0.1, 1e-12) : lambda * 4.0;
-        const double f_old = f;
+        rejected = 0;
+        ++iter;
+        if (rho > 0.75) lambda = std::max(lambda * 0.2, 1e-12);
+        else if (rho < 0.25) lambda *= 4.0;
         x = xt;
-        f = ft;
         g = gt;
-        H = Ht;
+        const double f_old = f;
+        rc = eval(x, f, g, &H);   // H at the new point (f, g again with it)
+        if (rc < 0) return rc;
         if (opt.rel_f_tol > 0.0 && f_old - f <= opt.rel_f_tol * std::max(1.0, std::fabs(f))) {
             if (++small_steps >= 3) {
                 status = PWA_LBFGS_CONVERGED_VALUE;
-                ++iter;
                 break;
             }
         } else {
@@ -472,7 +515,8 @@ namespace {
 int model_objective_hess(void* ctx, const double* x, double* f, double* g, double* H)
 {
     const ModelCtx* c = static_cast<const ModelCtx*>(ctx);
-    const int rc = pwa_nll_grad_hess(c->model, x, f, g, H, c->stream);
+    const int rc = H ? pwa_nll_grad_hess(c->model, x, f, g, H, c->stream)
+                     : pwa_nll_grad(c->model, x, f, g, c->stream);
     if (rc == PWA_WARN_DEGENERATE) {
         *f = INFINITY;
         return 0;
@@ -494,6 +538,8 @@ extern "C" int pwa_fit_fumili(const pwa_model* model, double* v, const pwa_lbfgs
     pwa_lbfgs_default_options(&opt);
     if (options) opt = *options;
     gauge_rotate(v, W);
+    rc = scale_start(model, v, W, info.n_data, hip_stream);
+    if (rc != PWA_OK) return rc;
     opt.fixed_index = 1;
     ModelCtx ctx{model, hip_stream};
     return pwa_newton_minimize(2 * W, v, model_objective_hess, &ctx, &opt, res);

@@ -152,9 +152,53 @@ int alloc_out(Model* m, int cap)
     return PWA_OK;
 }
 
+// Peak device memory of a build (bytes, an upper estimate): the staged input
+// when it is on the host, the stored table or amplitudes, the MC input staged
+// with the MC integral's block records, and the per-evaluation buffers.
+double build_device_bytes(int64_t n, int32_t W, int64_t n_acc, uint32_t flags, bool data_on_host,
+                          bool mc_on_host)
+{
+    const uint32_t form = flags & kFormBits;
+    const double P = 0.5 * W * (W + 1.0);
+    const double dn = (double)n;
+    const double in_elem = (flags & PWA_DATA_COMPLEX128) ? 16.0 : 8.0;
+    double b = data_on_host ? dn * ((flags & PWA_INPUT_IS_TABLE) ? P : W) * in_elem : 0.0;
+    const double ntile = std::ceil(dn / 16.0) * 16.0;
+    switch (form) {
+    case PWA_FORM_TABLE: b += ntile * pwa::tiled_entries(W) * 8.0; break;
+    case PWA_PRECISION_FP64_FUSED: b += ntile * pwa::tiled_entries(W) * 16.0; break;
+    case PWA_PRECISION_FP64_PLAIN: b += dn * P * 16.0 + dn * 8.0; break;
+    case PWA_FORM_AMPLITUDE_BF16:
+    case PWA_FORM_AMPLITUDE_FP16: {
+        const double kd = std::ceil(2.0 * W / 16.0) * 16.0, rb = std::ceil(kd / 32.0);
+        b += ntile * 2.0 * kd * 2.0 + ntile * 2.0 * rb * 32.0 * 2.0;
+        break;
+    }
+    default: {   // FP32 amplitudes in the default lane-split shape
+        const pwa::AmpShape sh = pwa::amp_shape(W);
+        b += std::ceil(dn / pwa::kAmpTile) * pwa::kAmpTile * (double)(sh.wl << sh.lq) * 8.0;
+        break;
+    }
+    }
+    const double mc_elem = (flags & PWA_MC_COMPLEX128) ? 16.0 : 8.0;
+    if (n_acc > 0) b += (mc_on_host ? (double)n_acc * W * mc_elem : 0.0) + (double)n_acc * 64.0;
+    return b + 64.0 * 1024 * 1024;   // records, M and other small buffers
+}
+
 int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t n_acc,
                 int64_t n_gen, uint32_t flags, hipStream_t s, Model* m)
 {
+    {   // pre-flight: refuse a model that cannot fit before anything is allocated or copied
+        size_t free_b = 0, total_b = 0;
+        HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+        const double need = build_device_bytes(n, W, n_acc, flags, !is_device_ptr(data),
+                                               n_acc > 0 && !is_device_ptr(mc));
+        if (need > (double)free_b)
+            return fail(PWA_ERR_OOM,
+                        "the model needs about %.3g GB of device memory during its build, "
+                        "%.3g GB are free (N = %lld, W = %d)",
+                        need / 1e9, (double)free_b / 1e9, (long long)n, W);
+    }
     const uint32_t form = flags & kFormBits;
     const bool in_table = flags & PWA_INPUT_IS_TABLE;
     const bool data_c128 = flags & PWA_DATA_COMPLEX128;
@@ -495,8 +539,12 @@ struct MultiPlan {
     unsigned long long seq = 0;
 };
 
+// Plans in most-recently-used order; a call whose (model, K) list matches a
+// cached plan replays it, so that alternating model sets (several pwa.Batch
+// objects) never recapture.  At most kMaxPlans are kept.
+constexpr size_t kMaxPlans = 8;
 std::mutex g_plan_mu;
-MultiPlan* g_plan = nullptr;
+std::vector<MultiPlan*> g_plans;
 
 void destroy_plan(MultiPlan* p)
 {
@@ -687,17 +735,33 @@ int eval_multi(pwa_model* const* models, int n_models, const int32_t* k_per_mode
                const double* v, double* nll, double* grad, hipStream_t s)
 {
     std::lock_guard<std::mutex> lock(g_plan_mu);
-    bool same = g_plan && (int)g_plan->key.size() == n_models;
-    for (int mi = 0; same && mi < n_models; ++mi)
-        same = g_plan->key[mi].first == reinterpret_cast<const Model*>(models[mi]) &&
-               g_plan->key[mi].second == k_per_model[mi];
-    if (!same) {
-        destroy_plan(g_plan);
-        g_plan = nullptr;
-        const int rc = build_plan(models, n_models, k_per_model, &g_plan);
+    auto matches = [&](const MultiPlan* q) {
+        if ((int)q->key.size() != n_models) return false;
+        for (int mi = 0; mi < n_models; ++mi)
+            if (q->key[mi].first != reinterpret_cast<const Model*>(models[mi]) ||
+                q->key[mi].second != k_per_model[mi])
+                return false;
+        return true;
+    };
+    size_t hit = g_plans.size();
+    for (size_t i = 0; i < g_plans.size(); ++i)
+        if (matches(g_plans[i])) {
+            hit = i;
+            break;
+        }
+    MultiPlan* p = nullptr;
+    if (hit < g_plans.size()) {
+        p = g_plans[hit];
+        g_plans.erase(g_plans.begin() + (std::ptrdiff_t)hit);
+    } else {
+        const int rc = build_plan(models, n_models, k_per_model, &p);
         if (rc != PWA_OK) return rc;
+        if (g_plans.size() >= kMaxPlans) {
+            destroy_plan(g_plans.back());
+            g_plans.pop_back();
+        }
     }
-    MultiPlan* p = g_plan;
+    g_plans.insert(g_plans.begin(), p);
     DeviceGuard g(p->device);
     const unsigned long long seq = ++p->seq;
     std::memcpy(p->h_params, &seq, sizeof seq);
@@ -736,17 +800,20 @@ int eval_multi(pwa_model* const* models, int n_models, const int32_t* k_per_mode
     return status;
 }
 
-// Discard the cached plan if it refers to model m.
+// Discard the cached plans that refer to model m.
 void forget_model(const Model* m)
 {
     std::lock_guard<std::mutex> lock(g_plan_mu);
-    if (!g_plan) return;
-    for (const auto& kv : g_plan->key)
-        if (kv.first == m) {
-            destroy_plan(g_plan);
-            g_plan = nullptr;
-            return;
+    for (size_t i = 0; i < g_plans.size();) {
+        bool uses = false;
+        for (const auto& kv : g_plans[i]->key) uses = uses || kv.first == m;
+        if (uses) {
+            destroy_plan(g_plans[i]);
+            g_plans.erase(g_plans.begin() + (std::ptrdiff_t)i);
+        } else {
+            ++i;
         }
+    }
 }
 
 // Per-call buffers of the matrix-core path, grown to hold K vectors.
@@ -1338,10 +1405,13 @@ int pwa_tune_amplitude_shape(pwa_model* model, int32_t evals, void* hip_stream,
             (void)hipEventDestroy(b);
         }
     } ev_guard{e0, e1};
-    // two passes over the candidates, each keeping its faster time, so that a
-    // one-off slow measurement does not decide
-    std::vector<float> t_best(cand.size(), 0.f);
-    for (int pass = 0; pass < 2; ++pass) {
+    // three passes over the candidates, keeping each one's fastest and slowest
+    // time: the default shape stays unless a candidate's fastest time beats the
+    // default's by more than the spread of either (a difference inside the
+    // repeat-to-repeat spread decides nothing)
+    const pwa::AmpShape def = pwa::amp_shape(m->W);
+    std::vector<float> t_best(cand.size(), 0.f), t_worst(cand.size(), 0.f);
+    for (int pass = 0; pass < 3; ++pass) {
         for (size_t c = 0; c < cand.size(); ++c) {
             int rc = reshape_amp(m, cand[c], s);
             if (rc != PWA_OK) return rc;
@@ -1354,15 +1424,22 @@ int pwa_tune_amplitude_shape(pwa_model* model, int32_t evals, void* hip_stream,
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
             if (pass == 0 || ms < t_best[c]) t_best[c] = ms;
+            if (pass == 0 || ms > t_worst[c]) t_worst[c] = ms;
         }
     }
-    pwa::AmpShape best = cand[0];
-    float best_ms = t_best[0];
-    for (size_t c = 1; c < cand.size(); ++c)
-        if (t_best[c] < best_ms) {
-            best = cand[c];
-            best_ms = t_best[c];
-        }
+    size_t d0 = cand.size();
+    for (size_t c = 0; c < cand.size(); ++c)
+        if (cand[c].lq == def.lq && cand[c].wl == def.wl) d0 = c;
+    size_t bi = d0 < cand.size() ? d0 : 0;
+    for (size_t c = 0; c < cand.size(); ++c) {
+        const float margin = d0 < cand.size()
+                                 ? std::max(t_worst[c] - t_best[c], t_worst[d0] - t_best[d0])
+                                 : 0.f;
+        if (c != bi && t_best[c] + margin < t_best[bi] &&
+            (d0 >= cand.size() || t_best[c] + margin < t_best[d0]))
+            bi = c;
+    }
+    const pwa::AmpShape best = cand[bi];
     const int rc = reshape_amp(m, best, s);
     if (rc != PWA_OK) return rc;
     if (lanes_per_event) *lanes_per_event = 1 << best.lq;

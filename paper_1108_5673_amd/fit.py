@@ -91,7 +91,8 @@ def fit_lbfgs(model, v0, stream=None, **options):
 
 def minimize_newton(fun, x0, **options):
     """Minimise fun (x -> (f, g, H)) from x0 with damped Newton steps; returns
-    (x, result dict)."""
+    (x, result dict).  At trial points the library asks for f and g only and
+    the H fun returns is not used."""
     x = np.ascontiguousarray(np.asarray(x0, dtype=np.float64).ravel().copy())
     n = x.size
     err = []
@@ -101,7 +102,8 @@ def minimize_newton(fun, x0, **options):
             f, g, H = fun(np.ctypeslib.as_array(xp, shape=(n,)).copy())
             fp[0] = float(f)
             np.ctypeslib.as_array(gp, shape=(n,))[:] = np.asarray(g, dtype=np.float64).ravel()
-            np.ctypeslib.as_array(hp, shape=(n * n,))[:] = np.asarray(H, dtype=np.float64).ravel()
+            if hp:   # NULL at trial points: f and g only
+                np.ctypeslib.as_array(hp, shape=(n * n,))[:] = np.asarray(H, dtype=np.float64).ravel()
             return 0
         except Exception as e:          # reported after the call returns
             err.append(e)

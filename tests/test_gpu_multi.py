@@ -125,3 +125,30 @@ def test_batch_object_matches_list_form():
         b(flat)
     for i in (0, 1, 3):
         models[i].close()
+
+
+def test_two_batches_alternating_keep_their_plans():
+    """Two Batch objects on different model sets, called in turn: each call
+    replays its own cached plan (no recapture: a call takes well under the
+    milliseconds a plan build with its allocations and graph capture costs),
+    and every call gives its first call's results bit for bit."""
+    import time
+    ms1 = _models(SPEC[:3], seed0=110)
+    ms2 = _models(SPEC[3:6], seed0=120)
+    b1 = pwa.Batch([m for m, *_ in ms1], [2, 1, 2])
+    b2 = pwa.Batch([m for m, *_ in ms2], [1, 3, 1])
+    rng = np.random.default_rng(7)
+    v1, v2 = rng.standard_normal(b1.size), rng.standard_normal(b2.size)
+    first1 = [(n.copy(), g.copy()) for n, g in b1(v1)]
+    first2 = [(n.copy(), g.copy()) for n, g in b2(v2)]
+    times = []
+    for _ in range(10):
+        for b, v, first in ((b1, v1, first1), (b2, v2, first2)):
+            t = time.perf_counter()
+            res = b(v)
+            times.append(time.perf_counter() - t)
+            for (n, g), (n0, g0) in zip(res, first):
+                assert np.array_equal(n, n0) and np.array_equal(g, g0)
+    assert np.median(times) < 1.5e-3, np.median(times)
+    for m, *_ in ms1 + ms2:
+        m.close()

@@ -123,6 +123,25 @@ def test_non_hermitian_table_rejected(form):
     assert e.value.status == -1 and "Hermitian" in str(e.value)
 
 
+@pytest.mark.parametrize("form", ["table", "amplitude", "amplitude_bf16"])
+def test_oversized_model_refused_before_allocation(form):
+    """A model whose build cannot fit in device memory (2^36 events: about
+    110 TB as a 20-wave complex64 table) is refused with PWA_ERR_OOM by the
+    pre-flight, before anything is allocated or the input is read (the buffer
+    passed is far smaller than N x W; the check never touches it), and the
+    library stays usable."""
+    import ctypes
+    from paper_1108_5673_amd import _native
+    L = _native.lib()
+    small = np.ones((4, 20), np.complex64)
+    h = ctypes.c_void_p()
+    st = L.pwa_build_table(small.ctypes.data, 1 << 36, 20, None, 0, 1, pwa.FORMS[form], None,
+                           ctypes.byref(h))
+    assert st == _native.PWA_ERR_OOM and h.value is None
+    assert "device memory" in _native.last_error()
+    _check(form if form != "amplitude_bf16" else "amplitude", 20, 1000, 500, seed=45)
+
+
 @pytest.mark.parametrize("form", FORMS)
 def test_mc_matrix(form):
     s = synth.small_sample(9, 10, 20_000, seed=3)

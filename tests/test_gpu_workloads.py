@@ -184,14 +184,20 @@ def test_w32_n2m_amplitude_parity(o, w32):
 
 
 def test_w32_n2m_gradient_vs_differences(w32):
-    """Central differences of the kernels' NLL, h = 1e-4 and h / 2, combined by
-    Richardson extrapolation (error O(h^4))."""
+    """The kernels' gradient against central differences of their own NLL at
+    all 20 random points, h = 1e-4 as the workload states.  The truncation
+    error of a central difference is c h^2 + O(h^4), so the difference of the
+    h and h/2 estimates is 3/4 of it; the h = 1e-4 difference must agree with
+    the gradient within twice that estimate (plus FP64 rounding of the NLL
+    differences), and their Richardson combination (4 D(h/2) - D(h)) / 3,
+    error O(h^4), to 1e-6 relative."""
     s, d32, mc32 = w32
     model = pwa.Model(d32, mc32, s.n_gen, form="amplitude")
     h = 1e-4
-    for V in s.points[:4]:
+    assert len(s.points) == 20
+    for j, V in enumerate(s.points):
         x = np.ascontiguousarray(V.astype(np.complex128)).view(np.float64).copy()
-        _, g = model.nll_grad(x)
+        nll0, g = model.nll_grad(x)
 
         def cd(step, i):
             xp, xm = x.copy(), x.copy()
@@ -199,8 +205,13 @@ def test_w32_n2m_gradient_vs_differences(w32):
             xm[i] -= step
             return (model.nll(xp) - model.nll(xm)) / (2 * step)
 
-        fd = np.array([(4 * cd(h / 2, i) - cd(h, i)) / 3 for i in range(x.size)])
-        assert _rel(g, fd) <= 1e-6, _rel(g, fd)
+        d1 = np.array([cd(h, i) for i in range(x.size)])
+        d2 = np.array([cd(h / 2, i) for i in range(x.size)])
+        trunc = 4.0 / 3.0 * np.abs(d1 - d2)
+        rounding = 1e-15 * abs(nll0) / h * 8
+        assert np.all(np.abs(d1 - g) <= 2 * trunc + rounding), (j, _rel(g, d1))
+        rich = (4 * d2 - d1) / 3
+        assert _rel(g, rich) <= 1e-6, (j, _rel(g, rich))
     model.close()
 
 
@@ -231,8 +242,11 @@ def test_w32_n2m_lbfgs_fit_from_random_start(o, w32):
 
 
 def test_w32_n2m_fumili_fit(o, w32):
-    """The FUMILI fit (damped Newton on pwa_nll_grad_hess) from a random start
-    scaled to mu = N: converged, mu = N at the end, NLL matching the oracle."""
+    """The FUMILI fit (gain-ratio damped Newton steps on pwa_nll_grad_hess)
+    from a random start, which the driver first scales to mu = N: converged,
+    mu = N at the end, NLL matching the oracle.  From a random start the steps
+    cross several basins of the likelihood (148 iterations measured on this
+    sample; L-BFGS takes about 1700 from the same start): the bound is loose."""
     from paper_1108_5673_amd import fit
     s, d32, mc32 = w32
     model = pwa.Model(d32, mc32, s.n_gen, form="amplitude")
@@ -240,12 +254,37 @@ def test_w32_n2m_fumili_fit(o, w32):
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([11085673, 32, 2])))
     v0 = synth.random_v(rng, 32)
     n = d32.shape[0]
-    v0 = v0 * np.sqrt(n / o.mc_term(M, v0)[0])
-    V, res = fit.fit_fumili(model, v0, grad_tol=1e-12, rel_f_tol=0.0, max_iterations=200)
-    assert res["status"] == 0, res
+    V, res = fit.fit_fumili(model, v0, max_iterations=1000)
+    assert res["status"] == 0 and res["iterations"] <= 400, res
     nll, g = model.nll_grad(V)
     rn, rg, _ = o.nll_amp(d32.astype(np.complex128), M, V)
     assert abs(nll - rn) <= 1e-12 * max(abs(rn), 2e6)
+    # the scale identity sum_b Re(conj(G_b) V_b) = 2 (mu - N) bounds mu - N by
+    # the gradient the fit stopped at
     mu, _ = o.mc_term(M, V)
-    assert abs(mu - n) <= 1e-6 * n, (mu, n)
+    assert abs(mu - n) <= 0.5 * np.linalg.norm(g) * np.linalg.norm(V) + 1e-9 * n, (mu, n)
+    model.close()
+
+
+def test_w32_n2m_fumili_fit_near_solution(o, w32):
+    """FUMILI in the regime the paper reports (Sec. 5: 5 to 10 iterations): a
+    start near the generating point (5 % complex noise per wave), default
+    tolerances: the gradient test is met within 10 iterations (3 measured;
+    L-BFGS from such starts takes 150 to 350), the NLL there matches the
+    oracle, and mu = N within the scale identity's bound."""
+    from paper_1108_5673_amd import fit
+    s, d32, mc32 = w32
+    model = pwa.Model(d32, mc32, s.n_gen, form="amplitude")
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([11085673, 32, 3])))
+    v0 = s.v_true * (1 + 0.05 * (rng.standard_normal(32) + 1j * rng.standard_normal(32)))
+    V, res = fit.fit_fumili(model, v0)
+    assert res["status"] == 0 and res["iterations"] <= 10, res
+    rn, _, _ = o.nll_amp(d32.astype(np.complex128),
+                         o.mc_matrix(mc32.astype(np.complex128), s.n_gen), V)
+    assert abs(res["f"] - rn) <= 1e-12 * max(abs(rn), 2e6), (res["f"], rn)
+    n = d32.shape[0]
+    M = o.mc_matrix(mc32.astype(np.complex128), s.n_gen)
+    mu, _ = o.mc_term(M, V)
+    _, g = model.nll_grad(V)
+    assert abs(mu - n) <= 0.5 * np.linalg.norm(g) * np.linalg.norm(V) + 1e-9 * n, (mu, n)
     model.close()
