@@ -109,7 +109,7 @@ def host_cpu():
 def mfma_flops(n_events, n_waves, k, v_parts):
     """Matrix-core FLOPs of one batched pass as the kernel issues them: per
     16-event tile (32 rows) and 32 vectors, the forward product (16-wide KD
-    steps x V parts) and the adjoint (32-row blocks x 2 slot steps x 2 weight
+    steps x V parts, two) and the adjoint (32-row blocks x 2 slot steps x 2 weight
     parts), each a 32x32x16 MFMA of 32768 FLOP."""
     kd = (2 * n_waves + 15) // 16 * 16
     rb = (kd + 31) // 32
@@ -146,7 +146,7 @@ def bench_batched(args):
         out["oracle"] = {"evals_per_s": len(ref) / (time.perf_counter() - t),
                          "cores": o.num_threads(),
                          "sample": "vectors 0, 85, 170, 255 on the FP64 amplitudes"}
-    for form, parts in (("amplitude_bf16", 3), ("amplitude_fp16", 2)):
+    for form, parts in (("amplitude_bf16", 2), ("amplitude_fp16", 2)):
         m = pwa.Model(d32, mc32, s.n_gen, form=form)
         for _ in range(2):
             pwa.nll_batched([m], [s.points])

@@ -114,8 +114,9 @@ typedef enum pwa_flags {
  * (complex128 input is rounded to float first; float16 results below 2^-14 in
  * magnitude are stored as zero); they evaluate through the
  * matrix cores: each call, single or batched, runs one pass over the events
- * for all its vectors, with V split into 16-bit parts (three for bfloat16, two
- * for float16), FP32 products and FP64 sums across events.
+ * for all its vectors, with V split into two 16-bit parts (16 significant bits
+ * for bfloat16, 22 for float16; the first-order share of the NLL of what the
+ * parts leave out is added back), FP32 products and FP64 sums across events.
  */
 int pwa_build_table(const void* data, int64_t n_data, int32_t n_waves,
                     const void* mc_amp, int64_t n_mc_acc, int64_t n_mc_gen,

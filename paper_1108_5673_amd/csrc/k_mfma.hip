@@ -35,10 +35,13 @@
 // V (float16 has a narrow exponent range); the assembly undoes it exactly:
 // ln I = ln I' + 2 ln s_k and g = g' / s_k.
 // Accuracy: the amplitudes are stored in the 16-bit type (the input of this
-// form).  V is split into 16-bit parts (three for bf16, two for fp16: about
-// 24 and 22 significant bits) whose products are accumulated, so that the
-// parameters, which every event shares, add no coherent 16-bit rounding; the
-// weights c are split into two parts (see Split below).  Per lane, log2 I of
+// form).  V is split into two 16-bit parts (about 16 significant bits for
+// bf16, 22 for fp16) whose products are accumulated; the part of V they leave
+// out changes every S_i coherently, and its first-order share of sum ln I,
+// 2 Re sum_a V_lo,a conj(g_a) (g the adjoint sums the kernel forms anyway), is
+// added back in the assembly, so that the parameters, which every event
+// shares, add no coherent 16-bit rounding to the NLL.  The weights c are split
+// into two parts (see Split below).  Per lane, log2 I of
 // the step's eight (event, vector) pairs is taken in FP32 (hardware v_log_f32)
 // and summed in FP32, then added to an FP64 lane sum.  The adjoint's FP32
 // accumulators add at most kFoldTiles tiles: they are then added into FP64
@@ -60,7 +63,7 @@ namespace pwa {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // Splitting a value into 16-bit parts.  bf16 has the exponent range of FP32,
-// so its parts (three for V, two for c) are plain successive remainders,
+// so its parts (two for V and two for c) are plain successive remainders,
 // accumulated together.  fp16 would make the low part subnormal for values
 // below about 0.125, and subnormal fp16 inputs do not reliably survive the
 // conversion and the matrix product, so an fp16 split keeps every part normal:
@@ -68,7 +71,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // and accumulated on its own, and the two accumulators are recombined exactly.
 template <typename T> struct Split;
 template <> struct Split<__bf16> {
-    static constexpr int kVParts = 3;
+    static constexpr int kVParts = 2;
     static constexpr bool kScaledLow = false;
 };
 template <> struct Split<_Float16> {
@@ -238,6 +241,38 @@ __device__ inline double vector_scale(const double* vk, int W)
     return ldexp(1.0, (int)rint(0.5 * log2(nn)));
 }
 
+// The 16-bit parts of one entry x of the scaled vector matrix (x = Re V_a / s
+// or -Im V_a / s) and the remainder they leave out, x minus their sum: bf16
+// takes two successive remainders, each rounded to nearest (16 significant
+// bits in all); fp16 a high part (zero below 2^-14) and the low part times
+// 2^11 (22 bits).  The remainder's share of the NLL is added back in the
+// assembly (k_assemble_mfma).
+template <typename T> struct VSplit {
+    T p[Split<T>::kVParts];
+    double rest;
+};
+template <typename T> __device__ inline VSplit<T> split_v(double x)
+{
+    VSplit<T> r;
+    if constexpr (Split<T>::kScaledLow) {
+        const T hi = split_hi<T>((float)x);
+        const double d = x - (double)(float)hi;
+        const T lo = round16<T>((float)(d * kLowScale));
+        r.p[0] = hi;
+        r.p[1] = lo;
+        r.rest = d - (double)(float)lo * (double)kLowUnscale;
+    } else {
+#pragma unroll
+        for (int q = 0; q < Split<T>::kVParts; ++q) {
+            const T y = round16<T>((float)x);
+            r.p[q] = y;
+            x -= (double)(float)y;
+        }
+        r.rest = x;
+    }
+    return r;
+}
+
 template <typename T>
 __global__ void k_prep_vmat16(const double* __restrict__ v, int K, int W, int NS, int n_cb,
                               int NP, T* __restrict__ vm, double* __restrict__ vscale)
@@ -260,19 +295,11 @@ __global__ void k_prep_vmat16(const double* __restrict__ v, int K, int W, int NS
             x = kd % 2 == 0 ? v[(size_t)k * 2 * W + 2 * a] / sk        // multiplies Re A_a
                             : -v[(size_t)k * 2 * W + 2 * a + 1] / sk;  // multiplies Im A_a
         }
-        if constexpr (Split<T>::kScaledLow) {
-            const T hi = split_hi<T>((float)x);
-            vm[g] = hi;
-            vm[(size_t)part_elems + g] = round16<T>((float)((x - (double)(float)hi) * kLowScale));
-        } else {
-            // successive remainders, each rounded to the 16-bit type
-            for (int p = 0; p < NP; ++p) {
-                const T y = round16<T>((float)x);
-                vm[(size_t)p * part_elems + g] = y;
-                x -= (double)(float)y;
-            }
-        }
+        const VSplit<T> sp = split_v<T>(x);
+#pragma unroll
+        for (int p = 0; p < Split<T>::kVParts; ++p) vm[(size_t)p * part_elems + g] = sp.p[p];
     }
+    (void)NP;
 }
 
 // ---- the fused forward + epilogue + adjoint kernel -------------------------
@@ -640,6 +667,7 @@ constexpr int kBatchAsmThreads = 256;
 // One block per vector k.  Every loop issues its loads in batches before
 // using them (a loop that adds each value as it arrives waits one memory round
 // trip per value).
+template <typename T>
 __global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt)
 {
     __shared__ double s_wave[kBatchAsmThreads / 64];
@@ -710,16 +738,28 @@ __global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt
         mu_part += s_v[2 * b] * s_m[b].x + s_v[2 * b + 1] * s_m[b].y;
     const double mu = block_sum_fixed(mu_part, s_wave);
     __syncthreads();   // s_part
+    // Component o of the scaled adjoint sums, g'_o (rows 2b, 2b + 1: Re, Im
+    // g'_b with g' = s g), and the first-order share of the part of V the
+    // split leaves out: with S' computed from V' - V'_lo, sum ln I' is low by
+    // 2 Re sum_b V'_lo,b conj(g'_b) (ln |S' + d|^2 = ln |S'|^2 + 2 Re(d / S') +
+    // O(d^2), and sum_i A_ib / S'_i = conj(g'_b)).  Entry o of the vector
+    // matrix is Re V'_b (o even) or -Im V'_b (o odd).
+    double corr = 0.0;
     if (threadIdx.x < nout) {
         double x = 0.0;
         for (int rr = 0; rr < R; ++rr) x += s_part[rr * nout + threadIdx.x];
-        x /= sk;
         const int b = threadIdx.x / 2, part = threadIdx.x % 2;
+        const double e = part == 0 ? s_v[2 * b] / sk : -s_v[2 * b + 1] / sk;
+        const double rest = split_v<T>(e).rest;
+        corr = 2.0 * (part == 0 ? rest : -rest) * x;
+        x /= sk;
         const double m = part == 0 ? s_m[b].x : s_m[b].y;
         store_system(bt.out + (size_t)k * (2 + 2 * W) + 2 + threadIdx.x, 2.0 * (m - x));
     }
+    const double dcorr = block_sum_fixed(corr, s_wave);
     if (threadIdx.x == 0) {
-        store_system(bt.out + (size_t)k * (2 + 2 * W), nbad > 0.0 ? INFINITY : (-dsum + mu));
+        store_system(bt.out + (size_t)k * (2 + 2 * W),
+                     nbad > 0.0 ? INFINITY : (-(dsum + dcorr) + mu));
         store_system(bt.out + (size_t)k * (2 + 2 * W) + 1, nbad);
     }
     if (!bt.done) return;   // results in device memory, stream-ordered: nothing to publish
@@ -831,7 +871,10 @@ hipError_t launch_mfma_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
     bt.out = b.out;
     bt.done = b.done;
     bt.seq = b.seq;
-    hipLaunchKernelGGL(k_assemble_mfma, dim3(b.K), dim3(kBatchAsmThreads), 0, s, bt);
+    if (m.form == kAmpBF16)
+        hipLaunchKernelGGL(k_assemble_mfma<__bf16>, dim3(b.K), dim3(kBatchAsmThreads), 0, s, bt);
+    else
+        hipLaunchKernelGGL(k_assemble_mfma<_Float16>, dim3(b.K), dim3(kBatchAsmThreads), 0, s, bt);
     return hipGetLastError();
 }
 
