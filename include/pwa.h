@@ -391,8 +391,11 @@ int pwa_lbfgs_minimize(int32_t n, double* x, pwa_objective fn, void* ctx,
  * Fit V on a model: minimise NLL(V) from v (2W doubles, host, overwritten with
  * the fitted V).  The NLL is invariant under a global phase of V, so the start
  * is first rotated to make V_0 real and non-negative and Im V_0 is then held
- * at zero (options->fixed_index is ignored); Re V_0 may change sign.  Each
- * objective call is one pwa_nll_grad on hip_stream.
+ * at zero (options->fixed_index is ignored); Re V_0 may change sign.  The
+ * start is then scaled to the minimum of Eq. 3 along its ray, s^2 = N / mu(V),
+ * when mu(V) > 0 (a start whose scale is far off otherwise takes the
+ * minimiser through other basins of the likelihood).  Each objective call is
+ * one pwa_nll_grad on hip_stream.
  */
 int pwa_fit_lbfgs(const pwa_model* model, double* v, const pwa_lbfgs_options* options,
                   pwa_lbfgs_result* res, void* hip_stream);

@@ -301,8 +301,9 @@ void gauge_rotate(double* v, int W)
 // -N ln s^2 + s^2 mu(V) (the data term gains -ln s^2 per event), whose minimum
 // is at s^2 = N / mu(V).  The fits start from that point of the start's ray
 // (mu(V) = sum_ab V_a V*_b M_ab from the model's M); nothing is done when
-// mu(V) is not positive (no MC events).  The FUMILI driver scales its start:
-// FUMILI's matrix has the curvature 4N along V, the true one 2N + 2 mu(V).
+// mu(V) is not positive (no MC events).  Both fit drivers scale their start:
+// it is the best point of the start's ray, and there FUMILI's matrix has the
+// true curvature along V (4N against 2N + 2 mu(V), equal at mu = N).
 int scale_start(const pwa_model* model, double* v, int W, int64_t n, void* stream)
 {
     std::vector<double> M((size_t)2 * W * W);
@@ -348,6 +349,8 @@ extern "C" int pwa_fit_lbfgs(const pwa_model* model, double* v, const pwa_lbfgs_
     pwa_lbfgs_default_options(&opt);
     if (options) opt = *options;
     gauge_rotate(v, W);
+    rc = scale_start(model, v, W, info.n_data, hip_stream);
+    if (rc != PWA_OK) return rc;
     opt.fixed_index = 1;
     ModelCtx ctx{model, hip_stream};
     return pwa_lbfgs_minimize(2 * W, v, model_objective, &ctx, &opt, res);
