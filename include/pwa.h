@@ -72,8 +72,10 @@ typedef enum pwa_flags {
     PWA_INPUT_IS_TABLE = 4,          /* `data` is an N x P packed Hermitian table, P = W(W+1)/2,
                                         entries (a, a') with a <= a' in row-major order of the
                                         upper triangle; any Hermitian positive semi-definite
-                                        per-event table is accepted, not only rank one.
-                                        Table forms only.                                        */
+                                        per-event table is accepted, not only rank one.  A
+                                        diagonal entry with a non-zero imaginary part makes
+                                        the build fail with PWA_ERR_INVALID (the stored
+                                        table keeps the diagonal real).  Table forms only.     */
     PWA_DATA_COMPLEX128 = 16,        /* `data` elements are complex128 (default complex64)        */
     PWA_MC_COMPLEX128 = 32           /* `mc_amp` elements are complex128 (default complex64)      */
 } pwa_flags;
@@ -104,6 +106,11 @@ typedef enum pwa_flags {
  *             it, not by N_acc).
  *   flags     pwa_flags.
  *   out       receives the new model; *out is NULL on error.
+ *
+ * Before anything is allocated or copied, the build estimates its peak device
+ * memory (staged input, stored table or amplitudes, MC staging and records)
+ * and returns PWA_ERR_OOM, with the estimate and the free memory in
+ * pwa_last_error(), when hipMemGetInfo reports less free.
  *
  * Table forms compute T_i,aa' in FP64 from the given amplitudes (each product
  * formed with a separately rounded multiply and add) and store it at the
