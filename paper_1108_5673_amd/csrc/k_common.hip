@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 #include "pwa_internal.h"
 #include "tail.h"
@@ -19,203 +20,12 @@
 namespace pwa {
 
 // ---- the MC integral: sum_j B_ja conj(B_jb) over accepted events ---------
-// A Hermitian rank-N_acc update, register-blocked: the waves form blocks of 4
-// and each thread accumulates the 4 x 4 complex products of one pair of
-// blocks (bp <= bq) in FP64 registers, over the events of its split of each
-// chunk (splits of the chunk's events when there are fewer than 256 pairs, up
-// to 3 pairs per thread beyond).  Chunks of E events are staged in LDS in the
-// input precision, the next chunk's loads in flight while the current one is
-// used.  Each block writes one record of 2P doubles in packed (a <= b) order;
-// k_colsum then sums the records in block order.
-constexpr int kGramMaxRows = 512;  // partial records of the MC matrix build
-constexpr int kGramMaxPairs = 3;   // block pairs per thread: nb(nb+1)/2 <= 768, W <= 152
-constexpr int kGramPre = 16;       // staged elements per thread and chunk (E x 4nb <= 4096)
-constexpr int kGramMfmaMaxTiles = 8;   // matrix-core build for 2W <= 128
+// Always on the FP64 matrix cores (below); k_colsum sums the block records.
+constexpr int kGramMaxRows = 512;      // partial records of the MC matrix build
+constexpr int kGramMfmaMaxTiles = 16;  // matrix-core build for 2W <= 256
 constexpr int kGramDepth = 8;          // steps of loads in flight per wavefront
 
-// events per chunk: as many as kGramPre elements per thread stage, in steps of 16
-int gram_chunk(int W)
-{
-    const int wp = 4 * ((W + 3) / 4);
-    int E = (kGramPre * 256 / wp) / 16 * 16;
-    if (E > 256) E = 256;
-    return E < 16 ? 16 : E;
-}
-
-int gram_rows(int64_t n_acc, int W)
-{
-    const int E = gram_chunk(W);
-    int64_t chunks = (n_acc + E - 1) / E;
-    if (chunks > kGramMaxRows) chunks = kGramMaxRows;
-    return (int)(chunks < 1 ? 1 : chunks);
-}
-
-template <bool C128, int NP>
-__global__ __launch_bounds__(256) void k_gram(const void* __restrict__ mc, int64_t n_acc, int W,
-                                              int E, double* __restrict__ partials)
-{
-    using In = typename std::conditional<C128, double2, float2>::type;
-    extern __shared__ double lds_g[];
-    In* s_b = reinterpret_cast<In*>(lds_g);   // E x wp
-    const In* src = reinterpret_cast<const In*>(mc);
-    const int nb = (W + 3) / 4, wp = 4 * nb;
-    const int npair = nb * (nb + 1) / 2;
-    const int P = W * (W + 1) / 2;
-    const int tid = threadIdx.x;
-    const int per = npair < 256 ? npair : 256;
-    const int splits = npair >= 256 ? 1 : 256 / npair;
-    const int split = tid / per, pair0 = tid % per;
-    const bool active = split < splits;
-    int bp[NP], bq[NP];
-    double acc[NP][32];
-#pragma unroll
-    for (int r = 0; r < NP; ++r) {
-        const int pl = pair0 + r * 256;
-        bp[r] = bq[r] = -1;
-        if (active && pl < npair) {
-            int rem = pl, row = 0;
-            while (rem >= nb - row) {
-                rem -= nb - row;
-                ++row;
-            }
-            bp[r] = row;
-            bq[r] = row + rem;
-        }
-#pragma unroll
-        for (int k = 0; k < 32; ++k) acc[r][k] = 0.0;
-    }
-
-    const int64_t nch = (n_acc + E - 1) / E;
-    const int64_t c0 = (int64_t)blockIdx.x * nch / gridDim.x;
-    const int64_t c1 = (int64_t)(blockIdx.x + 1) * nch / gridDim.x;
-    const int n_el = E * wp;
-    In pre[kGramPre];
-    auto load_chunk = [&](int64_t c) {
-        const int64_t j0 = c * E;
-#pragma unroll
-        for (int q = 0; q < kGramPre; ++q) {
-            const int idx = tid + 256 * q;
-            const int j = idx / wp, a = idx - (idx / wp) * wp;
-            In x;
-            x.x = 0.0;
-            x.y = 0.0;
-            if (idx < n_el && a < W && j0 + j < n_acc) x = src[(j0 + j) * W + a];
-            pre[q] = x;
-        }
-    };
-    if (c0 < c1) load_chunk(c0);
-    for (int64_t c = c0; c < c1; ++c) {
-#pragma unroll
-        for (int q = 0; q < kGramPre; ++q) {
-            const int idx = tid + 256 * q;
-            if (idx < n_el) s_b[idx] = pre[q];
-        }
-        __syncthreads();
-        if (c + 1 < c1) load_chunk(c + 1);
-        const int ne = (int)((n_acc - c * E) < E ? (n_acc - c * E) : E);
-        if (active) {
-#pragma unroll
-            for (int r = 0; r < NP; ++r) {
-                if (bp[r] < 0) continue;
-                for (int j = split; j < ne; j += splits) {
-                    const In* row = s_b + j * wp;
-                    double xr[4], xi[4], yr[4], yi[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const In x = row[4 * bp[r] + i], y = row[4 * bq[r] + i];
-                        xr[i] = (double)x.x;
-                        xi[i] = (double)x.y;
-                        yr[i] = (double)y.x;
-                        yi[i] = (double)y.y;
-                    }
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            // Re and Im of x conj(y), accumulated with one FMA per product
-                            double& re = acc[r][2 * (4 * i + k)];
-                            double& im = acc[r][2 * (4 * i + k) + 1];
-                            re = __fma_rn(xr[i], yr[k], re);
-                            re = __fma_rn(xi[i], yi[k], re);
-                            im = __fma_rn(xi[i], yr[k], im);
-                            im = __fma_rn(-xr[i], yi[k], im);
-                        }
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    // combine the splits of each pair in split order, half a block at a time,
-    // into the packed record
-    double* rec = partials + (int64_t)blockIdx.x * 2 * P;
-    double* s_part = lds_g;   // 256 x 16 doubles
-    for (int r = 0; r < NP; ++r) {
-        const int base = r * 256;
-        const int np_here = (npair - base) < 256 ? (npair - base) : 256;
-        if (np_here <= 0) break;
-        for (int half = 0; half < 2; ++half) {
-            __syncthreads();
-            if (active && bp[r] >= 0)
-#pragma unroll
-                for (int k = 0; k < 16; ++k) s_part[tid * 16 + k] = acc[r][16 * half + k];
-            __syncthreads();
-            for (int e = tid; e < np_here * 16; e += blockDim.x) {
-                const int pl = e / 16, k = e % 16;
-                double x = 0.0;
-                for (int sp = 0; sp < splits; ++sp) x += s_part[(sp * per + pl) * 16 + k];
-                // element (i, kk) of the block pair, real or imaginary part
-                const int el = 16 * half + k;
-                const int i = (el >> 1) / 4, kk = (el >> 1) % 4, part = el & 1;
-                int rem = base + pl, row = 0;
-                while (rem >= nb - row) {
-                    rem -= nb - row;
-                    ++row;
-                }
-                const int a = 4 * row + i, b = 4 * (row + rem) + kk;
-                if (a <= b && b < W) rec[2 * packed_index(W, a, b) + part] = x;
-            }
-        }
-    }
-}
-
-hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, double* partials,
-                       int rows, hipStream_t s, const LaunchEvents& ev)
-{
-    const int E = gram_chunk(W);
-    const int nb = (W + 3) / 4;
-    const int npair = nb * (nb + 1) / 2;
-    const int np = (npair + 255) / 256;
-    const size_t stage = (size_t)E * 4 * nb * (c128 ? 16 : 8);
-    const size_t lds = stage > 256 * 16 * 8 ? stage : 256 * 16 * 8;
-    const dim3 grid(rows), block(256);
-    const void* fns[6] = {(const void*)&k_gram<false, 1>, (const void*)&k_gram<false, 2>,
-                          (const void*)&k_gram<false, 3>, (const void*)&k_gram<true, 1>,
-                          (const void*)&k_gram<true, 2>, (const void*)&k_gram<true, 3>};
-    if (np < 1 || np > kGramMaxPairs) return hipErrorInvalidValue;
-    if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute(fns[(c128 ? 3 : 0) + np - 1],
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)lds);
-        if (e != hipSuccess) return e;
-    }
-#define PWA_GRAM(C, N)                                                                        \
-    hipExtLaunchKernelGGL((k_gram<C, N>), grid, block, lds, s, ev.start, ev.stop, 0, mc, n_acc, \
-                          W, E, partials)
-    if (c128) {
-        if (np == 1) PWA_GRAM(true, 1);
-        else if (np == 2) PWA_GRAM(true, 2);
-        else PWA_GRAM(true, 3);
-    } else {
-        if (np == 1) PWA_GRAM(false, 1);
-        else if (np == 2) PWA_GRAM(false, 2);
-        else PWA_GRAM(false, 3);
-    }
-#undef PWA_GRAM
-    return hipGetLastError();
-}
-
-// ---- the MC integral on the FP64 matrix cores (2W <= 128) -----------------
+// ---- the MC integral on the FP64 matrix cores (2W <= 256) -----------------
 // The real Gram matrix G = sum_j x_j x_j^T of x_j = [Re B_j0 .. Re B_j,W-1,
 // Im B_j0 .. Im B_j,W-1] (zero padded to 16 T) holds the Hermitian sum:
 //   sum_j B_ja conj(B_jb) = G[a][b] + G[W+a][W+b] + i (G[W+a][b] - G[a][W+b]).
@@ -309,26 +119,37 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const void* __restrict__ mc, 
     for (int e = threadIdx.x; e < NPAIR * 256; e += blockDim.x) rec[e] = s_acc[e];
 }
 
-// Wider rows (5 to 8 tiles, 2W <= 128): the tile pairs no longer fit one
-// wavefront's registers, so each of the block's four wavefronts owns a fixed
-// range of pairs (at most 9) and runs over every step of the block's range.
-// The events are staged through LDS in chunks of kGramLdsEvents (one row of
-// 16 T doubles per event, [Re B | Im B | 0]), loaded once per block with
-// contiguous loads, the next chunk's in flight while one is used; each
-// wavefront reads its tiles' values from LDS.  Every pair has one owner,
-// which writes its tiles straight into the block's record.
+// Wider rows (5 to 16 tiles, 2W <= 256): the tile pairs no longer fit one
+// wavefront's registers, so each of the block's NW wavefronts owns a fixed
+// range of pairs (at most 9: NW = 4 up to 8 tiles, 16 beyond) and runs over
+// every step of the block's range.  The events are staged through LDS in
+// chunks of kGramLdsEvents (one row of 16 T doubles per event,
+// [Re B | Im B | 0]), loaded once per block with contiguous loads, the next
+// chunk's in flight while one is used; each wavefront reads its tiles' values
+// from LDS.  Every pair has one owner, which writes its tiles straight into
+// the block's record.
 constexpr int kGramLdsEvents = 32;
 
-template <bool C128, int T>
-__global__ __launch_bounds__(256, 2) void k_gram_mfma_lds(const void* __restrict__ mc,
-                                                       int64_t n_acc, int W,
-                                                       double* __restrict__ records)
+template <int T> constexpr int gram_lds_waves() { return T <= 8 ? 4 : 16; }
+
+// f(std::integral_constant<int, w>{}) for the wavefront index w (uniform), so
+// that every pair index in f is a compile-time constant
+template <int NW, typename F, int... I>
+__device__ inline void for_wave(int wave, F&& f, std::integer_sequence<int, I...>)
 {
+    ((wave == I ? (f(std::integral_constant<int, I>{}), 0) : 0), ...);
+}
+
+template <bool C128, int T, int NW>
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void k_gram_mfma_lds(
+    const void* __restrict__ mc, int64_t n_acc, int W, double* __restrict__ records)
+{
+    constexpr int NT = 64 * NW;                        // threads
     constexpr int NPAIR = T * (T + 1) / 2;
-    constexpr int PPW = (NPAIR + 3) / 4;               // pairs per wavefront
+    constexpr int PPW = (NPAIR + NW - 1) / NW;         // pairs per wavefront
     constexpr int XW = 16 * T;                         // LDS row (doubles)
     constexpr int E = kGramLdsEvents;
-    constexpr int PRE = E * 64 / 256;                  // staged elements per thread (W <= 64)
+    constexpr int PRE = (E * 8 * T + NT - 1) / NT;     // staged elements per thread (W <= 8 T)
     using In = typename std::conditional<C128, double2, float2>::type;
     const In* src = reinterpret_cast<const In*>(mc);
     __shared__ double s_x[E * XW];
@@ -341,16 +162,16 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma_lds(const void* __restrict
     const int n_el = E * W;
 
     // the padding columns 2W .. 16 T stay zero
-    for (int e = tid; e < E * XW; e += 256) s_x[e] = 0.0;
+    for (int e = tid; e < E * XW; e += NT) s_x[e] = 0.0;
     In pre[PRE];
-    // element tid + 256 q of the chunk (event idx / W, wave idx % W); the
+    // element tid + NT q of the chunk (event idx / W, wave idx % W); the
     // address is clamped into the input (n_acc >= 1) and the value
     // multiplied by 0 or 1, so that no load is put behind a branch
     auto load_chunk = [&](int64_t c) {
         const int64_t j0 = c * E;
 #pragma unroll
         for (int q = 0; q < PRE; ++q) {
-            const int idx = tid + 256 * q;
+            const int idx = tid + NT * q;
             const int j = idx / W, a = idx - j * W;
             const bool ok = idx < n_el && j0 + j < n_acc;
             const In b = src[ok ? (j0 + j) * W + a : 0];
@@ -362,7 +183,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma_lds(const void* __restrict
     auto store_chunk = [&]() {
 #pragma unroll
         for (int q = 0; q < PRE; ++q) {
-            const int idx = tid + 256 * q;
+            const int idx = tid + NT * q;
             if (idx < n_el) {
                 const int j = idx / W, a = idx - j * W;
                 s_x[j * XW + a] = (double)pre[q].x;
@@ -392,6 +213,35 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma_lds(const void* __restrict
                                                                          0, 0, 0);
         }
     };
+    // 16 wavefronts (more than 8 tiles): the same products with this
+    // wavefront's pairs indexed at run time (wavefront-uniform, so scalar),
+    // one code path for every wavefront: two LDS reads per pair and step
+    // instead of one per tile, within the 128 registers of a 1024-thread block
+    int pt[PPW], pu[PPW];
+    if constexpr (NW != 4) {
+#pragma unroll
+        for (int pp = 0; pp < PPW; ++pp) {
+            int p = wave * PPW + pp, t = 0;
+            if (p >= NPAIR) p = NPAIR - 1;   // past the last pair: never used
+            while (p >= T - t) {
+                p -= T - t;
+                ++t;
+            }
+            pt[pp] = __builtin_amdgcn_readfirstlane(16 * t);
+            pu[pp] = __builtin_amdgcn_readfirstlane(16 * (t + p));
+        }
+    }
+    const int n_mine = NW != 4 ? min(PPW, max(0, NPAIR - wave * PPW)) : 0;
+    auto compute_rt = [&]() {
+        for (int st = 0; st < E / 4; ++st) {
+            const double* row = s_x + (4 * st + k) * XW + i;
+#pragma unroll
+            for (int pp = 0; pp < PPW; ++pp)
+                if (pp < n_mine)
+                    d[pp] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[pt[pp]], row[pu[pp]], d[pp],
+                                                                 0, 0, 0);
+        }
+    };
     auto write = [&](auto wv) {
         constexpr int P0 = decltype(wv)::value * PPW;
         constexpr int NP = (NPAIR - P0) < PPW ? (NPAIR - P0) : PPW;
@@ -407,23 +257,24 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma_lds(const void* __restrict
         store_chunk();
         __syncthreads();
         if (c + 1 < c1) load_chunk(c + 1);
-        switch (wave) {
-        case 0: compute(std::integral_constant<int, 0>{}); break;
-        case 1: compute(std::integral_constant<int, 1>{}); break;
-        case 2: compute(std::integral_constant<int, 2>{}); break;
-        default: compute(std::integral_constant<int, 3>{}); break;
-        }
+        if constexpr (NW == 4) for_wave<NW>(wave, compute, std::make_integer_sequence<int, NW>{});
+        else compute_rt();
     }
-    switch (wave) {
-    case 0: write(std::integral_constant<int, 0>{}); break;
-    case 1: write(std::integral_constant<int, 1>{}); break;
-    case 2: write(std::integral_constant<int, 2>{}); break;
-    default: write(std::integral_constant<int, 3>{}); break;
+    if constexpr (NW == 4) {
+        for_wave<NW>(wave, write, std::make_integer_sequence<int, NW>{});
+    } else {
+        double* rec = records + (int64_t)blockIdx.x * NPAIR * 256;
+#pragma unroll
+        for (int pp = 0; pp < PPW; ++pp)
+            if (pp < n_mine)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    rec[((wave * PPW + pp) * 4 + r) * 64 + lane] = d[pp][r];
     }
 }
 
-// tiles of 16 components of the MFMA build (0: W too large, use k_gram);
-// up to 4 tiles k_gram_mfma, 5 to 8 k_gram_mfma_lds
+// tiles of 16 components of the MFMA build (0: W too large for it);
+// up to 4 tiles k_gram_mfma, 5 to 16 k_gram_mfma_lds
 int gram_mfma_tiles(int W)
 {
     const int T = (2 * W + 15) / 16;
@@ -431,11 +282,13 @@ int gram_mfma_tiles(int W)
 }
 
 // blocks of the matrix-core build: at least 64 steps of 4 events each, up to
-// 512 (two wavefronts per SIMD)
-int gram_mfma_rows(int64_t n_acc)
+// 512 (two wavefronts per SIMD); 256 for the 16-wavefront blocks of more than
+// 8 tiles (one block per CU)
+int gram_mfma_rows(int64_t n_acc, int W)
 {
     int64_t r = ((n_acc + 3) / 4 + 63) / 64;
-    if (r > kGramMaxRows) r = kGramMaxRows;
+    const int cap = gram_mfma_tiles(W) > 8 ? kGramMaxRows / 2 : kGramMaxRows;
+    if (r > cap) r = cap;
     return (int)(r < 1 ? 1 : r);
 }
 
@@ -454,8 +307,9 @@ hipError_t launch_gram_mfma(const void* mc, bool c128, int64_t n_acc, int W, dou
     hipExtLaunchKernelGGL((k_gram_mfma<C, TT>), grid, block, 0, s, ev.start, ev.stop, 0, mc,  \
                           n_acc, W, records)
 #define PWA_GRAM_LDS(C, TT)                                                                      \
-    hipExtLaunchKernelGGL((k_gram_mfma_lds<C, TT>), grid, block, 0, s, ev.start, ev.stop, 0,  \
-                          mc, n_acc, W, records)
+    hipExtLaunchKernelGGL((k_gram_mfma_lds<C, TT, gram_lds_waves<TT>()>), grid,               \
+                          dim3(64 * gram_lds_waves<TT>()), 0, s, ev.start, ev.stop, 0, mc,    \
+                          n_acc, W, records)
     switch (T) {
     case 1: if (c128) PWA_GRAM_MFMA(true, 1); else PWA_GRAM_MFMA(false, 1); break;
     case 2: if (c128) PWA_GRAM_MFMA(true, 2); else PWA_GRAM_MFMA(false, 2); break;
@@ -465,6 +319,14 @@ hipError_t launch_gram_mfma(const void* mc, bool c128, int64_t n_acc, int W, dou
     case 6: if (c128) PWA_GRAM_LDS(true, 6); else PWA_GRAM_LDS(false, 6); break;
     case 7: if (c128) PWA_GRAM_LDS(true, 7); else PWA_GRAM_LDS(false, 7); break;
     case 8: if (c128) PWA_GRAM_LDS(true, 8); else PWA_GRAM_LDS(false, 8); break;
+    case 9: if (c128) PWA_GRAM_LDS(true, 9); else PWA_GRAM_LDS(false, 9); break;
+    case 10: if (c128) PWA_GRAM_LDS(true, 10); else PWA_GRAM_LDS(false, 10); break;
+    case 11: if (c128) PWA_GRAM_LDS(true, 11); else PWA_GRAM_LDS(false, 11); break;
+    case 12: if (c128) PWA_GRAM_LDS(true, 12); else PWA_GRAM_LDS(false, 12); break;
+    case 13: if (c128) PWA_GRAM_LDS(true, 13); else PWA_GRAM_LDS(false, 13); break;
+    case 14: if (c128) PWA_GRAM_LDS(true, 14); else PWA_GRAM_LDS(false, 14); break;
+    case 15: if (c128) PWA_GRAM_LDS(true, 15); else PWA_GRAM_LDS(false, 15); break;
+    case 16: if (c128) PWA_GRAM_LDS(true, 16); else PWA_GRAM_LDS(false, 16); break;
     default: return hipErrorInvalidValue;
     }
 #undef PWA_GRAM_MFMA
@@ -507,34 +369,6 @@ hipError_t launch_expand_gram(const double* colsum, int W, int64_t n_gen, double
     return hipGetLastError();
 }
 
-// packed column sums (2P doubles) -> full Hermitian W x W matrix scaled by 1/N_gen
-__global__ void k_expand_m(const double* __restrict__ packed, int W, double inv_gen,
-                           double2* __restrict__ M)
-{
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < W * W;
-         idx += gridDim.x * blockDim.x) {
-        const int a = idx / W, b = idx % W;
-        double2 x;
-        if (a <= b) {
-            const int e = packed_index(W, a, b);
-            x = make_double2(packed[2 * e] * inv_gen, packed[2 * e + 1] * inv_gen);
-        } else {
-            const int e = packed_index(W, b, a);
-            x = make_double2(packed[2 * e] * inv_gen, -packed[2 * e + 1] * inv_gen);
-        }
-        if (a == b) x.y = 0.0;
-        M[idx] = x;
-    }
-}
-
-hipError_t launch_expand_m(const double* packed_colsum, int W, int64_t n_gen, double* M,
-                           hipStream_t s)
-{
-    const int total = W * W;
-    hipLaunchKernelGGL(k_expand_m, dim3((total + 255) / 256), dim3(256), 0, s, packed_colsum, W,
-                       1.0 / (double)n_gen, (double2*)M);
-    return hipGetLastError();
-}
 
 // one wavefront per column; lane l sums rows l, l + 64, ... in order.  Rows
 // are `stride` doubles apart; the first `cols` columns are summed.

@@ -338,29 +338,25 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
 
     // ---- MC matrix ----
     HIP_TRY(hipMalloc(&m->d_M, sizeof(double) * 2 * W * W));
-    // the MC integral: on the FP64 matrix cores (real Gram tiles) for 2W <= 128,
-    // else register-blocked on the vector units (packed Hermitian records)
-    const bool gram_mc = pwa::gram_mfma_tiles(W) > 0;
-    const int grec = gram_mc ? pwa::gram_mfma_record(W) : 2 * P;
+    // the MC integral on the FP64 matrix cores (real Gram tiles, 2W <= 256)
+    if (pwa::gram_mfma_tiles(W) <= 0)
+        return fail(PWA_ERR_INVALID, "W = %d is too wide for the MC integral", W);
+    const int grec = pwa::gram_mfma_record(W);
     HIP_TRY(hipMalloc(&m->d_colsum, sizeof(double) * (size_t)std::max(std::max(m->rec_len, 2 * P), grec)));
     if (n_acc > 0) {
         Staged sm;
         rc = stage(mc, (size_t)n_acc * W * (mc_c128 ? 16 : 8), s, sm);
         if (rc != PWA_OK) return rc;
-        const int grows = gram_mc ? pwa::gram_mfma_rows(n_acc) : pwa::gram_rows(n_acc, W);
+        const int grows = pwa::gram_mfma_rows(n_acc, W);
         double* gpart = nullptr;
         HIP_TRY(hipMalloc(&gpart, sizeof(double) * grec * (size_t)grows));
         hipError_t e = hipStreamSynchronize(s);   // the MC input staged
         // dispatch-stamped start of the first kernel, plain event after the last
         if (e == hipSuccess)
-            e = gram_mc ? pwa::launch_gram_mfma(sm.ptr, mc_c128, n_acc, W, gpart, grows, s,
-                                                pwa::LaunchEvents{bt[2], nullptr})
-                        : pwa::launch_gram(sm.ptr, mc_c128, n_acc, W, gpart, grows, s,
-                                           pwa::LaunchEvents{bt[2], nullptr});
+            e = pwa::launch_gram_mfma(sm.ptr, mc_c128, n_acc, W, gpart, grows, s,
+                                      pwa::LaunchEvents{bt[2], nullptr});
         if (e == hipSuccess) e = pwa::launch_colsum(gpart, grows, grec, grec, m->d_colsum, s);
-        if (e == hipSuccess)
-            e = gram_mc ? pwa::launch_expand_gram(m->d_colsum, W, n_gen, m->d_M, s)
-                        : pwa::launch_expand_m(m->d_colsum, W, n_gen, m->d_M, s);
+        if (e == hipSuccess) e = pwa::launch_expand_gram(m->d_colsum, W, n_gen, m->d_M, s);
         if (e == hipSuccess) e = hipEventRecord(bt[3], s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         float ms = 0.f;

@@ -239,16 +239,11 @@ int table_read_threads(const Model& m);
 hipError_t launch_unpack_tiled(const void* src, bool c128, int64_t n, int W,
                                const uint32_t* pairs, void* dst, hipStream_t s);
 hipError_t launch_unpack_soa(const double* src, int64_t n, int P, double* dst, hipStream_t s);
-hipError_t launch_gram(const void* mc, bool c128, int64_t n_acc, int W, double* partials,
-                       int rows, hipStream_t s, const LaunchEvents& ev);
-hipError_t launch_expand_m(const double* packed_colsum, int W, int64_t n_gen, double* M,
-                           hipStream_t s);
-int gram_rows(int64_t n_acc, int W);
-// the MC integral on the FP64 matrix cores, for 2W <= 128: records of
+// the MC integral on the FP64 matrix cores, for 2W <= 256: records of
 // gram_mfma_record(W) doubles per block, summed by k_colsum, then expanded
 int gram_mfma_tiles(int W);   // 0 when W is too large
 int gram_mfma_record(int W);
-int gram_mfma_rows(int64_t n_acc);
+int gram_mfma_rows(int64_t n_acc, int W);
 hipError_t launch_gram_mfma(const void* mc, bool c128, int64_t n_acc, int W, double* records,
                             int rows, hipStream_t s, const LaunchEvents& ev);
 hipError_t launch_expand_gram(const double* colsum, int W, int64_t n_gen, double* M,

@@ -158,14 +158,17 @@ def test_mc_matrix(form):
 @pytest.mark.parametrize("w,n_acc", [(1, 1), (5, 63), (8, 1_001), (16, 4_097), (20, 64),
                                      (20, 65), (20, 40_017), (32, 20_011), (33, 777),
                                      (40, 3_001), (48, 10_007), (56, 999), (64, 9_999),
-                                     (65, 33), (65, 5_000), (128, 2_049)])
+                                     (65, 33), (65, 5_000), (72, 70_001), (80, 31),
+                                     (88, 4_095), (96, 300_007), (100, 1_025), (112, 12_345),
+                                     (120, 777), (121, 20_000), (128, 2_049), (128, 65_537)])
 def test_mc_matrix_sizes(c128, w, n_acc):
-    """M over ragged tails.  W <= 64 runs on the FP64 matrix cores: 1 to 4 tiles
-    of 16 components with every tile pair in one wavefront (several blocks and
-    steps per wavefront), 5 to 8 with the pairs split over the block's
-    wavefronts and the events staged through LDS (ragged chunks); wider W on
-    the vector units (several chunks per block, the register blocking's 1, 2
-    and 3 block pairs per thread, W up to 128)."""
+    """M over ragged tails, on the FP64 matrix cores in tiles of 16 of the 2W
+    real components: 1 to 4 tiles with every tile pair in one wavefront
+    (several blocks and steps per wavefront); 5 to 8 with the pairs split over
+    the block's 4 wavefronts at compile time and the events staged through LDS
+    (ragged chunks); 9 to 16 tiles (W 65..128) over 16 wavefronts with the
+    pairs indexed at run time (every tile count, a single event chunk, many
+    chunks per block, partly filled last tiles)."""
     s = synth.small_sample(w, 10, n_acc, seed=500 + w + n_acc)
     m = s.mc if c128 else s.mc.astype(np.complex64)
     model = pwa.Model(s.data.astype(np.complex64), m, 2 * n_acc + 1, form="amplitude")
