@@ -657,6 +657,200 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
     if (tid == 0 && blockIdx.y == 0) rec[0] = (double)*s_bad;
 }
 
+// Wider rows (NB > 4 blocks, W > 32): the block pairs no longer fit one
+// wavefront's registers, and repeating the pass per row group re-reads the
+// amplitudes and re-forms J every time.  Instead a block of 16 wavefronts
+// (one per CU) forms J once per event into LDS and each wavefront owns a fixed
+// range of at most ceil(pairs / 16) block pairs, indexed at run time
+// (wavefront-uniform, scalar registers) so that one code path serves every
+// wavefront within the 128 registers of a 1024-thread block:
+//   1. the tile's amplitudes into LDS, one row per event (as above);
+//   2. per half tile of 32 events: wavefront w takes events 2w and 2w + 1,
+//      32 lanes each; S over waves pi, pi + 32, ... and an xor butterfly
+//      over the 32 lanes, then w = 2 / I and J_p for p = pi + 32 m into an
+//      LDS row of 16 NB doubles (zero beyond 2W);
+//   3. per step of 4 events, one MFMA per owned pair with both operands read
+//      from the J rows (lane l: event l / 16 of the step, parameter l % 16).
+// Each pair has one owner, which writes its 16 x 16 block straight into the
+// block's record (same layout as above; row groups are not used).
+constexpr int kHessWideWaves = 16;
+constexpr int kHessWideHalf = 32;   // events per J stage
+
+__host__ __device__ inline size_t hess_wide_lds_bytes(int wpad, int nb)
+{
+    return (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4       // amplitude rows
+           + (size_t)kHessWideHalf * 16 * nb * 8                    // J rows
+           + 16 * 128 /* V */ + 16;
+}
+
+template <int NB>
+__global__ __launch_bounds__(64 * kHessWideWaves) void k_amp_hessian_wide(
+    const float4* __restrict__ amp, int64_t n_events, int64_t n_tiles, int W, int wpad, int lq,
+    int wl, VParams vp, double* __restrict__ recs)
+{
+    constexpr int NT = 64 * kHessWideWaves;
+    constexpr int NPAIR = NB * (NB + 1) / 2;
+    constexpr int PPW = (NPAIR + kHessWideWaves - 1) / kHessWideWaves;
+    constexpr int XW = 16 * NB;                       // J row (doubles)
+    constexpr int PRE = (kAmpTile * 8 * NB / 2 + NT - 1) / NT;   // float4 per thread (wpad <= 8 NB)
+    extern __shared__ double lds_d[];
+    char* lds = reinterpret_cast<char*>(lds_d);
+    const int stride = amp_lds_stride_words(wpad) * 4;
+    char* tile = lds;
+    double* s_j = reinterpret_cast<double*>(lds + (size_t)kAmpTile * stride);
+    double2* s_v = reinterpret_cast<double2*>(lds + (size_t)kAmpTile * stride +
+                                              (size_t)kHessWideHalf * XW * 8);
+    int* s_bad = reinterpret_cast<int*>(s_v + 128);
+    const int h = wpad >> 1;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    for (int a = tid; a < 128; a += NT)
+        s_v[a] = a < W ? make_double2(vsrc(vp)[2 * a], vsrc(vp)[2 * a + 1]) : make_double2(0.0, 0.0);
+    if (tid == 0) *s_bad = 0;
+
+    // this wavefront's block pairs (bp <= bq, row-major), as column offsets
+    int pt[PPW], pu[PPW];
+#pragma unroll
+    for (int pp = 0; pp < PPW; ++pp) {
+        int p = wave * PPW + pp, t = 0;
+        if (p >= NPAIR) p = NPAIR - 1;   // past the last pair: never used
+        while (p >= NB - t) {
+            p -= NB - t;
+            ++t;
+        }
+        pt[pp] = __builtin_amdgcn_readfirstlane(16 * t);
+        pu[pp] = __builtin_amdgcn_readfirstlane(16 * (t + p));
+    }
+    const int n_mine = min(PPW, max(0, NPAIR - wave * PPW));
+    hd4 D[PPW];
+#pragma unroll
+    for (int pp = 0; pp < PPW; ++pp) D[pp] = hd4{0.0, 0.0, 0.0, 0.0};
+    int nbad = 0;
+
+    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
+    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
+    const int n_f4 = kAmpTile * h;
+    float4 pre[PRE];
+    auto stage = [tile, stride, wl, lq](int f, float4 x) {
+        const int kl = f / (32 * wl), rem = f - kl * 32 * wl;
+        const int j = rem >> 6, ln = rem & 63;
+        const int ev = (kl << (6 - lq)) + (ln >> lq);
+        const int c = (ln & ((1 << lq) - 1)) * (wl >> 1) + j;
+        *reinterpret_cast<float4*>(tile + ev * stride + c * 16) = x;
+    };
+    auto load_tile = [&](int64_t t) {
+        const float4* src = amp + t * kAmpTile * h;
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) {
+            const int f = tid + NT * q;
+            pre[q] = f < n_f4 ? src[f] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    if (t0 < t1) load_tile(t0);
+    const int ke = lane >> 5;    // J stage: event of the wavefront's pair
+    const int pj = lane & 31;    // J stage: lane within the event
+    const int k = lane >> 4;     // MFMA: event of the step
+    const int i = lane & 15;     // MFMA: parameter within a block
+    for (int64_t t = t0; t < t1; ++t) {
+        __syncthreads();   // the previous tile's rows and J are no longer read
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) {
+            const int f = tid + NT * q;
+            if (f < n_f4) stage(f, pre[q]);
+        }
+        __syncthreads();
+        if (t + 1 < t1) load_tile(t + 1);
+        for (int half = 0; half < kAmpTile / kHessWideHalf; ++half) {
+            // 2. J of events 2 wave + ke of this half
+            {
+                const int eh = 2 * wave + ke;                 // event within the half
+                const int ev = kHessWideHalf * half + eh;     // event within the tile
+                const char* row = tile + ev * stride;
+                double sr = 0.0, si = 0.0;
+                for (int a = pj; a < W; a += 32) {
+                    const float2 x = *reinterpret_cast<const float2*>(row + a * 8);
+                    const double2 v = s_v[a];
+                    sr = __fma_rn(v.x, (double)x.x, sr);
+                    sr = __fma_rn(-v.y, (double)x.y, sr);
+                    si = __fma_rn(v.x, (double)x.y, si);
+                    si = __fma_rn(v.y, (double)x.x, si);
+                }
+                sr += xor_lane_f64<1>(sr);
+                si += xor_lane_f64<1>(si);
+                sr += xor_lane_f64<2>(sr);
+                si += xor_lane_f64<2>(si);
+                sr += xor_lane_f64<4>(sr);
+                si += xor_lane_f64<4>(si);
+                sr += xor_lane_f64<8>(sr);
+                si += xor_lane_f64<8>(si);
+                sr += xor_lane_f64<16>(sr);
+                si += xor_lane_f64<16>(si);
+                const double I = sr * sr + si * si;
+                const bool valid = t * kAmpTile + ev < n_events;
+                const bool ok = valid && (I > 0.0) && (I < INFINITY);
+                if (pj == 0 && valid && !ok) ++nbad;
+                // NaN for a degenerate event (its J, and so H, become NaN), 0 for padding
+                const double w = ok ? 2.0 * recip_f64(I) : (valid ? NAN : 0.0);
+                double* jrow = s_j + eh * XW;
+#pragma unroll
+                for (int m = 0; m < XW / 32; ++m) {
+                    const int p = pj + 32 * m;
+                    double jv = 0.0;
+                    if (p < 2 * W) {
+                        const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
+                        const double zr = __fma_rn(sr, (double)x.x, si * (double)x.y);
+                        const double zi = __fma_rn(sr, (double)x.y, -si * (double)x.x);
+                        jv = w * ((p & 1) ? -zi : zr);
+                    }
+                    jrow[p] = jv;
+                }
+                if constexpr (XW % 32 != 0) {
+                    const int p = pj + 32 * (XW / 32);
+                    if (p < XW) {
+                        double jv = 0.0;
+                        if (p < 2 * W) {
+                            const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
+                            const double zr = __fma_rn(sr, (double)x.x, si * (double)x.y);
+                            const double zi = __fma_rn(sr, (double)x.y, -si * (double)x.x);
+                            jv = w * ((p & 1) ? -zi : zr);
+                        }
+                        jrow[p] = jv;
+                    }
+                }
+            }
+            __syncthreads();
+            // 3. the owned block pairs over the half's 8 steps, one at a time
+            // (unrolled, the scheduler hoists later steps' loads past the 128
+            // registers and spills)
+#pragma unroll 1
+            for (int st = 0; st < kHessWideHalf / 4; ++st) {
+                const double* jr = s_j + (4 * st + k) * XW + i;
+#pragma unroll
+                for (int pp = 0; pp < PPW; ++pp)
+                    if (pp < n_mine)
+                        D[pp] = __builtin_amdgcn_mfma_f64_16x16x4f64(jr[pt[pp]], jr[pu[pp]], D[pp],
+                                                                     0, 0, 0);
+            }
+            __syncthreads();   // J rows free for the next half
+        }
+    }
+
+    nbad = wave_allsum_int(nbad);
+    if (lane == 0 && nbad) atomicAdd(s_bad, nbad);   // LDS, order-free integer count
+    double* rec = recs + (int64_t)blockIdx.x * hess_rec_len(W);
+    // element [i][j] of a pair's block is in lane j + 16 (i % 4), register i / 4
+#pragma unroll
+    for (int pp = 0; pp < PPW; ++pp)
+        if (pp < n_mine)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                rec[1 + (size_t)(wave * PPW + pp) * 256 + 16 * (4 * r + (lane >> 4)) + (lane & 15)] =
+                    D[pp][r];
+    __syncthreads();
+    if (tid == 0) rec[0] = (double)*s_bad;
+}
+
 // The matrix from the column sums of the block records (k_colsum: one
 // wavefront per column, fixed order); one thread per entry of the 2W x 2W
 // matrix (full, row-major), written to pinned host memory.
@@ -685,9 +879,13 @@ __global__ __launch_bounds__(256) void k_hess_expand(const double* __restrict__ 
         __hip_atomic_store(done + blockIdx.x, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// block columns: fewer when the row groups multiply the blocks
+// block columns: fewer when the row groups multiply the blocks; one
+// 16-wavefront block per CU for the wide rows (then also the row-group
+// kernel's column count, so that the record buffer never depends on the shape)
 int hess_grid(const Model& m)
 {
+    if (hess_nb(m.W) > 4)
+        return (int)std::min<int64_t>(m.cus, std::max<int64_t>(1, m.n_tiles));
     const int64_t want = std::max<int64_t>(64, 4 * (int64_t)m.cus / hess_groups(m.W));
     return (int)std::min<int64_t>(want, std::max<int64_t>(1, m.n_tiles));
 }
@@ -699,6 +897,21 @@ int hess_assemble_blocks(int W) { return (4 * W * W + 255) / 256; }
 template <int NB>
 static hipError_t launch_hessian_nb(const Model& m, const VParams& vp, double* recs, hipStream_t s)
 {
+    // the wide kernel when the stored rows are no wider than its staging
+    // assumes (every default or tuned shape; a shape set by hand may pad more)
+    if constexpr (NB > 4) {
+        if (m.wpad <= 8 * NB && hess_wide_lds_bytes(m.wpad, NB) <= kLdsBytes) {
+            const size_t lds = hess_wide_lds_bytes(m.wpad, NB);
+            const hipError_t e = hipFuncSetAttribute((const void*)&k_amp_hessian_wide<NB>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_amp_hessian_wide<NB>), dim3(hess_grid(m)),
+                               dim3(64 * kHessWideWaves), lds, s, (const float4*)m.d_data, m.n,
+                               m.n_tiles, m.W, m.wpad, m.amp_lq, m.amp_wl, vp, recs);
+            return hipGetLastError();
+        }
+    }
     const size_t lds = hess_lds_bytes<NB>(m.wpad);
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute((const void*)&k_amp_hessian<NB>,

@@ -35,6 +35,7 @@ __host__ __device__ inline int tiled_offdiag_index(int W, int a, int b)
 
 // Events per tile of the FP32 amplitude layout (padding unit).
 constexpr int kAmpTile = 64;
+constexpr size_t kLdsBytes = 160 * 1024;   // LDS per CU (gfx950)
 // Events per tile of the 16-bit matrix-core layout (two MFMA rows each).
 constexpr int kMfmaTile = 16;
 

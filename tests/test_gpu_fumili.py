@@ -2,10 +2,11 @@
 
 Against the oracle's plain definition (FP64 both sides, different summation
 orders: ||dH||_F / ||H||_F <= 1e-10) at sizes spanning several tiles and a
-ragged last tile, every pair-assignment path of the kernel (event splits for
-few 4x4 blocks, several blocks per thread for W = 64), degenerate events, and
-at 2x10^6 events x 32 waves through the identities that hold at any size:
-theta^T H theta = 4 N and H (i V) = 0.
+ragged last tile, both kernels (up to 4 blocks of 16 parameters, W <= 32: all
+block pairs in each wavefront; wider: J staged in LDS once per event and the
+block pairs split over 16 wavefronts, from 5 to 16 blocks, one and several
+tiles per block), degenerate events, and at 2x10^6 events x 32 waves through
+the identities that hold at any size: theta^T H theta = 4 N and H (i V) = 0.
 """
 import numpy as np
 import pytest
@@ -22,7 +23,8 @@ def _frob(a, b):
 
 
 @pytest.mark.parametrize("w,n", [(1, 1), (2, 70), (4, 1000), (7, 4099), (20, 5000), (33, 700),
-                                 (48, 2000), (64, 300), (77, 500), (100, 700), (128, 300)])
+                                 (48, 2000), (64, 300), (72, 70_001), (77, 500), (100, 700),
+                                 (113, 9_999), (128, 300), (128, 20_033)])
 def test_fumili_matches_oracle(w, n):
     o = oracle.get()
     s = synth.small_sample(w, n, 3 * n + 7, seed=4000 + 10 * w + n, n_points=2)
