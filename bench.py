@@ -109,14 +109,16 @@ def host_cpu():
 def mfma_flops(n_events, n_waves, k, v_parts):
     """Matrix-core FLOPs of one batched pass as the kernel issues them: per
     16-event tile (32 rows) and 32 vectors, the forward product (16-wide KD
-    steps x V parts, two) and the adjoint (32-row blocks x 2 slot steps x 2 weight
-    parts), each a 32x32x16 MFMA of 32768 FLOP."""
+    steps x V parts, 32x32x16 MFMAs of 32768 FLOP) and the adjoint (per full
+    32-row block 2 slot steps x 2 weight parts of the same MFMA; a last block
+    of 16 rows as 2 vector blocks x 2 weight parts of the 16x16x32 MFMA,
+    16384 FLOP each)."""
     kd = (2 * n_waves + 15) // 16 * 16
-    rb = (kd + 31) // 32
+    rf, rem = (kd // 16) // 2, (kd // 16) % 2
     tiles = (n_events + 15) // 16
     col_blocks = (k + 31) // 32
-    per = (kd // 16) * v_parts + rb * 2 * 2
-    return tiles * col_blocks * per * 32768
+    per = ((kd // 16) * v_parts + rf * 2 * 2) * 32768 + rem * 2 * 2 * 16384
+    return tiles * col_blocks * per
 
 
 def mfma_algorithmic_flops(n_events, n_waves, k, v_parts):

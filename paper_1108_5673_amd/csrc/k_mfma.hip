@@ -29,7 +29,11 @@
 //     operand of an MFMA whose 16 k-slots are the rows 16 s .. 16 s + 15 of the
 //     tile; the A operand (lane l: output row l % 32, the same 8 slots) comes
 //     from a second copy of the tile stored in that slot order.
-//     So S never leaves the registers.
+//     So S never leaves the registers.  When KD is an odd multiple of 16 the
+//     last 16 gradient rows run on the 16x16x32 MFMA instead of a 32-row block
+//     that would be half padding: one lane-16 swap of the two halves' weight
+//     registers makes them its A operand (16 vectors x 32 slots), the stored
+//     rows its B operand.
 // Scale: each vector enters as V_k / s_k with s_k the power of two nearest
 // ||V_k||_2, so S, I and c = S / I stay near unit magnitude whatever the size of
 // V (float16 has a narrow exponent range); the assembly undoes it exactly:
@@ -61,6 +65,8 @@
 namespace pwa {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 // Splitting a value into 16-bit parts.  bf16 has the exponent range of FP32,
 // so its parts (two for V and two for c) are plain successive remainders,
@@ -91,6 +97,10 @@ template <> struct H16<__bf16> {
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
     }
+    __device__ static f32x4 mfma16(V8 a, V8 b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
 };
 template <> struct H16<_Float16> {
     typedef _Float16 V8 __attribute__((ext_vector_type(8)));
@@ -98,6 +108,10 @@ template <> struct H16<_Float16> {
     __device__ static f32x16 mfma(V8 a, V8 b, f32x16 c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+    __device__ static f32x4 mfma16(V8 a, V8 b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
     }
 };
 
@@ -190,12 +204,26 @@ __device__ inline int mfma_slot(int e, int p)
 // Tiles of 16 events; the buffers are zeroed before packing (padding events,
 // KD columns beyond 2W and adjoint rows beyond 2W stay zero).
 // af: [tile][32 rows][KD]            (forward A operand: rows 2e = x_e, 2e + 1 = x'_e)
-// at: [tile][RB * 32 rows][32 slots] (adjoint A operand: row 2b = [Re A_eb | Im A_eb],
+// at: [tile][mfma_at_tile_elems(KD)] (adjoint operand rows: row 2b = [Re A_eb | Im A_eb],
 //                                     row 2b + 1 = [-Im A_eb | Re A_eb] at slots
-//                                     mfma_slot(e, 0 | 1))
+//                                     mfma_slot(e, 0 | 1)); rows in full blocks of
+//     32 rows x 32 slots (the A operand of the 32x32x16 MFMA, lane l: row l % 32);
+//     when KD is an odd multiple of 16 the last 16 rows form one block in the B
+//     operand order of the 16x16x32 MFMA: lane l holds row 32 RF + l % 16 at the 8
+//     slots of lane group q = l / 16 in the order q -> 16 (q & 1) + 8 (q >> 1) (the
+//     order in which one lane-16 swap of the two halves' weights delivers them)
+__device__ inline int64_t mfma_at_offset(int KD, int64_t tile, int row, int slot)
+{
+    const int rf = KD / 32;   // full 32-row blocks
+    int64_t o = tile * mfma_at_tile_elems(KD);
+    if (row < 32 * rf) return o + (int64_t)row * 32 + slot;
+    const int q = (slot >> 4) + 2 * ((slot >> 3) & 1);
+    return o + rf * 1024 + (int64_t)((row - 32 * rf) + 16 * q) * 8 + (slot & 7);
+}
+
 template <typename T>
 __global__ void k_pack_mfma(const void* __restrict__ src, bool c128, int64_t n, int W, int KD,
-                            int RB, T* __restrict__ af, T* __restrict__ at)
+                            T* __restrict__ af, T* __restrict__ at)
 {
     const int64_t total = n * (int64_t)W;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
@@ -221,11 +249,11 @@ __global__ void k_pack_mfma(const void* __restrict__ src, bool c128, int64_t n, 
         x[1] = yi;
         x[KD] = yi;
         x[KD + 1] = nr;
-        T* y = at + (tile * RB * 32 + 2 * a) * 32 + mfma_slot(e, 0);
-        y[0] = yr;
-        y[1] = yi;
-        y[32] = ni;
-        y[33] = yr;
+        const int s0 = mfma_slot(e, 0), s1 = mfma_slot(e, 1);
+        at[mfma_at_offset(KD, tile, 2 * a, s0)] = yr;
+        at[mfma_at_offset(KD, tile, 2 * a, s1)] = yi;
+        at[mfma_at_offset(KD, tile, 2 * a + 1, s0)] = ni;
+        at[mfma_at_offset(KD, tile, 2 * a + 1, s1)] = yr;
     }
 }
 
@@ -311,9 +339,12 @@ __global__ void k_prep_vmat16(const double* __restrict__ v, int K, int W, int NS
 // n_bad counts the vector's lane sums that met a degenerate event, so it is
 // non-zero exactly when one did) and rec_g = G[0 .. KD) of the vector (the
 // wavefront's FP64 sums rounded to FP32; rows 2b, 2b + 1 are Re g_b and Im g_b).
-// Up to 8 wavefronts per block (two per SIMD, 256 registers each); the wider
-// row lengths (NS > 4) need more registers and run 4 (one per SIMD).
+// Up to 8 wavefronts per block (two per SIMD, at most 256 registers each); the
+// wider row lengths (NS > 4) need more registers and run 4 (one per SIMD).
 template <int NS> constexpr int mfma_waves() { return NS <= 4 ? 8 : 4; }
+// FP64 fold slots per lane: 16 per full 32-row block of the adjoint, and 8
+// (two 16-vector blocks of 4) for a last block of 16 rows
+template <int NS> constexpr int mfma_fold_regs() { return 16 * (NS / 2) + ((NS & 1) ? 8 : 0); }
 // An FP32 adjoint accumulator is folded into FP64 once it has added at least
 // kFoldTiles tiles (so never more than kFoldTiles + 1).
 constexpr int kFoldTiles = 32;
@@ -325,7 +356,11 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
     double* __restrict__ rec_d, float* __restrict__ rec_g)
 {
     constexpr int KD = 16 * NS;
-    constexpr int RB = (NS + 1) / 2;
+    constexpr bool REM = (NS & 1) != 0;     // a last adjoint block of 16 rows
+    constexpr int RF = NS / 2;              // full 32-row adjoint blocks
+    constexpr int RFA = RF > 0 ? RF : 1;    // array extent
+    constexpr int AT = mfma_at_tile_elems(KD);
+    constexpr int NF = mfma_fold_regs<NS>();
     using V8 = typename H16<T>::V8;
     using V2 = typename H16<T>::V2;
 
@@ -346,23 +381,32 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
                 vm + p * part_elems + ((size_t)((cb * NS + s) * 2 + h) * 32 + c) * 8);
     constexpr bool SL = Split<T>::kScaledLow;
     const SplitMul<T> smul = make_split_multipliers<T>();
-    f32x16 g[RB], gl[SL ? RB : 1];
+    // adjoint accumulators: g (full blocks, 32 rows x 32 vectors) and gr (the
+    // last 16 rows: 16 vectors x 16 rows per block of vectors); gl, grl the
+    // scaled low parts of fp16
+    f32x16 g[RFA], gl[SL ? RFA : 1];
+    f32x4 gr[2], grl[SL ? 2 : 1];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) g[rb] = f32x16{};
+    for (int rb = 0; rb < RFA; ++rb) g[rb] = f32x16{};
 #pragma unroll
-    for (int rb = 0; rb < (SL ? RB : 1); ++rb) gl[rb] = f32x16{};
+    for (int rb = 0; rb < (SL ? RFA : 1); ++rb) gl[rb] = f32x16{};
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) gr[nb] = f32x4{};
+#pragma unroll
+    for (int nb = 0; nb < (SL ? 2 : 1); ++nb) grl[nb] = f32x4{};
     double dsum = 0.0;
-    // FP64 sums of the adjoint accumulators: slot [wave][rb][q][lane], each
-    // owned by one lane (no synchronisation needed)
-    __shared__ double s_gacc[mfma_waves<NS>() * RB * 16 * 64];
-    double* gacc = s_gacc + (size_t)wave * RB * 16 * 64 + lane;
+    // FP64 sums of the adjoint accumulators: slot [wave][j][lane] (j: 16 rb + q
+    // for the full blocks, 16 RF + 4 nb + r for the last one), each owned by
+    // one lane (no synchronisation needed)
+    __shared__ double s_gacc[mfma_waves<NS>() * NF * 64];
+    double* gacc = s_gacc + (size_t)wave * NF * 64 + lane;
 #pragma unroll
-    for (int j = 0; j < RB * 16; ++j) gacc[64 * j] = 0.0;
+    for (int j = 0; j < NF; ++j) gacc[64 * j] = 0.0;
     int since_fold = 0;   // tiles added to g, gl since they were last folded
     auto fold = [&]() {
         since_fold = 0;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+        for (int rb = 0; rb < RF; ++rb)
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 float x = g[rb][q];
@@ -371,21 +415,37 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
                 __hip_atomic_fetch_add(gacc + 64 * (16 * rb + q), (double)x, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
             }
+        if constexpr (REM) {
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) g[rb] = f32x16{};
+            for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-        for (int rb = 0; rb < (SL ? RB : 1); ++rb) gl[rb] = f32x16{};
+                for (int r = 0; r < 4; ++r) {
+                    float x = gr[nb][r];
+                    if constexpr (SL) x = fmaf(grl[nb][r], kLowUnscale, x);
+                    __hip_atomic_fetch_add(gacc + 64 * (16 * RF + 4 * nb + r), (double)x,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RFA; ++rb) g[rb] = f32x16{};
+#pragma unroll
+        for (int rb = 0; rb < (SL ? RFA : 1); ++rb) gl[rb] = f32x16{};
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) gr[nb] = f32x4{};
+#pragma unroll
+        for (int nb = 0; nb < (SL ? 2 : 1); ++nb) grl[nb] = f32x4{};
     };
 
     const int64_t t0 = (int64_t)blockIdx.x * n_tiles / chunks;
     const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / chunks;
-    // operands of one tile: forward rows (32 rows x KD) and adjoint rows (RB x
-    // 32 rows x 32 slots)
+    // operands of one tile: forward rows (32 rows x KD) and adjoint rows (RF
+    // blocks of 32 rows x 32 slots, and the last 16 rows)
     struct OpsA {
         V8 a[NS];
     };
     struct OpsB {
-        V8 b[RB][2];
+        V8 b[RFA][2];
+        V8 br;
     };
     auto load_a = [&](OpsA& o, int64_t t) {
         const T* ta = af + t * 32 * KD;
@@ -393,12 +453,44 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
         for (int s = 0; s < NS; ++s) o.a[s] = *reinterpret_cast<const V8*>(ta + c * KD + 16 * s + 8 * h);
     };
     auto load_b = [&](OpsB& o, int64_t t) {
-        const T* tt = at + t * RB * 32 * 32;
+        const T* tt = at + t * AT;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+        for (int rb = 0; rb < RF; ++rb)
 #pragma unroll
             for (int s2 = 0; s2 < 2; ++s2)
                 o.b[rb][s2] = *reinterpret_cast<const V8*>(tt + (rb * 32 + c) * 32 + 16 * s2 + 8 * h);
+        if constexpr (REM) o.br = *reinterpret_cast<const V8*>(tt + RF * 1024 + lane * 8);
+    };
+    // The last 16 adjoint rows on the 16x16x32 MFMA, once both halves' weights
+    // of the tile are formed: D[vector][row] += C^T Y with the weights as the A
+    // operand (lane l: vector l % 16 of a block of 16, 8 slots of lane group
+    // l / 16).  A lane-16 swap of the two halves' registers turns them (lane
+    // (c, h): vector c, slots 16 s2 + 8 h ..) into exactly that: the first
+    // register then holds vectors 0..15 and the second vectors 16..31, at slot
+    // groups 0, 16, 8, 24 (the order of the stored rows).
+    auto swap16 = [](V8& x0, V8& x1) {
+        u32x4 a = __builtin_bit_cast(u32x4, x0), b = __builtin_bit_cast(u32x4, x1);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const auto r = __builtin_amdgcn_permlane16_swap(a[d], b[d], false, false);
+            a[d] = r[0];
+            b[d] = r[1];
+        }
+        x0 = __builtin_bit_cast(V8, a);
+        x1 = __builtin_bit_cast(V8, b);
+    };
+    auto rem_adj = [&](const OpsB& o, V8 c0, V8 c1, V8 l0, V8 l1) {
+        swap16(c0, c1);
+        swap16(l0, l1);
+        gr[0] = H16<T>::mfma16(c0, o.br, gr[0]);
+        gr[1] = H16<T>::mfma16(c1, o.br, gr[1]);
+        if constexpr (SL) {
+            grl[0] = H16<T>::mfma16(l0, o.br, grl[0]);
+            grl[1] = H16<T>::mfma16(l1, o.br, grl[1]);
+        } else {
+            gr[0] = H16<T>::mfma16(l0, o.br, gr[0]);
+            gr[1] = H16<T>::mfma16(l1, o.br, gr[1]);
+        }
     };
     // S of the tile's 16 events x 32 vectors
     auto forward = [&](const OpsA& o) {
@@ -432,6 +524,7 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
         // take the general path.
         const int nvalid = (int)min<int64_t>(kMfmaTile, n_events - t * kMfmaTile);
         float lsum = 0.f;
+        V8 chis[2], clos[2];
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
             V8 chi, clo;
@@ -465,12 +558,15 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
                 clo[2 * r + 1] = lo[1];
             }
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
+            for (int rb = 0; rb < RF; ++rb) {
                 g[rb] = H16<T>::mfma(o.b[rb][s2], chi, g[rb]);
                 if constexpr (SL) gl[rb] = H16<T>::mfma(o.b[rb][s2], clo, gl[rb]);
                 else g[rb] = H16<T>::mfma(o.b[rb][s2], clo, g[rb]);
             }
+            chis[s2] = chi;
+            clos[s2] = clo;
         }
+        if constexpr (REM) rem_adj(o, chis[0], chis[1], clos[0], clos[1]);
         dsum += (double)lsum * 0.69314718055994530942;   // log2 -> ln
     };
 
@@ -532,7 +628,7 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
             for (int m = i * kFwd / 8; m < (i + 1) * kFwd / 8; ++m) fwd_mfma(an, nx, nxl, m);
             if (i >= 4) {
 #pragma unroll
-                for (int j = (i - 4) * 2 * RB / 4; j < (i - 3) * 2 * RB / 4; ++j)
+                for (int j = (i - 4) * 2 * RF / 4; j < (i - 3) * 2 * RF / 4; ++j)
                     adj_mfma(o, chi0, clo0, 0, j);
             }
             if (i < 4) {
@@ -553,7 +649,8 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int j = 0; j < 2 * RB; ++j) adj_mfma(o, chi1, clo1, 1, j);
+        for (int j = 0; j < 2 * RF; ++j) adj_mfma(o, chi1, clo1, 1, j);
+        if constexpr (REM) rem_adj(o, chi0, chi1, clo0, clo1);
         float lsum = l0 + l1;
         // positive normal: class bit 8
         if (!(__builtin_amdgcn_classf(p0, 0x100) && __builtin_amdgcn_classf(p1, 0x100))) {
@@ -629,18 +726,31 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
             if (since_fold >= kFoldTiles) fold();
         }
     }
-    fold();   // the FP64 sums now hold everything; g, gl are zero
+    fold();   // the FP64 sums now hold everything; the accumulators are zero
     // records of this wavefront: G column c (vector 32 cb + c), rows
-    // 8 j + 4 h + i of each row block, and the vector's sum ln I (lanes c and c + 32)
-    const size_t rec_idx = ((size_t)blockIdx.x * n_cb + cb) * 32 + c;
+    // 8 j + 4 h + i of each full row block; of the last 16 rows, row
+    // 32 RF + l % 16 of vectors 16 nb + 4 (l / 16) + r; and the vector's sum
+    // ln I (lanes c and c + 32)
+    const size_t rec0 = ((size_t)blockIdx.x * n_cb + cb) * 32;
+    const size_t rec_idx = rec0 + c;
     float* gcol = rec_g + rec_idx * KD;
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < RF; ++rb)
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int r = rb * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
-            if (r < KD) gcol[r] = (float)gacc[64 * (16 * rb + q)];
+            gcol[r] = (float)gacc[64 * (16 * rb + q)];
         }
+    if constexpr (REM) {
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int vec = 16 * nb + 4 * (lane >> 4) + r;
+                rec_g[(rec0 + vec) * KD + 32 * RF + (lane & 15)] =
+                    (float)gacc[64 * (16 * RF + 4 * nb + r)];
+            }
+    }
     const double other = __shfl_xor(dsum, 32);
     if (h == 0) {
         rec_d[2 * rec_idx] = dsum + other;
@@ -783,11 +893,10 @@ hipError_t launch_pack_mfma(const void* src, bool c128, int64_t n, int W, bool b
     const int64_t total = n * (int64_t)W;
     if (bf)
         hipLaunchKernelGGL(k_pack_mfma<__bf16>, dim3(grid_for(total, 256)), dim3(256), 0, s, src,
-                           c128, n, W, m.kd, m.rb, (__bf16*)m.d_data, (__bf16*)m.d_at);
+                           c128, n, W, m.kd, (__bf16*)m.d_data, (__bf16*)m.d_at);
     else
         hipLaunchKernelGGL(k_pack_mfma<_Float16>, dim3(grid_for(total, 256)), dim3(256), 0, s,
-                           src, c128, n, W, m.kd, m.rb, (_Float16*)m.d_data,
-                           (_Float16*)m.d_at);
+                           src, c128, n, W, m.kd, (_Float16*)m.d_data, (_Float16*)m.d_at);
     return hipGetLastError();
 }
 

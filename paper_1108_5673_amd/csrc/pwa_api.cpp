@@ -170,8 +170,8 @@ double build_device_bytes(int64_t n, int32_t W, int64_t n_acc, uint32_t flags, b
     case PWA_PRECISION_FP64_PLAIN: b += dn * P * 16.0 + dn * 8.0; break;
     case PWA_FORM_AMPLITUDE_BF16:
     case PWA_FORM_AMPLITUDE_FP16: {
-        const double kd = std::ceil(2.0 * W / 16.0) * 16.0, rb = std::ceil(kd / 32.0);
-        b += ntile * 2.0 * kd * 2.0 + ntile * 2.0 * rb * 32.0 * 2.0;
+        const int kd = (2 * W + 15) / 16 * 16;
+        b += ntile * 2.0 * kd * 2.0 + ntile / 16.0 * pwa::mfma_at_tile_elems(kd) * 2.0;
         break;
     }
     default: {   // FP32 amplitudes in the default lane-split shape
@@ -307,7 +307,7 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
         m->rb = (m->kd + 31) / 32;
         m->n_tiles = (n + pwa::kMfmaTile - 1) / pwa::kMfmaTile;
         m->data_bytes = m->n_tiles * 32 * (int64_t)m->kd * 2;   // 32 rows per tile
-        const size_t at_bytes = (size_t)m->n_tiles * m->rb * 32 * 32 * 2;
+        const size_t at_bytes = (size_t)m->n_tiles * pwa::mfma_at_tile_elems(m->kd) * 2;
         HIP_TRY(hipMalloc(&m->d_data, m->data_bytes));
         HIP_TRY(hipMalloc(&m->d_at, at_bytes));
         // padding events, columns 2W .. kd and adjoint rows 2W .. 32 rb stay zero
@@ -1258,7 +1258,7 @@ int pwa_model_info(const pwa_model* model, pwa_info* out)
     case pwa::kTable64Plain: out->stream_bytes = 2 * m->n * m->P * 16; break;
     case pwa::kAmpBF16:
     case pwa::kAmpFP16:
-        out->stream_bytes = m->n_tiles * 32 * (int64_t)(m->kd + 32 * m->rb) * 2;   // both copies
+        out->stream_bytes = m->n_tiles * (int64_t)(32 * m->kd + pwa::mfma_at_tile_elems(m->kd)) * 2;   // both copies
         break;
     default: out->stream_bytes = m->n * m->W * 8; break;
     }

@@ -38,6 +38,14 @@ constexpr int kAmpTile = 64;
 constexpr size_t kLdsBytes = 160 * 1024;   // LDS per CU (gfx950)
 // Events per tile of the 16-bit matrix-core layout (two MFMA rows each).
 constexpr int kMfmaTile = 16;
+// 16-bit elements of one tile of the matrix forms' adjoint operand copy, for
+// KD = 2W rounded up to 16: full blocks of 32 rows x 32 slots, and when KD is
+// an odd multiple of 16 a last block of 16 rows in the 16x16x32 operand order
+// (512 elements)
+__host__ __device__ constexpr int mfma_at_tile_elems(int kd)
+{
+    return ((kd / 16) & 1) ? (kd / 32) * 1024 + 512 : (kd / 32) * 1024;
+}
 
 // Lane-split layout of the FP32 amplitude form (k_amp.hip): an event is held
 // by q = 2^lq neighbouring lanes with wl (even) waves each, so rows are q wl
