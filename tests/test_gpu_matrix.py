@@ -25,9 +25,11 @@ leaves the normal range, and adds a lane's eight in FP32 before an FP64 lane
 sum (8 u |log2 I'| more); per event at most 2^-21 + 10 u |log2 I'|.  The weights c are
 split into two 16-bit parts (relative error 2^-16 for bfloat16, 2^-22 for
 float16), and an FP32 adjoint accumulator adds at most kFoldTiles + 1 = 33
-tiles (four MFMA steps of 16 products each per tile) before it is folded
-into FP64, plus one rounding each for the fold and the FP32 record:
-gamma = (4 x 33 + 6) u per accumulated term.  Per point, with
+tiles (per tile four 32x32x16 MFMA steps of 16 products each, or for the
+last 16 gradient rows two 16x16x32 steps of 32; at most four accumulator
+roundings either way) before it is folded into FP64, plus one rounding each
+for the fold and the FP32 record: gamma = (4 x 33 + 6) u per accumulated
+term.  Per point, with
 a_b = sum_i |A_ib| / |S_i| (the sum of |terms| of g_b):
   |dNLL|   <= 4 sum_i 2 e_i / |S_i| + sum_i 2 (v_i / |S_i|)^2
               + ln 2 sum_i (2^-21 + 10 u |log2 I'_i|) + 1e-9 |NLL|,
