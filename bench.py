@@ -106,10 +106,11 @@ def host_cpu():
     return {"model": model, "nproc": len(os.sched_getaffinity(0)), "logical_cpus": os.cpu_count()}
 
 
-def mfma_flops(n_events, n_waves, k, v_parts):
+def mfma_flops(n_events, n_waves, k, v_parts, bf16=False):
     """Matrix-core FLOPs of one batched pass as the kernel issues them: per
     16-event tile (32 rows) and 32 vectors, the forward product (16-wide KD
-    steps x V parts, 32x32x16 MFMAs of 32768 FLOP) and the adjoint (per full
+    steps x V parts, 32x32x16 MFMAs of 32768 FLOP; one step fewer for bf16
+    when 2W mod 16 is 1..8) and the adjoint (per full
     32-row block 2 slot steps x 2 weight parts of the same MFMA; a last block
     of 16 rows as 2 vector blocks x 2 weight parts of the 16x16x32 MFMA,
     16384 FLOP each)."""
@@ -117,7 +118,10 @@ def mfma_flops(n_events, n_waves, k, v_parts):
     rf, rem = (kd // 16) // 2, (kd // 16) % 2
     tiles = (n_events + 15) // 16
     col_blocks = (k + 31) // 32
-    per = ((kd // 16) * v_parts + rf * 2 * 2) * 32768 + rem * 2 * 2 * 16384
+    fwd = (kd // 16) * v_parts
+    if bf16 and 0 < (2 * n_waves) % 16 <= 8:
+        fwd -= 1   # the second part's last K-step rides in the first part's padding
+    per = (fwd + rf * 2 * 2) * 32768 + rem * 2 * 2 * 16384
     return tiles * col_blocks * per
 
 
@@ -166,7 +170,7 @@ def bench_batched(args):
         dt = (time.perf_counter() - t) / reps
         ms, n = m.timing()
         kus = 1e3 * ms / max(1, n)
-        fl = mfma_flops(s.data.shape[0], 20, 256, parts)
+        fl = mfma_flops(s.data.shape[0], 20, 256, parts, bf16=(form == "amplitude_bf16"))
         fa = mfma_algorithmic_flops(s.data.shape[0], 20, 256, parts)
         r = {"evals_per_s": 256 / dt, "batch_us": 1e6 * dt, "kernel_us": kus,
              "mfma_tflops": fa / (kus * 1e-6) / 1e12, "mfma_peak_tflops": 2500.0,

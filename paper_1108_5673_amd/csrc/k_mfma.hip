@@ -34,6 +34,11 @@
 //     that would be half padding: one lane-16 swap of the two halves' weight
 //     registers makes them its A operand (16 vectors x 32 slots), the stored
 //     rows its B operand.
+// Merged last step (bf16, 2W mod 16 in 1..8): the last 16-wide K-step holds
+// at most 8 real columns, so its upper 8 slots repeat them (both rows of an
+// event) and the first V part's matrix holds there the second part's rows of
+// those columns: one MFMA adds both parts of that step, and the second part
+// runs NS - 1 steps.
 // Scale: each vector enters as V_k / s_k with s_k the power of two nearest
 // ||V_k||_2, so S, I and c = S / I stay near unit magnitude whatever the size of
 // V (float16 has a narrow exponent range); the assembly undoes it exactly:
@@ -223,7 +228,7 @@ __device__ inline int64_t mfma_at_offset(int KD, int64_t tile, int row, int slot
 
 template <typename T>
 __global__ void k_pack_mfma(const void* __restrict__ src, bool c128, int64_t n, int W, int KD,
-                            T* __restrict__ af, T* __restrict__ at)
+                            bool merge, T* __restrict__ af, T* __restrict__ at)
 {
     const int64_t total = n * (int64_t)W;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
@@ -249,6 +254,12 @@ __global__ void k_pack_mfma(const void* __restrict__ src, bool c128, int64_t n, 
         x[1] = yi;
         x[KD] = yi;
         x[KD + 1] = nr;
+        if (merge && 2 * a >= KD - 16) {   // the merged last step's repeated columns
+            x[8] = yr;
+            x[9] = yi;
+            x[KD + 8] = yi;
+            x[KD + 9] = nr;
+        }
         const int s0 = mfma_slot(e, 0), s1 = mfma_slot(e, 1);
         at[mfma_at_offset(KD, tile, 2 * a, s0)] = yr;
         at[mfma_at_offset(KD, tile, 2 * a, s1)] = yi;
@@ -303,7 +314,7 @@ template <typename T> __device__ inline VSplit<T> split_v(double x)
 
 template <typename T>
 __global__ void k_prep_vmat16(const double* __restrict__ v, int K, int W, int NS, int n_cb,
-                              int NP, T* __restrict__ vm, double* __restrict__ vscale)
+                              bool merge, T* __restrict__ vm, double* __restrict__ vscale)
 {
     const int part_elems = n_cb * NS * 2 * 32 * 8;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < part_elems;
@@ -315,19 +326,24 @@ __global__ void k_prep_vmat16(const double* __restrict__ v, int K, int W, int NS
         const int cb = g / (512 * NS);
         const int k = 32 * cb + c;
         const int kd = 16 * s + 8 * h + t;
-        double x = 0.0;
-        if (k < K && kd < 2 * W) {
-            const double sk = vector_scale(v + (size_t)k * 2 * W, W);
-            if (kd == 0) vscale[k] = sk;
-            const int a = kd / 2;
-            x = kd % 2 == 0 ? v[(size_t)k * 2 * W + 2 * a] / sk        // multiplies Re A_a
-                            : -v[(size_t)k * 2 * W + 2 * a + 1] / sk;  // multiplies Im A_a
-        }
-        const VSplit<T> sp = split_v<T>(x);
+        // entry e of the scaled vector matrix: Re V_a / s (e = 2a, multiplies
+        // Re A_a) or -Im V_a / s (e = 2a + 1, multiplies Im A_a)
+        double sk = 1.0;
+        if (k < K) sk = vector_scale(v + (size_t)k * 2 * W, W);
+        auto entry = [&](int e) {
+            if (k >= K || e >= 2 * W) return 0.0;
+            const int a = e / 2;
+            return e % 2 == 0 ? v[(size_t)k * 2 * W + 2 * a] / sk
+                              : -v[(size_t)k * 2 * W + 2 * a + 1] / sk;
+        };
+        if (k < K && kd == 0) vscale[k] = sk;
+        const VSplit<T> sp = split_v<T>(entry(kd));
 #pragma unroll
         for (int p = 0; p < Split<T>::kVParts; ++p) vm[(size_t)p * part_elems + g] = sp.p[p];
+        // merged last step: the first part's upper 8 slots of the last K-step
+        // hold the second part of the entries 8 below (their repeated columns)
+        if (merge && s == NS - 1 && h == 1) vm[g] = split_v<T>(entry(kd - 8)).p[1];
     }
-    (void)NP;
 }
 
 // ---- the fused forward + epilogue + adjoint kernel -------------------------
@@ -349,7 +365,7 @@ template <int NS> constexpr int mfma_fold_regs() { return 16 * (NS / 2) + ((NS &
 // kFoldTiles tiles (so never more than kFoldTiles + 1).
 constexpr int kFoldTiles = 32;
 
-template <typename T, int NS, int NP>
+template <typename T, int NS, int NP, bool MRG>
 __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
     const T* __restrict__ af, const T* __restrict__ at, const T* __restrict__ vm,
     int64_t n_events, int64_t n_tiles, int n_cols, int n_cb, int chunks,
@@ -380,6 +396,7 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
             vp[p][s] = *reinterpret_cast<const V8*>(
                 vm + p * part_elems + ((size_t)((cb * NS + s) * 2 + h) * 32 + c) * 8);
     constexpr bool SL = Split<T>::kScaledLow;
+    static_assert(!MRG || (!SL && NP == 2), "the merged last step adds two parts in one accumulator");
     const SplitMul<T> smul = make_split_multipliers<T>();
     // adjoint accumulators: g (full blocks, 32 rows x 32 vectors) and gr (the
     // last 16 rows: 16 vectors x 16 rows per block of vectors); gl, grl the
@@ -508,7 +525,10 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
 #pragma unroll
             for (int p = NP - 1; p >= 0; --p)   // smallest parts first
 #pragma unroll
-                for (int s = 0; s < NS; ++s) acc = H16<T>::mfma(o.a[s], vp[p][s], acc);
+                for (int s = 0; s < NS; ++s) {
+                    if (MRG && p == 1 && s == NS - 1) continue;   // in part 0's last step
+                    acc = H16<T>::mfma(o.a[s], vp[p][s], acc);
+                }
         }
         return acc;
     };
@@ -577,12 +597,16 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
     // beside a share of the forward MFMAs, and pieces 4..7 also the adjoint
     // MFMAs of half 0.  The wavefront issues each piece's vector instructions
     // while its MFMAs run.
-    constexpr int kFwd = SL ? 2 * NS : NS * NP;
+    constexpr int kFwd = SL ? 2 * NS : NS * NP - (MRG ? 1 : 0);
     auto fwd_mfma = [&](const OpsA& an, f32x16& nx, f32x16& nxl, int m) {
         if constexpr (SL) {
             const int s = m >> 1;
             if (m & 1) nxl = H16<T>::mfma(an.a[s], vp[1][s], nxl);
             else nx = H16<T>::mfma(an.a[s], vp[0][s], nx);
+        } else if constexpr (MRG) {
+            // part 1 over its first NS - 1 steps, then part 0 over all NS
+            if (m < NS - 1) nx = H16<T>::mfma(an.a[m], vp[1][m], nx);
+            else nx = H16<T>::mfma(an.a[m - (NS - 1)], vp[0][m - (NS - 1)], nx);
         } else {
             const int p = NP - 1 - m / NS, s = m % NS;   // smallest parts first
             nx = H16<T>::mfma(an.a[s], vp[p][s], nx);
@@ -893,10 +917,10 @@ hipError_t launch_pack_mfma(const void* src, bool c128, int64_t n, int W, bool b
     const int64_t total = n * (int64_t)W;
     if (bf)
         hipLaunchKernelGGL(k_pack_mfma<__bf16>, dim3(grid_for(total, 256)), dim3(256), 0, s, src,
-                           c128, n, W, m.kd, (__bf16*)m.d_data, (__bf16*)m.d_at);
+                           c128, n, W, m.kd, m.fwd_merge, (__bf16*)m.d_data, (__bf16*)m.d_at);
     else
         hipLaunchKernelGGL(k_pack_mfma<_Float16>, dim3(grid_for(total, 256)), dim3(256), 0, s,
-                           src, c128, n, W, m.kd, (_Float16*)m.d_data, (_Float16*)m.d_at);
+                           src, c128, n, W, m.kd, false, (_Float16*)m.d_data, (_Float16*)m.d_at);
     return hipGetLastError();
 }
 
@@ -916,7 +940,16 @@ static void launch_main(const Model& m, const MfmaBatch& b, hipStream_t s, const
     constexpr int NP = mfma_v_parts<T>();
     const int wpb = b.n_cb < mfma_waves<NS>() ? b.n_cb : mfma_waves<NS>();
     const int gy = (b.n_cb + wpb - 1) / wpb;
-    hipExtLaunchKernelGGL((k_amp_mfma<T, NS, NP>), dim3(b.chunks, gy), dim3(64 * wpb), 0,
+    if constexpr (!Split<T>::kScaledLow) {
+        if (m.fwd_merge) {
+            hipExtLaunchKernelGGL((k_amp_mfma<T, NS, NP, true>), dim3(b.chunks, gy),
+                                  dim3(64 * wpb), 0, s, ev.start, ev.stop, 0, (const T*)m.d_data,
+                                  (const T*)m.d_at, (const T*)b.vm, m.n, m.n_tiles, b.K, b.n_cb,
+                                  b.chunks, b.rec_d, b.rec_g);
+            return;
+        }
+    }
+    hipExtLaunchKernelGGL((k_amp_mfma<T, NS, NP, false>), dim3(b.chunks, gy), dim3(64 * wpb), 0,
                           s, ev.start, ev.stop, 0, (const T*)m.d_data, (const T*)m.d_at,
                           (const T*)b.vm, m.n, m.n_tiles, b.K, b.n_cb, b.chunks, b.rec_d,
                           b.rec_g);
@@ -947,7 +980,7 @@ static hipError_t run_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
     const int NS = m.kd / 16;
     const int part_elems = b.n_cb * NS * 2 * 32 * 8;
     hipLaunchKernelGGL(k_prep_vmat16<T>, dim3(grid_for(part_elems, 256)), dim3(256), 0, s, b.v,
-                       b.K, m.W, NS, b.n_cb, mfma_v_parts<T>(), (T*)b.vm, b.vscale);
+                       b.K, m.W, NS, b.n_cb, m.fwd_merge, (T*)b.vm, b.vscale);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return dispatch_ns<T>(m, b, s, ev);

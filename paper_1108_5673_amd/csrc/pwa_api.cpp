@@ -305,6 +305,7 @@ int build_model(const void* data, int64_t n, int32_t W, const void* mc, int64_t 
     } else if (form == PWA_FORM_AMPLITUDE_BF16 || form == PWA_FORM_AMPLITUDE_FP16) {
         m->kd = (2 * W + 15) / 16 * 16;
         m->rb = (m->kd + 31) / 32;
+        m->fwd_merge = form == PWA_FORM_AMPLITUDE_BF16 && (2 * W) % 16 != 0 && (2 * W) % 16 <= 8;
         m->n_tiles = (n + pwa::kMfmaTile - 1) / pwa::kMfmaTile;
         m->data_bytes = m->n_tiles * 32 * (int64_t)m->kd * 2;   // 32 rows per tile
         const size_t at_bytes = (size_t)m->n_tiles * pwa::mfma_at_tile_elems(m->kd) * 2;

@@ -159,6 +159,8 @@ struct Model {
     void* d_at = nullptr;           // second copy of the event tiles (adjoint operand order)
     int32_t kd = 0;                 // row length 2W padded to a multiple of 16
     int32_t rb = 0;                 // adjoint row blocks of 32 (ceil(kd / 32))
+    bool fwd_merge = false;         // bf16 with 2W mod 16 in 1..8: the second V part's last
+                                    // forward K-step rides in the first part's padding slots
     int32_t vec_cap = 0;            // vectors the per-call buffers below can hold
     double* d_vb = nullptr;         // vec_cap x 2W parameter vectors, then vec_cap scales (device)
     double* h_vstage = nullptr;     // vec_cap x 2W pinned staging for d_vb
