@@ -157,25 +157,28 @@ __device__ __attribute__((always_inline)) void amp_block(const float4* __restric
     st.held = 1.0;
     st.nbad = 0;
 
-    // this wavefront's contiguous part of the block's steps
+    // this wavefront's steps: k0 + wave, k0 + wave + nwaves, ... (the block's
+    // wavefronts stream its range together); the run position of the held
+    // intensities counts the wavefront's own steps (every lane of an event
+    // holds the same I, so any lane may keep it)
     const int64_t n_steps = k1 - k0;
-    const int64_t ka = k0 + n_steps * wave / nwaves;
-    const int64_t kb = k0 + n_steps * (wave + 1) / nwaves;
-    if (ka < kb) {
+    const int64_t J = n_steps > wave ? (n_steps - wave + nwaves - 1) / nwaves : 0;
+    if (J > 0) {
         constexpr int64_t kStepVecs = 32 * WL;   // 64 lanes x WL / 2 vectors
         const float4* base = amp + lane;
         const int R_shift = 6 - lq;
+        auto kof = [&](int64_t j) { return k0 + wave + (int64_t)nwaves * j; };
         AmpRegs<WL> ra, rb;
-        amp_load(ra, base + ka * kStepVecs);
-        for (int64_t k = ka; k < kb; k += 2) {
-            const bool has_b = k + 1 < kb;
-            if (has_b) amp_load(rb, base + (k + 1) * kStepVecs);
-            amp_step<WL, GRAD>(ra, st, (k << R_shift) + (lane >> lq), n_events, lq, sub,
-                               (int)(k & (q - 1)));
-            if (k + 2 < kb) amp_load(ra, base + (k + 2) * kStepVecs);
+        amp_load(ra, base + kof(0) * kStepVecs);
+        for (int64_t j = 0; j < J; j += 2) {
+            const bool has_b = j + 1 < J;
+            if (has_b) amp_load(rb, base + kof(j + 1) * kStepVecs);
+            amp_step<WL, GRAD>(ra, st, (kof(j) << R_shift) + (lane >> lq), n_events, lq, sub,
+                               (int)(j & (q - 1)));
+            if (j + 2 < J) amp_load(ra, base + kof(j + 2) * kStepVecs);
             if (has_b)
-                amp_step<WL, GRAD>(rb, st, ((k + 1) << R_shift) + (lane >> lq), n_events, lq, sub,
-                                   (int)((k + 1) & (q - 1)));
+                amp_step<WL, GRAD>(rb, st, (kof(j + 1) << R_shift) + (lane >> lq), n_events, lq,
+                                   sub, (int)((j + 1) & (q - 1)));
         }
         st.dsum += log(st.held);   // a run cut short by the end of the range
     }
