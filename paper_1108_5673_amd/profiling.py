@@ -157,8 +157,13 @@ def summarize(fetch_csv: str, write_csv: str, out_json: str) -> dict:
 
 def _is_bf16(name: str) -> bool:
     """bf16 instance of a kernel template, by its demangled or mangled name
-    (the Itanium mangling of __bf16 is DF16b, of _Float16 DF16_)."""
-    return "bf16" in name or "DF16b" in name
+    (the Itanium mangling of __bf16 is DF16b, of _Float16 DF16_).  The kernel
+    has only the two 16-bit instances, and some demanglers cannot read DF16b
+    (they print neither type name), so everything not marked as _Float16 is
+    the bf16 instance."""
+    if "bf16" in name or "DF16b" in name:
+        return True
+    return not ("DF16_" in name or "_Float16" in name)
 
 
 def busy(derived_csv: str, raw_csv: str, out_json: str) -> dict:
