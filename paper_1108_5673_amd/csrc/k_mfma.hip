@@ -381,7 +381,7 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
     using V2 = typename H16<T>::V2;
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int h = lane >> 5, c = lane & 31;
     const int cb = (int)(blockDim.x >> 6) * blockIdx.y + wave;
     if (cb >= n_cb) return;   // no barrier follows
@@ -453,8 +453,11 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
         for (int nb = 0; nb < (SL ? 2 : 1); ++nb) grl[nb] = f32x4{};
     };
 
-    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / chunks;
-    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / chunks;
+    // tile indices fit in 32 bits (the host checks n_tiles); 32-bit scalar
+    // indices and 32-bit lane offsets from a scalar tile base keep the
+    // address arithmetic off the vector ALU
+    const int t0 = (int)((int64_t)blockIdx.x * n_tiles / chunks);
+    const int t1 = (int)((int64_t)(blockIdx.x + 1) * n_tiles / chunks);
     // operands of one tile: forward rows (32 rows x KD) and adjoint rows (RF
     // blocks of 32 rows x 32 slots, and the last 16 rows)
     struct OpsA {
@@ -464,19 +467,24 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
         V8 b[RFA][2];
         V8 br;
     };
-    auto load_a = [&](OpsA& o, int64_t t) {
-        const T* ta = af + t * 32 * KD;
+    const uint32_t a_off = (uint32_t)(c * KD + 8 * h);
+    const uint32_t b_off = (uint32_t)(c * 32 + 8 * h);
+    const uint32_t r_off = (uint32_t)(RF * 1024 + lane * 8);
+    auto load_a = [&](OpsA& o, int t) {
+        const T* ta = af + (int64_t)t * (32 * KD);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) o.a[s] = *reinterpret_cast<const V8*>(ta + c * KD + 16 * s + 8 * h);
+        for (int s = 0; s < NS; ++s)
+            o.a[s] = *reinterpret_cast<const V8*>(ta + (size_t)a_off + 16 * s);
     };
-    auto load_b = [&](OpsB& o, int64_t t) {
-        const T* tt = at + t * AT;
+    auto load_b = [&](OpsB& o, int t) {
+        const T* tt = at + (int64_t)t * AT;
 #pragma unroll
         for (int rb = 0; rb < RF; ++rb)
 #pragma unroll
             for (int s2 = 0; s2 < 2; ++s2)
-                o.b[rb][s2] = *reinterpret_cast<const V8*>(tt + (rb * 32 + c) * 32 + 16 * s2 + 8 * h);
-        if constexpr (REM) o.br = *reinterpret_cast<const V8*>(tt + RF * 1024 + lane * 8);
+                o.b[rb][s2] =
+                    *reinterpret_cast<const V8*>(tt + (size_t)b_off + rb * 1024 + 16 * s2);
+        if constexpr (REM) o.br = *reinterpret_cast<const V8*>(tt + (size_t)r_off);
     };
     // The last 16 adjoint rows on the 16x16x32 MFMA, once both halves' weights
     // of the tile are formed: D[vector][row] += C^T Y with the weights as the A
@@ -532,7 +540,7 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
         }
         return acc;
     };
-    auto finish = [&](const f32x16& acc, const OpsB& o, int64_t t, auto fast_tag) {
+    auto finish = [&](const f32x16& acc, const OpsB& o, int t, auto fast_tag) {
         constexpr bool fast = decltype(fast_tag)::value;
         // Epilogue and adjoint, in two halves of 8 registers (the adjoint MFMA
         // of half s2 takes registers 8 s2 .. 8 s2 + 7).  Registers (q, q + 1),
@@ -542,7 +550,7 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
         // has to be counted (its NLL is +inf whatever the sum, and its weight
         // 0 * inf or x * NaN is NaN); the last tile and the padding columns
         // take the general path.
-        const int nvalid = (int)min<int64_t>(kMfmaTile, n_events - t * kMfmaTile);
+        const int nvalid = (int)min<int64_t>(kMfmaTile, n_events - (int64_t)t * kMfmaTile);
         float lsum = 0.f;
         V8 chis[2], clos[2];
 #pragma unroll
@@ -694,9 +702,9 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
     // validity tests: a degenerate event makes the lane's log sum non-finite).
     // Operands are loaded a step ahead; loads and products past the last full
     // tile repeat that tile and are not used.
-    const int64_t t_full = 32 * cb + 32 <= n_cols ? n_events / kMfmaTile : 0;
-    const int64_t tf = max(t0, min(t1, t_full));
-    int64_t t = t0;
+    const int t_full = 32 * cb + 32 <= n_cols ? (int)(n_events / kMfmaTile) : 0;
+    const int tf = max(t0, min(t1, t_full));
+    int t = t0;
     if (tf - t0 >= 2) {
         OpsA a0, a1;
         OpsB b0, b1;
@@ -724,7 +732,7 @@ __global__ __launch_bounds__(64 * mfma_waves<NS>()) void k_amp_mfma(
     }
     // the rest (a chunk with fewer than two full tiles, the last tile, padded
     // columns): one tile at a time, the next tile's operands loaded ahead
-    auto run = [&](const OpsA& oa, const OpsB& ob, int64_t tt) {
+    auto run = [&](const OpsA& oa, const OpsB& ob, int tt) {
         if (tt < t_full) finish(forward(oa), ob, tt, std::true_type{});
         else finish(forward(oa), ob, tt, std::false_type{});
     };
@@ -978,6 +986,7 @@ static hipError_t run_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
                             const LaunchEvents& ev)
 {
     const int NS = m.kd / 16;
+    if (m.n_tiles > INT32_MAX) return hipErrorInvalidValue;   // 32-bit tile indices
     const int part_elems = b.n_cb * NS * 2 * 32 * 8;
     hipLaunchKernelGGL(k_prep_vmat16<T>, dim3(grid_for(part_elems, 256)), dim3(256), 0, s, b.v,
                        b.K, m.W, NS, b.n_cb, m.fwd_merge, (T*)b.vm, b.vscale);
