@@ -27,7 +27,8 @@ constexpr int kGramDepth = 8;          // steps of loads in flight per wavefront
 
 // ---- the MC integral on the FP64 matrix cores (2W <= 256) -----------------
 // The real Gram matrix G = sum_j x_j x_j^T of x_j = [Re B_j0 .. Re B_j,W-1,
-// Im B_j0 .. Im B_j,W-1] (zero padded to 16 T) holds the Hermitian sum:
+// Im B_j0 .. Im B_j,W-1] (padded to 16 T; the padding rows and columns of G
+// are never read) holds the Hermitian sum:
 //   sum_j B_ja conj(B_jb) = G[a][b] + G[W+a][W+b] + i (G[W+a][b] - G[a][W+b]).
 // G is a product with the events as its inner dimension, on
 // v_mfma_f64_16x16x4f64 (D += A B with A 16 x 4, B 4 x 16): tile pair
@@ -49,7 +50,9 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const void* __restrict__ mc, 
 {
     constexpr int NPAIR = T * (T + 1) / 2;
     using In = typename std::conditional<C128, double2, float2>::type;
+    using R = typename std::conditional<C128, double, float>::type;   // one real component
     const In* src = reinterpret_cast<const In*>(mc);
+    const R* srcr = reinterpret_cast<const R*>(mc);
     __shared__ double s_acc[NPAIR * 4 * 64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -61,13 +64,28 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const void* __restrict__ mc, 
     const int64_t n_steps = (n_acc + 3) / 4;
     const int64_t s0 = (int64_t)blockIdx.x * n_steps / gridDim.x;
     const int64_t s1 = (int64_t)(blockIdx.x + 1) * n_steps / gridDim.x;
-    // component 16 t + i of this lane's event of step st, 0 beyond the data:
-    // the address is clamped into the input (n_acc >= 1) and the value
-    // multiplied by 0 or 1, so that every load is used and none is put behind
-    // a branch
-    auto load = [&](double (&x)[T], int64_t st) {
+    // Steps whose four events all exist: component 16 t + i of this lane's
+    // event is the real value off[t] places after the step's first event
+    // (Re B_c at 2 (k W + c), Im B_c at 2 (k W + c) + 1), read from a scalar
+    // step base with a 32-bit lane offset.  The padding components (16 t + i
+    // >= 2W) read component 0 instead: they only reach the Gram rows and
+    // columns beyond 2W, which the expansion never reads.
+    uint32_t off[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int c = 16 * t + i;
+        const int cc = c < 2 * W ? c : 0;
+        off[t] = (uint32_t)(2 * (k * W + (cc < W ? cc : cc - W)) + (cc < W ? 0 : 1));
+    }
+    auto load_full = [&](double (&x)[T], int64_t st) {
+        const R* base = srcr + st * (int64_t)(8 * W);
+#pragma unroll
+        for (int t = 0; t < T; ++t) x[t] = (double)base[(size_t)off[t]];
+    };
+    // any step: events beyond the data, and the padding components, give 0
+    auto load_checked = [&](double (&x)[T], int64_t st) {
         const int64_t j = 4 * st + k;
-        const bool ev_ok = st < s1 && j < n_acc;
+        const bool ev_ok = j < n_acc;
         const int64_t jj = ev_ok ? j : 0;
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -86,19 +104,32 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const void* __restrict__ mc, 
             for (int u = t; u < T; ++u, ++p)
                 d[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t], x[u], d[p], 0, 0, 0);
     };
-    // this wavefront's steps: first, first + 4, ... below s1, kGramDepth per
-    // trip, each slot of the register ring refilled kGramDepth steps ahead as
-    // soon as it is used (a step past s1 loads zeros)
+    // this wavefront's full steps: first, first + 4, ... below s_full,
+    // kGramDepth per trip, each slot of the register ring refilled kGramDepth
+    // steps ahead as soon as it is used (refills past the last full step
+    // repeat it and are not added)
+    const int64_t s_full = min(s1, n_acc / 4);
     const int64_t first = s0 + wave;
-    const int64_t n_my = first < s1 ? (s1 - first + 3) / 4 : 0;
-    double xs[kGramDepth][T];
+    const int64_t n_my = first < s_full ? (s_full - first + 3) / 4 : 0;
+    if (n_my > 0) {
+        const int64_t last = s_full - 1;
+        double xs[kGramDepth][T];
 #pragma unroll
-    for (int q = 0; q < kGramDepth; ++q) load(xs[q], first + 4 * q);
-    for (int64_t q0 = 0; q0 < n_my; q0 += kGramDepth) {
+        for (int q = 0; q < kGramDepth; ++q) load_full(xs[q], min(first + 4 * q, last));
+        for (int64_t q0 = 0; q0 < n_my; q0 += kGramDepth) {
 #pragma unroll
-        for (int q = 0; q < kGramDepth; ++q) {
-            accumulate(xs[q]);
-            load(xs[q], first + 4 * (q0 + q + kGramDepth));
+            for (int q = 0; q < kGramDepth; ++q) {
+                if (q0 + q < n_my) accumulate(xs[q]);
+                load_full(xs[q], min(first + 4 * (q0 + q + kGramDepth), last));
+            }
+        }
+    }
+    // the step with fewer than four events (only in the last block's range)
+    for (int64_t st = s_full; st < s1; ++st) {
+        if ((st - s0) % 4 == wave) {
+            double x[T];
+            load_checked(x, st);
+            accumulate(x);
         }
     }
 
