@@ -437,17 +437,20 @@ __device__ inline double2 strided_record_sum(const TailArgs& ta, int col, int fi
     double2 acc = make_double2(0.0, 0.0);
     const double* base = ta.rec + col;
     for (int r = first; r < ta.rows; r += kBatch * step) {
+        // every load is issued (a row past the last reads the last and is not
+        // added), so that none sits behind a branch
         double2 x[kBatch];
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
-            const int row = r + k * step;
-            x[k] = row < ta.rows ? *reinterpret_cast<const double2*>(base + (int64_t)row * ta.rec_len)
-                                 : make_double2(0.0, 0.0);
+            const int row = min(r + k * step, ta.rows - 1);
+            x[k] = *reinterpret_cast<const double2*>(base + (int64_t)row * ta.rec_len);
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
-            acc.x += x[k].x;
-            acc.y += x[k].y;
+            if (r + k * step < ta.rows) {
+                acc.x += x[k].x;
+                acc.y += x[k].y;
+            }
         }
     }
     return acc;

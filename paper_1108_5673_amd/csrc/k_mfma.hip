@@ -312,38 +312,89 @@ template <typename T> __device__ inline VSplit<T> split_v(double x)
     return r;
 }
 
+// Per-vector values the assembly needs besides the records, kVPrep(W)
+// doubles per vector: [s_k, mu_k, m (Re m_b, Im m_b for b < W), the
+// remainders the 16-bit split leaves out of each entry of the scaled column
+// (2W)], with m_b = sum_a V_a M_ab and mu_k = Re sum_b conj(V_b) m_b.
+__host__ __device__ inline int vprep_len(int W) { return 4 * W + 2; }
+
+constexpr int kPrepThreads = 256;
+
+// One block per column k of the vector matrix (32 n_cb columns; those past K
+// are zero): V_k is read once (from device or mapped host memory), its scale
+// s_k formed, and the column's entries written in the layout the main
+// kernel's B operand reads (lane c of half h holds entries 16 s + 8 h ..
+// 16 s + 8 h + 7 of step s), one array per part; then the vector's
+// assembly values above.
 template <typename T>
-__global__ void k_prep_vmat16(const double* __restrict__ v, int K, int W, int NS, int n_cb,
-                              bool merge, T* __restrict__ vm, double* __restrict__ vscale)
+__global__ __launch_bounds__(kPrepThreads) void k_prep_vmat16(
+    const double* __restrict__ v, int K, int W, int NS, int n_cb, bool merge,
+    const double2* __restrict__ M, T* __restrict__ vm, double* __restrict__ vprep)
 {
-    const int part_elems = n_cb * NS * 2 * 32 * 8;
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < part_elems;
-         g += gridDim.x * blockDim.x) {
-        const int t = g % 8;
-        const int c = (g / 8) % 32;
-        const int h = (g / 256) % 2;
-        const int s = (g / 512) % NS;
-        const int cb = g / (512 * NS);
-        const int k = 32 * cb + c;
-        const int kd = 16 * s + 8 * h + t;
-        // entry e of the scaled vector matrix: Re V_a / s (e = 2a, multiplies
-        // Re A_a) or -Im V_a / s (e = 2a + 1, multiplies Im A_a)
-        double sk = 1.0;
-        if (k < K) sk = vector_scale(v + (size_t)k * 2 * W, W);
-        auto entry = [&](int e) {
-            if (k >= K || e >= 2 * W) return 0.0;
-            const int a = e / 2;
-            return e % 2 == 0 ? v[(size_t)k * 2 * W + 2 * a] / sk
-                              : -v[(size_t)k * 2 * W + 2 * a + 1] / sk;
-        };
-        if (k < K && kd == 0) vscale[k] = sk;
+    __shared__ double s_v[2 * PWA_MAX_WAVES_MATRIX];
+    __shared__ double s_wave[kPrepThreads / 64];
+    const int k = blockIdx.x;
+    const int cb = k / 32, c = k % 32;
+    const bool real = k < K;   // uniform over the block
+    const int b = threadIdx.x;
+    // the first 16 rows of column b of M, loaded while V arrives
+    constexpr int kB = 16;
+    double2 x0[kB];
+#pragma unroll
+    for (int j = 0; j < kB; ++j)
+        x0[j] = real && b < W && j < W ? M[j * W + b] : make_double2(0.0, 0.0);
+    for (int e = threadIdx.x; e < 2 * W; e += blockDim.x)
+        s_v[e] = real ? v[(size_t)k * 2 * W + e] : 0.0;
+    __syncthreads();
+    const double sk = real ? vector_scale(s_v, W) : 1.0;
+    // entry e of the scaled column: Re V_a / s (e = 2a, multiplies Re A_a) or
+    // -Im V_a / s (e = 2a + 1, multiplies Im A_a)
+    auto entry = [&](int e) {
+        if (!real || e >= 2 * W) return 0.0;
+        return e % 2 == 0 ? s_v[e] / sk : -s_v[e] / sk;
+    };
+    const size_t part_elems = (size_t)n_cb * NS * 2 * 32 * 8;
+    for (int kd = threadIdx.x; kd < 16 * NS; kd += blockDim.x) {
+        const int st = kd / 16, h = (kd / 8) % 2, t = kd % 8;
+        const size_t g = ((size_t)((cb * NS + st) * 2 + h) * 32 + c) * 8 + t;
         const VSplit<T> sp = split_v<T>(entry(kd));
 #pragma unroll
-        for (int p = 0; p < Split<T>::kVParts; ++p) vm[(size_t)p * part_elems + g] = sp.p[p];
+        for (int p = 0; p < Split<T>::kVParts; ++p) vm[p * part_elems + g] = sp.p[p];
         // merged last step: the first part's upper 8 slots of the last K-step
         // hold the second part of the entries 8 below (their repeated columns)
-        if (merge && s == NS - 1 && h == 1) vm[g] = split_v<T>(entry(kd - 8)).p[1];
+        if (merge && st == NS - 1 && h == 1) vm[g] = split_v<T>(entry(kd - 8)).p[1];
     }
+    if (!real) return;
+    // m_b = sum_a V_a M_ab (thread b), rows in order, 16 at a time
+    double mr = 0.0, mi = 0.0, mu_part = 0.0;
+    if (b < W) {
+        for (int a0 = 0; a0 < W; a0 += kB) {
+            double2 x[kB];
+#pragma unroll
+            for (int j = 0; j < kB; ++j)
+                x[j] = a0 == 0 ? x0[j]
+                               : (a0 + j < W ? M[(a0 + j) * W + b] : make_double2(0.0, 0.0));
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                const int a = a0 + j < W ? a0 + j : 0;
+                const double vr = s_v[2 * a], vi = s_v[2 * a + 1];
+                mr += vr * x[j].x - vi * x[j].y;
+                mi += vr * x[j].y + vi * x[j].x;
+            }
+        }
+        mu_part = s_v[2 * b] * mr + s_v[2 * b + 1] * mi;
+    }
+    const double mu = block_sum_fixed(mu_part, s_wave);
+    double* vp = vprep + (size_t)k * vprep_len(W);
+    if (threadIdx.x == 0) {
+        vp[0] = sk;
+        vp[1] = mu;
+    }
+    if (b < W) {
+        vp[2 + 2 * b] = mr;
+        vp[3 + 2 * b] = mi;
+    }
+    for (int o = threadIdx.x; o < 2 * W; o += blockDim.x) vp[2 + 2 * W + o] = split_v<T>(entry(o)).rest;
 }
 
 // ---- the fused forward + epilogue + adjoint kernel -------------------------
@@ -796,9 +847,7 @@ struct BatchTail {
     const float* rec_g;    // chunks x n_cb x 32 x KD
     int chunks, n_cb, KD, W, K;
     int64_t n_events;
-    const double* v;       // K x 2W (device)
-    const double* vscale;  // K scales s_k (device)
-    const double2* M;      // W x W
+    const double* vprep;   // K x vprep_len(W) per-vector values (device)
     double* out;           // K x (2 + 2W) (pinned host memory, or device memory)
     unsigned long long* done;   // K completion words (pinned host memory), or null
     unsigned long long seq;
@@ -813,15 +862,12 @@ template <typename T>
 __global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt)
 {
     __shared__ double s_wave[kBatchAsmThreads / 64];
-    __shared__ double s_v[2 * PWA_MAX_WAVES_MATRIX];
-    __shared__ double2 s_m[PWA_MAX_WAVES_MATRIX];
     __shared__ double s_part[kBatchAsmThreads];
     const int k = blockIdx.x;
     const int W = bt.W;
     const int cb = k / 32, c0 = k % 32;
-    const double* vk = bt.v + (size_t)k * 2 * W;
+    const double* vp = bt.vprep + (size_t)k * vprep_len(W);
     auto ridx = [&](int ch, int cc) { return ((size_t)ch * bt.n_cb + cb) * 32 + cc; };
-    for (int a = threadIdx.x; a < 2 * W; a += blockDim.x) s_v[a] = vk[a];
     // sum ln I and n_bad over chunks
     double d = 0.0, nb = 0.0;
     for (int ch = threadIdx.x; ch < bt.chunks; ch += blockDim.x) {
@@ -831,55 +877,41 @@ __global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt
     }
     // gradient records: output o = 2 b + part (G row o: Re g_b, Im g_b) over R
     // chunk ranges (thread o + 2W r takes chunks r, r + R, ... in order; the R
-    // partial sums are added in order at the end).  Issued here, in batches of
-    // 48, so that their loads overlap the reductions and M below.
+    // partial sums are added in order at the end), loaded in batches of 48
     const int nout = 2 * W;
     const int R = kBatchAsmThreads / nout;
     const int o = threadIdx.x % nout, r = threadIdx.x / nout;
+    double m = 0.0, rest = 0.0;
+    if (threadIdx.x < nout) {
+        m = vp[2 + threadIdx.x];
+        rest = vp[2 + nout + threadIdx.x];
+    }
     if (r < R) {
+        // component o of this vector's record of chunk ch: gk[ch * cstride]
+        // (the records of all chunks hold fewer than 2^31 values)
+        const float* gk = bt.rec_g + ridx(0, c0) * bt.KD + o;
+        const int cstride = bt.n_cb * 32 * bt.KD;
         double x = 0.0;
         constexpr int kB = 48;
         for (int ch0 = r; ch0 < bt.chunks; ch0 += kB * R) {
+            // every load is issued (a chunk past the last reads the last and
+            // is not added), so that none sits behind a branch that waits
             float u[kB];
 #pragma unroll
             for (int j = 0; j < kB; ++j) {
-                const int ch = ch0 + j * R;
-                u[j] = ch < bt.chunks ? bt.rec_g[ridx(ch, c0) * bt.KD + o] : 0.f;
+                const int ch = min(ch0 + j * R, bt.chunks - 1);
+                u[j] = gk[ch * cstride];
             }
 #pragma unroll
-            for (int j = 0; j < kB; ++j) x += (double)u[j];
+            for (int j = 0; j < kB; ++j)
+                if (ch0 + j * R < bt.chunks) x += (double)u[j];
         }
         s_part[threadIdx.x] = x;
     }
-    __syncthreads();   // s_v
-    const double sk = bt.vscale[k];
+    const double sk = vp[0];
+    const double mu = vp[1];
     const double dsum = block_sum_fixed(d, s_wave) + 2.0 * (double)bt.n_events * log(sk);
-    const double nbad = block_sum_fixed(nb, s_wave);
-    // m_b = sum_a V_a M_ab, column b of M loaded in batches
-    for (int b = threadIdx.x; b < W; b += blockDim.x) {
-        double mr = 0.0, mi = 0.0;
-        constexpr int kB = 16;
-        for (int a0 = 0; a0 < W; a0 += kB) {
-            double2 x[kB];
-#pragma unroll
-            for (int j = 0; j < kB; ++j)
-                x[j] = a0 + j < W ? bt.M[(a0 + j) * W + b] : make_double2(0.0, 0.0);
-#pragma unroll
-            for (int j = 0; j < kB; ++j) {
-                const int a = a0 + j < W ? a0 + j : 0;
-                const double vr = s_v[2 * a], vi = s_v[2 * a + 1];
-                mr += vr * x[j].x - vi * x[j].y;
-                mi += vr * x[j].y + vi * x[j].x;
-            }
-        }
-        s_m[b] = make_double2(mr, mi);
-    }
-    __syncthreads();
-    double mu_part = 0.0;
-    for (int b = threadIdx.x; b < W; b += blockDim.x)
-        mu_part += s_v[2 * b] * s_m[b].x + s_v[2 * b + 1] * s_m[b].y;
-    const double mu = block_sum_fixed(mu_part, s_wave);
-    __syncthreads();   // s_part
+    const double nbad = block_sum_fixed(nb, s_wave);   // also orders s_part
     // Component o of the scaled adjoint sums, g'_o (rows 2b, 2b + 1: Re, Im
     // g'_b with g' = s g), and the first-order share of the part of V the
     // split leaves out: with S' computed from V' - V'_lo, sum ln I' is low by
@@ -890,12 +922,9 @@ __global__ __launch_bounds__(kBatchAsmThreads) void k_assemble_mfma(BatchTail bt
     if (threadIdx.x < nout) {
         double x = 0.0;
         for (int rr = 0; rr < R; ++rr) x += s_part[rr * nout + threadIdx.x];
-        const int b = threadIdx.x / 2, part = threadIdx.x % 2;
-        const double e = part == 0 ? s_v[2 * b] / sk : -s_v[2 * b + 1] / sk;
-        const double rest = split_v<T>(e).rest;
+        const int part = threadIdx.x % 2;
         corr = 2.0 * (part == 0 ? rest : -rest) * x;
         x /= sk;
-        const double m = part == 0 ? s_m[b].x : s_m[b].y;
         store_system(bt.out + (size_t)k * (2 + 2 * W) + 2 + threadIdx.x, 2.0 * (m - x));
     }
     const double dcorr = block_sum_fixed(corr, s_wave);
@@ -987,9 +1016,9 @@ static hipError_t run_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
 {
     const int NS = m.kd / 16;
     if (m.n_tiles > INT32_MAX) return hipErrorInvalidValue;   // 32-bit tile indices
-    const int part_elems = b.n_cb * NS * 2 * 32 * 8;
-    hipLaunchKernelGGL(k_prep_vmat16<T>, dim3(grid_for(part_elems, 256)), dim3(256), 0, s, b.v,
-                       b.K, m.W, NS, b.n_cb, m.fwd_merge, (T*)b.vm, b.vscale);
+    hipLaunchKernelGGL(k_prep_vmat16<T>, dim3(32 * b.n_cb), dim3(kPrepThreads), 0, s, b.v, b.K,
+                       m.W, NS, b.n_cb, m.fwd_merge, (const double2*)m.d_M, (T*)b.vm,
+                       b.vprep);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return dispatch_ns<T>(m, b, s, ev);
@@ -1015,10 +1044,8 @@ hipError_t launch_mfma_batch(const Model& m, const MfmaBatch& b, hipStream_t s,
     bt.KD = m.kd;
     bt.W = m.W;
     bt.K = b.K;
-    bt.v = b.v;
-    bt.vscale = b.vscale;
+    bt.vprep = b.vprep;
     bt.n_events = m.n;
-    bt.M = (const double2*)m.d_M;
     bt.out = b.out;
     bt.done = b.done;
     bt.seq = b.seq;
@@ -1062,7 +1089,7 @@ bool noalloc_layout(const Model& m, int K, NoAllocLayout* L)
 {
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     const int n_cb = (K + 31) / 32;
-    const size_t head = up(sizeof(double) * (size_t)K) + up(mfma_vm_bytes(m, n_cb));
+    const size_t head = up(sizeof(double) * vprep_len(m.W) * (size_t)K) + up(mfma_vm_bytes(m, n_cb));
     const size_t per_chunk = (size_t)n_cb * 32 * (2 * sizeof(double) + sizeof(float) * m.kd);
     if (head + per_chunk > kNoAllocScratchBytes) return false;
     int chunks = mfma_chunks(m, n_cb);
@@ -1070,8 +1097,8 @@ bool noalloc_layout(const Model& m, int K, NoAllocLayout* L)
     if ((size_t)chunks > fit) chunks = (int)fit;
     L->n_cb = n_cb;
     L->chunks = chunks;
-    L->vscale_off = 0;
-    L->vm_off = up(sizeof(double) * (size_t)K);
+    L->vprep_off = 0;
+    L->vm_off = up(sizeof(double) * vprep_len(m.W) * (size_t)K);
     L->rec_d_off = head;
     L->rec_g_off = head + up((size_t)chunks * n_cb * 32 * 2 * sizeof(double));
     return L->rec_g_off + (size_t)chunks * n_cb * 32 * sizeof(float) * m.kd <=

@@ -829,9 +829,10 @@ int mfma_reserve(Model* m, int K, int n_cb, int chunks)
         m->d_brec = nullptr;
         m->vec_cap = 0;
         const int cb_cap = (cap + 31) / 32;
-        HIP_TRY(hipMalloc(&m->d_vb, sizeof(double) * (2 * W + 1) * (size_t)cap));
+        HIP_TRY(hipMalloc(&m->d_vb, sizeof(double) * (4 * W + 2) * (size_t)cap));
+        // the vectors, read by the kernels straight from mapped host memory
         HIP_TRY(hipHostMalloc((void**)&m->h_vstage, sizeof(double) * 2 * W * (size_t)cap,
-                              hipHostMallocDefault));
+                              hipHostMallocCoherent | hipHostMallocMapped));
         HIP_TRY(hipMalloc(&m->d_vm, pwa::mfma_vm_bytes(*m, cb_cap)));
         // chunks x column blocks stays near 2048 (or below) for every K up to cap
         size_t rec_rows = 0;
@@ -870,12 +871,12 @@ int eval_mfma(Model* m, const double* v, int K, hipStream_t s, bool timed)
     const int chunks = pwa::mfma_chunks(*m, n_cb);
     int rc = mfma_reserve(m, K, n_cb, chunks);
     if (rc != PWA_OK) return rc;
+    // the previous call has finished (its results were awaited), so no
+    // kernel still reads the staging buffer
     std::memcpy(m->h_vstage, v, sizeof(double) * 2 * W * (size_t)K);
-    HIP_TRY(hipMemcpyAsync(m->d_vb, m->h_vstage, sizeof(double) * 2 * W * (size_t)K,
-                           hipMemcpyHostToDevice, s));
     pwa::MfmaBatch b;
-    b.v = m->d_vb;
-    b.vscale = m->d_vb + (size_t)2 * W * m->vec_cap;
+    b.v = m->h_vstage;
+    b.vprep = m->d_vb;
     b.vm = m->d_vm;
     b.rec_d = m->d_brec;
     b.rec_g = (float*)(m->d_brec + 2 * 32 * m->brec_rows);
@@ -1147,7 +1148,7 @@ int pwa_nll_batched_noalloc(const pwa_model* model, int32_t k, const double* v_d
     char* b8 = static_cast<char*>(base);
     pwa::MfmaBatch b;
     b.v = v_dev;
-    b.vscale = reinterpret_cast<double*>(b8 + L.vscale_off);
+    b.vprep = reinterpret_cast<double*>(b8 + L.vprep_off);
     b.vm = b8 + L.vm_off;
     b.rec_d = reinterpret_cast<double*>(b8 + L.rec_d_off);
     b.rec_g = reinterpret_cast<float*>(b8 + L.rec_g_off);

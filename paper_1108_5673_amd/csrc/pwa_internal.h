@@ -162,8 +162,8 @@ struct Model {
     bool fwd_merge = false;         // bf16 with 2W mod 16 in 1..8: the second V part's last
                                     // forward K-step rides in the first part's padding slots
     int32_t vec_cap = 0;            // vectors the per-call buffers below can hold
-    double* d_vb = nullptr;         // vec_cap x 2W parameter vectors, then vec_cap scales (device)
-    double* h_vstage = nullptr;     // vec_cap x 2W pinned staging for d_vb
+    double* d_vb = nullptr;         // vec_cap x (4W + 2) per-vector values (device)
+    double* h_vstage = nullptr;     // vec_cap x 2W parameter vectors (mapped host memory)
     void* d_vm = nullptr;           // split vector matrix
     double* d_hrec = nullptr;       // FUMILI matrix: per-block records
     double* h_hout = nullptr;       // FUMILI matrix: 2W x 2W result (pinned host)
@@ -216,8 +216,8 @@ struct MultiLaunch {
 
 // One call of the matrix-core path: K vectors, device buffers and outputs.
 struct MfmaBatch {
-    const double* v;            // K x 2W (device)
-    double* vscale;             // K power-of-two scales of the vectors (device)
+    const double* v;            // K x 2W (device, or mapped host memory)
+    double* vprep;              // K x (4W + 2): scale, mu, V M, split remainders (device)
     void* vm;                   // split vector matrix (device)
     double* rec_d;              // chunks x n_cb x 32 x 2: sum ln I, n_bad (device)
     float* rec_g;               // chunks x n_cb x 32 x kd: G columns, Re/Im g_b (device)
@@ -287,7 +287,7 @@ constexpr int kNoAllocMaxDevices = 64;
 constexpr int kNoAllocMaxVectors = 1024;
 struct NoAllocLayout {
     int n_cb, chunks;
-    size_t vscale_off, vm_off, rec_d_off, rec_g_off;   // byte offsets in the scratch array
+    size_t vprep_off, vm_off, rec_d_off, rec_g_off;    // byte offsets in the scratch array
 };
 hipError_t noalloc_scratch(int device, void** out);
 bool noalloc_layout(const Model& m, int K, NoAllocLayout* L);
