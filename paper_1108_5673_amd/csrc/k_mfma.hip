@@ -312,12 +312,6 @@ template <typename T> __device__ inline VSplit<T> split_v(double x)
     return r;
 }
 
-// Per-vector values the assembly needs besides the records, kVPrep(W)
-// doubles per vector: [s_k, mu_k, m (Re m_b, Im m_b for b < W), the
-// remainders the 16-bit split leaves out of each entry of the scaled column
-// (2W)], with m_b = sum_a V_a M_ab and mu_k = Re sum_b conj(V_b) m_b.
-__host__ __device__ inline int vprep_len(int W) { return 4 * W + 2; }
-
 constexpr int kPrepThreads = 256;
 
 // One block per column k of the vector matrix (32 n_cb columns; those past K

@@ -829,7 +829,7 @@ int mfma_reserve(Model* m, int K, int n_cb, int chunks)
         m->d_brec = nullptr;
         m->vec_cap = 0;
         const int cb_cap = (cap + 31) / 32;
-        HIP_TRY(hipMalloc(&m->d_vb, sizeof(double) * (4 * W + 2) * (size_t)cap));
+        HIP_TRY(hipMalloc(&m->d_vb, sizeof(double) * pwa::vprep_len(W) * (size_t)cap));
         // the vectors, read by the kernels straight from mapped host memory
         HIP_TRY(hipHostMalloc((void**)&m->h_vstage, sizeof(double) * 2 * W * (size_t)cap,
                               hipHostMallocCoherent | hipHostMallocMapped));

@@ -162,7 +162,7 @@ struct Model {
     bool fwd_merge = false;         // bf16 with 2W mod 16 in 1..8: the second V part's last
                                     // forward K-step rides in the first part's padding slots
     int32_t vec_cap = 0;            // vectors the per-call buffers below can hold
-    double* d_vb = nullptr;         // vec_cap x (4W + 2) per-vector values (device)
+    double* d_vb = nullptr;         // vec_cap x vprep_len(W) per-vector values (device)
     double* h_vstage = nullptr;     // vec_cap x 2W parameter vectors (mapped host memory)
     void* d_vm = nullptr;           // split vector matrix
     double* d_hrec = nullptr;       // FUMILI matrix: per-block records
@@ -214,10 +214,16 @@ struct MultiLaunch {
     MultiClass cls[kMultiClasses];
 };
 
+// Per-vector values the matrix-core assembly needs besides the records,
+// vprep_len(W) doubles per vector: [s_k, mu_k, m (Re m_b, Im m_b for b < W),
+// the remainders the 16-bit split leaves out of each entry of the scaled
+// column (2W)], with m_b = sum_a V_a M_ab and mu_k = Re sum_b conj(V_b) m_b.
+__host__ __device__ inline int vprep_len(int W) { return 4 * W + 2; }
+
 // One call of the matrix-core path: K vectors, device buffers and outputs.
 struct MfmaBatch {
     const double* v;            // K x 2W (device, or mapped host memory)
-    double* vprep;              // K x (4W + 2): scale, mu, V M, split remainders (device)
+    double* vprep;              // K x vprep_len(W): scale, mu, V M, split remainders (device)
     void* vm;                   // split vector matrix (device)
     double* rec_d;              // chunks x n_cb x 32 x 2: sum ln I, n_bad (device)
     float* rec_g;               // chunks x n_cb x 32 x kd: G columns, Re/Im g_b (device)

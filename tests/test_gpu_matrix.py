@@ -215,3 +215,31 @@ def test_matrix_repeatable(form):
     b = pwa.nll_batched([model], [s.points])[0]
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     model.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_matrix_buffer_reuse_and_growth(form):
+    """One model, calls of different K in turn: a larger call grows the
+    per-call buffers (the vector staging the kernels read, the per-vector
+    values, the records), and a repeat of the first call afterwards gives the
+    same results bit for bit (the same K, so the same event chunks); the
+    larger call is held to the derived bounds against the oracle."""
+    o = oracle.get()
+    w, n, n_mc = 12, 3000, 4000
+    s = synth.small_sample(w, n, n_mc, seed=6, n_points=300)
+    d32, mc32 = s.data.astype(np.complex64), s.mc.astype(np.complex64)
+    model = pwa.Model(d32, mc32, n_mc, form=form)
+    P, Q = s.points[:40], s.points
+    a1 = pwa.nll_batched([model], [P])[0]
+    b = pwa.nll_batched([model], [Q])[0]
+    a2 = pwa.nll_batched([model], [P])[0]
+    assert np.array_equal(a1[0], a2[0]) and np.array_equal(a1[1], a2[1])
+    A = _round16(d32, form)
+    M = o.mc_matrix(mc32.astype(np.complex128), n_mc)
+    for j in (0, 150, 299):
+        rn, rg, nbad = o.nll_amp(A, M, Q[j])
+        assert nbad == 0
+        b_nll, b_g = _bounds(A, Q[j], form, rn, rg)
+        assert abs(b[0][j] - rn) <= b_nll, (j, b[0][j], rn, b_nll)
+        assert np.linalg.norm(b[1][j] - rg) <= b_g, (j, _rel(b[1][j], rg))
+    model.close()
