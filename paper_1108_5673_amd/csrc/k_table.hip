@@ -355,8 +355,30 @@ struct SubTile {
     // 16-byte offset.  Full slots load unconditionally; only the last,
     // partly filled slot is predicated on the lane.  The table is read once
     // per evaluation, so the loads are non-temporal.
+    //
+    // From 8 slots on, every load is issued without a branch (written with
+    // run-time slot tests, the compiler turned the wide shapes' loads into
+    // one branch per slot that waited for its load, so that one load at a
+    // time was in flight): a lane whose entry lies past the P stored entries
+    // reads the last stored entry instead.  Its coefficient is zero, so it
+    // adds nothing to I, and the U entry it feeds is never read.
     __device__ void load(const char* tb, int sub, int P, int lane)
     {
+        if constexpr (K >= 8) {
+            const int kl = (P - 1) >> 6;   // last slot holding entries
+            const int nl = P - 64 * kl;    // entries in it
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int kk = k < kl ? k : kl;
+                const int nk = k < kl ? 64 : nl;
+                const int ln = k < kl ? lane : (k == kl ? min(lane, nl - 1) : nl - 1);
+                const char* sb = tb + (int64_t)kk * 64 * VPT * 16;
+#pragma unroll
+                for (int v = 0; v < VS; ++v)
+                    x[k][v] = VT::load(sb + ((sub * VS + v) * nk + ln) * 16);
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const char* sb = tb + (int64_t)k * 64 * VPT * 16;
@@ -569,12 +591,22 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
     for (int k = 0; k < K; ++k) { ur[k] = 0.0; ui[k] = 0.0; }
     FusedState fs{0.0, 1.0, 0};
 
-    for (int64_t u = 0; u < U; u += 2) {
-        if (u + 1 < U) b.load(base_of(u + 1), part_of(u + 1), P, lane);
-        process_subtile<S, K, E, GRAD>(a, s_c, lane, u, first_of(u), n_events, ur, ui, fs);
-        if (u + 1 < U) {
-            if (u + 2 < U) a.load(base_of(u + 2), part_of(u + 2), P, lane);
-            process_subtile<S, K, E, GRAD>(b, s_c, lane, u + 1, first_of(u + 1), n_events, ur, ui, fs);
+    if constexpr (K < 24) {
+        for (int64_t u = 0; u < U; u += 2) {
+            if (u + 1 < U) b.load(base_of(u + 1), part_of(u + 1), P, lane);
+            process_subtile<S, K, E, GRAD>(a, s_c, lane, u, first_of(u), n_events, ur, ui, fs);
+            if (u + 1 < U) {
+                if (u + 2 < U) a.load(base_of(u + 2), part_of(u + 2), P, lane);
+                process_subtile<S, K, E, GRAD>(b, s_c, lane, u + 1, first_of(u + 1), n_events, ur,
+                                               ui, fs);
+            }
+        }
+    } else {
+        // 24 or 32 slots: one buffer (two, with the accumulators, take 400 or
+        // more registers and spill at 32); its loads are in flight together
+        for (int64_t u = 0; u < U; ++u) {
+            if (u > 0) a.load(base_of(u), part_of(u), P, lane);
+            process_subtile<S, K, E, GRAD>(a, s_c, lane, u, first_of(u), n_events, ur, ui, fs);
         }
     }
 
@@ -739,7 +771,7 @@ int select_kslots(int P, bool c128)
 {
     (void)c128;
     const int need = (P + 63) / 64;
-    const int opts[] = {1, 2, 4, 8, 16, 33};
+    const int opts[] = {1, 2, 4, 8, 12, 16, 24, 32};
     for (int k : opts)
         if (k >= need) return k;
     return -1;
@@ -773,16 +805,20 @@ static bool with_shape(int K, int E, F&& f)
         PWA_SHAPE(4, 4)
         PWA_SHAPE(4, 8)
         PWA_SHAPE(8, 2)
+        PWA_SHAPE(12, 2)
         PWA_SHAPE(16, 2)
-        PWA_SHAPE(33, 2)
+        PWA_SHAPE(24, 2)
+        PWA_SHAPE(32, 2)
     } else {
         PWA_SHAPE(1, 8)
         PWA_SHAPE(2, 4)
         PWA_SHAPE(4, 2)
         PWA_SHAPE(4, 4)
         PWA_SHAPE(8, 1)
+        PWA_SHAPE(12, 1)
         PWA_SHAPE(16, 1)
-        PWA_SHAPE(33, 1)
+        PWA_SHAPE(24, 1)
+        PWA_SHAPE(32, 1)
     }
 #undef PWA_SHAPE
     return false;
