@@ -69,8 +69,8 @@ def _check(form, w, n, n_mc, seed, points=2, nll_rtol=1e-10, g_rtol=1e-9):
 
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("w,n", [(1, 1), (1, 33), (2, 17), (3, 100), (4, 1000), (7, 4099),
-                                 (11, 777), (20, 2049), (23, 300), (32, 1500), (48, 513),
-                                 (64, 130)])
+                                 (11, 777), (20, 2049), (23, 300), (32, 1500), (36, 400),
+                                 (44, 300), (48, 513), (56, 200), (64, 130)])
 def test_parity_small(form, w, n):
     _check(form, w, n, 3 * n + 7, seed=100 * w + n)
 
