@@ -502,11 +502,15 @@ __device__ inline double4 block_sum4(double4 x)
 // form; both enter as G_b = 2 (m_b - x_b)).  Role 0 forms the NLL and n_bad,
 // role 1 + b the gradient component b.  Every thread issues all of its loads
 // (its records in batches of kBatch, its share of M) before adding any, so
-// that the whole block waits about one memory round trip.
-__device__ void assemble_role_g(const double* v, const TailArgs& ta, int role,
+// that the whole block waits about one memory round trip per batch; V is
+// read from LDS.
+__device__ void assemble_role_g(const double* vg, const TailArgs& ta, int role,
                                 unsigned long long* word)
 {
+    __shared__ double s_v[2 * PWA_MAX_WAVES_AMPLITUDE];
     const int W = ta.W;
+    for (int e = threadIdx.x; e < 2 * W; e += blockDim.x) s_v[e] = vg[e];
+    const double* v = s_v;
     const int NT = blockDim.x;
     const int col = role == 0 ? 0 : 2 * role;   // record column of this role
     const int b = role - 1;
@@ -553,11 +557,24 @@ __device__ void assemble_role_g(const double* v, const TailArgs& ta, int role,
             mt.y += ti;
         }
     };
+    __syncthreads();   // s_v
 #pragma unroll
     for (int q = 0; q < kMaxM; ++q)
         if (threadIdx.x + q * NT < n_m) add_m(threadIdx.x + q * NT, mv[q]);
-    for (int k = threadIdx.x + kMaxM * NT; k < n_m; k += NT)
-        add_m(k, ta.M[role == 0 ? k : k * W + b]);
+    // the rest of M (W^2 > kMaxM NT), in the same order, kMaxM loads at a
+    // time issued before any is used (an entry past the last reads the last
+    // and is not added)
+    for (int k0 = threadIdx.x + kMaxM * NT; k0 < n_m; k0 += kMaxM * NT) {
+        double2 xm[kMaxM];
+#pragma unroll
+        for (int q = 0; q < kMaxM; ++q) {
+            const int k = min(k0 + q * NT, n_m - 1);
+            xm[q] = ta.M[role == 0 ? k : k * W + b];
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxM; ++q)
+            if (k0 + q * NT < n_m) add_m(k0 + q * NT, xm[q]);
+    }
     const double4 tot = block_sum4(make_double4(acc.x, acc.y, mt.x, mt.y));
     if (threadIdx.x == 0) {
         if (role == 0) {
