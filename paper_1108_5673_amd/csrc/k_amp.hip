@@ -433,9 +433,11 @@ namespace pwa {
 // Per block of 4 wavefronts, tiles of 64 events:
 //   1. the tile's amplitudes into LDS, one row per event (de-interleaving the
 //      lane-split layout);
-//   2. wavefront w takes events 16 w .. 16 w + 15 in 4 steps; per step the 16
-//      lanes of an event form partial S over waves i, i + 16, ..., sum them by
-//      an xor butterfly, then I, w = 2 / I and their J values in FP64;
+//   2. wavefront w takes events 16 w .. 16 w + 15: first S, I and w = 2 / I of
+//      all 16 at once (lane l: event l % 16, a quarter of the waves, two xor
+//      exchanges), then 4 steps of 4 events in which each lane fetches its
+//      event's S and w from the lane that formed them and forms its J values
+//      in FP64;
 //   3. one MFMA per block pair (bp of the block's group of rows, bq >= bp).
 // Row groups: the block pairs of rows g R .. g R + R - 1 (R = NB up to 4 blocks,
 // 2 up to 8, else 1) are one group along the grid's second dimension, each
@@ -562,13 +564,17 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
                 pre[q] = f < n_f4 ? src[f] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
-#pragma unroll 1
-        for (int st = 0; st < 4; ++st) {
-            const int ev = 16 * wave + 4 * st + ki;
+        // S, I and w = 2 / I of this wavefront's 16 events, once per event:
+        // lane l takes event l % 16 and the waves a = l / 16, l / 16 + 4, ...,
+        // and two xor exchanges (lanes 16 and 32 apart) add the four quarters,
+        // so every lane holds its event's S
+        double esr = 0.0, esi = 0.0, ew = 0.0;
+        {
+            const int eg = lane & 15, aq = lane >> 4;
+            const int ev = 16 * wave + eg;
             const char* row = tile + ev * stride;
-            // S over waves pi, pi + 16, ...; then summed over the event's 16 lanes
             double sr = 0.0, si = 0.0;
-            for (int a = pi; a < W; a += 16) {
+            for (int a = aq; a < W; a += 4) {
                 const float2 x = *reinterpret_cast<const float2*>(row + a * 8);
                 const double2 v = s_v[a];
                 sr = __fma_rn(v.x, (double)x.x, sr);
@@ -576,20 +582,29 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
                 si = __fma_rn(v.x, (double)x.y, si);
                 si = __fma_rn(v.y, (double)x.x, si);
             }
-            sr += xor_lane_f64<1>(sr);
-            si += xor_lane_f64<1>(si);
-            sr += xor_lane_f64<2>(sr);
-            si += xor_lane_f64<2>(si);
-            sr += xor_lane_f64<4>(sr);
-            si += xor_lane_f64<4>(si);
-            sr += xor_lane_f64<8>(sr);
-            si += xor_lane_f64<8>(si);
+            sr += xor_lane_f64<16>(sr);
+            si += xor_lane_f64<16>(si);
+            sr += xor_lane_f64<32>(sr);
+            si += xor_lane_f64<32>(si);
             const double I = sr * sr + si * si;
             const bool valid = t * kAmpTile + ev < n_events;
             const bool ok = valid && (I > 0.0) && (I < INFINITY);
-            if (pi == 0 && valid && !ok) ++nbad;
+            if (aq == 0 && valid && !ok) ++nbad;
             // NaN for a degenerate event (its J, and so H, become NaN), 0 for padding
-            const double w = ok ? 2.0 * recip_f64(I) : (valid ? NAN : 0.0);
+            esr = sr;
+            esi = si;
+            ew = ok ? 2.0 * recip_f64(I) : (valid ? NAN : 0.0);
+        }
+#pragma unroll 1
+        for (int st = 0; st < 4; ++st) {
+            const int ev = 16 * wave + 4 * st + ki;
+            const char* row = tile + ev * stride;
+            // this lane's event (4 st + ki of the wavefront's 16) from the
+            // lane that formed it
+            const int src = 4 * st + ki;
+            const double sr = __shfl(esr, src);
+            const double si = __shfl(esi, src);
+            const double w = __shfl(ew, src);
             // J_k[p] for parameter p = 16 b + pi: w Re z (p even) or -w Im z (p odd),
             // z = conj(S) A_{p / 2}
             auto jval = [&](int b) {
