@@ -25,6 +25,12 @@ counter set:
         SQ_INSTS_VALU SQ_BUSY_CU_CYCLES GRBM_GUI_ACTIVE -d <dir> -o raw \\
         --output-format csv -- python3 -m paper_1108_5673_amd.profiling run-batched
     python3 -m paper_1108_5673_amd.profiling busy <derived csv> <raw csv> <out.json>
+
+The same counters for the FUMILI matrix kernel (k_amp_hessian, nll_grad_hess on
+the 1M-event, 20-wave sample in the FP32 amplitude form):
+
+    rocprofv3 --pmc ... -- python3 -m paper_1108_5673_amd.profiling run-hess
+    python3 -m paper_1108_5673_amd.profiling counters k_amp_hessian <csv> ... <out.json>
 """
 from __future__ import annotations
 
@@ -93,6 +99,25 @@ def run_batched(reps: int = 4) -> None:
         torch.cuda.synchronize()
         m.close()
     print("profiling run done: %d batched passes of 256 vectors per form" % reps, flush=True)
+
+
+def run_hess(reps: int = 4) -> None:
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    import paper_1108_5673_amd as pwa
+    from paper_1108_5673_amd import synth
+
+    torch.cuda.init()
+    s = synth.make_sample("w20_n1m")
+    m = pwa.Model(s.data.astype(np.complex64), s.mc.astype(np.complex64), s.n_gen,
+                  form="amplitude")
+    for k in range(reps):
+        m.nll_grad_hess(s.points[k])
+    torch.cuda.synchronize()
+    m.close()
+    print("profiling run done: %d NLL + gradient + FUMILI matrix calls" % reps, flush=True)
 
 
 def _rows(path: str):
@@ -191,9 +216,32 @@ def busy(derived_csv: str, raw_csv: str, out_json: str) -> dict:
     return res
 
 
+def counters(needle: str, csvs, out_json: str) -> dict:
+    """Medians over the dispatches of the kernels named like `needle` of every
+    counter in the given rocprofv3 counter-collection files."""
+    res = {"kernel": needle, "counters": {}, "dispatches": {}, "names": []}
+    vals = {}
+    for path in csvs:
+        for r in _rows(path):
+            if needle in r["Kernel_Name"]:
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                if r["Kernel_Name"] not in res["names"]:
+                    res["names"].append(r["Kernel_Name"])
+    res["counters"] = {k: statistics.median(v) for k, v in vals.items()}
+    res["dispatches"] = {k: len(v) for k, v in vals.items()}
+    with open(out_json, "w") as fo:
+        json.dump(res, fo, indent=1)
+        fo.write("\n")
+    return res
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "run":
         run(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
+    elif len(sys.argv) >= 2 and sys.argv[1] == "run-hess":
+        run_hess(int(sys.argv[2]) if len(sys.argv) > 2 else 4)
+    elif len(sys.argv) >= 5 and sys.argv[1] == "counters":
+        print(json.dumps(counters(sys.argv[2], sys.argv[3:-1], sys.argv[-1]), indent=1))
     elif len(sys.argv) >= 2 and sys.argv[1] == "run-batched":
         run_batched(int(sys.argv[2]) if len(sys.argv) > 2 else 4)
     elif len(sys.argv) == 5 and sys.argv[1] == "busy":
