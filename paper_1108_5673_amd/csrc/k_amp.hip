@@ -606,15 +606,17 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
             const double si = __shfl(esi, src);
             const double w = __shfl(ew, src);
             // J_k[p] for parameter p = 16 b + pi: w Re z (p even) or -w Im z (p odd),
-            // z = conj(S) A_{p / 2}
+            // z = conj(S) A_{p / 2}: Re z = Sr Ar + Si Ai, -Im z = Si Ar - Sr Ai, so
+            // J = c1 Ar + c2 Ai with a lane's (c1, c2) = w (Sr, Si) or w (Si, -Sr)
+            // (the parity of p is the lane's)
+            const double c1 = w * ((pi & 1) ? si : sr);
+            const double c2 = w * ((pi & 1) ? -sr : si);
             auto jval = [&](int b) {
                 const int p = 16 * b + pi;
                 double j = 0.0;
                 if (p < 2 * W) {
                     const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
-                    const double zr = __fma_rn(sr, (double)x.x, si * (double)x.y);
-                    const double zi = __fma_rn(sr, (double)x.y, -si * (double)x.x);
-                    j = w * ((p & 1) ? -zi : zr);
+                    j = __fma_rn(c1, (double)x.x, c2 * (double)x.y);
                 }
                 return j;
             };
