@@ -812,6 +812,9 @@ __global__ __launch_bounds__(64 * kHessWideWaves) void k_amp_hessian_wide(
                 if (pj == 0 && valid && !ok) ++nbad;
                 // NaN for a degenerate event (its J, and so H, become NaN), 0 for padding
                 const double w = ok ? 2.0 * recip_f64(I) : (valid ? NAN : 0.0);
+                // J = c1 Re A + c2 Im A (the parity of p = pj + 32 m is the lane's)
+                const double c1 = w * ((pj & 1) ? si : sr);
+                const double c2 = w * ((pj & 1) ? -sr : si);
                 double* jrow = s_j + eh * XW;
 #pragma unroll
                 for (int m = 0; m < XW / 32; ++m) {
@@ -819,9 +822,7 @@ __global__ __launch_bounds__(64 * kHessWideWaves) void k_amp_hessian_wide(
                     double jv = 0.0;
                     if (p < 2 * W) {
                         const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
-                        const double zr = __fma_rn(sr, (double)x.x, si * (double)x.y);
-                        const double zi = __fma_rn(sr, (double)x.y, -si * (double)x.x);
-                        jv = w * ((p & 1) ? -zi : zr);
+                        jv = __fma_rn(c1, (double)x.x, c2 * (double)x.y);
                     }
                     jrow[p] = jv;
                 }
@@ -831,9 +832,7 @@ __global__ __launch_bounds__(64 * kHessWideWaves) void k_amp_hessian_wide(
                         double jv = 0.0;
                         if (p < 2 * W) {
                             const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
-                            const double zr = __fma_rn(sr, (double)x.x, si * (double)x.y);
-                            const double zi = __fma_rn(sr, (double)x.y, -si * (double)x.x);
-                            jv = w * ((p & 1) ? -zi : zr);
+                            jv = __fma_rn(c1, (double)x.x, c2 * (double)x.y);
                         }
                         jrow[p] = jv;
                     }
