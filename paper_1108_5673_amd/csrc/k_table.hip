@@ -591,7 +591,7 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
     for (int k = 0; k < K; ++k) { ur[k] = 0.0; ui[k] = 0.0; }
     FusedState fs{0.0, 1.0, 0};
 
-    if constexpr (K < 24) {
+    if constexpr (K < 20) {
         for (int64_t u = 0; u < U; u += 2) {
             if (u + 1 < U) b.load(base_of(u + 1), part_of(u + 1), P, lane);
             process_subtile<S, K, E, GRAD>(a, s_c, lane, u, first_of(u), n_events, ur, ui, fs);
@@ -602,8 +602,9 @@ __global__ __launch_bounds__((fused_threads<S, K, E>())) void k_table_fused(
             }
         }
     } else {
-        // 24 or 32 slots: one buffer (two, with the accumulators, take 400 or
-        // more registers and spill at 32); its loads are in flight together
+        // 20 or more slots: one buffer (two, with the accumulators, take 400
+        // or more registers from 24 slots and spill at 32); its loads are in
+        // flight together
         for (int64_t u = 0; u < U; ++u) {
             if (u > 0) a.load(base_of(u), part_of(u), P, lane);
             process_subtile<S, K, E, GRAD>(a, s_c, lane, u, first_of(u), n_events, ur, ui, fs);
@@ -771,7 +772,7 @@ int select_kslots(int P, bool c128)
 {
     (void)c128;
     const int need = (P + 63) / 64;
-    const int opts[] = {1, 2, 4, 8, 12, 16, 24, 32};
+    const int opts[] = {1, 2, 4, 8, 12, 16, 20, 24, 28, 32};
     for (int k : opts)
         if (k >= need) return k;
     return -1;
@@ -807,7 +808,9 @@ static bool with_shape(int K, int E, F&& f)
         PWA_SHAPE(8, 2)
         PWA_SHAPE(12, 2)
         PWA_SHAPE(16, 2)
+        PWA_SHAPE(20, 2)
         PWA_SHAPE(24, 2)
+        PWA_SHAPE(28, 2)
         PWA_SHAPE(32, 2)
     } else {
         PWA_SHAPE(1, 8)
@@ -817,7 +820,9 @@ static bool with_shape(int K, int E, F&& f)
         PWA_SHAPE(8, 1)
         PWA_SHAPE(12, 1)
         PWA_SHAPE(16, 1)
+        PWA_SHAPE(20, 1)
         PWA_SHAPE(24, 1)
+        PWA_SHAPE(28, 1)
         PWA_SHAPE(32, 1)
     }
 #undef PWA_SHAPE
