@@ -459,6 +459,10 @@ __host__ __device__ inline int amp_lds_stride_words(int wpad)
 }
 
 __host__ __device__ inline int hess_nb(int W) { return (2 * W + 15) / 16; }
+// Complex entries per LDS row of k_amp_hessian: at least 8 NB, so that
+// parameter 16 b + i of every block reads entry (16 b + i) / 2 of its row; the
+// entries past the stored wpad are zero.
+__host__ __device__ inline int hess_row_waves(int wpad, int nb) { return wpad > 8 * nb ? wpad : 8 * nb; }
 __host__ __device__ inline int hess_npair(int W)
 {
     const int nb = hess_nb(W);
@@ -476,7 +480,7 @@ inline int hess_groups(int W)
 template <int NB>
 __host__ __device__ constexpr size_t hess_lds_bytes(int wpad)
 {
-    const size_t tile = (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4;
+    const size_t tile = (size_t)kAmpTile * amp_lds_stride_words(hess_row_waves(wpad, NB)) * 4;
     const size_t combine = (size_t)64 * hess_rows_per_group(NB) * NB * 4 * 8;
     return (tile > combine ? tile : combine) + 16 * 128 /* V */ + 16;
 }
@@ -492,7 +496,8 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
     constexpr int R = hess_rows_per_group(NB);
     extern __shared__ double lds_d[];
     char* lds = reinterpret_cast<char*>(lds_d);
-    const int stride = amp_lds_stride_words(wpad) * 4;
+    const int row_waves = hess_row_waves(wpad, NB);
+    const int stride = amp_lds_stride_words(row_waves) * 4;
     const size_t main_bytes = hess_lds_bytes<NB>(wpad) - 16 * 128 - 16;
     char* tile = lds;
     double2* s_v = reinterpret_cast<double2*>(lds + main_bytes);
@@ -510,6 +515,13 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
     for (int a = tid; a < 128; a += blockDim.x)
         s_v[a] = a < W ? make_double2(vsrc(vp)[2 * a], vsrc(vp)[2 * a + 1]) : make_double2(0.0, 0.0);
     if (tid == 0) *s_bad = 0;
+    // the row entries past the stored ones, read by the padding parameters
+    // (staging never writes them; the loop's first barrier orders this)
+    const int n_extra = row_waves - wpad;
+    for (int e = tid; e < kAmpTile * n_extra; e += blockDim.x) {
+        const int ev = e / n_extra, a = wpad + e % n_extra;
+        *reinterpret_cast<float2*>(tile + ev * stride + a * 8) = make_float2(0.f, 0.f);
+    }
 
     hd4 D[R][NB];
 #pragma unroll
@@ -574,7 +586,12 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
             const int ev = 16 * wave + eg;
             const char* row = tile + ev * stride;
             double sr = 0.0, si = 0.0;
-            for (int a = aq; a < W; a += 4) {
+            // every entry a < 8 NB of the row is stored or zero and V is zero
+            // past W, so the loop runs to 8 NB without a test (the extra
+            // terms add exact zeros) and its loads are issued together
+#pragma unroll
+            for (int m = 0; m < 2 * NB; ++m) {
+                const int a = aq + 4 * m;
                 const float2 x = *reinterpret_cast<const float2*>(row + a * 8);
                 const double2 v = s_v[a];
                 sr = __fma_rn(v.x, (double)x.x, sr);
@@ -611,14 +628,12 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
             // (the parity of p is the lane's)
             const double c1 = w * ((pi & 1) ? si : sr);
             const double c2 = w * ((pi & 1) ? -sr : si);
+            // a parameter past 2W reads a zero entry of the row, so its J is
+            // zero (NaN for a degenerate event, in rows and columns of the
+            // block pairs that are never read); no load waits behind a branch
             auto jval = [&](int b) {
-                const int p = 16 * b + pi;
-                double j = 0.0;
-                if (p < 2 * W) {
-                    const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
-                    j = __fma_rn(c1, (double)x.x, c2 * (double)x.y);
-                }
-                return j;
+                const float2 x = *reinterpret_cast<const float2*>(row + (8 * b + (pi >> 1)) * 8);
+                return __fma_rn(c1, (double)x.x, c2 * (double)x.y);
             };
             double Jv[NB];
 #pragma unroll
@@ -688,7 +703,10 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
 //   2. per half tile of 32 events: wavefront w takes events 2w and 2w + 1,
 //      32 lanes each; S over waves pi, pi + 32, ... and an xor butterfly
 //      over the 32 lanes, then w = 2 / I and J_p for p = pi + 32 m into an
-//      LDS row of 16 NB doubles (zero beyond 2W);
+//      LDS row of 16 NB doubles (zero beyond 2W, or NaN for a degenerate
+//      event, in rows and columns of the blocks that are never read); the
+//      amplitude rows hold hess_wide_row_waves entries, those past the stored
+//      wpad zero, so that neither loop tests its index against W;
 //   3. per step of 4 events, one MFMA per owned pair with both operands read
 //      from the J rows (lane l: event l / 16 of the step, parameter l % 16).
 // Each pair has one owner, which writes its 16 x 16 block straight into the
@@ -696,9 +714,15 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
 constexpr int kHessWideWaves = 16;
 constexpr int kHessWideHalf = 32;   // events per J stage
 
+// Complex entries per amplitude row of the wide kernel (wpad <= 8 NB): a
+// multiple of 32, so that lane pi of the S loop reads pi + 32 m for a fixed
+// count of m.
+__host__ __device__ constexpr int hess_wide_row_waves(int nb) { return 32 * ((8 * nb + 31) / 32); }
+
 __host__ __device__ inline size_t hess_wide_lds_bytes(int wpad, int nb)
 {
-    return (size_t)kAmpTile * amp_lds_stride_words(wpad) * 4       // amplitude rows
+    (void)wpad;
+    return (size_t)kAmpTile * amp_lds_stride_words(hess_wide_row_waves(nb)) * 4   // amplitude rows
            + (size_t)kHessWideHalf * 16 * nb * 8                    // J rows
            + 16 * 128 /* V */ + 16;
 }
@@ -713,9 +737,10 @@ __global__ __launch_bounds__(64 * kHessWideWaves) void k_amp_hessian_wide(
     constexpr int PPW = (NPAIR + kHessWideWaves - 1) / kHessWideWaves;
     constexpr int XW = 16 * NB;                       // J row (doubles)
     constexpr int PRE = (kAmpTile * 8 * NB / 2 + NT - 1) / NT;   // float4 per thread (wpad <= 8 NB)
+    constexpr int RW = hess_wide_row_waves(NB);
     extern __shared__ double lds_d[];
     char* lds = reinterpret_cast<char*>(lds_d);
-    const int stride = amp_lds_stride_words(wpad) * 4;
+    const int stride = amp_lds_stride_words(RW) * 4;
     char* tile = lds;
     double* s_j = reinterpret_cast<double*>(lds + (size_t)kAmpTile * stride);
     double2* s_v = reinterpret_cast<double2*>(lds + (size_t)kAmpTile * stride +
@@ -728,6 +753,13 @@ __global__ __launch_bounds__(64 * kHessWideWaves) void k_amp_hessian_wide(
     for (int a = tid; a < 128; a += NT)
         s_v[a] = a < W ? make_double2(vsrc(vp)[2 * a], vsrc(vp)[2 * a + 1]) : make_double2(0.0, 0.0);
     if (tid == 0) *s_bad = 0;
+    // the row entries past the stored ones (staging never writes them; the
+    // loop's first barrier orders this)
+    const int n_extra = RW - wpad;
+    for (int e = tid; e < kAmpTile * n_extra; e += NT) {
+        const int ev = e / n_extra, a = wpad + e % n_extra;
+        *reinterpret_cast<float2*>(tile + ev * stride + a * 8) = make_float2(0.f, 0.f);
+    }
 
     // this wavefront's block pairs (bp <= bq, row-major), as column offsets
     int pt[PPW], pu[PPW];
@@ -788,7 +820,11 @@ __global__ __launch_bounds__(64 * kHessWideWaves) void k_amp_hessian_wide(
                 const int ev = kHessWideHalf * half + eh;     // event within the tile
                 const char* row = tile + ev * stride;
                 double sr = 0.0, si = 0.0;
-                for (int a = pj; a < W; a += 32) {
+                // entries up to RW are stored or zero and V is zero past W:
+                // no test, the loads issued together, the extra terms zero
+#pragma unroll
+                for (int m = 0; m < RW / 32; ++m) {
+                    const int a = pj + 32 * m;
                     const float2 x = *reinterpret_cast<const float2*>(row + a * 8);
                     const double2 v = s_v[a];
                     sr = __fma_rn(v.x, (double)x.x, sr);
@@ -816,25 +852,18 @@ __global__ __launch_bounds__(64 * kHessWideWaves) void k_amp_hessian_wide(
                 const double c1 = w * ((pj & 1) ? si : sr);
                 const double c2 = w * ((pj & 1) ? -sr : si);
                 double* jrow = s_j + eh * XW;
+                // a parameter past 2W reads a zero entry (p / 2 < 8 NB <= RW)
 #pragma unroll
                 for (int m = 0; m < XW / 32; ++m) {
                     const int p = pj + 32 * m;
-                    double jv = 0.0;
-                    if (p < 2 * W) {
-                        const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
-                        jv = __fma_rn(c1, (double)x.x, c2 * (double)x.y);
-                    }
-                    jrow[p] = jv;
+                    const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
+                    jrow[p] = __fma_rn(c1, (double)x.x, c2 * (double)x.y);
                 }
                 if constexpr (XW % 32 != 0) {
                     const int p = pj + 32 * (XW / 32);
                     if (p < XW) {
-                        double jv = 0.0;
-                        if (p < 2 * W) {
-                            const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
-                            jv = __fma_rn(c1, (double)x.x, c2 * (double)x.y);
-                        }
-                        jrow[p] = jv;
+                        const float2 x = *reinterpret_cast<const float2*>(row + (p >> 1) * 8);
+                        jrow[p] = __fma_rn(c1, (double)x.x, c2 * (double)x.y);
                     }
                 }
             }
