@@ -170,12 +170,19 @@ __device__ __attribute__((always_inline)) void amp_block(const float4* __restric
         auto kof = [&](int64_t j) { return k0 + wave + (int64_t)nwaves * j; };
         AmpRegs<WL> ra, rb;
         amp_load(ra, base + kof(0) * kStepVecs);
+        // No load is under a test: past the last step a load reads the step
+        // just loaded again (cached; it is not used).  A load under a test
+        // made the compiler copy its registers at the join, which waited for
+        // the load it had just issued; now each step waits only for its own
+        // buffer while the other buffer's loads stay in flight.
         for (int64_t j = 0; j < J; j += 2) {
             const bool has_b = j + 1 < J;
-            if (has_b) amp_load(rb, base + kof(j + 1) * kStepVecs);
+            const int64_t j1 = has_b ? j + 1 : j;
+            amp_load(rb, base + kof(j1) * kStepVecs);
             amp_step<WL, GRAD>(ra, st, (kof(j) << R_shift) + (lane >> lq), n_events, lq, sub,
                                (int)(j & (q - 1)));
-            if (j + 2 < J) amp_load(ra, base + kof(j + 2) * kStepVecs);
+            const int64_t j2 = j + 2 < J ? j + 2 : j1;
+            amp_load(ra, base + kof(j2) * kStepVecs);
             if (has_b)
                 amp_step<WL, GRAD>(rb, st, (kof(j + 1) << R_shift) + (lane >> lq), n_events, lq,
                                    sub, (int)((j + 1) & (q - 1)));
