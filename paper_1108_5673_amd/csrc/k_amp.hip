@@ -439,7 +439,8 @@ namespace pwa {
 // register r), so the J values a lane forms feed the matrix cores directly.
 // Per block of 4 wavefronts, tiles of 64 events:
 //   1. the tile's amplitudes into LDS, one row per event (de-interleaving the
-//      lane-split layout);
+//      lane-split layout), each row at least 8 NB entries long and zero past
+//      the stored ones, so that no read of a row tests its index;
 //   2. wavefront w takes events 16 w .. 16 w + 15: first S, I and w = 2 / I of
 //      all 16 at once (lane l: event l % 16, a quarter of the waves, two xor
 //      exchanges), then 4 steps of 4 events in which each lane fetches its

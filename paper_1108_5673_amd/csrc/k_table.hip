@@ -768,6 +768,9 @@ static const void* fused_fn()
     return (const void*)&k_table_fused<S, K, E, true>;
 }
 
+// Slots of 64 stored entries per lane: the fewest instantiated count that
+// holds the P entries of an event.  From 8 on the counts step by 4 (every
+// even count was measured and gave nothing more); 32 holds W <= 64.
 int select_kslots(int P, bool c128)
 {
     (void)c128;
