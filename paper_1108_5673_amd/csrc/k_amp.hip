@@ -443,9 +443,9 @@ namespace pwa {
 //      the stored ones, so that no read of a row tests its index;
 //   2. wavefront w takes events 16 w .. 16 w + 15: first S, I and w = 2 / I of
 //      all 16 at once (lane l: event l % 16, a quarter of the waves, two xor
-//      exchanges), then 4 steps of 4 events in which each lane fetches its
-//      event's S and w from the lane that formed them and forms its J values
-//      in FP64;
+//      exchanges, then w S), then 4 steps of 4 events in which each lane
+//      fetches its event's w S from the lane that formed it and forms its J
+//      values in FP64;
 //   3. one MFMA per block pair (bp of the block's group of rows, bq >= bp).
 // Row groups: the block pairs of rows g R .. g R + R - 1 (R = NB up to 4 blocks,
 // 2 up to 8, else 1) are one group along the grid's second dimension, each
@@ -616,9 +616,9 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
             const bool ok = valid && (I > 0.0) && (I < INFINITY);
             if (aq == 0 && valid && !ok) ++nbad;
             // NaN for a degenerate event (its J, and so H, become NaN), 0 for padding
-            esr = sr;
-            esi = si;
             ew = ok ? 2.0 * recip_f64(I) : (valid ? NAN : 0.0);
+            esr = ew * sr;   // w Sr and w Si, the J coefficients of the event
+            esi = ew * si;
         }
 #pragma unroll 1
         for (int st = 0; st < 4; ++st) {
@@ -627,15 +627,14 @@ __global__ __launch_bounds__(kHessThreads) void k_amp_hessian(const float4* __re
             // this lane's event (4 st + ki of the wavefront's 16) from the
             // lane that formed it
             const int src = 4 * st + ki;
-            const double sr = __shfl(esr, src);
-            const double si = __shfl(esi, src);
-            const double w = __shfl(ew, src);
+            const double wsr = __shfl(esr, src);
+            const double wsi = __shfl(esi, src);
             // J_k[p] for parameter p = 16 b + pi: w Re z (p even) or -w Im z (p odd),
             // z = conj(S) A_{p / 2}: Re z = Sr Ar + Si Ai, -Im z = Si Ar - Sr Ai, so
-            // J = c1 Ar + c2 Ai with a lane's (c1, c2) = w (Sr, Si) or w (Si, -Sr)
-            // (the parity of p is the lane's)
-            const double c1 = w * ((pi & 1) ? si : sr);
-            const double c2 = w * ((pi & 1) ? -sr : si);
+            // J = c1 Ar + c2 Ai with a lane's (c1, c2) = (w Sr, w Si) or
+            // (w Si, -w Sr) (the parity of p is the lane's)
+            const double c1 = (pi & 1) ? wsi : wsr;
+            const double c2 = (pi & 1) ? -wsr : wsi;
             // a parameter past 2W reads a zero entry of the row, so its J is
             // zero (NaN for a degenerate event, in rows and columns of the
             // block pairs that are never read); no load waits behind a branch
