@@ -111,3 +111,24 @@ def test_counters_takes_medians_over_files(tmp_path):
 ])
 def test_busy_files_each_instance_under_its_type(name, bf16):
     assert profiling._is_bf16(name) == bf16
+
+
+@pytest.mark.parametrize("bf16,counted", [(True, 6.509e6), (False, 7.011e6)])
+def test_batched_mfma_flops_agree_with_the_instruction_counter(bf16, counted):
+    """bench.py's issued matrix-core FLOPs of one batched pass (10^6 events,
+    W = 20, K = 256, V in two parts) against the matrix-core instructions the
+    hardware counted for that pass (SQ_INSTS_MFMA medians per dispatch in
+    profiles/amp_mfma_w20_n1m_k256_busy.md): the pass issues per 16-event
+    tile and 32 vectors 6 forward (5 for bf16, whose second V part's last
+    K-step rides in the first part's padding) and 4 adjoint 32x32x16 MFMAs of
+    32768 FLOP and 4 adjoint 16x16x32 MFMAs of 16384 FLOP."""
+    bench = _bench_module()
+    n, w, k = 1_000_000, 20, 256
+    per_tile_col = {"32x32x16": (5 if bf16 else 6) + 4, "16x16x32": 4}
+    tile_cols = (n // 16) * (k // 32)
+    insts = tile_cols * sum(per_tile_col.values())
+    # the counter reads 0.14-0.16 % more instructions than this count
+    assert abs(insts / counted - 1) < 2e-3
+    flops = tile_cols * (per_tile_col["32x32x16"] * 32768 + per_tile_col["16x16x32"] * 16384)
+    assert bench.mfma_flops(n, w, k, 2, bf16=bf16) == flops
+    assert bench.mfma_algorithmic_flops(n, w, k, 2) == 8 * n * w * k * 4
