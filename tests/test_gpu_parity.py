@@ -351,3 +351,27 @@ def test_read_ceiling():
     # 200 stored entries per event at W = 20: 10 diagonal pairs + 190 off-diagonal
     assert r["bytes"] == 200_000 * 200 * 8 and r["ms"] > 0 and 0 < r["gbs"] < 50_000
     model.close()
+
+
+@pytest.mark.parametrize("form,e", [("table", 8), ("table_fp64", 4)])
+def test_table_subtile_override(form, e, monkeypatch):
+    """The sub-tile widths kept for tuning (PWA_TABLE_SUBTILE, read when a
+    model is built): 8 events per sub-tile for the complex64 table at W = 20,
+    4 for the complex128 one, against the oracle with a ragged last tile."""
+    monkeypatch.setenv("PWA_TABLE_SUBTILE", str(e))
+    _check(form, 20, 2049, 3 * 2049 + 7, seed=2017)
+
+
+def test_table_subtile_override_falls_back(monkeypatch):
+    """A width with no kernel instance is ignored: the model keeps its default
+    shape and gives the default model's results bit for bit."""
+    s = synth.small_sample(20, 1500, 2000, seed=2018, n_points=1)
+    d, m = s.data.astype(np.complex64), s.mc.astype(np.complex64)
+    ref = pwa.Model(d, m, 4000, form="table")
+    monkeypatch.setenv("PWA_TABLE_SUBTILE", "3")
+    odd = pwa.Model(d, m, 4000, form="table")
+    (n0, g0), (n1, g1) = ref.nll_grad(s.points[0]), odd.nll_grad(s.points[0])
+    assert n0 == n1 and np.array_equal(g0, g1)
+    assert odd.info()["grid_blocks"] == ref.info()["grid_blocks"]
+    ref.close()
+    odd.close()
